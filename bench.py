@@ -1,0 +1,188 @@
+"""Benchmark: time-to-solution of the mixed-precision temporal+Schur (3D ILU)
+BiCGStab solve against the plain FP64 4D even-odd Schur BiCGStab solve, on one
+MI355X, plus the dominant operator kernel's HBM throughput.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload clover_32x256]
+
+A step is one solve M x = eta to a true relative residual of 1e-10 from a
+device-resident Gaussian source to a device-resident solution, including the
+source preparation, all iterations, the reconstruction and the FP64 true-residual
+checks; the one-off set-up (link layouts, time-line products, clover term) is
+timed separately.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-solution @1e-10 resid (mixed vs FP64 even-odd); operator HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="clover_32x256")
+    ap.add_argument("--prec", default="F32", help="inner precision of the mixed solve")
+    ap.add_argument("--no-baseline", action="store_true", help="skip the FP64 even-odd solve")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-prof", action="store_true", help="no per-kernel events in the timed region")
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, applies):
+    """The FP64 oracle's preconditioned operator timed on a 16^3x16 slab of the workload
+    (same anisotropy, mass, clover and link ensemble parameters); one apply costs the
+    same per site, so the solve time is extrapolated by volume and by the GPU solve's
+    apply count."""
+    import numpy as np
+
+    import synth
+    from oracle.schemes import Operator
+
+    sample = (16, 16, 16, 16)
+    xi = cfg["xi"]
+    U = synth.make_links(sample, cfg["eps_s"], cfg["eps_t"], cfg["seed"])
+    eta = synth.make_source(sample, 2000)
+    op = Operator(U, cfg["m0"], xi, -1.0, cfg["csw_s"] / xi, cfg["csw_t"])
+    op.prec("TEMPORAL_SCHUR", eta)  # warm-up
+    ts = []
+    t_end = time.perf_counter() + 12.0
+    while time.perf_counter() < t_end or len(ts) < 2:
+        t0 = time.perf_counter()
+        op.prec("TEMPORAL_SCHUR", eta)
+        ts.append(time.perf_counter() - t0)
+    t_apply = float(np.median(ts))
+    lx, ly, lz, lt = cfg["dims"]
+    scale = (lx * ly * lz * lt) / float(np.prod(sample))
+    return {
+        "value": t_apply * scale * applies,
+        "unit": "s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{len(ts)} oracle applies of S_L M S_R on a 16^3x16 slab of the workload, "
+                   f"median {t_apply:.3f} s, x{scale:.0f} volume x{applies} applies of the GPU "
+                   f"solve (extrapolated; NumPy single-threaded element-wise work)"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the multi-GPU path is a design note only)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_0910_0992_amd import Operator
+
+    cfg = synth.WORKLOADS[args.workload]
+    dims, xi, m0 = cfg["dims"], cfg["xi"], cfg["m0"]
+    c_s, c_t = cfg["csw_s"] / xi, cfg["csw_t"]
+    dev = torch.device("cuda", 0)
+    print(f"[bench] workload {args.workload} dims {dims}: generating inputs", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    U = synth.make_links(dims, cfg["eps_s"], cfg["eps_t"], cfg["seed"])
+    eta_h = synth.make_source(dims, 2000)
+    print(f"[bench] inputs ready in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    Ud = torch.from_numpy(U).to(dev)
+    eta = torch.from_numpy(eta_h).to(dev)
+    del U
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = Operator(Ud, m0, xi, c_s, c_t, -1)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    del Ud
+    plaq = op.plaquette()
+    print(f"[bench] set-up {setup_s:.2f} s, plaquette s/t {plaq[0]:.4f}/{plaq[1]:.4f}", file=sys.stderr,
+          flush=True)
+
+    def run(scheme, prec, steps, warmup, prof):
+        infos = []
+        for _ in range(warmup):
+            op.solve(eta, scheme=scheme, prec=prec, tol=1e-10)
+            print(f"[bench] warm-up {scheme}/{prec} done", file=sys.stderr, flush=True)
+        if prof:
+            op.profile(True)
+            op.profile_reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            x, info = op.solve(eta, scheme=scheme, prec=prec, tol=1e-10)
+            infos.append(info)
+            print(f"[bench] {scheme}/{prec} step {k}: {info['ms']:.1f} ms, {info['iters']} iters, "
+                  f"{info['outer_iters']} cycles, true resid {info['true_rel_resid']:.2e}",
+                  file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        stats = op.profile_stats() if prof else {}
+        if prof:
+            op.profile(False)
+        return wall / steps, infos, stats, x
+
+    tts, infos, stats, x = run("TEMPORAL_SCHUR", args.prec, args.steps, args.warmup, not args.no_prof)
+    res = {
+        "metric": METRIC,
+        "value": tts,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": tts * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec.lower().replace("f16n", "f16+norm") + " inner / f64 outer",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"Wilson-clover {dims[0]}^3x{dims[3]}, xi={xi}, csw_s={cfg['csw_s']}, "
+                         f"csw_t={cfg['csw_t']}, m0={m0}, eps_s={cfg['eps_s']}, eps_t={cfg['eps_t']}, "
+                         "antiperiodic time; temporal+3D-ILU mixed-precision BiCGStab to 1e-10"),
+            "scheme": "TEMPORAL_SCHUR",
+            "solver": "BiCGStab + FP64 defect correction",
+            "inner_prec": args.prec,
+        },
+        "iters": infos[-1]["iters"],
+        "applies": infos[-1]["applies"],
+        "outer_cycles": infos[-1]["outer_iters"],
+        "true_rel_resid": max(i["true_rel_resid"] for i in infos),
+        "setup_s": setup_s,
+        "plaquette_s_t": plaq,
+    }
+    if stats:
+        ops = {k: v for k, v in stats.items() if k not in ("blas", "reduce_finish", "pack_unpack")}
+        dom = max(ops, key=lambda k: ops[k]["ms"])
+        d = stats[dom]
+        avg_ms = d["ms"] / d["launches"]
+        bytes_per = d["bytes"] / d["launches"]
+        gbs = bytes_per / (avg_ms * 1e-3) / 1e9
+        res["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": gbs, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                           "avg_ms": avg_ms, "bytes_per_launch": bytes_per, "launches": d["launches"]}
+        res["kernels"] = {k: {"launches": v["launches"], "avg_ms": v["ms"] / v["launches"],
+                              "GBs": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None,
+                              "share": v["ms"] / sum(s["ms"] for s in stats.values())}
+                          for k, v in stats.items()}
+    if not args.no_baseline:
+        btts, binfos, _, xb = run("SCHUR4D", "F64", max(1, args.steps - 1), min(args.warmup, 1), False)
+        res["fp64_even_odd_tts_s"] = btts
+        res["fp64_even_odd_iters"] = binfos[-1]["iters"]
+        res["speedup_vs_fp64_even_odd"] = btts / tts
+        rel = (torch.linalg.vector_norm(x - xb) / torch.linalg.vector_norm(xb)).item()
+        res["rel_diff_vs_fp64_even_odd_solution"] = rel
+    res["cpu_baseline"] = None if args.no_cpu else cpu_baseline(cfg, res["applies"])
+    op.close()
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * tprec.h - C ABI of the temporally preconditioned anisotropic Wilson / SW
+ * fermion solver for AMD Instinct MI355X (gfx950).
+ *
+ * Method: B. Joo, R. G. Edwards, M. J. Peardon, "An anisotropic preconditioning
+ * for the Wilson fermion matrix on the lattice" (arXiv:0910.0992).  Section
+ * references below are to that paper.
+ *
+ * The library solves (Sec. I)  M x = eta  with (Sec. II)
+ *     M = A + mu - D_t - D_s / gamma_f,   mu = m0 + 1 + 3 / gamma_f,
+ * on an Lx x Ly x Lz x Lt lattice, periodic in space, with time boundary
+ * phase b = +1 (periodic) or -1 (antiperiodic).  A is the SW clover term
+ * (zero for Wilson fermions).  The temporal matrix T (Sec. II.A) is inverted
+ * exactly per time line, and combined with 3D even-odd ("temporal + Schur")
+ * preconditioning (Sec. II.B).
+ *
+ * Conventions
+ *   Canonical spinor: complex128, C order [Lt][Lz][Ly][Lx][4 spin][3 colour],
+ *     spin in the Dirac-Pauli basis (gamma_t = diag(1,1,-1,-1)),
+ *     gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_5 = g_x g_y g_z g_t.
+ *   Canonical links: complex128 [4 dir][Lt][Lz][Ly][Lx][3][3], dir 0=x 1=y 2=z 3=t;
+ *     U_mu(x) multiplies psi(x + mu) in the forward hop.
+ *   Every spinor pointer passed to an apply/solve entry point is a DEVICE
+ *   pointer to a canonical spinor, owned by the caller.  The library never
+ *   frees caller memory and keeps no caller pointer after a call returns.
+ *   Requirements: Lx, Ly, Lz even and >= 2, Lt >= 2; SCHUR4D needs Lt even.
+ *
+ * Streams and synchronisation
+ *   All GPU work is enqueued on the stream set with tp_ctx_set_stream (default:
+ *   the null stream).  Apply entry points do not synchronise.  tp_solve and
+ *   the create functions synchronise the stream (they need scalars on the host).
+ *   A handle may be used by one host thread at a time.
+ *
+ * Errors
+ *   Every entry point returns a tp_status.  On failure a message is available
+ *   from tp_last_error() (thread-local, valid until the next call on the thread).
+ */
+#ifndef TPREC_H
+#define TPREC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tp_status;
+enum {
+  TP_OK = 0,
+  TP_EINVAL = -1,      /* null pointer, bad enum value, NaN/Inf in an input     */
+  TP_EDIMS = -2,       /* odd spatial extent, Lt < 2, odd Lt for SCHUR4D        */
+  TP_ESINGULAR = -3,   /* closure matrix or clover block numerically singular  */
+  TP_ENOCONV = -4,     /* solver hit its iteration cap; x holds the best iterate */
+  TP_EBREAKDOWN = -5,  /* BiCGStab breakdown that restarts could not cure      */
+  TP_ENOMEM = -6,      /* device allocation failed                             */
+  TP_EHIP = -7         /* other HIP runtime error                              */
+};
+
+enum { TP_HOST = 0, TP_DEVICE = 1 };
+
+/* Preconditioning schemes (Sec. II.A-B). */
+enum {
+  TP_UNPREC = 0,          /* M itself                                              */
+  TP_SCHUR4D = 1,         /* 4D even-odd Schur: diag(A+mu, S-hat) with p4 parity  */
+  TP_TEMPORAL = 2,        /* C_L M C_R  (eq:ContaminatedUnprec for clover)        */
+  TP_TEMPORAL_SCHUR = 3   /* S_L M S_R with p3 parity: eq:TPrecFull (Wilson),
+                             eq:TPrecPartial = 3D ILU (clover)                    */
+};
+
+enum { TP_CGNR = 0, TP_BICGSTAB = 1 };
+
+/* Arithmetic/storage precision of the operator applies. */
+enum {
+  TP_F64 = 0,    /* FP64 storage and arithmetic                                  */
+  TP_F32 = 1,    /* FP32 storage and arithmetic                                  */
+  TP_F16N = 2    /* FP16 spinors with one FP32 scale per half-spinor and site,
+                    FP32 links and clover, FP32 arithmetic                        */
+};
+
+typedef struct tp_ctx_s* tp_ctx;
+typedef struct tp_gauge_s* tp_gauge;
+typedef struct tp_clover_s* tp_clover;
+typedef struct tp_op_s* tp_op;
+
+/* ---- context ------------------------------------------------------------- */
+
+/* Lattice geometry (dims = {Lx, Ly, Lz, Lt}), fermion time boundary phase
+ * bc_t = +1 or -1 (Sec. II.A, the corner of T), and HIP device ordinal.
+ * Returns TP_EDIMS for odd spatial extents or Lt < 2. */
+tp_status tp_ctx_create(const int32_t dims[4], int32_t bc_t, int32_t device, tp_ctx* out);
+tp_status tp_ctx_destroy(tp_ctx ctx);
+/* hip_stream is a hipStream_t (NULL = default stream). */
+tp_status tp_ctx_set_stream(tp_ctx ctx, void* hip_stream);
+
+/* ---- gauge field ------------------------------------------------------------
+ * Copies the canonical links (host or device pointer, per `where`) into the
+ * library's layouts and prepares the per-time-line products used by T^-1:
+ * W(t) = U_t(t) U_t(t+1) ... U_t(Lt-1) with the boundary phase folded into the
+ * last link; W(0) is the Polyakov loop (Sec. II.A, the closed form of X). */
+tp_status tp_gauge_create(tp_ctx ctx, const void* links, int32_t where, tp_gauge* out);
+tp_status tp_gauge_destroy(tp_gauge g);
+/* Mean plaquette diagnostics: spatial and temporal (1/3 Re tr) averages. */
+tp_status tp_gauge_plaquette(tp_gauge g, double* plaq_s, double* plaq_t);
+
+/* ---- clover term --------------------------------------------------------------
+ * A = -(c_t/2) sum_i sigma_{it} F_{it} - (c_s/2) sum_{i<j} sigma_{ij} F_{ij}
+ * (Sec. II, SW term) from four-leaf clover F_{mu nu}.  c_s, c_t are the
+ * literal coefficients of that formula. */
+tp_status tp_clover_create(tp_gauge g, double c_s, double c_t, tp_clover* out);
+tp_status tp_clover_destroy(tp_clover c);
+
+/* ---- operator -------------------------------------------------------------------
+ * Binds M to (links, clover or NULL for Wilson, m0, gamma_f).  Computes the
+ * closure of the temporal inverse per line, K = (I - mu^-Lt P)^-1 with P the
+ * Polyakov loop including the phase (the Woodbury matrix Lambda of Sec. II.A),
+ * in FP64; returns TP_ESINGULAR if its condition number exceeds 1e12.  Also
+ * factorises (A + mu) per site for SCHUR4D (TP_ESINGULAR on a zero pivot). */
+tp_status tp_op_create(tp_gauge g, tp_clover c, double m0, double gamma_f, tp_op* out);
+tp_status tp_op_destroy(tp_op op);
+
+/* ---- applies (canonical device spinors in and out, dst != src) -----------------
+ * `prec` selects the precision of the internal apply (TP_F64/F32/F16N); input
+ * and output stay complex128.  `dagger` = 1 applies the adjoint. */
+
+/* M psi (Sec. II). */
+tp_status tp_apply_M(tp_op op, int32_t prec, void* dst, const void* src, int32_t dagger);
+/* D_s psi = sum_i [P-^i U_i(x) psi(x+i) + P+^i U_i(x-i)^dag psi(x-i)] (Sec. II). */
+tp_status tp_apply_Ds(tp_op op, int32_t prec, void* dst, const void* src);
+/* A psi, or (A+mu) psi when plus_mu = 1, or (A+mu)^-1 psi when plus_mu = -1. */
+tp_status tp_apply_clover(tp_op op, int32_t prec, void* dst, const void* src, int32_t plus_mu);
+/* T^-1 (dagger=0) or (T^dagger)^-1 (dagger=1) on all four spins, each spatial
+ * site independently (Sec. II.A, SMW algorithm). */
+tp_status tp_apply_Tinv(tp_op op, int32_t prec, void* dst, const void* src, int32_t dagger);
+/* C_L = P+ + P- T^-1 and C_R = P- + P+ (T^dagger)^-1 (Sec. II.A). */
+tp_status tp_apply_CL(tp_op op, int32_t prec, void* dst, const void* src);
+tp_status tp_apply_CR(tp_op op, int32_t prec, void* dst, const void* src);
+/* The preconditioned operator Mt of `scheme` on the full lattice:
+ *   UNPREC M; SCHUR4D diag(A+mu, (A+mu) - D_w^oe (A+mu)^-1 D_w^eo) in p4 parity;
+ *   TEMPORAL C_L M C_R; TEMPORAL_SCHUR S_L M S_R in p3 parity. */
+tp_status tp_apply_prec(tp_op op, int32_t scheme, int32_t prec, void* dst, const void* src,
+                        int32_t dagger);
+/* eta~ = S_L eta and x = S_R y, with M = S_L^-1 Mt S_R^-1 for `scheme`
+ * (SCHUR4D: S_L = L^-1, S_R = U^-1 of the LDU factorisation, Sec. II.B). */
+tp_status tp_prepare_source(tp_op op, int32_t scheme, int32_t prec, void* eta_tilde,
+                            const void* eta);
+tp_status tp_reconstruct(tp_op op, int32_t scheme, int32_t prec, void* x, const void* y);
+
+/* ---- solve ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t scheme;          /* TP_UNPREC ... TP_TEMPORAL_SCHUR                       */
+  int32_t solver;          /* TP_CGNR or TP_BICGSTAB                                */
+  int32_t prec;            /* inner precision: TP_F64, TP_F32, TP_F16N              */
+  int32_t max_iter;        /* cap on inner Krylov iterations summed over restarts  */
+  int32_t max_restarts;    /* cap on outer (defect-correction) cycles               */
+  int32_t use_x0;          /* 1: x holds the initial guess on entry                 */
+  int32_t estimate_kappa;  /* 1 (CGNR only): Lanczos estimate of kappa(Mt^dag Mt)  */
+  int32_t reserved;
+  double tol;              /* target true relative residual |eta - M x| / |eta|     */
+  double inner_tol;        /* relative reduction per inner solve; 0 = default
+                              (1e-12 F64, 1e-6 F32, 2e-3 F16N)                      */
+} tp_solve_params;
+
+typedef struct {
+  int32_t iters;           /* inner Krylov iterations, all cycles                   */
+  int32_t outer_iters;     /* defect-correction cycles                              */
+  int32_t applies;         /* preconditioned-operator applies                       */
+  int32_t restarts;        /* BiCGStab breakdown restarts                           */
+  double true_rel_resid;   /* FP64 |eta - M x| / |eta| at exit                      */
+  double prec_rel_resid;   /* last inner relative residual                          */
+  double kappa_est;        /* Lanczos kappa of Mt^dag Mt (CGNR), else 0             */
+  double lambda_min, lambda_max;
+  double ms;               /* wall time of the solve                                */
+} tp_solve_info;
+
+/* Solves M x = eta (canonical device spinors) to the FP64 true relative
+ * residual `tol`: eta~ = S_L r, Krylov on Mt y = eta~ in `prec`, x += S_R y,
+ * r = eta - M x in FP64, repeated until |r| <= tol |eta| (defect correction).
+ * Returns TP_ENOCONV with x = best iterate if the caps are reached. */
+tp_status tp_solve(tp_op op, const tp_solve_params* params, void* x, const void* eta,
+                   tp_solve_info* info);
+
+/* ---- gradient ----------------------------------------------------------------------
+ * For L(x, lambda) with lambda = M^-dagger dL/dx*: per link U_mu(s),
+ *   Y = sum_a [P-^mu x(s+mu)]_a lambda(s)_a^dag,  Z = sum_a [P+^mu x(s)]_a lambda(s+mu)_a^dag,
+ *   raw:        grad_U = k_mu b_mu(s) (Y + Z^dag)^dag   (d L = Re <grad_U, dU>),
+ *   projected:  G = k_mu b_mu(s) TH[i U (Y + Z^dag)]    (dL/dh = tr(omega G) for
+ *               U -> exp(i h omega) U),  TH = traceless hermitian part,
+ * with k_t = 1, k_i = 1/gamma_f, b_mu(s) = bc_t on time links of the last slice.
+ * The clover term is held fixed.  grad_links: device complex128 [4][Lt][Lz][Ly][Lx][3][3]. */
+tp_status tp_force(tp_op op, const void* x, const void* lambda, void* grad_links,
+                   int32_t projected);
+
+/* ---- diagnostics -------------------------------------------------------------------- */
+const char* tp_status_string(tp_status s);
+const char* tp_last_error(void);
+/* Per-kernel timing with HIP events on the bound stream. */
+tp_status tp_prof_enable(tp_ctx ctx, int32_t on);
+tp_status tp_prof_reset(tp_ctx ctx);
+/* id in [0, tp_prof_count()): launches, summed milliseconds, algorithmic bytes. */
+int32_t tp_prof_count(void);
+const char* tp_prof_name(int32_t id);
+tp_status tp_prof_get(tp_ctx ctx, int32_t id, int64_t* launches, double* total_ms,
+                      double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TPREC_H */

@@ -1,0 +1,252 @@
+"""Python binding: Operator handles, applies, solve and the autograd Function.
+
+Argument marshalling only (tensor data pointers, the current stream); all
+arithmetic runs in libtprec.so.
+"""
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+
+
+def _stream_ptr(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _prec(p):
+    key = p.upper() if isinstance(p, str) else p
+    if isinstance(key, str):
+        if key not in L.PRECS:
+            raise ValueError(f"precision {p!r}: one of {list(L.PRECS)}")
+        return L.PRECS[key]
+    return int(key)
+
+
+def _scheme(s):
+    if isinstance(s, str):
+        if s.upper() not in L.SCHEMES:
+            raise ValueError(f"scheme {s!r}: one of {list(L.SCHEMES)}")
+        return L.SCHEMES[s.upper()]
+    return int(s)
+
+
+class Operator:
+    """M = A + mu - D_t - D_s/gamma_f bound to a gauge field, on one GPU.
+
+    links: complex128 tensor [4, Lt, Lz, Ly, Lx, 3, 3] (CPU or CUDA).
+    c_s, c_t: the literal SW coefficients (both 0 for Wilson fermions).
+    bc_t: +1 periodic or -1 antiperiodic in time.
+    """
+
+    def __init__(self, links, m0, gamma_f, c_s=0.0, c_t=0.0, bc_t=-1, device=0):
+        self._lib = L.load()
+        lib = self._lib
+        if links.dtype != torch.complex128 or links.dim() != 7 or links.shape[0] != 4:
+            raise ValueError("links must be complex128 [4, Lt, Lz, Ly, Lx, 3, 3]")
+        lt, lz, ly, lx = links.shape[1:5]
+        self.dims = (lx, ly, lz, lt)
+        self.device = torch.device("cuda", device)
+        self.m0, self.gamma_f, self.c_s, self.c_t, self.bc_t = m0, gamma_f, c_s, c_t, bc_t
+        self.mu = m0 + 1.0 + 3.0 / gamma_f
+        self._ctx = C.c_void_p()
+        self._gauge = C.c_void_p()
+        self._clover = C.c_void_p()
+        self._op = C.c_void_p()
+        d = (C.c_int32 * 4)(*self.dims)
+        L.check(lib.tp_ctx_create(d, int(bc_t), int(device), C.byref(self._ctx)))
+        self._bind_stream()
+        links = links.contiguous()
+        where = L.TP_DEVICE if links.is_cuda else L.TP_HOST
+        L.check(lib.tp_gauge_create(self._ctx, C.c_void_p(links.data_ptr()), where,
+                                    C.byref(self._gauge)))
+        if c_s != 0.0 or c_t != 0.0:
+            L.check(lib.tp_clover_create(self._gauge, float(c_s), float(c_t), C.byref(self._clover)))
+        L.check(lib.tp_op_create(self._gauge, self._clover, float(m0), float(gamma_f),
+                                 C.byref(self._op)))
+
+    # ---- plumbing --------------------------------------------------------------
+    def _bind_stream(self):
+        L.check(self._lib.tp_ctx_set_stream(self._ctx, _stream_ptr(self.device)))
+
+    @property
+    def spinor_shape(self):
+        lx, ly, lz, lt = self.dims
+        return (lt, lz, ly, lx, 4, 3)
+
+    def _in(self, psi):
+        if psi.dtype != torch.complex128 or tuple(psi.shape) != self.spinor_shape:
+            raise ValueError(f"spinor must be complex128 {self.spinor_shape}")
+        return psi.to(self.device).contiguous()
+
+    def _out(self):
+        return torch.empty(self.spinor_shape, dtype=torch.complex128, device=self.device)
+
+    def _call(self, fn, *args):
+        self._bind_stream()
+        L.check(fn(*args))
+
+    def close(self):
+        lib = getattr(self, "_lib", None)
+        if lib is None:
+            return
+        if self._op:
+            lib.tp_op_destroy(self._op)
+        if self._clover:
+            lib.tp_clover_destroy(self._clover)
+        if self._gauge:
+            lib.tp_gauge_destroy(self._gauge)
+        if self._ctx:
+            lib.tp_ctx_destroy(self._ctx)
+        self._op = self._clover = self._gauge = self._ctx = C.c_void_p()
+        self._lib = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- applies -------------------------------------------------------------------
+    def _unary(self, fn, psi, *extra):
+        src = self._in(psi)
+        dst = self._out()
+        self._call(fn, self._op, *extra[:1], C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()),
+                   *extra[1:])
+        return dst
+
+    def apply_M(self, psi, prec="F64", dagger=False):
+        return self._unary(self._lib.tp_apply_M, psi, _prec(prec), int(dagger))
+
+    def apply_Ds(self, psi, prec="F64"):
+        return self._unary(self._lib.tp_apply_Ds, psi, _prec(prec))
+
+    def apply_clover(self, psi, prec="F64", plus_mu=0):
+        return self._unary(self._lib.tp_apply_clover, psi, _prec(prec), int(plus_mu))
+
+    def apply_Tinv(self, psi, prec="F64", dagger=False):
+        return self._unary(self._lib.tp_apply_Tinv, psi, _prec(prec), int(dagger))
+
+    def apply_CL(self, psi, prec="F64"):
+        return self._unary(self._lib.tp_apply_CL, psi, _prec(prec))
+
+    def apply_CR(self, psi, prec="F64"):
+        return self._unary(self._lib.tp_apply_CR, psi, _prec(prec))
+
+    def apply_prec(self, psi, scheme, prec="F64", dagger=False):
+        src = self._in(psi)
+        dst = self._out()
+        self._call(self._lib.tp_apply_prec, self._op, _scheme(scheme), _prec(prec),
+                   C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), int(dagger))
+        return dst
+
+    def prepare_source(self, eta, scheme, prec="F64"):
+        src = self._in(eta)
+        dst = self._out()
+        self._call(self._lib.tp_prepare_source, self._op, _scheme(scheme), _prec(prec),
+                   C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()))
+        return dst
+
+    def reconstruct(self, y, scheme, prec="F64"):
+        src = self._in(y)
+        dst = self._out()
+        self._call(self._lib.tp_reconstruct, self._op, _scheme(scheme), _prec(prec),
+                   C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()))
+        return dst
+
+    # ---- solve -----------------------------------------------------------------------
+    def solve(self, eta, scheme="TEMPORAL_SCHUR", solver="BICGSTAB", prec="F64", tol=1e-10,
+              inner_tol=0.0, max_iter=0, max_restarts=0, x0=None, estimate_kappa=False,
+              raise_on_noconv=True):
+        """x with |eta - M x| <= tol |eta|; returns (x, info dict)."""
+        src = self._in(eta)
+        x = self._in(x0).clone() if x0 is not None else self._out()
+        P = L.SolveParams(scheme=_scheme(scheme), solver=L.SOLVERS[solver.upper()], prec=_prec(prec),
+                          max_iter=int(max_iter), max_restarts=int(max_restarts),
+                          use_x0=int(x0 is not None), estimate_kappa=int(estimate_kappa),
+                          reserved=0, tol=float(tol), inner_tol=float(inner_tol))
+        info = L.SolveInfo()
+        self._bind_stream()
+        st = self._lib.tp_solve(self._op, C.byref(P), C.c_void_p(x.data_ptr()),
+                                C.c_void_p(src.data_ptr()), C.byref(info))
+        d = info.as_dict()
+        d["status"] = st
+        if st != L.TP_OK and (raise_on_noconv or st != L.TP_ENOCONV):
+            L.check(st)
+        return x, d
+
+    def force(self, x, lam, projected=True):
+        """Link gradient from x and lambda (see tp_force): [4, Lt, Lz, Ly, Lx, 3, 3]."""
+        xs, ls = self._in(x), self._in(lam)
+        lx, ly, lz, lt = self.dims
+        g = torch.empty((4, lt, lz, ly, lx, 3, 3), dtype=torch.complex128, device=self.device)
+        self._call(self._lib.tp_force, self._op, C.c_void_p(xs.data_ptr()),
+                   C.c_void_p(ls.data_ptr()), C.c_void_p(g.data_ptr()), int(bool(projected)))
+        return g
+
+    def plaquette(self):
+        ps, pt = C.c_double(), C.c_double()
+        self._call(self._lib.tp_gauge_plaquette, self._gauge, C.byref(ps), C.byref(pt))
+        return ps.value, pt.value
+
+    # ---- per-kernel timing --------------------------------------------------------------
+    def profile(self, on=True):
+        self._call(self._lib.tp_prof_enable, self._ctx, int(on))
+
+    def profile_reset(self):
+        self._call(self._lib.tp_prof_reset, self._ctx)
+
+    def profile_stats(self):
+        out = {}
+        n = self._lib.tp_prof_count()
+        for k in range(n):
+            cnt, ms, by = C.c_int64(), C.c_double(), C.c_double()
+            self._call(self._lib.tp_prof_get, self._ctx, k, C.byref(cnt), C.byref(ms), C.byref(by))
+            if cnt.value:
+                out[self._lib.tp_prof_name(k).decode()] = dict(launches=cnt.value, ms=ms.value,
+                                                                bytes=by.value)
+        return out
+
+
+def _g5(v):
+    """gamma5 = [[0,-1],[-1,0]] on (upper, lower) spin pairs (Dirac-Pauli basis)."""
+    return -torch.cat([v[..., 2:, :], v[..., :2, :]], dim=-2)
+
+
+def solve(links, eta, m0, gamma_f, c_s=0.0, c_t=0.0, bc_t=-1, **kw):
+    op = Operator(links, m0, gamma_f, c_s, c_t, bc_t)
+    try:
+        return op.solve(eta, **kw)
+    finally:
+        op.close()
+
+
+class SolveFn(torch.autograd.Function):
+    """x = M(U)^-1 eta with a hand-written backward.
+
+    Backward: lambda solves M^dagger lambda = g (as M (g5 lambda) = g5 g, with the
+    same preconditioned solver), grad_eta = lambda, and grad_U is the hopping
+    term's link gradient (tp_force, raw form) with the SW term held fixed.
+    Conventions follow torch: dL = Re <grad, dz>.
+    """
+
+    @staticmethod
+    def forward(ctx, links, eta, m0, gamma_f, c_s=0.0, c_t=0.0, bc_t=-1, scheme="TEMPORAL_SCHUR",
+                prec="F64", tol=1e-10):
+        op = Operator(links.detach(), m0, gamma_f, c_s, c_t, bc_t, device=eta.device.index or 0)
+        x, _ = op.solve(eta.detach(), scheme=scheme, prec=prec, tol=tol)
+        ctx.op = op
+        ctx.opts = dict(scheme=scheme, prec=prec, tol=tol)
+        ctx.save_for_backward(x)
+        return x
+
+    @staticmethod
+    def backward(ctx, g):
+        (x,) = ctx.saved_tensors
+        op = ctx.op
+        y, _ = op.solve(_g5(g.contiguous()), **ctx.opts)
+        lam = _g5(y)
+        grad_links = op.force(x, lam, projected=False) if ctx.needs_input_grad[0] else None
+        op.close()
+        ctx.op = None
+        return grad_links, lam, None, None, None, None, None, None, None, None

@@ -1,0 +1,668 @@
+// C ABI of the tprec library: handle life cycle, argument checks, canonical
+// <-> internal conversions around every apply, and the solve / force entry
+// points.  Every entry point catches TpError and returns its status.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <complex>
+#include <vector>
+
+#include "tp_internal.h"
+
+tp_status op_solve(tp_op op, const tp_solve_params& P, Field& x64, const Field& eta64,
+                   tp_solve_info& info);
+
+const char* const kKernelNames[KID_COUNT] = {
+    "pack_unpack",     "site_p3",        "schur4d_eo_clover_inv", "schur4d_oe_clover",
+    "line_scan_plain", "ilu_k2a",        "ilu_k2b",               "ilu_k3",
+    "line_scan_stencil", "blas",         "reduce_finish",         "force"};
+
+namespace {
+thread_local std::string g_last_error;
+
+template <typename F>
+tp_status guard(F&& f) {
+  try {
+    f();
+    g_last_error.clear();
+    return TP_OK;
+  } catch (const TpError& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return TP_ENOMEM;
+  }
+}
+
+void check_prec(int prec) {
+  if (prec != TP_F64 && prec != TP_F32 && prec != TP_F16N) TP_THROW(TP_EINVAL, "bad precision");
+}
+void check_scheme(int s) {
+  if (s < TP_UNPREC || s > TP_TEMPORAL_SCHUR) TP_THROW(TP_EINVAL, "bad scheme");
+}
+void need(const void* p, const char* what) {
+  if (!p) TP_THROW(TP_EINVAL, std::string("null pointer: ") + what);
+}
+void set_device(tp_ctx ctx) { HIP_CHECK(hipSetDevice(ctx->device)); }
+
+// The spin matrices of the Dirac-Pauli basis and the chiral projections of
+// sigma_{mu nu} used to build the clover blocks on the device.
+typedef std::complex<double> zc;
+void gammas(zc g[4][4][4]) {
+  const zc I(0, 1);
+  zc s[3][2][2] = {{{0, 1}, {1, 0}}, {{0, -I}, {I, 0}}, {{1, 0}, {0, -1}}};
+  for (int m = 0; m < 4; ++m)
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) g[m][a][b] = 0;
+  for (int k = 0; k < 3; ++k)
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        g[k][a][2 + b] = -I * s[k][a][b];
+        g[k][2 + a][b] = I * s[k][a][b];
+      }
+  g[3][0][0] = g[3][1][1] = 1;
+  g[3][2][2] = g[3][3][3] = -1;
+}
+
+// sig[p][chi][r][c] = coef_p * (V_chi^dag sigma_p V_chi)[r][c] / 2 with
+// V_+ = (1, -1)/sqrt2 and V_- = (1, 1)/sqrt2 on the (upper, lower) spin pairs.
+void clover_sigma_table(double cs, double ct, double sig[6][2][2][2][2]) {
+  zc g[4][4][4];
+  gammas(g);
+  const int planes[6][2] = {{0, 3}, {1, 3}, {2, 3}, {0, 1}, {0, 2}, {1, 2}};
+  for (int p = 0; p < 6; ++p) {
+    int mu = planes[p][0], nu = planes[p][1];
+    double coef = p < 3 ? -0.5 * ct : -0.5 * cs;
+    zc sg[4][4];
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        zc v = 0;
+        for (int c = 0; c < 4; ++c) v += g[mu][a][c] * g[nu][c][b] - g[nu][a][c] * g[mu][c][b];
+        sg[a][b] = 0.5 * v;
+      }
+    for (int chi = 0; chi < 2; ++chi) {
+      double sgn = chi == 0 ? -1.0 : 1.0;  // V_+ lower component -1, V_- +1
+      for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) {
+          // (V^dag S V)[r][c] = (S[r][c] + sgn S[r][2+c] + sgn S[2+r][c] + S[2+r][2+c]) / 2
+          zc v = 0.5 * (sg[r][c] + sgn * sg[r][2 + c] + sgn * sg[2 + r][c] + sg[2 + r][2 + c]);
+          v *= 0.5 * coef;
+          sig[p][chi][r][c][0] = v.real();
+          sig[p][chi][r][c][1] = v.imag();
+        }
+    }
+  }
+}
+
+Lattice make_lattice(const int32_t d[4]) {
+  Lattice L;
+  for (int k = 0; k < 4; ++k) L.L[k] = d[k];
+  L.Vs = d[0] * d[1] * d[2];
+  L.Vs2 = L.Vs / 2;
+  L.V = (int64_t)L.Vs * d[3];
+  L.V2 = L.V / 2;
+  L.g.Lx = d[0];
+  L.g.Ly = d[1];
+  L.g.Lz = d[2];
+  L.g.Lt = d[3];
+  L.g.Lxh = d[0] / 2;
+  L.g.Vs2 = L.Vs2;
+  L.g.V2 = L.V2;
+  return L;
+}
+
+Field& tmp_field(tp_op op, int prec, int k) { return ws_get(op, prec, 100 + k); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- memory / profiling helpers
+void tp_set_error(const std::string& m) { g_last_error = m; }
+
+void* dev_alloc(size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) return nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    TP_THROW(e == hipErrorOutOfMemory ? TP_ENOMEM : TP_EHIP,
+             std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  return p;
+}
+void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+Field field_alloc(const Lattice& lat, int prec) {
+  Field f;
+  f.prec = prec;
+  f.V2 = lat.V2;
+  f.data = dev_alloc(size_t(2) * 12 * lat.V2 * f.elem_bytes());
+  HIP_CHECK(hipMemset(f.data, 0, size_t(2) * 12 * lat.V2 * f.elem_bytes()));
+  if (prec == TP_F16N) {
+    f.nrm = static_cast<float*>(dev_alloc(size_t(2) * 2 * lat.V2 * sizeof(float)));
+    HIP_CHECK(hipMemset(f.nrm, 0, size_t(2) * 2 * lat.V2 * sizeof(float)));
+  }
+  f.owned = true;
+  return f;
+}
+void field_free(Field& f) {
+  if (f.owned) {
+    dev_free(f.data);
+    dev_free(f.nrm);
+  }
+  f.data = nullptr;
+  f.nrm = nullptr;
+}
+
+ProfScope::ProfScope(tp_ctx c, int k, double b) : ctx(c), kid(k), bytes(b), slot(0), on(c && c->prof) {
+  if (!on) return;
+  if (ctx->ev_used >= 4096) prof_flush(ctx);
+  if (ctx->ev_used == ctx->ev_pool.size()) {
+    hipEvent_t a, e;
+    HIP_CHECK(hipEventCreate(&a));
+    HIP_CHECK(hipEventCreate(&e));
+    ctx->ev_pool.push_back({a, e});
+    ctx->ev_pending.push_back({0, 0.0, false});
+  }
+  slot = ctx->ev_used++;
+  ctx->ev_pending[slot] = {kid, bytes, false};
+  HIP_CHECK(hipEventRecord(ctx->ev_pool[slot].first, ctx->stream));
+}
+ProfScope::~ProfScope() {
+  if (!on) return;
+  (void)hipEventRecord(ctx->ev_pool[slot].second, ctx->stream);
+  ctx->ev_pending[slot].done = true;
+}
+
+// Accumulates the recorded (start, stop) pairs.  While a profiled launch is still
+// open (its stop event not yet recorded) nothing is flushed; a later call will.
+void prof_flush(tp_ctx ctx) {
+  if (!ctx || ctx->ev_used == 0) return;
+  for (size_t k = 0; k < ctx->ev_used; ++k)
+    if (!ctx->ev_pending[k].done) return;
+  HIP_CHECK(hipEventSynchronize(ctx->ev_pool[ctx->ev_used - 1].second));
+  for (size_t k = 0; k < ctx->ev_used; ++k) {
+    float ms = 0;
+    HIP_CHECK(hipEventElapsedTime(&ms, ctx->ev_pool[k].first, ctx->ev_pool[k].second));
+    ProfSlot& s = ctx->prof_slots[ctx->ev_pending[k].kid];
+    s.launches++;
+    s.ms += ms;
+    s.bytes += ctx->ev_pending[k].bytes;
+  }
+  ctx->ev_used = 0;
+}
+
+// Canonical-in / canonical-out wrapper for the internal applies.
+template <typename F>
+tp_status apply_wrap(tp_op op, int prec, void* dst, const void* src, bool l4, bool g5, F&& f) {
+  return guard([&] {
+    need(op, "op");
+    need(dst, "dst");
+    need(src, "src");
+    check_prec(prec);
+    if (dst == src) TP_THROW(TP_EINVAL, "dst and src must differ");
+    tp_ctx ctx = op->g->ctx;
+    set_device(ctx);
+    if (l4 && ctx->lat.L[3] % 2) TP_THROW(TP_EDIMS, "SCHUR4D needs an even time extent");
+    Field& a = tmp_field(op, prec, 0);
+    Field& b = tmp_field(op, prec, 1);
+    launch_pack(ctx, static_cast<const double2*>(src), a, l4, g5);
+    f(a, b);
+    launch_unpack(ctx, b, static_cast<double2*>(dst), l4, g5);
+  });
+}
+
+
+// ---------------------------------------------------------------- C ABI
+extern "C" {
+
+const char* tp_status_string(tp_status s) {
+  switch (s) {
+    case TP_OK: return "ok";
+    case TP_EINVAL: return "invalid argument";
+    case TP_EDIMS: return "unsupported lattice dimensions";
+    case TP_ESINGULAR: return "numerically singular matrix";
+    case TP_ENOCONV: return "solver did not converge";
+    case TP_EBREAKDOWN: return "solver breakdown";
+    case TP_ENOMEM: return "out of device memory";
+    case TP_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* tp_last_error(void) { return g_last_error.c_str(); }
+
+tp_status tp_ctx_create(const int32_t dims[4], int32_t bc_t, int32_t device, tp_ctx* out) {
+  return guard([&] {
+    need(dims, "dims");
+    need(out, "out");
+    *out = nullptr;
+    for (int k = 0; k < 3; ++k)
+      if (dims[k] < 2 || dims[k] % 2) TP_THROW(TP_EDIMS, "spatial extents must be even and >= 2");
+    if (dims[3] < 2) TP_THROW(TP_EDIMS, "time extent must be >= 2");
+    if (bc_t != 1 && bc_t != -1) TP_THROW(TP_EINVAL, "bc_t must be +1 or -1");
+    if ((int64_t)dims[0] * dims[1] * dims[2] * (int64_t)dims[3] > (int64_t)1 << 31)
+      TP_THROW(TP_EDIMS, "volume too large");
+    int ndev = 0;
+    HIP_CHECK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) TP_THROW(TP_EINVAL, "bad device ordinal");
+    tp_ctx c = new tp_ctx_s();
+    c->lat = make_lattice(dims);
+    c->bc = bc_t;
+    c->device = device;
+    try {
+      HIP_CHECK(hipSetDevice(device));
+      c->red_partial = static_cast<double*>(dev_alloc(sizeof(double) * 8 * kRedBlocks));
+      c->red_result = static_cast<double*>(dev_alloc(sizeof(double) * 8));
+      HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&c->red_host), sizeof(double) * 8,
+                              hipHostMallocDefault));
+    } catch (...) {
+      dev_free(c->red_partial);
+      dev_free(c->red_result);
+      delete c;
+      throw;
+    }
+    *out = c;
+  });
+}
+
+tp_status tp_ctx_destroy(tp_ctx ctx) {
+  return guard([&] {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (auto& e : ctx->ev_pool) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    dev_free(ctx->red_partial);
+    dev_free(ctx->red_result);
+    if (ctx->red_host) (void)hipHostFree(ctx->red_host);
+    delete ctx;
+  });
+}
+
+tp_status tp_ctx_set_stream(tp_ctx ctx, void* stream) {
+  return guard([&] {
+    need(ctx, "ctx");
+    prof_flush(ctx);
+    ctx->stream = static_cast<hipStream_t>(stream);
+  });
+}
+
+tp_status tp_gauge_create(tp_ctx ctx, const void* links, int32_t where, tp_gauge* out) {
+  return guard([&] {
+    need(ctx, "ctx");
+    need(links, "links");
+    need(out, "out");
+    if (where != TP_HOST && where != TP_DEVICE) TP_THROW(TP_EINVAL, "bad `where`");
+    *out = nullptr;
+    set_device(ctx);
+    const Lattice& L = ctx->lat;
+    tp_gauge g = new tp_gauge_s();
+    g->ctx = ctx;
+    try {
+      size_t lb = size_t(4) * L.V * 9 * sizeof(double2);
+      g->canon = static_cast<double2*>(dev_alloc(lb));
+      HIP_CHECK(hipMemcpyAsync(g->canon, links, lb,
+                               where == TP_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                               ctx->stream));
+      g->u3_d = static_cast<double2*>(dev_alloc(lb));
+      g->u3_f = static_cast<float2*>(dev_alloc(lb / 2));
+      g->u4_d = static_cast<double2*>(dev_alloc(lb));
+      g->u4_f = static_cast<float2*>(dev_alloc(lb / 2));
+      g->w_d = static_cast<double2*>(dev_alloc(size_t(2) * 9 * L.V2 * sizeof(double2)));
+      g->w_f = static_cast<float2*>(dev_alloc(size_t(2) * 9 * L.V2 * sizeof(float2)));
+      g->poly = static_cast<double2*>(dev_alloc(size_t(2) * 9 * L.Vs2 * sizeof(double2)));
+      launch_pack_links(ctx, g);
+      launch_wline(ctx, g);
+      HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    } catch (...) {
+      tp_gauge_destroy(g);
+      throw;
+    }
+    *out = g;
+  });
+}
+
+tp_status tp_gauge_destroy(tp_gauge g) {
+  return guard([&] {
+    if (!g) return;
+    (void)hipSetDevice(g->ctx->device);
+    (void)hipStreamSynchronize(g->ctx->stream);
+    dev_free(g->canon);
+    dev_free(g->u3_d);
+    dev_free(g->u3_f);
+    dev_free(g->u4_d);
+    dev_free(g->u4_f);
+    dev_free(g->w_d);
+    dev_free(g->w_f);
+    dev_free(g->poly);
+    delete g;
+  });
+}
+
+tp_status tp_gauge_plaquette(tp_gauge g, double* ps, double* pt) {
+  return guard([&] {
+    need(g, "gauge");
+    need(ps, "plaq_s");
+    need(pt, "plaq_t");
+    tp_ctx ctx = g->ctx;
+    set_device(ctx);
+    const Lattice& L = ctx->lat;
+    int64_t nb = (L.V + 255) / 256;
+    double* part = static_cast<double*>(dev_alloc(sizeof(double) * 2 * nb));
+    std::vector<double> h(2 * nb);
+    try {
+      launch_plaquette(ctx, g, part);
+      HIP_CHECK(hipMemcpyAsync(h.data(), part, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost,
+                               ctx->stream));
+      HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    } catch (...) {
+      dev_free(part);
+      throw;
+    }
+    dev_free(part);
+    double s = 0, t = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+      s += h[2 * b];
+      t += h[2 * b + 1];
+    }
+    *ps = s / (3.0 * L.V);
+    *pt = t / (3.0 * L.V);
+  });
+}
+
+tp_status tp_clover_create(tp_gauge g, double c_s, double c_t, tp_clover* out) {
+  return guard([&] {
+    need(g, "gauge");
+    need(out, "out");
+    if (!isfinite(c_s) || !isfinite(c_t)) TP_THROW(TP_EINVAL, "clover coefficients");
+    *out = nullptr;
+    tp_ctx ctx = g->ctx;
+    set_device(ctx);
+    const Lattice& L = ctx->lat;
+    tp_clover c = new tp_clover_s();
+    c->g = g;
+    c->cs = c_s;
+    c->ct = c_t;
+    try {
+      size_t cb = size_t(2) * 36 * L.V2;
+      c->a3_d = static_cast<double2*>(dev_alloc(cb * sizeof(double2)));
+      c->a3_f = static_cast<float2*>(dev_alloc(cb * sizeof(float2)));
+      c->a4_d = static_cast<double2*>(dev_alloc(cb * sizeof(double2)));
+      c->a4_f = static_cast<float2*>(dev_alloc(cb * sizeof(float2)));
+      double sig[6][2][2][2][2];
+      clover_sigma_table(c_s, c_t, sig);
+      launch_clover_build(ctx, c, sig);
+      HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    } catch (...) {
+      tp_clover_destroy(c);
+      throw;
+    }
+    *out = c;
+  });
+}
+
+tp_status tp_clover_destroy(tp_clover c) {
+  return guard([&] {
+    if (!c) return;
+    (void)hipSetDevice(c->g->ctx->device);
+    (void)hipStreamSynchronize(c->g->ctx->stream);
+    dev_free(c->a3_d);
+    dev_free(c->a3_f);
+    dev_free(c->a4_d);
+    dev_free(c->a4_f);
+    delete c;
+  });
+}
+
+tp_status tp_op_create(tp_gauge g, tp_clover c, double m0, double gamma_f, tp_op* out) {
+  return guard([&] {
+    need(g, "gauge");
+    need(out, "out");
+    if (!isfinite(m0) || !isfinite(gamma_f) || gamma_f <= 0) TP_THROW(TP_EINVAL, "m0 / gamma_f");
+    if (c && c->g != g) TP_THROW(TP_EINVAL, "clover built from another gauge field");
+    *out = nullptr;
+    tp_ctx ctx = g->ctx;
+    set_device(ctx);
+    const Lattice& L = ctx->lat;
+    tp_op op = new tp_op_s();
+    op->g = g;
+    op->c = c;
+    op->m0 = m0;
+    op->gf = gamma_f;
+    op->mu = m0 + 1.0 + 3.0 / gamma_f;
+    double* cond = nullptr;
+    int* bad = nullptr;
+    try {
+      if (!(op->mu > 0)) TP_THROW(TP_EINVAL, "mass term mu = m0 + 1 + 3/gamma_f must be positive");
+      op->gclos = static_cast<double2*>(dev_alloc(size_t(2) * 9 * L.Vs2 * sizeof(double2)));
+      size_t cb = size_t(2) * 36 * L.V2;
+      op->a4_mu = static_cast<double2*>(dev_alloc(cb * sizeof(double2)));
+      op->a4_inv = static_cast<double2*>(dev_alloc(cb * sizeof(double2)));
+      op->a4_mu_f = static_cast<float2*>(dev_alloc(cb * sizeof(float2)));
+      op->a4_inv_f = static_cast<float2*>(dev_alloc(cb * sizeof(float2)));
+      op->a3_mu = static_cast<double2*>(dev_alloc(cb * sizeof(double2)));
+      op->a3_inv = static_cast<double2*>(dev_alloc(cb * sizeof(double2)));
+      op->a3_mu_f = static_cast<float2*>(dev_alloc(cb * sizeof(float2)));
+      op->a3_inv_f = static_cast<float2*>(dev_alloc(cb * sizeof(float2)));
+      std::vector<double> pw(L.L[3] + 1);
+      std::vector<float> pwf(L.L[3] + 1);
+      for (int k = 0; k <= L.L[3]; ++k) {
+        pw[k] = pow(op->mu, -double(k));
+        pwf[k] = float(pw[k]);
+      }
+      op->mupow_d = static_cast<double*>(dev_alloc(sizeof(double) * pw.size()));
+      op->mupow_f = static_cast<float*>(dev_alloc(sizeof(float) * pwf.size()));
+      HIP_CHECK(hipMemcpy(op->mupow_d, pw.data(), sizeof(double) * pw.size(), hipMemcpyHostToDevice));
+      HIP_CHECK(hipMemcpy(op->mupow_f, pwf.data(), sizeof(float) * pwf.size(), hipMemcpyHostToDevice));
+      cond = static_cast<double*>(dev_alloc(sizeof(double) * 2 * L.Vs2));
+      bad = static_cast<int*>(dev_alloc(sizeof(int)));
+      HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
+      launch_closure(ctx, op, cond);
+      launch_clover_derived(ctx, op, bad);
+      std::vector<double> hc(2 * L.Vs2);
+      int hb = 0;
+      HIP_CHECK(hipMemcpyAsync(hc.data(), cond, sizeof(double) * hc.size(), hipMemcpyDeviceToHost,
+                               ctx->stream));
+      HIP_CHECK(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+      HIP_CHECK(hipStreamSynchronize(ctx->stream));
+      double worst = 0;
+      for (double v : hc) worst = std::max(worst, isfinite(v) ? v : INFINITY);
+      if (!(worst <= 1e12))
+        TP_THROW(TP_ESINGULAR, "closure (I - mu^-Lt P) is singular or ill-conditioned");
+      if (hb) TP_THROW(TP_ESINGULAR, "(A + mu) has a numerically singular 6x6 block");
+    } catch (...) {
+      dev_free(cond);
+      dev_free(bad);
+      tp_op_destroy(op);
+      throw;
+    }
+    dev_free(cond);
+    dev_free(bad);
+    *out = op;
+  });
+}
+
+tp_status tp_op_destroy(tp_op op) {
+  return guard([&] {
+    if (!op) return;
+    (void)hipSetDevice(op->g->ctx->device);
+    (void)hipStreamSynchronize(op->g->ctx->stream);
+    ws_free(op);
+    dev_free(op->gclos);
+    dev_free(op->a4_mu);
+    dev_free(op->a4_inv);
+    dev_free(op->a4_mu_f);
+    dev_free(op->a4_inv_f);
+    dev_free(op->a3_mu);
+    dev_free(op->a3_inv);
+    dev_free(op->a3_mu_f);
+    dev_free(op->a3_inv_f);
+    dev_free(op->mupow_d);
+    dev_free(op->mupow_f);
+    delete op;
+  });
+}
+
+tp_status tp_apply_M(tp_op op, int32_t prec, void* dst, const void* src, int32_t dagger) {
+  return apply_wrap(op, prec, dst, src, false, dagger != 0,
+                    [&](Field& a, Field& b) { op_apply_M(op, prec, a, b, false); });
+}
+
+tp_status tp_apply_Ds(tp_op op, int32_t prec, void* dst, const void* src) {
+  return apply_wrap(op, prec, dst, src, false, false, [&](Field& a, Field& b) {
+    SiteCoef cf{0.0, 0.0, 0.0, 1.0, 0.0};
+    launch_site_p3(op, prec, a, b, nullptr, cf, 0, 0, 2, false);
+  });
+}
+
+tp_status tp_apply_clover(tp_op op, int32_t prec, void* dst, const void* src, int32_t plus_mu) {
+  return apply_wrap(op, prec, dst, src, false, false, [&](Field& a, Field& b) {
+    int kind = plus_mu == 0 ? 1 : (plus_mu > 0 ? 2 : 3);
+    if (kind == 1 && !op->c) {
+      blas(op->g->ctx, B_ZERO, 0, 2, {nullptr, &b});
+      return;
+    }
+    SiteCoef cf{0.0, 1.0, 0.0, 0.0, 0.0};
+    launch_site_p3(op, prec, a, b, nullptr, cf, kind, 0, 2, false);
+  });
+}
+
+tp_status tp_apply_Tinv(tp_op op, int32_t prec, void* dst, const void* src, int32_t dagger) {
+  return apply_wrap(op, prec, dst, src, false, false, [&](Field& a, Field& b) {
+    for (int p = 0; p < 2; ++p) launch_line_plain(op, prec, dagger ? LM_TDINV : LM_TINV, p, a, b);
+  });
+}
+
+tp_status tp_apply_CL(tp_op op, int32_t prec, void* dst, const void* src) {
+  return apply_wrap(op, prec, dst, src, false, false, [&](Field& a, Field& b) {
+    for (int p = 0; p < 2; ++p) launch_line_plain(op, prec, LM_CL, p, a, b);
+  });
+}
+
+tp_status tp_apply_CR(tp_op op, int32_t prec, void* dst, const void* src) {
+  return apply_wrap(op, prec, dst, src, false, false, [&](Field& a, Field& b) {
+    for (int p = 0; p < 2; ++p) launch_line_plain(op, prec, LM_CR, p, a, b);
+  });
+}
+
+tp_status tp_apply_prec(tp_op op, int32_t scheme, int32_t prec, void* dst, const void* src,
+                        int32_t dagger) {
+  return guard([&] {
+    check_scheme(scheme);
+    if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
+    tp_status s = apply_wrap(op, prec, dst, src, scheme_layout4(scheme), dagger != 0,
+                             [&](Field& a, Field& b) { op_apply_prec(op, scheme, prec, a, b, false); });
+    if (s != TP_OK) TP_THROW(s, g_last_error);
+  });
+}
+
+tp_status tp_prepare_source(tp_op op, int32_t scheme, int32_t prec, void* et, const void* eta) {
+  return guard([&] {
+    check_scheme(scheme);
+    if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
+    tp_status s = apply_wrap(op, prec, et, eta, scheme_layout4(scheme), false,
+                             [&](Field& a, Field& b) { op_prepare(op, scheme, prec, a, b); });
+    if (s != TP_OK) TP_THROW(s, g_last_error);
+  });
+}
+
+tp_status tp_reconstruct(tp_op op, int32_t scheme, int32_t prec, void* x, const void* y) {
+  return guard([&] {
+    check_scheme(scheme);
+    if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
+    tp_status s = apply_wrap(op, prec, x, y, scheme_layout4(scheme), false,
+                             [&](Field& a, Field& b) { op_reconstruct(op, scheme, prec, a, b); });
+    if (s != TP_OK) TP_THROW(s, g_last_error);
+  });
+}
+
+tp_status tp_solve(tp_op op, const tp_solve_params* params, void* x, const void* eta,
+                   tp_solve_info* info) {
+  tp_status st = TP_OK;
+  tp_status g = guard([&] {
+    need(op, "op");
+    need(params, "params");
+    need(x, "x");
+    need(eta, "eta");
+    need(info, "info");
+    if (x == eta) TP_THROW(TP_EINVAL, "x and eta must differ");
+    const tp_solve_params& P = *params;
+    check_scheme(P.scheme);
+    check_prec(P.prec);
+    if (P.solver != TP_CGNR && P.solver != TP_BICGSTAB) TP_THROW(TP_EINVAL, "bad solver");
+    if (P.scheme == TP_SCHUR4D && P.prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
+    if (!(P.tol >= 0) || !(P.inner_tol >= 0)) TP_THROW(TP_EINVAL, "tolerances");
+    tp_ctx ctx = op->g->ctx;
+    set_device(ctx);
+    bool l4 = scheme_layout4(P.scheme);
+    if (l4 && ctx->lat.L[3] % 2) TP_THROW(TP_EDIMS, "SCHUR4D needs an even time extent");
+    Field& eta64 = ws_get(op, TP_F64, 60);
+    Field& x64 = ws_get(op, TP_F64, 61);
+    launch_pack(ctx, static_cast<const double2*>(eta), eta64, l4, false);
+    if (P.use_x0) launch_pack(ctx, static_cast<const double2*>(x), x64, l4, false);
+    st = op_solve(op, P, x64, eta64, *info);
+    launch_unpack(ctx, x64, static_cast<double2*>(x), l4, false);
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    prof_flush(ctx);
+    if (st != TP_OK)
+      g_last_error = st == TP_ENOCONV ? "iteration cap reached before the target residual"
+                                      : "Krylov breakdown";
+  });
+  if (g != TP_OK) return g;
+  return st;
+}
+
+tp_status tp_force(tp_op op, const void* x, const void* lambda, void* grad, int32_t projected) {
+  return guard([&] {
+    need(op, "op");
+    need(x, "x");
+    need(lambda, "lambda");
+    need(grad, "grad_links");
+    tp_ctx ctx = op->g->ctx;
+    set_device(ctx);
+    Field& a = tmp_field(op, TP_F64, 0);
+    Field& b = tmp_field(op, TP_F64, 1);
+    launch_pack(ctx, static_cast<const double2*>(x), a, false, false);
+    launch_pack(ctx, static_cast<const double2*>(lambda), b, false, false);
+    launch_force(op, a, b, static_cast<double2*>(grad), projected != 0);
+  });
+}
+
+tp_status tp_prof_enable(tp_ctx ctx, int32_t on) {
+  return guard([&] {
+    need(ctx, "ctx");
+    prof_flush(ctx);
+    ctx->prof = on != 0;
+  });
+}
+
+tp_status tp_prof_reset(tp_ctx ctx) {
+  return guard([&] {
+    need(ctx, "ctx");
+    prof_flush(ctx);
+    for (auto& s : ctx->prof_slots) s = ProfSlot{};
+  });
+}
+
+int32_t tp_prof_count(void) { return KID_COUNT; }
+const char* tp_prof_name(int32_t id) { return (id >= 0 && id < KID_COUNT) ? kKernelNames[id] : ""; }
+
+tp_status tp_prof_get(tp_ctx ctx, int32_t id, int64_t* launches, double* ms, double* bytes) {
+  return guard([&] {
+    need(ctx, "ctx");
+    if (id < 0 || id >= KID_COUNT) TP_THROW(TP_EINVAL, "kernel id");
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    prof_flush(ctx);
+    if (launches) *launches = ctx->prof_slots[id].launches;
+    if (ms) *ms = ctx->prof_slots[id].ms;
+    if (bytes) *bytes = ctx->prof_slots[id].bytes;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,305 @@
+// Level-1 kernels for the Krylov solvers: fused updates with FP64 reductions.
+// Work unit = one half spinor (6 complex) of one site, so FP16 fields with a
+// scale per half spinor are updated consistently.  Reductions are deterministic:
+// a fixed grid writes per-block partials, one block sums them in a fixed order.
+#include "tp_internal.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+template <typename S>
+struct BlasK {
+  SpinorF<S> f[6][2];
+  double a[2], b[2], c[2];
+  int par0;
+  int64_t V2, n;
+  double* partial;
+};
+
+TP_DEV void block_reduce(double (&acc)[4], int nred, double* partial) {
+  __shared__ double sh[kBlock / 64][4];
+  for (int k = 0; k < nred; ++k) {
+    double v = acc[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < (unsigned)nred) {
+    double s = 0;
+    for (int w = 0; w < kBlock / 64; ++w) s += sh[w][threadIdx.x];
+    partial[(int64_t)blockIdx.x * 8 + threadIdx.x] = s;
+  }
+}
+
+template <typename R> TP_DEV cx<R> cc(const double* z) { return cx<R>{R(z[0]), R(z[1])}; }
+
+template <typename S, int OP>
+__global__ void __launch_bounds__(kBlock) k_blas(BlasK<S> k) {
+  using R = typename Prec<S>::R;
+  double acc[4] = {0, 0, 0, 0};
+  const cx<R> A = cc<R>(k.a), B = cc<R>(k.b), C = cc<R>(k.c);
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < k.n;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    int p = k.par0 + int(u / (2 * k.V2));
+    int h = int((u / k.V2) & 1);
+    int64_t i = u % k.V2;
+    cx<R> x[6], y[6], z[6], w[6], v[6];
+    if constexpr (OP == B_ZERO) {
+      for (int c = 0; c < 6; ++c) y[c] = czero<R>();
+      store_half<S, R>(k.f[1][p], h, i, y);
+    } else if constexpr (OP == B_COPY) {
+      load_half<S, R>(k.f[0][p], h, i, x);
+      store_half<S, R>(k.f[1][p], h, i, x);
+    } else if constexpr (OP == B_AXPY) {
+      load_half<S, R>(k.f[0][p], h, i, x);
+      load_half<S, R>(k.f[1][p], h, i, y);
+      for (int c = 0; c < 6; ++c) y[c] += cmul(A, x[c]);
+      store_half<S, R>(k.f[1][p], h, i, y);
+    } else if constexpr (OP == B_XPAY) {
+      load_half<S, R>(k.f[0][p], h, i, x);
+      load_half<S, R>(k.f[1][p], h, i, y);
+      for (int c = 0; c < 6; ++c) y[c] = x[c] + cmul(A, y[c]);
+      store_half<S, R>(k.f[1][p], h, i, y);
+    } else if constexpr (OP == B_AXPBYPCZ) {
+      load_half<S, R>(k.f[0][p], h, i, x);
+      load_half<S, R>(k.f[1][p], h, i, y);
+      load_half<S, R>(k.f[2][p], h, i, z);
+      for (int c = 0; c < 6; ++c) z[c] = cmul(A, x[c]) + cmul(B, y[c]) + cmul(C, z[c]);
+      store_half<S, R>(k.f[2][p], h, i, z);
+    } else if constexpr (OP == B_NORM2) {
+      load_half<S, R>(k.f[0][p], h, i, x);
+      for (int c = 0; c < 6; ++c) acc[0] += double(norm2(x[c]));
+    } else if constexpr (OP == B_DOT || OP == B_DOT_NORM) {
+      load_half<S, R>(k.f[0][p], h, i, x);
+      load_half<S, R>(k.f[1][p], h, i, y);
+      for (int c = 0; c < 6; ++c) {
+        acc[0] += double(x[c].re) * double(y[c].re) + double(x[c].im) * double(y[c].im);
+        acc[1] += double(x[c].re) * double(y[c].im) - double(x[c].im) * double(y[c].re);
+        if constexpr (OP == B_DOT_NORM) acc[2] += double(norm2(y[c]));
+      }
+    } else if constexpr (OP == B_CAXPY_NORM) {
+      load_half<S, R>(k.f[0][p], h, i, x);
+      load_half<S, R>(k.f[1][p], h, i, y);
+      for (int c = 0; c < 6; ++c) {
+        y[c] += cmul(A, x[c]);
+        acc[0] += double(norm2(y[c]));
+      }
+      store_half<S, R>(k.f[1][p], h, i, y);
+    } else if constexpr (OP == B_DOT2_TS) {
+      load_half<S, R>(k.f[0][p], h, i, x);  // t
+      load_half<S, R>(k.f[1][p], h, i, y);  // s
+      for (int c = 0; c < 6; ++c) {
+        acc[0] += double(x[c].re) * double(y[c].re) + double(x[c].im) * double(y[c].im);
+        acc[1] += double(x[c].re) * double(y[c].im) - double(x[c].im) * double(y[c].re);
+        acc[2] += double(norm2(x[c]));
+      }
+    } else if constexpr (OP == B_BICG_UPDATE) {
+      // f0 = x, f1 = p, f2 = s, f3 = t, f4 = r (out), f5 = rhat
+      load_half<S, R>(k.f[0][p], h, i, x);
+      load_half<S, R>(k.f[1][p], h, i, y);
+      load_half<S, R>(k.f[2][p], h, i, z);
+      load_half<S, R>(k.f[3][p], h, i, w);
+      load_half<S, R>(k.f[5][p], h, i, v);
+      for (int c = 0; c < 6; ++c) {
+        x[c] += cmul(A, y[c]) + cmul(B, z[c]);
+        z[c] = z[c] - cmul(B, w[c]);  // r = s - omega t
+        acc[0] += double(v[c].re) * double(z[c].re) + double(v[c].im) * double(z[c].im);
+        acc[1] += double(v[c].re) * double(z[c].im) - double(v[c].im) * double(z[c].re);
+        acc[2] += double(norm2(z[c]));
+      }
+      store_half<S, R>(k.f[0][p], h, i, x);
+      store_half<S, R>(k.f[4][p], h, i, z);
+    } else if constexpr (OP == B_G5) {
+      load_half<S, R>(k.f[0][p], h, i, x);
+      for (int c = 0; c < 6; ++c) x[c] = -x[c];
+      store_half<S, R>(k.f[1][p], 1 - h, i, x);
+    }
+  }
+  constexpr int nred = (OP == B_NORM2 || OP == B_CAXPY_NORM) ? 1
+                     : (OP == B_DOT) ? 2
+                     : (OP == B_DOT_NORM || OP == B_DOT2_TS || OP == B_BICG_UPDATE) ? 3 : 0;
+  if constexpr (nred > 0) block_reduce(acc, nred, k.partial);
+}
+
+// y (precision SY) = x (precision SX), or y += x when ACC.
+template <typename SX, typename SY, bool ACC>
+__global__ void __launch_bounds__(kBlock) k_convert(SpinorF<SX> x0, SpinorF<SX> x1, SpinorF<SY> y0,
+                                                    SpinorF<SY> y1, int par0, int64_t V2, int64_t n) {
+  using RX = typename Prec<SX>::R;
+  using RY = typename Prec<SY>::R;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    int p = par0 + int(u / (2 * V2));
+    int h = int((u / V2) & 1);
+    int64_t i = u % V2;
+    cx<RX> a[6];
+    load_half<SX, RX>(p ? x1 : x0, h, i, a);
+    cx<RY> b[6];
+    if constexpr (ACC) load_half<SY, RY>(p ? y1 : y0, h, i, b);
+    for (int c = 0; c < 6; ++c) {
+      cx<RY> t = cx<RY>{RY(a[c].re), RY(a[c].im)};
+      b[c] = ACC ? b[c] + t : t;
+    }
+    store_half<SY, RY>(p ? y1 : y0, h, i, b);
+  }
+}
+
+__global__ void k_finish(const double* partial, int nblocks, int nred, double* result) {
+  __shared__ double sh[kBlock];
+  for (int k = 0; k < nred; ++k) {
+    double s = 0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partial[(int64_t)b * 8 + k];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) result[k] = sh[0];
+    __syncthreads();
+  }
+}
+
+template <typename S>
+SpinorF<S> fv(const Field* f, int p) {
+  if (!f) {
+    SpinorF<S> z{};
+    return z;
+  }
+  return f->template par<S>(p);
+}
+
+template <typename S, int OP>
+int blas_go(tp_ctx ctx, int par0, int npar, const Field* const* fs, BlasArgs k) {
+  BlasK<S> a;
+  for (int q = 0; q < 6; ++q)
+    for (int p = 0; p < 2; ++p) a.f[q][p] = fv<S>(fs[q], p);
+  for (int r = 0; r < 2; ++r) { a.a[r] = k.a[r]; a.b[r] = k.b[r]; a.c[r] = k.c[r]; }
+  a.par0 = par0;
+  a.V2 = ctx->lat.V2;
+  a.n = (int64_t)npar * 2 * a.V2;
+  a.partial = ctx->red_partial;
+  int64_t nb = (a.n + kBlock - 1) / kBlock;
+  if (nb > kRedBlocks) nb = kRedBlocks;
+  hipLaunchKernelGGL((k_blas<S, OP>), dim3((unsigned)nb), dim3(kBlock), 0, ctx->stream, a);
+  LAUNCH_CHECK();
+  return int(nb);
+}
+
+template <int OP>
+int blas_prec(tp_ctx ctx, int prec, int par0, int npar, const Field* const* fs, BlasArgs k) {
+  switch (prec) {
+    case TP_F64: return blas_go<double2, OP>(ctx, par0, npar, fs, k);
+    case TP_F32: return blas_go<float2, OP>(ctx, par0, npar, fs, k);
+    default: return blas_go<__half2, OP>(ctx, par0, npar, fs, k);
+  }
+}
+
+template <typename SX, typename SY, bool ACC>
+void conv_go(tp_ctx ctx, int par0, int npar, const Field& x, const Field& y) {
+  int64_t V2 = ctx->lat.V2;
+  int64_t n = (int64_t)npar * 2 * V2;
+  int64_t nb = (n + kBlock - 1) / kBlock;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL((k_convert<SX, SY, ACC>), dim3((unsigned)nb), dim3(kBlock), 0, ctx->stream,
+                     x.template par<SX>(0), x.template par<SX>(1), y.template par<SY>(0),
+                     y.template par<SY>(1), par0, V2, n);
+  LAUNCH_CHECK();
+}
+
+template <typename SX, bool ACC>
+void conv_y(tp_ctx ctx, int par0, int npar, const Field& x, const Field& y) {
+  switch (y.prec) {
+    case TP_F64: conv_go<SX, double2, ACC>(ctx, par0, npar, x, y); break;
+    case TP_F32: conv_go<SX, float2, ACC>(ctx, par0, npar, x, y); break;
+    default: conv_go<SX, __half2, ACC>(ctx, par0, npar, x, y); break;
+  }
+}
+
+template <bool ACC>
+void conv(tp_ctx ctx, int par0, int npar, const Field& x, const Field& y) {
+  switch (x.prec) {
+    case TP_F64: conv_y<double2, ACC>(ctx, par0, npar, x, y); break;
+    case TP_F32: conv_y<float2, ACC>(ctx, par0, npar, x, y); break;
+    default: conv_y<__half2, ACC>(ctx, par0, npar, x, y); break;
+  }
+}
+
+}  // namespace
+
+void blas(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<const Field*> fl,
+          BlasArgs k, double* red_out) {
+  const Field* fs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  {
+    int q = 0;
+    for (const Field* f : fl) fs[q++] = f;
+  }
+  const Field* x = fs[0];
+  const Field* y = fs[1];
+  int prec = x ? x->prec : y->prec;
+  double S = double(x ? x->elem_bytes() : y->elem_bytes()) * 12;
+  double n = double(npar) * ctx->lat.V2;
+  if (op == B_CONVERT || op == B_MIXED_ACC) {
+    ProfScope ps(ctx, KID_BLAS, n * (S + double(y->elem_bytes()) * 12 * (op == B_MIXED_ACC ? 2 : 1)));
+    if (op == B_CONVERT) conv<false>(ctx, par0, npar, *x, *y);
+    else conv<true>(ctx, par0, npar, *x, *y);
+    return;
+  }
+  int nb = 0, nred = 0;
+  {
+    double passes = 2;
+    switch (op) {
+      case B_AXPY: case B_XPAY: case B_DOT_NORM: case B_CAXPY_NORM: case B_DOT2_TS: passes = 3; break;
+      case B_AXPBYPCZ: passes = 4; break;
+      case B_BICG_UPDATE: passes = 7; break;
+      case B_NORM2: passes = 1; break;
+      case B_ZERO: passes = 1; break;
+      default: break;
+    }
+    ProfScope ps(ctx, KID_BLAS, n * S * passes);
+    switch (op) {
+      case B_ZERO: nb = blas_prec<B_ZERO>(ctx, prec, par0, npar, fs, k); break;
+      case B_COPY: nb = blas_prec<B_COPY>(ctx, prec, par0, npar, fs, k); break;
+      case B_AXPY: nb = blas_prec<B_AXPY>(ctx, prec, par0, npar, fs, k); break;
+      case B_XPAY: nb = blas_prec<B_XPAY>(ctx, prec, par0, npar, fs, k); break;
+      case B_AXPBYPCZ: nb = blas_prec<B_AXPBYPCZ>(ctx, prec, par0, npar, fs, k); break;
+      case B_NORM2: nb = blas_prec<B_NORM2>(ctx, prec, par0, npar, fs, k); nred = 1; break;
+      case B_DOT: nb = blas_prec<B_DOT>(ctx, prec, par0, npar, fs, k); nred = 2; break;
+      case B_DOT_NORM: nb = blas_prec<B_DOT_NORM>(ctx, prec, par0, npar, fs, k); nred = 3; break;
+      case B_CAXPY_NORM: nb = blas_prec<B_CAXPY_NORM>(ctx, prec, par0, npar, fs, k); nred = 1; break;
+      case B_DOT2_TS: nb = blas_prec<B_DOT2_TS>(ctx, prec, par0, npar, fs, k); nred = 3; break;
+      case B_BICG_UPDATE:  // fields: x, p, s, t, r, rhat
+        nb = blas_prec<B_BICG_UPDATE>(ctx, prec, par0, npar, fs, k);
+        nred = 3;
+        break;
+      case B_G5: nb = blas_prec<B_G5>(ctx, prec, par0, npar, fs, k); break;
+      default: TP_THROW(TP_EINVAL, "blas op");
+    }
+  }
+  if (nred > 0) {
+    {
+      ProfScope ps(ctx, KID_REDUCE, double(nb) * 8 * 8);
+      hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, ctx->stream, ctx->red_partial, nb, nred,
+                         ctx->red_result);
+      LAUNCH_CHECK();
+    }
+    HIP_CHECK(hipMemcpyAsync(ctx->red_host, ctx->red_result, sizeof(double) * nred,
+                             hipMemcpyDeviceToHost, ctx->stream));
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    prof_flush(ctx);
+    for (int q = 0; q < nred; ++q) red_out[q] = ctx->red_host[q];
+  }
+}
+
+// Sum of the first `nblocks` partials written by a norm-producing site kernel.
+double finish_norm(tp_ctx ctx, int nblocks) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, ctx->stream, ctx->red_partial, nblocks, 1,
+                     ctx->red_result);
+  LAUNCH_CHECK();
+  HIP_CHECK(hipMemcpyAsync(ctx->red_host, ctx->red_result, sizeof(double), hipMemcpyDeviceToHost,
+                           ctx->stream));
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  prof_flush(ctx);
+  return ctx->red_host[0];
+}

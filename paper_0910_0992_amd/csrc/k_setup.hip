@@ -1,0 +1,559 @@
+// One-off and layout kernels: canonical <-> internal spinor layouts, link
+// packing, the per-time-line products W(t) and the FP64 closure of T^-1,
+// the clover term in its chiral block form and (A + mu)^-1.
+#include "tp_internal.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+TP_DEV void canon_coords(int64_t n, const Geom& g, int& x, int& y, int& z, int& t) {
+  x = int(n % g.Lx);
+  int64_t r = n / g.Lx;
+  y = int(r % g.Ly);
+  r /= g.Ly;
+  z = int(r % g.Lz);
+  t = int(r / g.Lz);
+}
+
+// internal (parity, index) of a site for the p3 or p4 layout
+TP_DEV void site_pi(const Geom& g, bool l4, int x, int y, int z, int t, int& p, int64_t& i) {
+  int64_t f3 = (int64_t)(x + g.Lx * (y + g.Ly * z));
+  if (l4) {
+    p = (x + y + z + t) & 1;
+    i = (f3 + (int64_t)g.Lx * g.Ly * g.Lz * t) >> 1;
+  } else {
+    p = (x + y + z) & 1;
+    i = (int64_t)t * g.Vs2 + (f3 >> 1);
+  }
+}
+
+template <typename S>
+__global__ void k_pack(const double2* __restrict__ canon, SpinorF<S> f0, SpinorF<S> f1, Geom g,
+                       int64_t V, bool l4, bool g5) {
+  using R = typename Prec<S>::R;
+  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= V) return;
+  int x, y, z, t;
+  canon_coords(n, g, x, y, z, t);
+  int p;
+  int64_t i;
+  site_pi(g, l4, x, y, z, t, p, i);
+  cx<R> v[12];
+  const double2* src = canon + n * 12;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    double2 d = src[c];
+    v[c] = cx<R>{R(d.x), R(d.y)};
+  }
+  if (g5) {  // gamma5 = [[0,-1],[-1,0]] in the Dirac-Pauli basis
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      cx<R> a = v[c];
+      v[c] = -v[6 + c];
+      v[6 + c] = -a;
+    }
+  }
+  store_spinor<S, R>(p ? f1 : f0, i, v);
+}
+
+template <typename S>
+__global__ void k_unpack(double2* __restrict__ canon, SpinorF<S> f0, SpinorF<S> f1, Geom g,
+                         int64_t V, bool l4, bool g5) {
+  using R = typename Prec<S>::R;
+  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= V) return;
+  int x, y, z, t;
+  canon_coords(n, g, x, y, z, t);
+  int p;
+  int64_t i;
+  site_pi(g, l4, x, y, z, t, p, i);
+  cx<R> v[12];
+  load_spinor<S, R>(p ? f1 : f0, i, v);
+  if (g5) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      cx<R> a = v[c];
+      v[c] = -v[6 + c];
+      v[6 + c] = -a;
+    }
+  }
+  double2* dst = canon + n * 12;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) dst[c] = make_double2(double(v[c].re), double(v[c].im));
+}
+
+// links: canon [4][V][9] -> p3 FP64/FP32 and p4 FP64, phase b folded into U_t(Lt-1)
+__global__ void k_pack_links(const double2* __restrict__ canon, double2* u3d, float2* u3f,
+                             double2* u4d, float2* u4f, Geom g, int64_t V, double b) {
+  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int mu = blockIdx.y;
+  if (n >= V) return;
+  int x, y, z, t;
+  canon_coords(n, g, x, y, z, t);
+  double ph = (mu == 3 && t == g.Lt - 1) ? b : 1.0;
+  int p3, p4;
+  int64_t i3, i4;
+  site_pi(g, false, x, y, z, t, p3, i3);
+  site_pi(g, true, x, y, z, t, p4, i4);
+  const double2* src = canon + ((int64_t)mu * V + n) * 9;
+  int64_t V2 = V / 2;
+  double2* d3 = u3d + ((int64_t)(mu * 2 + p3) * 9) * V2 + i3;
+  float2* f3 = u3f + ((int64_t)(mu * 2 + p3) * 9) * V2 + i3;
+  double2* d4 = u4d + ((int64_t)(mu * 2 + p4) * 9) * V2 + i4;
+  float2* f4 = u4f + ((int64_t)(mu * 2 + p4) * 9) * V2 + i4;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    double2 e = src[k];
+    e.x *= ph;
+    e.y *= ph;
+    d3[(int64_t)k * V2] = e;
+    f3[(int64_t)k * V2] = make_float2(float(e.x), float(e.y));
+    d4[(int64_t)k * V2] = e;
+    f4[(int64_t)k * V2] = make_float2(float(e.x), float(e.y));
+  }
+}
+
+TP_DEV void mm3(const cx<double>* a, const cx<double>* b, cx<double>* c) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      cx<double> s = cmul(a[3 * i], b[j]);
+      s += cmul(a[3 * i + 1], b[3 + j]);
+      s += cmul(a[3 * i + 2], b[6 + j]);
+      c[3 * i + j] = s;
+    }
+}
+
+// W(t) = U'(t) U'(t+1) ... U'(Lt-1) per time line (U' has the phase folded in).
+// One thread per line: an Lt-step product, run once per gauge field.
+__global__ void k_wline(const double2* __restrict__ u3d, double2* wd, float2* wf, double2* poly,
+                        Geom g) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  int p = blockIdx.y;
+  if (s >= g.Vs2) return;
+  int64_t V2 = g.V2;
+  const double2* ut = u3d + ((int64_t)(3 * 2 + p) * 9) * V2;
+  double2* w = wd + (int64_t)p * 9 * V2;
+  float2* w32 = wf + (int64_t)p * 9 * V2;
+  cx<double> acc[9], u[9], nw[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = cx<double>{(k % 4 == 0) ? 1.0 : 0.0, 0.0};
+  for (int t = g.Lt - 1; t >= 0; --t) {
+    int64_t i = (int64_t)t * g.Vs2 + s;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      double2 e = ut[(int64_t)k * V2 + i];
+      u[k] = cx<double>{e.x, e.y};
+    }
+    mm3(u, acc, nw);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      acc[k] = nw[k];
+      w[(int64_t)k * V2 + i] = make_double2(nw[k].re, nw[k].im);
+      w32[(int64_t)k * V2 + i] = make_float2(float(nw[k].re), float(nw[k].im));
+    }
+  }
+  double2* pl = poly + (int64_t)p * 9 * g.Vs2;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) pl[(int64_t)k * g.Vs2 + s] = make_double2(acc[k].re, acc[k].im);
+}
+
+TP_DEV bool inv3(const cx<double>* m, cx<double>* r) {
+  // adjugate / determinant
+  cx<double> c00 = cmul(m[4], m[8]) - cmul(m[5], m[7]);
+  cx<double> c01 = cmul(m[5], m[6]) - cmul(m[3], m[8]);
+  cx<double> c02 = cmul(m[3], m[7]) - cmul(m[4], m[6]);
+  cx<double> det = cmul(m[0], c00) + cmul(m[1], c01) + cmul(m[2], c02);
+  double dn = norm2(det);
+  if (!(dn > 0.0)) return false;
+  cx<double> id = cx<double>{det.re / dn, -det.im / dn};
+  r[0] = cmul(c00, id);
+  r[3] = cmul(c01, id);
+  r[6] = cmul(c02, id);
+  r[1] = cmul(cmul(m[2], m[7]) - cmul(m[1], m[8]), id);
+  r[4] = cmul(cmul(m[0], m[8]) - cmul(m[2], m[6]), id);
+  r[7] = cmul(cmul(m[1], m[6]) - cmul(m[0], m[7]), id);
+  r[2] = cmul(cmul(m[1], m[5]) - cmul(m[2], m[4]), id);
+  r[5] = cmul(cmul(m[2], m[3]) - cmul(m[0], m[5]), id);
+  r[8] = cmul(cmul(m[0], m[4]) - cmul(m[1], m[3]), id);
+  return true;
+}
+
+TP_DEV double norm1(const cx<double>* m) {
+  double best = 0;
+  for (int j = 0; j < 3; ++j) {
+    double s = 0;
+    for (int i = 0; i < 3; ++i) s += sqrt(norm2(m[3 * i + j]));
+    best = fmax(best, s);
+  }
+  return best;
+}
+
+// Closure of the temporal inverse per line: K = (I - mu^-Lt P)^-1 and G = K P / mu,
+// so that delta = G sigma(0) for T^-1 and delta' = G^dagger rho(Lt-1) for T^dagger^-1.
+__global__ void k_closure(const double2* __restrict__ poly, double2* gclos, double* cond,
+                          Geom g, double mu, double mu_mlt) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  int p = blockIdx.y;
+  if (s >= g.Vs2) return;
+  const double2* pl = poly + (int64_t)p * 9 * g.Vs2;
+  cx<double> P[9], A[9], K[9], G[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    double2 e = pl[(int64_t)k * g.Vs2 + s];
+    P[k] = cx<double>{e.x, e.y};
+    A[k] = cx<double>{(k % 4 == 0 ? 1.0 : 0.0) - mu_mlt * e.x, -mu_mlt * e.y};
+  }
+  double c;
+  if (inv3(A, K)) {
+    c = norm1(A) * norm1(K);
+    mm3(K, P, G);
+  } else {
+    c = INFINITY;
+    for (int k = 0; k < 9; ++k) G[k] = cx<double>{0, 0};
+  }
+  if (!isfinite(c)) c = INFINITY;
+  cond[(int64_t)p * g.Vs2 + s] = c;
+  double2* go = gclos + (int64_t)p * 9 * g.Vs2;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) go[(int64_t)k * g.Vs2 + s] = make_double2(G[k].re / mu, G[k].im / mu);
+}
+
+// ---- clover ------------------------------------------------------------------------------
+struct SigTab {
+  double2 s[6][2][2][2];  // plane, chirality, row, col:  coef_p * V_chi^dag sigma_p V_chi / 2
+};
+
+TP_DEV void load_link(const double2* canon, const Geom& g, int64_t V, int mu, int x, int y, int z,
+                      int t, cx<double>* u) {
+  x = (x + g.Lx) % g.Lx;
+  y = (y + g.Ly) % g.Ly;
+  z = (z + g.Lz) % g.Lz;
+  t = (t + g.Lt) % g.Lt;
+  int64_t n = (int64_t)x + (int64_t)g.Lx * (y + (int64_t)g.Ly * (z + (int64_t)g.Lz * t));
+  const double2* src = canon + ((int64_t)mu * V + n) * 9;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) u[k] = cx<double>{src[k].x, src[k].y};
+}
+TP_DEV void dag3(const cx<double>* a, cx<double>* b) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) b[3 * i + j] = conj(a[3 * j + i]);
+}
+TP_DEV void chain4(const cx<double>* a, const cx<double>* b, const cx<double>* c,
+                   const cx<double>* d, cx<double>* out) {
+  cx<double> t1[9], t2[9];
+  mm3(a, b, t1);
+  mm3(t1, c, t2);
+  mm3(t2, d, out);
+}
+
+// F_{mu nu}(x) = (Q - Q^dag)/8 - tr/3 with Q the four leaves, all oriented mu -> nu.
+TP_DEV void field_strength(const double2* canon, const Geom& g, int64_t V, int mu, int nu, int x,
+                           int y, int z, int t, cx<double>* F) {
+  int e[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
+  auto L = [&](int d, int am, int an, cx<double>* u) {  // U_d(x + am*mu + an*nu)
+    load_link(canon, g, V, d, x + am * e[mu][0] + an * e[nu][0], y + am * e[mu][1] + an * e[nu][1],
+              z + am * e[mu][2] + an * e[nu][2], t + am * e[mu][3] + an * e[nu][3], u);
+  };
+  cx<double> a[9], b[9], c[9], d[9], cd[9], dd[9], leaf[9], Q[9];
+  for (int k = 0; k < 9; ++k) Q[k] = cx<double>{0, 0};
+  // leaf 1: U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
+  L(mu, 0, 0, a); L(nu, 1, 0, b); L(mu, 0, 1, c); L(nu, 0, 0, d);
+  dag3(c, cd); dag3(d, dd); chain4(a, b, cd, dd, leaf);
+  for (int k = 0; k < 9; ++k) Q[k] += leaf[k];
+  // leaf 2: U_nu(x) U_mu(x-mu+nu)^dag U_nu(x-mu)^dag U_mu(x-mu)
+  L(nu, 0, 0, a); L(mu, -1, 1, b); L(nu, -1, 0, c); L(mu, -1, 0, d);
+  { cx<double> bd[9]; dag3(b, bd); dag3(c, cd); chain4(a, bd, cd, d, leaf); }
+  for (int k = 0; k < 9; ++k) Q[k] += leaf[k];
+  // leaf 3: U_mu(x-mu)^dag U_nu(x-mu-nu)^dag U_mu(x-mu-nu) U_nu(x-nu)
+  L(mu, -1, 0, a); L(nu, -1, -1, b); L(mu, -1, -1, c); L(nu, 0, -1, d);
+  { cx<double> ad[9], bd[9]; dag3(a, ad); dag3(b, bd); chain4(ad, bd, c, d, leaf); }
+  for (int k = 0; k < 9; ++k) Q[k] += leaf[k];
+  // leaf 4: U_nu(x-nu)^dag U_mu(x-nu) U_nu(x+mu-nu) U_mu(x)^dag
+  L(nu, 0, -1, a); L(mu, 0, -1, b); L(nu, 1, -1, c); L(mu, 0, 0, d);
+  { cx<double> ad[9]; dag3(a, ad); dag3(d, dd); chain4(ad, b, c, dd, leaf); }
+  for (int k = 0; k < 9; ++k) Q[k] += leaf[k];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) F[3 * i + j] = 0.125 * (Q[3 * i + j] - conj(Q[3 * j + i]));
+  cx<double> tr = (1.0 / 3.0) * (F[0] + F[4] + F[8]);
+  F[0] -= tr; F[4] -= tr; F[8] -= tr;
+}
+
+TP_DEV void store_herm6(const cx<double>* m /*36 row-major*/, double2* d3, float2* f3, int64_t st,
+                        int64_t i3, double2* d4, int64_t i4, float2* f4 = nullptr) {
+  // slots 0..2: diagonal pairs, 3..17: lower triangle row-major
+  int slot = 0;
+  for (int k = 0; k < 3; ++k, ++slot) {
+    double2 v = make_double2(m[(2 * k) * 7].re, m[(2 * k + 1) * 7].re);
+    if (d3) d3[(int64_t)slot * st + i3] = v;
+    if (f3) f3[(int64_t)slot * st + i3] = make_float2(float(v.x), float(v.y));
+    if (d4) d4[(int64_t)slot * st + i4] = v;
+    if (f4) f4[(int64_t)slot * st + i4] = make_float2(float(v.x), float(v.y));
+  }
+  for (int r = 1; r < 6; ++r)
+    for (int c = 0; c < r; ++c, ++slot) {
+      double2 v = make_double2(m[6 * r + c].re, m[6 * r + c].im);
+      if (d3) d3[(int64_t)slot * st + i3] = v;
+      if (f3) f3[(int64_t)slot * st + i3] = make_float2(float(v.x), float(v.y));
+      if (d4) d4[(int64_t)slot * st + i4] = v;
+      if (f4) f4[(int64_t)slot * st + i4] = make_float2(float(v.x), float(v.y));
+    }
+}
+
+__global__ void k_clover_build(const double2* __restrict__ canon, double2* a3d, float2* a3f,
+                               double2* a4d, float2* a4f, Geom g, int64_t V, SigTab sig) {
+  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= V) return;
+  int x, y, z, t;
+  canon_coords(n, g, x, y, z, t);
+  const int planes[6][2] = {{0, 3}, {1, 3}, {2, 3}, {0, 1}, {0, 2}, {1, 2}};
+  cx<double> B[2][36];
+  for (int c = 0; c < 2; ++c)
+    for (int k = 0; k < 36; ++k) B[c][k] = cx<double>{0, 0};
+  for (int pl = 0; pl < 6; ++pl) {
+    double2 nz = sig.s[pl][0][0][0];
+    double mag = fabs(nz.x) + fabs(nz.y) + fabs(sig.s[pl][0][0][1].x) + fabs(sig.s[pl][0][0][1].y) +
+                 fabs(sig.s[pl][1][0][0].x) + fabs(sig.s[pl][1][0][0].y) +
+                 fabs(sig.s[pl][1][0][1].x) + fabs(sig.s[pl][1][0][1].y);
+    if (mag == 0.0) continue;  // coefficient zero
+    cx<double> F[9];
+    field_strength(canon, g, V, planes[pl][0], planes[pl][1], x, y, z, t, F);
+    for (int c = 0; c < 2; ++c)
+      for (int s = 0; s < 2; ++s)
+        for (int sp = 0; sp < 2; ++sp) {
+          cx<double> w = cx<double>{sig.s[pl][c][s][sp].x, sig.s[pl][c][s][sp].y};
+          for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) B[c][(3 * s + a) * 6 + 3 * sp + b] += cmul(w, F[3 * a + b]);
+        }
+  }
+  int p3, p4;
+  int64_t i3, i4;
+  site_pi(g, false, x, y, z, t, p3, i3);
+  site_pi(g, true, x, y, z, t, p4, i4);
+  int64_t V2 = V / 2;
+  for (int c = 0; c < 2; ++c) {
+    double2* d3 = a3d + ((int64_t)p3 * 36 + 18 * c) * V2;
+    float2* f3 = a3f + ((int64_t)p3 * 36 + 18 * c) * V2;
+    double2* d4 = a4d + ((int64_t)p4 * 36 + 18 * c) * V2;
+    float2* f4 = a4f + ((int64_t)p4 * 36 + 18 * c) * V2;
+    store_herm6(B[c], d3, f3, V2, i3, d4, i4, f4);
+  }
+}
+
+TP_DEV void load_herm6(const double2* base, int64_t st, int64_t i, cx<double>* m) {
+  int slot = 0;
+  for (int k = 0; k < 3; ++k, ++slot) {
+    double2 v = base[(int64_t)slot * st + i];
+    m[(2 * k) * 7] = cx<double>{v.x, 0};
+    m[(2 * k + 1) * 7] = cx<double>{v.y, 0};
+  }
+  for (int r = 1; r < 6; ++r)
+    for (int c = 0; c < r; ++c, ++slot) {
+      double2 v = base[(int64_t)slot * st + i];
+      m[6 * r + c] = cx<double>{v.x, v.y};
+      m[6 * c + r] = cx<double>{v.x, -v.y};
+    }
+}
+
+// Gauss-Jordan with partial pivoting on a 6x6 complex matrix (FP64).
+TP_DEV bool inv6(cx<double>* a, cx<double>* inv) {
+  for (int i = 0; i < 36; ++i) inv[i] = cx<double>{(i % 7 == 0) ? 1.0 : 0.0, 0.0};
+  double scale = 0;
+  for (int i = 0; i < 6; ++i) scale = fmax(scale, sqrt(norm2(a[7 * i])));
+  for (int col = 0; col < 6; ++col) {
+    int piv = col;
+    double best = norm2(a[6 * col + col]);
+    for (int r = col + 1; r < 6; ++r) {
+      double v = norm2(a[6 * r + col]);
+      if (v > best) { best = v; piv = r; }
+    }
+    if (!(sqrt(best) > 1e-13 * scale)) return false;
+    if (piv != col)
+      for (int k = 0; k < 6; ++k) {
+        cx<double> t1 = a[6 * col + k]; a[6 * col + k] = a[6 * piv + k]; a[6 * piv + k] = t1;
+        cx<double> t2 = inv[6 * col + k]; inv[6 * col + k] = inv[6 * piv + k]; inv[6 * piv + k] = t2;
+      }
+    cx<double> d = a[6 * col + col];
+    double dn = norm2(d);
+    cx<double> id = cx<double>{d.re / dn, -d.im / dn};
+    for (int k = 0; k < 6; ++k) {
+      a[6 * col + k] = cmul(a[6 * col + k], id);
+      inv[6 * col + k] = cmul(inv[6 * col + k], id);
+    }
+    for (int r = 0; r < 6; ++r) {
+      if (r == col) continue;
+      cx<double> f = a[6 * r + col];
+      for (int k = 0; k < 6; ++k) {
+        a[6 * r + k] -= cmul(f, a[6 * col + k]);
+        inv[6 * r + k] -= cmul(f, inv[6 * col + k]);
+      }
+    }
+  }
+  return true;
+}
+
+// From the stored A/2 blocks (layout p3 or p4), write (A+mu)/2 and (A+mu)^-1/2 blocks.
+__global__ void k_clover_derived(const double2* __restrict__ a, double2* amu, double2* ainv,
+                                 float2* amu_f, float2* ainv_f, int64_t V2, double mu, int* bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int p = blockIdx.y;
+  if (i >= V2) return;
+  for (int c = 0; c < 2; ++c) {
+    int64_t off = ((int64_t)p * 36 + 18 * c) * V2;
+    cx<double> m[36], inv[36];
+    if (a) {
+      load_herm6(a + off, V2, i, m);
+    } else {
+      for (int k = 0; k < 36; ++k) m[k] = cx<double>{0, 0};
+    }
+    for (int k = 0; k < 6; ++k) m[7 * k].re += 0.5 * mu;  // (A + mu)/2
+    store_herm6(m, amu + off, amu_f ? amu_f + off : nullptr, V2, i, nullptr, 0);
+    // (A+mu)^-1/2 = [(A+mu)/2]^-1 / 4
+    if (!inv6(m, inv)) {
+      bad[0] = 1;
+      for (int k = 0; k < 36; ++k) inv[k] = cx<double>{0, 0};
+    }
+    for (int k = 0; k < 36; ++k) inv[k] = 0.25 * inv[k];
+    // symmetrise (hermitian up to rounding)
+    for (int r = 0; r < 6; ++r)
+      for (int cc = 0; cc < r; ++cc) {
+        cx<double> l = 0.5 * (inv[6 * r + cc] + conj(inv[6 * cc + r]));
+        inv[6 * r + cc] = l;
+      }
+    store_herm6(inv, ainv + off, ainv_f ? ainv_f + off : nullptr, V2, i, nullptr, 0);
+  }
+}
+
+// Plaquette averages (1/3 Re tr) over spatial and temporal planes: per-block partials.
+__global__ void k_plaquette(const double2* __restrict__ canon, Geom g, int64_t V, double* part) {
+  __shared__ double sh[2][kBlock];
+  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double ps = 0, pt = 0;
+  if (n < V) {
+    int x, y, z, t;
+    canon_coords(n, g, x, y, z, t);
+    const int planes[6][2] = {{0, 1}, {0, 2}, {1, 2}, {0, 3}, {1, 3}, {2, 3}};
+    int e[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
+    for (int pl = 0; pl < 6; ++pl) {
+      int mu = planes[pl][0], nu = planes[pl][1];
+      cx<double> a[9], b[9], c[9], d[9], cd[9], dd[9], leaf[9];
+      load_link(canon, g, V, mu, x, y, z, t, a);
+      load_link(canon, g, V, nu, x + e[mu][0], y + e[mu][1], z + e[mu][2], t + e[mu][3], b);
+      load_link(canon, g, V, mu, x + e[nu][0], y + e[nu][1], z + e[nu][2], t + e[nu][3], c);
+      load_link(canon, g, V, nu, x, y, z, t, d);
+      dag3(c, cd);
+      dag3(d, dd);
+      chain4(a, b, cd, dd, leaf);
+      double re = (leaf[0].re + leaf[4].re + leaf[8].re) / 3.0;
+      if (pl < 3) ps += re; else pt += re;
+    }
+  }
+  sh[0][threadIdx.x] = ps;
+  sh[1][threadIdx.x] = pt;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sh[0][0];
+    part[2 * blockIdx.x + 1] = sh[1][0];
+  }
+}
+
+inline unsigned nblk(int64_t n, int64_t b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+template <typename S>
+void pack_t(tp_ctx ctx, const double2* canon, Field& dst, bool l4, bool g5) {
+  const Lattice& L = ctx->lat;
+  hipLaunchKernelGGL(k_pack<S>, dim3(nblk(L.V)), dim3(kBlock), 0, ctx->stream, canon,
+                     dst.template par<S>(0), dst.template par<S>(1), L.g, L.V, l4, g5);
+  LAUNCH_CHECK();
+}
+template <typename S>
+void unpack_t(tp_ctx ctx, const Field& src, double2* canon, bool l4, bool g5) {
+  const Lattice& L = ctx->lat;
+  hipLaunchKernelGGL(k_unpack<S>, dim3(nblk(L.V)), dim3(kBlock), 0, ctx->stream, canon,
+                     src.template par<S>(0), src.template par<S>(1), L.g, L.V, l4, g5);
+  LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void launch_pack(tp_ctx ctx, const double2* canon, Field& dst, bool l4, bool g5) {
+  ProfScope ps(ctx, KID_PACK, double(ctx->lat.V) * (192 + 12 * dst.elem_bytes()));
+  switch (dst.prec) {
+    case TP_F64: pack_t<double2>(ctx, canon, dst, l4, g5); break;
+    case TP_F32: pack_t<float2>(ctx, canon, dst, l4, g5); break;
+    default: pack_t<__half2>(ctx, canon, dst, l4, g5); break;
+  }
+}
+
+void launch_unpack(tp_ctx ctx, const Field& src, double2* canon, bool l4, bool g5) {
+  ProfScope ps(ctx, KID_PACK, double(ctx->lat.V) * (192 + 12 * src.elem_bytes()));
+  switch (src.prec) {
+    case TP_F64: unpack_t<double2>(ctx, src, canon, l4, g5); break;
+    case TP_F32: unpack_t<float2>(ctx, src, canon, l4, g5); break;
+    default: unpack_t<__half2>(ctx, src, canon, l4, g5); break;
+  }
+}
+
+void launch_pack_links(tp_ctx ctx, tp_gauge g) {
+  const Lattice& L = ctx->lat;
+  hipLaunchKernelGGL(k_pack_links, dim3(nblk(L.V), 4), dim3(kBlock), 0, ctx->stream, g->canon,
+                     g->u3_d, g->u3_f, g->u4_d, g->u4_f, L.g, L.V, double(ctx->bc));
+  LAUNCH_CHECK();
+}
+
+void launch_wline(tp_ctx ctx, tp_gauge g) {
+  const Lattice& L = ctx->lat;
+  hipLaunchKernelGGL(k_wline, dim3((L.Vs2 + 63) / 64, 2), dim3(64), 0, ctx->stream, g->u3_d,
+                     g->w_d, g->w_f, g->poly, L.g);
+  LAUNCH_CHECK();
+}
+
+void launch_closure(tp_ctx ctx, tp_op op, double* cond) {
+  const Lattice& L = ctx->lat;
+  double mu_mlt = pow(op->mu, -double(L.L[3]));
+  hipLaunchKernelGGL(k_closure, dim3((L.Vs2 + 63) / 64, 2), dim3(64), 0, ctx->stream,
+                     op->g->poly, op->gclos, cond, L.g, op->mu, mu_mlt);
+  LAUNCH_CHECK();
+}
+
+void launch_clover_build(tp_ctx ctx, tp_clover c, const double sig[6][2][2][2][2]) {
+  const Lattice& L = ctx->lat;
+  SigTab t;
+  for (int p = 0; p < 6; ++p)
+    for (int ch = 0; ch < 2; ++ch)
+      for (int r = 0; r < 2; ++r)
+        for (int q = 0; q < 2; ++q) t.s[p][ch][r][q] = make_double2(sig[p][ch][r][q][0], sig[p][ch][r][q][1]);
+  hipLaunchKernelGGL(k_clover_build, dim3(nblk(L.V, 64)), dim3(64), 0, ctx->stream, c->g->canon,
+                     c->a3_d, c->a3_f, c->a4_d, c->a4_f, L.g, L.V, t);
+  LAUNCH_CHECK();
+}
+
+void launch_clover_derived(tp_ctx ctx, tp_op op, int* bad) {
+  const Lattice& L = ctx->lat;
+  const double2* a4 = op->c ? op->c->a4_d : nullptr;
+  const double2* a3 = op->c ? op->c->a3_d : nullptr;
+  hipLaunchKernelGGL(k_clover_derived, dim3(nblk(L.V2, 64), 2), dim3(64), 0, ctx->stream, a4,
+                     op->a4_mu, op->a4_inv, op->a4_mu_f, op->a4_inv_f, L.V2, op->mu, bad);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_clover_derived, dim3(nblk(L.V2, 64), 2), dim3(64), 0, ctx->stream, a3,
+                     op->a3_mu, op->a3_inv, op->a3_mu_f, op->a3_inv_f, L.V2, op->mu, bad);
+  LAUNCH_CHECK();
+}
+
+void launch_plaquette(tp_ctx ctx, tp_gauge g, double* part) {
+  const Lattice& L = ctx->lat;
+  hipLaunchKernelGGL(k_plaquette, dim3(nblk(L.V)), dim3(kBlock), 0, ctx->stream, g->canon, L.g,
+                     L.V, part);
+  LAUNCH_CHECK();
+}

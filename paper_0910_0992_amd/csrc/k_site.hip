@@ -1,0 +1,421 @@
+// Site-parallel stencil kernels: the fermion matrix and its pieces on the p3
+// ("line") layout, the 4D even-odd Schur pieces on the p4 layout, and the
+// link-gradient kernel.  One thread per output site; spin projection in the
+// Dirac-Pauli basis (only two colour matvecs per hop direction).
+#include "tp_internal.h"
+#include "tp_hop.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+template <typename S>
+struct SiteArgsP3 {
+  SpinorF<S> src[2], dst[2], in2[2];
+  LinkF<typename Prec<S>::L> u[2][4];  // [parity][direction]
+  const typename Prec<S>::L* clov[2];
+  double c_mu, c_A, c_t, c_s, c_in;
+  Geom g;
+  int par0;
+  int64_t n;  // number of output sites (npar * V2)
+  double* partial;
+};
+
+template <typename S, bool DT, bool DS, bool CLOV, bool IN2, bool NORM>
+__global__ void __launch_bounds__(kBlock) k_site_p3(SiteArgsP3<S> a) {
+  using R = typename Prec<S>::R;
+  using Lt = typename Prec<S>::L;
+  __shared__ double red[kBlock / 64];
+  double acc = 0.0;
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < a.n;
+       n += (int64_t)gridDim.x * blockDim.x) {
+    int p = a.par0 + int(n / a.g.V2);
+    int64_t i = n % a.g.V2;
+    int t = int(i / a.g.Vs2);
+    int s = int(i % a.g.Vs2);
+    cx<R> out[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) out[c] = czero<R>();
+    if (a.c_mu != 0.0 || CLOV) {
+      cx<R> psi[12];
+      load_spinor<S, R>(a.src[p], i, psi);
+      R cm = R(a.c_mu);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) out[c] = cm * psi[c];
+      if constexpr (CLOV) {
+        cx<R> ap[12];
+        clover_apply<R, Lt>(a.clov[p], a.g.V2, i, psi, ap);
+        R ca = R(a.c_A);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) out[c] += ca * ap[c];
+      }
+    }
+    if constexpr (DT) {
+      hop_time_p3<S, R, Lt>(a.src[p], a.u[p][3], a.g, t, s, R(a.c_t), out);
+    }
+    if constexpr (DS) {
+      hop_space_p3<S, R, Lt>(a.src[1 - p], a.u[p], a.u[1 - p], a.g, p, t, s, R(0.5 * a.c_s), out);
+    }
+    if constexpr (IN2) {
+      cx<R> e[12];
+      load_spinor<S, R>(a.in2[p], i, e);
+      R ci = R(a.c_in);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) out[c] += ci * e[c];
+    }
+    if constexpr (NORM) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc += double(norm2(out[c]));
+    }
+    store_spinor<S, R>(a.dst[p], i, out);
+  }
+  if constexpr (NORM) {
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0;
+      for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+      a.partial[(int64_t)blockIdx.x * 8] = s;
+    }
+  }
+}
+
+// ---- 4D even-odd Schur (p4 layout) ---------------------------------------------------------
+template <typename S>
+struct ArgsP4 {
+  SpinorF<S> src, dst, in2;  // src on parity 1-p; dst and in2 on parity p
+  LinkF<typename Prec<S>::L> u[2][4];
+  const typename Prec<S>::L* clov;  // blocks on parity p
+  double c_h, c_in, inv_gf;
+  Geom g;
+  int p;
+};
+
+// CL: 0 none; 1 clover applied to (c_in*in2 + c_h*D_w src); 2 clover applied to in2,
+// then + c_h*D_w src.
+template <typename S, bool HOP, bool IN2, int CL>
+__global__ void __launch_bounds__(kBlock) k_schur4d(ArgsP4<S> a) {
+  using R = typename Prec<S>::R;
+  using Lt = typename Prec<S>::L;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.g.V2) return;
+  cx<R> v[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = czero<R>();
+  if constexpr (IN2) {
+    cx<R> e[12];
+    load_spinor<S, R>(a.in2, i, e);
+    if constexpr (CL == 2) {
+      clover_apply<R, Lt>(a.clov, a.g.V2, i, e, v);
+    } else {
+      R ci = R(a.c_in);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) v[c] = ci * e[c];
+    }
+  }
+  if constexpr (HOP) {
+    hop_4d_p4<S, R, Lt>(a.src, a.u[a.p], a.u[1 - a.p], a.g, a.p, i, R(a.c_h), R(a.c_h * a.inv_gf), v);
+  }
+  if constexpr (CL == 1) {
+    cx<R> w[12];
+    clover_apply<R, Lt>(a.clov, a.g.V2, i, v, w);
+    store_spinor<S, R>(a.dst, i, w);
+  } else {
+    store_spinor<S, R>(a.dst, i, v);
+  }
+}
+
+// ---- link gradient ----------------------------------------------------------------------------
+// Per link U_mu(s):  K = Y + Z^dag with
+//   Y_ca = sum_a [P-^mu x(s+mu)]_{a c} conj(lambda(s)_{a a'}),
+//   Z_ca = sum_a [P+^mu x(s)]_{a c} conj(lambda(s+mu)_{a a'});
+// raw gradient k b K^dag, projected k b TH(i U K).
+TP_DEV void proj_full(int mu, bool minus, const cx<double>* x, cx<double>* out) {
+  // out = (1 -+ gamma_mu)/2 x, as a full 4-spinor
+  if (mu == 3) {
+    for (int c = 0; c < 12; ++c) out[c] = czero<double>();
+    int off = minus ? 6 : 0;
+    for (int c = 0; c < 6; ++c) out[off + c] = x[off + c];
+    return;
+  }
+  cx<double> h[6], a[3], b[3];
+  double sg = minus ? 1.0 : -1.0;  // h = x_up + sg * i s_k x_lo
+  if (mu == 0) is_k<0, double>(x + 6, x + 9, a, b);
+  else if (mu == 1) is_k<1, double>(x + 6, x + 9, a, b);
+  else is_k<2, double>(x + 6, x + 9, a, b);
+  for (int c = 0; c < 3; ++c) { h[c] = x[c] + sg * a[c]; h[3 + c] = x[3 + c] + sg * b[c]; }
+  if (mu == 0) is_k<0, double>(h, h + 3, a, b);
+  else if (mu == 1) is_k<1, double>(h, h + 3, a, b);
+  else is_k<2, double>(h, h + 3, a, b);
+  // lower = -sg * i s_k h
+  for (int c = 0; c < 3; ++c) {
+    out[c] = 0.5 * h[c];
+    out[3 + c] = 0.5 * h[3 + c];
+    out[6 + c] = (-0.5 * sg) * a[c];
+    out[9 + c] = (-0.5 * sg) * b[c];
+  }
+}
+
+__global__ void k_force(SpinorF<double2> x0, SpinorF<double2> x1, SpinorF<double2> l0,
+                        SpinorF<double2> l1, const double2* __restrict__ canon, double2* grad,
+                        Geom g, int64_t V, double inv_gf, double b, int projected) {
+  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int mu = blockIdx.y;
+  if (n >= V) return;
+  int x = int(n % g.Lx);
+  int64_t r = n / g.Lx;
+  int y = int(r % g.Ly);
+  r /= g.Ly;
+  int z = int(r % g.Lz);
+  int t = int(r / g.Lz);
+  int xs[4] = {x, y, z, t};
+  int ls[4] = {g.Lx, g.Ly, g.Lz, g.Lt};
+  xs[mu] = xs[mu] + 1 == ls[mu] ? 0 : xs[mu] + 1;
+  auto p3 = [&](int X, int Y, int Z, int T, int& p, int64_t& i) {
+    p = (X + Y + Z) & 1;
+    i = (int64_t)T * g.Vs2 + ((X + g.Lx * (Y + g.Ly * Z)) >> 1);
+  };
+  int pa, pb;
+  int64_t ia, ib;
+  p3(x, y, z, t, pa, ia);
+  p3(xs[0], xs[1], xs[2], xs[3], pb, ib);
+  cx<double> xa[12], xb[12], la[12], lb[12], px[12];
+  load_spinor<double2, double>(pa ? x1 : x0, ia, xa);
+  load_spinor<double2, double>(pb ? x1 : x0, ib, xb);
+  load_spinor<double2, double>(pa ? l1 : l0, ia, la);
+  load_spinor<double2, double>(pb ? l1 : l0, ib, lb);
+  cx<double> K[9];
+  for (int k = 0; k < 9; ++k) K[k] = czero<double>();
+  proj_full(mu, true, xb, px);  // P- x(s+mu)
+  for (int c = 0; c < 3; ++c)
+    for (int a = 0; a < 3; ++a) {
+      cx<double> s = czero<double>();
+      for (int al = 0; al < 4; ++al) s += cmulc(la[3 * al + a], px[3 * al + c]);
+      K[3 * c + a] += s;  // Y_ca
+    }
+  proj_full(mu, false, xa, px);  // P+ x(s)
+  for (int c = 0; c < 3; ++c)
+    for (int a = 0; a < 3; ++a) {
+      cx<double> s = czero<double>();
+      for (int al = 0; al < 4; ++al) s += cmulc(lb[3 * al + a], px[3 * al + c]);
+      K[3 * a + c] += conj(s);  // (Z^dag)_ac = conj(Z_ca)
+    }
+  double fac = (mu == 3 ? 1.0 : inv_gf) * ((mu == 3 && t == g.Lt - 1) ? b : 1.0);
+  double2* out = grad + ((int64_t)mu * V + n) * 9;
+  if (!projected) {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        cx<double> v = fac * conj(K[3 * j + i]);
+        out[3 * i + j] = make_double2(v.re, v.im);
+      }
+    return;
+  }
+  const double2* u = canon + ((int64_t)mu * V + n) * 9;
+  cx<double> U[9], M[9];
+  for (int k = 0; k < 9; ++k) U[k] = cx<double>{u[k].x, u[k].y};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      cx<double> s = czero<double>();
+      for (int k = 0; k < 3; ++k) s += cmul(U[3 * i + k], K[3 * k + j]);
+      M[3 * i + j] = ti(s);  // i U K
+    }
+  double tr = (M[0].re + M[4].re + M[8].re) / 3.0;  // tr of (M + M^dag)/2 over 3
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      cx<double> h = 0.5 * (M[3 * i + j] + conj(M[3 * j + i]));
+      if (i == j) h.re -= tr;
+      out[3 * i + j] = make_double2(fac * h.re, fac * h.im);
+    }
+}
+
+template <typename S>
+SpinorF<S> view(const Field* f, int p) {
+  if (!f) {
+    SpinorF<S> z;
+    z.p[0] = z.p[1] = nullptr;
+    z.nrm[0] = z.nrm[1] = nullptr;
+    z.stride = 0;
+    return z;
+  }
+  return f->template par<S>(p);
+}
+
+template <typename S>
+struct LinkSrc;
+template <> struct LinkSrc<double2> {
+  static const double2* get(tp_gauge g, bool l4) { return l4 ? g->u4_d : g->u3_d; }
+};
+template <> struct LinkSrc<float2> {
+  static const float2* get(tp_gauge g, bool l4) { return l4 ? g->u4_f : g->u3_f; }
+};
+template <> struct LinkSrc<__half2> {
+  static const float2* get(tp_gauge g, bool l4) { return l4 ? g->u4_f : g->u3_f; }
+};
+
+template <typename S>
+void fill_links(tp_gauge g, bool l4, LinkF<typename Prec<S>::L> (&u)[2][4], int64_t V2) {
+  const typename Prec<S>::L* base = LinkSrc<S>::get(g, l4);
+  for (int p = 0; p < 2; ++p)
+    for (int d = 0; d < 4; ++d) {
+      u[p][d].p = base + (int64_t)(d * 2 + p) * 9 * V2;
+      u[p][d].stride = V2;
+    }
+}
+
+template <typename S>
+const typename Prec<S>::L* clover_base(tp_op op, int kind, bool l4);
+template <> const double2* clover_base<double2>(tp_op op, int kind, bool l4) {
+  if (kind == 1) return op->c ? (l4 ? op->c->a4_d : op->c->a3_d) : nullptr;
+  if (kind == 2) return l4 ? op->a4_mu : op->a3_mu;
+  if (kind == 3) return l4 ? op->a4_inv : op->a3_inv;
+  return nullptr;
+}
+template <> const float2* clover_base<float2>(tp_op op, int kind, bool l4) {
+  if (kind == 1) return op->c ? (l4 ? op->c->a4_f : op->c->a3_f) : nullptr;
+  if (kind == 2) return l4 ? op->a4_mu_f : op->a3_mu_f;
+  if (kind == 3) return l4 ? op->a4_inv_f : op->a3_inv_f;
+  return nullptr;
+}
+template <> const float2* clover_base<__half2>(tp_op op, int kind, bool l4) {
+  return clover_base<float2>(op, kind, l4);
+}
+
+template <typename S, bool DT, bool DS, bool CLOV, bool IN2, bool NORM>
+void site_go(tp_op op, SiteArgsP3<S>& a, int64_t nblocks) {
+  tp_ctx ctx = op->g->ctx;
+  hipLaunchKernelGGL((k_site_p3<S, DT, DS, CLOV, IN2, NORM>), dim3((unsigned)nblocks), dim3(kBlock), 0,
+                     ctx->stream, a);
+  LAUNCH_CHECK();
+}
+
+template <typename S, bool DT, bool DS, bool CLOV>
+void site_in2(tp_op op, SiteArgsP3<S>& a, int64_t nb, bool in2, bool norm) {
+  if (in2) {
+    if (norm) site_go<S, DT, DS, CLOV, true, true>(op, a, nb);
+    else site_go<S, DT, DS, CLOV, true, false>(op, a, nb);
+  } else {
+    if (norm) site_go<S, DT, DS, CLOV, false, true>(op, a, nb);
+    else site_go<S, DT, DS, CLOV, false, false>(op, a, nb);
+  }
+}
+
+template <typename S>
+int site_t(tp_op op, const Field& src, Field& dst, const Field* in2, SiteCoef cf, int ck, int par0,
+           int npar, bool norm) {
+  tp_ctx ctx = op->g->ctx;
+  const Lattice& L = ctx->lat;
+  SiteArgsP3<S> a;
+  for (int p = 0; p < 2; ++p) {
+    a.src[p] = view<S>(&src, p);
+    a.dst[p] = view<S>(&dst, p);
+    a.in2[p] = view<S>(in2, p);
+  }
+  fill_links<S>(op->g, false, a.u, L.V2);
+  const typename Prec<S>::L* cb = clover_base<S>(op, ck, false);
+  bool clov = cb != nullptr && cf.c_A != 0.0;
+  for (int p = 0; p < 2; ++p) a.clov[p] = cb ? cb + (int64_t)p * 36 * L.V2 : nullptr;
+  a.c_mu = cf.c_mu;
+  a.c_A = cf.c_A;
+  a.c_t = cf.c_t;
+  a.c_s = cf.c_s;
+  a.c_in = cf.c_in;
+  a.g = L.g;
+  a.par0 = par0;
+  a.n = (int64_t)npar * L.V2;
+  a.partial = ctx->red_partial;
+  int64_t nb = (a.n + kBlock - 1) / kBlock;
+  if (norm) nb = nb < kRedBlocks ? nb : kRedBlocks;
+  bool dt = cf.c_t != 0.0, ds = cf.c_s != 0.0;
+  bool i2 = in2 != nullptr;
+  if (dt && ds) {
+    if (clov) site_in2<S, true, true, true>(op, a, nb, i2, norm);
+    else site_in2<S, true, true, false>(op, a, nb, i2, norm);
+  } else if (ds) {
+    if (clov) site_in2<S, false, true, true>(op, a, nb, i2, norm);
+    else site_in2<S, false, true, false>(op, a, nb, i2, norm);
+  } else if (dt) {
+    if (clov) site_in2<S, true, false, true>(op, a, nb, i2, norm);
+    else site_in2<S, true, false, false>(op, a, nb, i2, norm);
+  } else {
+    if (clov) site_in2<S, false, false, true>(op, a, nb, i2, norm);
+    else site_in2<S, false, false, false>(op, a, nb, i2, norm);
+  }
+  return norm ? int(nb) : 0;
+}
+
+template <typename S, bool HOP, bool IN2, int CL>
+void s4_go(tp_ctx ctx, ArgsP4<S>& a) {
+  unsigned nb = (unsigned)((a.g.V2 + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL((k_schur4d<S, HOP, IN2, CL>), dim3(nb), dim3(kBlock), 0, ctx->stream, a);
+  LAUNCH_CHECK();
+}
+
+template <typename S>
+void schur4d_t(tp_op op, int mode, int p, const Field* src, Field& dst, const Field* in2, double c_h,
+               double c_in, int ck) {
+  tp_ctx ctx = op->g->ctx;
+  const Lattice& L = ctx->lat;
+  ArgsP4<S> a;
+  a.src = view<S>(src, 1 - p);
+  a.dst = view<S>(&dst, p);
+  a.in2 = view<S>(in2, p);
+  fill_links<S>(op->g, true, a.u, L.V2);
+  const typename Prec<S>::L* cb = clover_base<S>(op, ck, true);
+  a.clov = cb ? cb + (int64_t)p * 36 * L.V2 : nullptr;
+  a.c_h = c_h;
+  a.c_in = c_in;
+  a.inv_gf = 1.0 / op->gf;
+  a.g = L.g;
+  a.p = p;
+  switch (mode) {
+    case 0: s4_go<S, true, false, 1>(ctx, a); break;
+    case 1: s4_go<S, true, true, 2>(ctx, a); break;
+    case 2: s4_go<S, true, true, 0>(ctx, a); break;
+    case 3: s4_go<S, true, true, 1>(ctx, a); break;
+    default: s4_go<S, false, true, 2>(ctx, a); break;
+  }
+}
+
+}  // namespace
+
+int launch_site_p3(tp_op op, int prec, const Field& src, Field& dst, const Field* in2, SiteCoef cf,
+                   int ck, int par0, int npar, bool norm) {
+  tp_ctx ctx = op->g->ctx;
+  const Lattice& L = ctx->lat;
+  double S = double(src.elem_bytes()) * 12;
+  double Lb = prec == TP_F64 ? 144 : 72;
+  double bytes = double(npar) * L.V2 * (2 * S + (cf.c_s != 0 ? S + 6 * Lb : 0) +
+                                        (cf.c_t != 0 ? 2 * Lb : 0) + (ck ? 4 * Lb : 0) + (in2 ? S : 0));
+  ProfScope ps(ctx, KID_SITE_P3, bytes);
+  switch (prec) {
+    case TP_F64: return site_t<double2>(op, src, dst, in2, cf, ck, par0, npar, norm);
+    case TP_F32: return site_t<float2>(op, src, dst, in2, cf, ck, par0, npar, norm);
+    default: return site_t<__half2>(op, src, dst, in2, cf, ck, par0, npar, norm);
+  }
+}
+
+void launch_schur4d(tp_op op, int prec, int mode, int p, const Field* src, Field& dst, const Field* in2,
+                    double c_h, double c_in, int ck) {
+  tp_ctx ctx = op->g->ctx;
+  const Lattice& L = ctx->lat;
+  double S = double(dst.elem_bytes()) * 12;
+  double Lb = prec == TP_F64 ? 144 : 72;
+  double C = prec == TP_F64 ? 576 : 288;
+  double bytes = double(L.V2) * (S + (mode != 4 ? S + 8 * Lb : 0) + (in2 ? S : 0) + (ck ? C : 0));
+  ProfScope ps(ctx, mode == 0 ? KID_SCHUR4D_EO : KID_SCHUR4D_OE, bytes);
+  switch (prec) {
+    case TP_F64: schur4d_t<double2>(op, mode, p, src, dst, in2, c_h, c_in, ck); break;
+    default: schur4d_t<float2>(op, mode, p, src, dst, in2, c_h, c_in, ck); break;
+  }
+}
+
+void launch_force(tp_op op, const Field& x, const Field& lam, double2* grad, bool projected) {
+  tp_ctx ctx = op->g->ctx;
+  const Lattice& L = ctx->lat;
+  ProfScope ps(ctx, KID_FORCE, double(L.V) * 4 * (4 * 192 + 144 + 144));
+  hipLaunchKernelGGL(k_force, dim3((unsigned)((L.V + 127) / 128), 4), dim3(128), 0, ctx->stream,
+                     x.par<double2>(0), x.par<double2>(1), lam.par<double2>(0), lam.par<double2>(1),
+                     op->g->canon, grad, L.g, L.V, 1.0 / op->gf, double(ctx->bc), projected ? 1 : 0);
+  LAUNCH_CHECK();
+}

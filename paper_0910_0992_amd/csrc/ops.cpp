@@ -1,0 +1,591 @@
+// Composite operators and the Krylov solvers, on internal fields.
+//
+// Schemes (Sec. II.A-B):
+//   UNPREC          M
+//   SCHUR4D         p4 parity: Mt = diag(A+mu, S-hat), S-hat = (A+mu) - D_w^oe (A+mu)^-1 D_w^eo
+//   TEMPORAL        Mt = C_L M C_R = 1 + C_L (A - D_s/gamma_f) C_R   (eq:ContaminatedUnprec)
+//   TEMPORAL_SCHUR  p3 parity: Mt3 = S_L M S_R.  Wilson: diag(1, 1 - Dbar^oe Dbar^eo/gamma_f^2)
+//                   (eq:TPrecFull); clover: eq:TPrecPartial (3D ILU), applied as
+//                     a_o  = C_R^o psi_o                                  (K1)
+//                     u    = D_s^eo a_o / gamma_f                          (K2a)
+//                     y    = A^ee C_R^e (C_L^e u + psi_e)                  (K2a)
+//                     chi_e = psi_e + C_L^e y                              (K2b)
+//                     n_e  = C_R^e C_L^e (y - u)                           (K2b)
+//                     chi_o = psi_o + C_L^o [A^oo a_o + D_s^oe n_e / gamma_f]  (K3)
+//                   which is the appendix's ILU sequence with t1 = C_L u, t2 = C_L y,
+//                   C_R(t2 - t1) = C_R C_L (y - u) and the Dbar/Abar products expanded.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <algorithm>
+#include <chrono>
+#include <map>
+
+#include "tp_internal.h"
+
+struct Workspace {
+  std::map<std::pair<int, int>, Field> f;
+};
+
+Field& ws_get(tp_op op, int prec, int slot) {
+  if (!op->ws) op->ws = new Workspace();
+  auto key = std::make_pair(prec, slot);
+  auto it = op->ws->f.find(key);
+  if (it != op->ws->f.end()) return it->second;
+  Field nf = field_alloc(op->g->ctx->lat, prec);
+  return op->ws->f.emplace(key, nf).first->second;
+}
+
+void ws_free(tp_op op) {
+  if (!op->ws) return;
+  for (auto& kv : op->ws->f) field_free(kv.second);
+  delete op->ws;
+  op->ws = nullptr;
+}
+
+bool scheme_layout4(int scheme) { return scheme == TP_SCHUR4D; }
+
+namespace {
+
+// workspace slot numbers
+enum {
+  W_T1 = 0, W_T2, W_T3, W_T4, W_G5A, W_G5B, W_PREP,
+  // solver vectors
+  W_R = 16, W_RHAT, W_P, W_V, W_S, W_T, W_X, W_B, W_Y, W_Z, W_D,
+  W_X64 = 40, W_R64, W_ETA64, W_TMP64
+};
+
+BlasArgs cplx(double ar, double ai, double br = 0, double bi = 0, double cr = 0, double ci = 0) {
+  BlasArgs k;
+  k.a[0] = ar; k.a[1] = ai; k.b[0] = br; k.b[1] = bi; k.c[0] = cr; k.c[1] = ci;
+  return k;
+}
+
+// S-hat on the odd p4 parity: dst_o = (A+mu) src_o - D^oe (A+mu)^-1 D^eo src_o
+void schur4d_odd(tp_op op, int prec, const Field& src, Field& dst) {
+  Field& t = ws_get(op, prec, W_T1);
+  launch_schur4d(op, prec, 0, 0, &src, t, nullptr, 1.0, 0.0, 3);
+  launch_schur4d(op, prec, 1, 1, &t, dst, &src, -1.0, 0.0, 2);
+}
+
+// Wilson S_o on the odd p3 parity: dst_o = src_o - C_L D_s (C_R C_L) D_s C_R src_o / gamma_f^2
+void wilson_so_odd(tp_op op, int prec, const Field& src, Field& dst) {
+  Field& aup = ws_get(op, prec, W_T1);
+  Field& m = ws_get(op, prec, W_T2);
+  launch_ilu_k1(op, prec, src, aup);
+  LineStencilArgs s2{};
+  s2.nb_up = &aup;
+  s2.nb_lo = &src;
+  s2.c_s = 1.0;
+  s2.c_out = 1.0;
+  launch_line_stencil(op, prec, LM_CRCL, 0, s2, m);
+  LineStencilArgs s3{};
+  s3.nb_up = &m;
+  s3.nb_lo = &m;
+  s3.base = &src;
+  s3.c_s = -1.0 / (op->gf * op->gf);
+  s3.c_out = 1.0;
+  s3.c_base = 1.0;
+  launch_line_stencil(op, prec, LM_CL, 1, s3, dst);
+}
+
+void ilu_full(tp_op op, int prec, const Field& src, Field& dst) {
+  Field& aup = ws_get(op, prec, W_T1);
+  Field& y = ws_get(op, prec, W_T2);
+  Field& u = ws_get(op, prec, W_T3);
+  Field& n = ws_get(op, prec, W_T4);
+  launch_ilu_k1(op, prec, src, aup);
+  launch_ilu_k2a(op, prec, src, aup, y, u);
+  launch_ilu_k2b(op, prec, src, y, u, dst, n);
+  launch_ilu_k3(op, prec, src, aup, n, dst);
+}
+
+void temporal_full(tp_op op, int prec, const Field& src, Field& dst) {
+  Field& a = ws_get(op, prec, W_T1);
+  launch_line_plain(op, prec, LM_CR, 0, src, a);
+  launch_line_plain(op, prec, LM_CR, 1, src, a);
+  for (int p = 0; p < 2; ++p) {
+    LineStencilArgs s{};
+    s.nb_up = &a;
+    s.nb_lo = &a;
+    s.self = &a;
+    s.base = &src;
+    s.c_s = -1.0 / op->gf;
+    s.c_A = 1.0;
+    s.c_out = 1.0;
+    s.c_base = 1.0;
+    launch_line_stencil(op, prec, LM_CL, p, s, dst);
+  }
+}
+
+void apply_M_noalias(tp_op op, int prec, const Field& src, Field& dst) {
+  SiteCoef cf{op->mu, 1.0, -1.0, -1.0 / op->gf, 0.0};
+  launch_site_p3(op, prec, src, dst, nullptr, cf, op->c ? 1 : 0, 0, 2, false);
+}
+
+void apply_M_p4(tp_op op, int prec, const Field& src, Field& dst) {
+  // M psi on parity p = (A+mu) psi_p - D_w psi_(1-p)
+  launch_schur4d(op, prec, 1, 0, &src, dst, &src, -1.0, 0.0, 2);
+  launch_schur4d(op, prec, 1, 1, &src, dst, &src, -1.0, 0.0, 2);
+}
+
+void prec_noalias(tp_op op, int scheme, int prec, const Field& src, Field& dst) {
+  switch (scheme) {
+    case TP_UNPREC:
+      apply_M_noalias(op, prec, src, dst);
+      break;
+    case TP_SCHUR4D:
+      schur4d_odd(op, prec, src, dst);
+      launch_schur4d(op, prec, 4, 0, nullptr, dst, &src, 0.0, 0.0, 2);  // (A+mu) psi_e
+      break;
+    case TP_TEMPORAL:
+      temporal_full(op, prec, src, dst);
+      break;
+    case TP_TEMPORAL_SCHUR:
+      if (op->c) {
+        ilu_full(op, prec, src, dst);
+      } else {
+        wilson_so_odd(op, prec, src, dst);
+        blas(op->g->ctx, B_COPY, 0, 1, {&src, &dst});
+      }
+      break;
+    default:
+      TP_THROW(TP_EINVAL, "unknown scheme");
+  }
+}
+
+// The operator the Krylov solver iterates on: the whole of Mt, or its odd block
+// when the even block is trivial (SCHUR4D; Wilson TEMPORAL_SCHUR).
+struct KrylovOp {
+  tp_op op;
+  int scheme, prec;
+  int par0, npar;
+  void apply(const Field& src, Field& dst, bool dagger) const {
+    tp_ctx ctx = op->g->ctx;
+    const Field* in = &src;
+    Field* out = &dst;
+    Field* ga = nullptr;
+    if (dagger) {
+      ga = &ws_get(op, prec, W_G5A);
+      blas(ctx, B_G5, par0, npar, {&src, ga});
+      in = ga;
+      out = &ws_get(op, prec, W_G5B);
+    }
+    if (npar == 1) {
+      if (scheme == TP_SCHUR4D) schur4d_odd(op, prec, *in, *out);
+      else wilson_so_odd(op, prec, *in, *out);
+    } else {
+      prec_noalias(op, scheme, prec, *in, *out);
+    }
+    if (dagger) blas(ctx, B_G5, par0, npar, {out, &dst});
+  }
+};
+
+}  // namespace
+
+void op_apply_M(tp_op op, int prec, const Field& src, Field& dst, bool dagger) {
+  tp_ctx ctx = op->g->ctx;
+  if (!dagger) {
+    apply_M_noalias(op, prec, src, dst);
+    return;
+  }
+  Field& a = ws_get(op, prec, W_G5A);
+  Field& b = ws_get(op, prec, W_G5B);
+  blas(ctx, B_G5, 0, 2, {&src, &a});
+  apply_M_noalias(op, prec, a, b);
+  blas(ctx, B_G5, 0, 2, {&b, &dst});
+}
+
+void op_apply_prec(tp_op op, int scheme, int prec, const Field& src, Field& dst, bool dagger) {
+  tp_ctx ctx = op->g->ctx;
+  if (!dagger) {
+    prec_noalias(op, scheme, prec, src, dst);
+    return;
+  }
+  Field& a = ws_get(op, prec, W_G5A);
+  Field& b = ws_get(op, prec, W_G5B);
+  blas(ctx, B_G5, 0, 2, {&src, &a});
+  prec_noalias(op, scheme, prec, a, b);
+  blas(ctx, B_G5, 0, 2, {&b, &dst});
+}
+
+void op_prepare(tp_op op, int scheme, int prec, const Field& eta, Field& et) {
+  tp_ctx ctx = op->g->ctx;
+  switch (scheme) {
+    case TP_UNPREC:
+      blas(ctx, B_COPY, 0, 2, {&eta, &et});
+      break;
+    case TP_SCHUR4D: {
+      // eta~_o = eta_o + D_w^oe (A+mu)^-1 eta_e ;  eta~_e = eta_e
+      Field& t = ws_get(op, prec, W_PREP);
+      launch_schur4d(op, prec, 4, 0, nullptr, t, &eta, 0.0, 0.0, 3);
+      launch_schur4d(op, prec, 2, 1, &t, et, &eta, 1.0, 1.0, 0);
+      blas(ctx, B_COPY, 0, 1, {&eta, &et});
+      break;
+    }
+    case TP_TEMPORAL:
+      launch_line_plain(op, prec, LM_CL, 0, eta, et);
+      launch_line_plain(op, prec, LM_CL, 1, eta, et);
+      break;
+    case TP_TEMPORAL_SCHUR: {
+      // eta~_e = C_L^e eta_e ; eta~_o = C_L^o [eta_o + D_s^oe C_R^e C_L^e eta_e / gamma_f]
+      Field& t = ws_get(op, prec, W_PREP);
+      launch_line_plain(op, prec, LM_CL, 0, eta, et);
+      launch_line_plain(op, prec, LM_CRCL, 0, eta, t);
+      LineStencilArgs s{};
+      s.nb_up = &t;
+      s.nb_lo = &t;
+      s.self = &eta;
+      s.c_s = 1.0 / op->gf;
+      s.c_self = 1.0;
+      s.c_out = 1.0;
+      launch_line_stencil(op, prec, LM_CL, 1, s, et);
+      break;
+    }
+    default:
+      TP_THROW(TP_EINVAL, "unknown scheme");
+  }
+}
+
+void op_reconstruct(tp_op op, int scheme, int prec, const Field& y, Field& x) {
+  tp_ctx ctx = op->g->ctx;
+  switch (scheme) {
+    case TP_UNPREC:
+      blas(ctx, B_COPY, 0, 2, {&y, &x});
+      break;
+    case TP_SCHUR4D: {
+      // x_o = y_o ; x_e = y_e + (A+mu)^-1 D_w^eo y_o
+      Field& t = ws_get(op, prec, W_PREP);
+      launch_schur4d(op, prec, 0, 0, &y, t, nullptr, 1.0, 0.0, 3);
+      blas(ctx, B_COPY, 0, 2, {&y, &x});
+      blas(ctx, B_AXPY, 0, 1, {&t, &x}, cplx(1, 0));
+      break;
+    }
+    case TP_TEMPORAL:
+      launch_line_plain(op, prec, LM_CR, 0, y, x);
+      launch_line_plain(op, prec, LM_CR, 1, y, x);
+      break;
+    case TP_TEMPORAL_SCHUR: {
+      // x_o = C_R^o y_o ; x_e = C_R^e [y_e + C_L^e D_s^eo x_o / gamma_f]
+      Field& t = ws_get(op, prec, W_PREP);
+      launch_line_plain(op, prec, LM_CR, 1, y, x);
+      LineStencilArgs s{};
+      s.nb_up = &x;
+      s.nb_lo = &x;
+      s.base = &y;
+      s.c_s = 1.0 / op->gf;
+      s.c_out = 1.0;
+      s.c_base = 1.0;
+      launch_line_stencil(op, prec, LM_CL, 0, s, t);
+      launch_line_plain(op, prec, LM_CR, 0, t, x);
+      break;
+    }
+    default:
+      TP_THROW(TP_EINVAL, "unknown scheme");
+  }
+}
+
+// ---------------------------------------------------------------- Krylov solvers
+namespace {
+
+struct KrylovResult {
+  int iters = 0, applies = 0, restarts = 0;
+  double rel = 0;
+  bool converged = false, breakdown = false, stalled = false;
+  std::vector<double> alphas, betas;
+};
+
+double nrm2(tp_ctx ctx, const KrylovOp& A, const Field& x) {
+  double r[4];
+  blas(ctx, B_NORM2, A.par0, A.npar, {&x}, BlasArgs{}, r);
+  return r[0];
+}
+
+// van der Vorst's BiCGStab on A y = b from y = 0; stops on |r| <= eps |b| (recursive).
+KrylovResult bicgstab(const KrylovOp& A, const Field& b, Field& y, double eps, int maxit) {
+  tp_ctx ctx = A.op->g->ctx;
+  int pr = A.prec, p0 = A.par0, np = A.npar;
+  Field& r = ws_get(A.op, pr, W_R);
+  Field& rh = ws_get(A.op, pr, W_RHAT);
+  Field& p = ws_get(A.op, pr, W_P);
+  Field& v = ws_get(A.op, pr, W_V);
+  Field& s = ws_get(A.op, pr, W_S);
+  Field& t = ws_get(A.op, pr, W_T);
+  KrylovResult res;
+  double red[4];
+  blas(ctx, B_ZERO, p0, np, {nullptr, &y});
+  blas(ctx, B_COPY, p0, np, {&b, &r});
+  blas(ctx, B_COPY, p0, np, {&b, &rh});
+  blas(ctx, B_COPY, p0, np, {&b, &p});
+  blas(ctx, B_DOT_NORM, p0, np, {&rh, &r}, BlasArgs{}, red);
+  double bn2 = red[2];
+  if (bn2 == 0.0) {
+    res.converged = true;
+    return res;
+  }
+  double rho_r = red[0], rho_i = red[1];
+  double r2 = bn2;
+  const double tgt2 = eps * eps * bn2;
+  double best2 = bn2;
+  int best_it = 0;
+  while (res.iters < maxit) {
+    // guard: stop on divergence, or when no new minimum appeared for a long stretch
+    if (r2 > 1e8 * best2 || res.iters - best_it > std::max(500, 2 * best_it)) {
+      res.stalled = true;
+      break;
+    }
+    A.apply(p, v, false);
+    res.applies++;
+    blas(ctx, B_DOT, p0, np, {&rh, &v}, BlasArgs{}, red);
+    double den = red[0] * red[0] + red[1] * red[1];
+    if (den == 0.0 || !isfinite(den)) { res.breakdown = true; break; }
+    // alpha = rho / <rhat, v>
+    double al_r = (rho_r * red[0] + rho_i * red[1]) / den;
+    double al_i = (rho_i * red[0] - rho_r * red[1]) / den;
+    blas(ctx, B_COPY, p0, np, {&r, &s});
+    blas(ctx, B_CAXPY_NORM, p0, np, {&v, &s}, cplx(-al_r, -al_i), red);
+    double s2 = red[0];
+    res.iters++;
+    if (s2 <= tgt2) {
+      blas(ctx, B_AXPY, p0, np, {&p, &y}, cplx(al_r, al_i));
+      r2 = s2;
+      res.converged = true;
+      break;
+    }
+    A.apply(s, t, false);
+    res.applies++;
+    blas(ctx, B_DOT2_TS, p0, np, {&t, &s}, BlasArgs{}, red);
+    if (red[2] == 0.0 || !isfinite(red[2])) { res.breakdown = true; break; }
+    double om_r = red[0] / red[2], om_i = red[1] / red[2];
+    blas(ctx, B_BICG_UPDATE, p0, np, {&y, &p, &s, &t, &r, &rh}, cplx(al_r, al_i, om_r, om_i), red);
+    double rn_r = red[0], rn_i = red[1];
+    r2 = red[2];
+    if (!isfinite(r2)) { res.breakdown = true; break; }
+    if (r2 < best2) { best2 = r2; best_it = res.iters; }
+    if (r2 <= tgt2) { res.converged = true; break; }
+    // beta = (rho_new / rho) (alpha / omega)
+    double rr = rho_r * rho_r + rho_i * rho_i;
+    double q_r = (rn_r * rho_r + rn_i * rho_i) / rr, q_i = (rn_i * rho_r - rn_r * rho_i) / rr;
+    double oo = om_r * om_r + om_i * om_i;
+    if (oo == 0.0 || rr == 0.0) { res.breakdown = true; break; }
+    double w_r = (al_r * om_r + al_i * om_i) / oo, w_i = (al_i * om_r - al_r * om_i) / oo;
+    double be_r = q_r * w_r - q_i * w_i, be_i = q_r * w_i + q_i * w_r;
+    // p = r + beta (p - omega v) = r - beta omega v + beta p
+    double bo_r = be_r * om_r - be_i * om_i, bo_i = be_r * om_i + be_i * om_r;
+    blas(ctx, B_AXPBYPCZ, p0, np, {&r, &v, &p}, cplx(1, 0, -bo_r, -bo_i, be_r, be_i));
+    rho_r = rn_r;
+    rho_i = rn_i;
+    if (rho_r * rho_r + rho_i * rho_i < 1e-60 * bn2 * bn2) {
+      // rho breakdown: restart the shadow residual
+      blas(ctx, B_COPY, p0, np, {&r, &rh});
+      blas(ctx, B_COPY, p0, np, {&r, &p});
+      rho_r = r2;
+      rho_i = 0;
+      res.restarts++;
+    }
+  }
+  res.rel = sqrt(r2 / bn2);
+  return res;
+}
+
+// CG on A^dag A y = A^dag b from y = 0; stops on |b - A y| <= eps |b|.
+KrylovResult cgnr(const KrylovOp& A, const Field& b, Field& y, double eps, int maxit) {
+  tp_ctx ctx = A.op->g->ctx;
+  int pr = A.prec, p0 = A.par0, np = A.npar;
+  Field& r = ws_get(A.op, pr, W_R);
+  Field& z = ws_get(A.op, pr, W_Z);
+  Field& p = ws_get(A.op, pr, W_P);
+  Field& w = ws_get(A.op, pr, W_V);
+  KrylovResult res;
+  double red[4];
+  blas(ctx, B_ZERO, p0, np, {nullptr, &y});
+  blas(ctx, B_COPY, p0, np, {&b, &r});
+  double bn2 = nrm2(ctx, A, b);
+  if (bn2 == 0.0) {
+    res.converged = true;
+    return res;
+  }
+  A.apply(r, z, true);
+  res.applies++;
+  blas(ctx, B_COPY, p0, np, {&z, &p});
+  double zz = nrm2(ctx, A, z);
+  double r2 = bn2;
+  const double tgt2 = eps * eps * bn2;
+  while (res.iters < maxit) {
+    A.apply(p, w, false);
+    double ww = nrm2(ctx, A, w);
+    if (ww == 0.0 || !isfinite(ww)) { res.breakdown = true; break; }
+    double alpha = zz / ww;
+    blas(ctx, B_AXPY, p0, np, {&p, &y}, cplx(alpha, 0));
+    blas(ctx, B_CAXPY_NORM, p0, np, {&w, &r}, cplx(-alpha, 0), red);
+    r2 = red[0];
+    A.apply(r, z, true);
+    res.applies += 2;
+    double zz_new = nrm2(ctx, A, z);
+    double beta = zz_new / zz;
+    res.alphas.push_back(alpha);
+    res.betas.push_back(beta);
+    res.iters++;
+    if (r2 <= tgt2) { res.converged = true; break; }
+    blas(ctx, B_XPAY, p0, np, {&z, &p}, cplx(beta, 0));
+    zz = zz_new;
+  }
+  res.rel = sqrt(r2 / bn2);
+  return res;
+}
+
+// Extreme eigenvalues of the symmetric tridiagonal matrix (d, e) by Sturm bisection.
+double sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x) {
+  int cnt = 0;
+  double q = 1.0;
+  for (size_t k = 0; k < d.size(); ++k) {
+    double off = k ? e[k - 1] * e[k - 1] : 0.0;
+    q = d[k] - x - (k ? off / (q == 0.0 ? 1e-300 : q) : 0.0);
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+double tri_eig(const std::vector<double>& d, const std::vector<double>& e, int which) {
+  double lo = 1e300, hi = -1e300;
+  for (size_t k = 0; k < d.size(); ++k) {
+    double rad = (k ? fabs(e[k - 1]) : 0) + (k + 1 < d.size() ? fabs(e[k]) : 0);
+    lo = std::min(lo, d[k] - rad);
+    hi = std::max(hi, d[k] + rad);
+  }
+  // which = 0: smallest (count >= 1), 1: largest (count >= n)
+  double target = which == 0 ? 1 : double(d.size());
+  for (int it = 0; it < 200; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (sturm_count(d, e, mid) >= target) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+void lanczos_kappa(const KrylovResult& kr, double& lmin, double& lmax) {
+  size_t n = kr.alphas.size();
+  lmin = lmax = 0;
+  if (n == 0) return;
+  std::vector<double> d(n), e(n > 1 ? n - 1 : 0);
+  for (size_t k = 0; k < n; ++k) {
+    d[k] = 1.0 / kr.alphas[k] + (k ? kr.betas[k - 1] / kr.alphas[k - 1] : 0.0);
+    if (k + 1 < n) e[k] = sqrt(kr.betas[k]) / kr.alphas[k];
+  }
+  lmin = tri_eig(d, e, 0);
+  lmax = tri_eig(d, e, 1);
+}
+
+// r = eta - M x in FP64, returns |r|^2
+double true_residual(tp_op op, bool l4, const Field& x, const Field& eta, Field& r) {
+  tp_ctx ctx = op->g->ctx;
+  if (!l4) {
+    SiteCoef cf{-op->mu, -1.0, 1.0, 1.0 / op->gf, 1.0};
+    int nb = launch_site_p3(op, TP_F64, x, r, &eta, cf, op->c ? 1 : 0, 0, 2, true);
+    return finish_norm(ctx, nb);
+  }
+  apply_M_p4(op, TP_F64, x, r);
+  blas(ctx, B_XPAY, 0, 2, {&eta, &r}, cplx(-1, 0));
+  double red[4];
+  blas(ctx, B_NORM2, 0, 2, {&r}, BlasArgs{}, red);
+  return red[0];
+}
+
+}  // namespace
+
+tp_status op_solve(tp_op op, const tp_solve_params& P, Field& x64, const Field& eta64,
+                   tp_solve_info& info) {
+  tp_ctx ctx = op->g->ctx;
+  auto t0 = std::chrono::steady_clock::now();
+  bool l4 = scheme_layout4(P.scheme);
+  int pr = P.prec;
+  Field& r64 = ws_get(op, TP_F64, W_R64);
+  double red[4];
+  blas(ctx, B_NORM2, 0, 2, {&eta64}, BlasArgs{}, red);
+  double eta2 = red[0];
+  if (!isfinite(eta2)) TP_THROW(TP_EINVAL, "source contains NaN or Inf");
+  if (!P.use_x0) blas(ctx, B_ZERO, 0, 2, {nullptr, &x64});
+  info = tp_solve_info{};
+  if (eta2 == 0.0) {
+    blas(ctx, B_ZERO, 0, 2, {nullptr, &x64});
+    info.true_rel_resid = 0;
+    return TP_OK;
+  }
+  double r2 = true_residual(op, l4, x64, eta64, r64);
+  double tol = P.tol > 0 ? P.tol : 1e-10;
+  double inner_default = pr == TP_F64 ? 0.0 : (pr == TP_F32 ? 1e-6 : 2e-3);
+  double inner = P.inner_tol > 0 ? P.inner_tol : inner_default;
+  int max_iter = P.max_iter > 0 ? P.max_iter : 100000;
+  int max_restarts = P.max_restarts > 0 ? P.max_restarts : 50;
+  KrylovOp A{op, P.scheme, pr, 0, 2};
+  bool sub = (P.scheme == TP_SCHUR4D) || (P.scheme == TP_TEMPORAL_SCHUR && !op->c);
+  if (sub) {
+    A.par0 = 1;
+    A.npar = 1;
+  }
+  Field& rin = ws_get(op, pr, W_B);
+  Field& et = ws_get(op, pr, W_D);
+  Field& y = ws_get(op, pr, W_Y);
+  Field& d = ws_get(op, pr, W_X);
+  Field& xsave = ws_get(op, TP_F64, W_TMP64);
+  tp_status st = TP_OK;
+  int solver = P.solver;
+  int failures = 0;  // cycles rolled back
+  while (sqrt(r2 / eta2) > tol) {
+    if (info.outer_iters >= max_restarts || info.iters >= max_iter) { st = TP_ENOCONV; break; }
+    // inner source in the inner precision
+    const Field* rsrc = &r64;
+    if (pr != TP_F64) {
+      blas(ctx, B_CONVERT, 0, 2, {&r64, &rin});
+      rsrc = &rin;
+    }
+    op_prepare(op, P.scheme, pr, *rsrc, et);
+    // relative target for this cycle
+    double need = 0.5 * tol * sqrt(eta2 / r2);
+    double eps = std::max(inner, need);
+    if (pr == TP_F64) eps = need;
+    eps = std::min(eps, 0.5);
+    KrylovResult kr = solver == TP_CGNR ? cgnr(A, et, y, eps, max_iter - info.iters)
+                                        : bicgstab(A, et, y, eps, max_iter - info.iters);
+    info.iters += kr.iters;
+    info.applies += kr.applies;
+    info.restarts += kr.restarts;
+    info.prec_rel_resid = kr.rel;
+    if (P.estimate_kappa && P.solver == TP_CGNR && info.outer_iters == 0) {
+      lanczos_kappa(kr, info.lambda_min, info.lambda_max);
+      info.kappa_est = info.lambda_min > 0 ? info.lambda_max / info.lambda_min : 0;
+    }
+    // fill the trivially solved even block
+    if (sub) {
+      if (P.scheme == TP_SCHUR4D) launch_schur4d(op, pr, 4, 0, nullptr, y, &et, 0.0, 0.0, 3);
+      else blas(ctx, B_COPY, 0, 1, {&et, &y});
+    }
+    op_reconstruct(op, P.scheme, pr, y, d);
+    blas(ctx, B_COPY, 0, 2, {&x64, &xsave});
+    blas(ctx, B_MIXED_ACC, 0, 2, {&d, &x64});
+    double r2_prev = r2;
+    r2 = true_residual(op, l4, x64, eta64, r64);
+    info.outer_iters++;
+    if (getenv("TPREC_VERBOSE"))
+      fprintf(stderr, "[tprec] cycle %d: inner %d iters rel %.3e (eps %.1e)%s%s, true %.3e\n",
+              info.outer_iters, kr.iters, kr.rel, eps, kr.converged ? "" : " not-converged",
+              kr.breakdown ? " breakdown" : "", sqrt(r2 / eta2));
+    if (!(r2 < r2_prev)) {
+      // the cycle did not help (inner divergence or breakdown in the low precision):
+      // undo it and continue with CGNR, whose residual cannot grow
+      blas(ctx, B_COPY, 0, 2, {&xsave, &x64});
+      r2 = true_residual(op, l4, x64, eta64, r64);
+      ++failures;
+      if (solver == TP_CGNR) {
+        st = kr.breakdown || kr.stalled ? TP_EBREAKDOWN : TP_ENOCONV;
+        break;
+      }
+      solver = TP_CGNR;
+    }
+  }
+  info.true_rel_resid = sqrt(r2 / eta2);
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  prof_flush(ctx);
+  info.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}

@@ -1,0 +1,270 @@
+// Device-side arithmetic and storage helpers for gfx950.
+//
+// Complex numbers, SU(3) matrix-vector products, Dirac-Pauli spin projection
+// and the storage formats of spinors, links and clover blocks.  All fields are
+// stored as structure-of-arrays "planes": plane c of a field holds component c
+// of every site contiguously, so the 64 lanes of a wavefront that handle 64
+// consecutive sites issue one fully coalesced load per component.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#define TP_DEV __device__ __forceinline__
+#define TP_HD __host__ __device__ __forceinline__
+
+template <typename R>
+struct cx {
+  R re, im;
+};
+
+template <typename R> TP_DEV cx<R> mk(R a, R b) { return cx<R>{a, b}; }
+template <typename R> TP_DEV cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R> TP_DEV cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R> TP_DEV cx<R> operator-(cx<R> a) { return {-a.re, -a.im}; }
+template <typename R> TP_DEV cx<R> operator*(R s, cx<R> a) { return {s * a.re, s * a.im}; }
+template <typename R> TP_DEV cx<R>& operator+=(cx<R>& a, cx<R> b) { a.re += b.re; a.im += b.im; return a; }
+template <typename R> TP_DEV cx<R>& operator-=(cx<R>& a, cx<R> b) { a.re -= b.re; a.im -= b.im; return a; }
+template <typename R> TP_DEV cx<R> cmul(cx<R> a, cx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// conj(a) * b
+template <typename R> TP_DEV cx<R> cmulc(cx<R> a, cx<R> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename R> TP_DEV cx<R> conj(cx<R> a) { return {a.re, -a.im}; }
+template <typename R> TP_DEV cx<R> ti(cx<R> a) { return {-a.im, a.re}; }   // i a
+template <typename R> TP_DEV cx<R> tmi(cx<R> a) { return {a.im, -a.re}; }  // -i a
+template <typename R> TP_DEV R norm2(cx<R> a) { return a.re * a.re + a.im * a.im; }
+template <typename R> TP_DEV cx<R> czero() { return {R(0), R(0)}; }
+
+// ---- SU(3) -------------------------------------------------------------------------
+template <typename R>
+struct su3 {
+  cx<R> e[9];  // row-major
+};
+
+// out = U v
+template <typename R> TP_DEV void mv(const su3<R>& u, const cx<R>* v, cx<R>* out) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cx<R> s = cmul(u.e[3 * a], v[0]);
+    s += cmul(u.e[3 * a + 1], v[1]);
+    s += cmul(u.e[3 * a + 2], v[2]);
+    out[a] = s;
+  }
+}
+// out = U^dagger v
+template <typename R> TP_DEV void mvd(const su3<R>& u, const cx<R>* v, cx<R>* out) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cx<R> s = cmulc(u.e[a], v[0]);
+    s += cmulc(u.e[3 + a], v[1]);
+    s += cmulc(u.e[6 + a], v[2]);
+    out[a] = s;
+  }
+}
+
+// ---- storage -----------------------------------------------------------------------
+// Spinor storage element types: double2 (FP64), float2 (FP32), __half2 (FP16 with
+// an FP32 scale per half-spinor and site).  Links and clover blocks use double2 or
+// float2.
+template <typename S> struct Prec;
+template <> struct Prec<double2> { using R = double; using L = double2; static constexpr bool half = false; };
+template <> struct Prec<float2> { using R = float; using L = float2; static constexpr bool half = false; };
+template <> struct Prec<__half2> { using R = float; using L = float2; static constexpr bool half = true; };
+
+template <typename R, typename S> TP_DEV cx<R> ld(const S* p) {
+  S v = *p;
+  return {R(v.x), R(v.y)};
+}
+template <> TP_DEV cx<float> ld<float, __half2>(const __half2* p) {
+  float2 f = __half22float2(*p);
+  return {f.x, f.y};
+}
+template <typename R> TP_DEV void st(double2* p, cx<R> v) { *p = make_double2(double(v.re), double(v.im)); }
+template <typename R> TP_DEV void st(float2* p, cx<R> v) { *p = make_float2(float(v.re), float(v.im)); }
+template <typename R> TP_DEV void st(__half2* p, cx<R> v) { *p = __floats2half2_rn(float(v.re), float(v.im)); }
+
+// A spinor field of one parity, seen as two half-spinor fields: h = 0 holds spins
+// 0-1 (the P+ = (1+gamma_t)/2 subspace in the Dirac-Pauli basis), h = 1 spins 2-3.
+// Each half is 6 planes [6][stride] (component = spin_in_half*3 + colour); for FP16,
+// nrm[h] holds one FP32 scale per site.  The two halves may live in different
+// buffers, so a field can be assembled from the halves of two others.
+template <typename S>
+struct SpinorF {
+  S* p[2];
+  float* nrm[2];
+  int64_t stride;
+};
+
+template <typename S, typename R = typename Prec<S>::R>
+TP_DEV void load_half(const SpinorF<S>& f, int h, int64_t i, cx<R>* v) {
+  const S* b = f.p[h];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) v[c] = ld<R, S>(b + (int64_t)c * f.stride + i);
+  if constexpr (Prec<S>::half) {
+    R s = f.nrm[h][i];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = s * v[c];
+  }
+}
+
+template <typename S, typename R = typename Prec<S>::R>
+TP_DEV void store_half(const SpinorF<S>& f, int h, int64_t i, const cx<R>* v) {
+  S* b = f.p[h];
+  if constexpr (Prec<S>::half) {
+    R m = R(0);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+    R inv = m > R(0) ? R(1) / m : R(0);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) st(b + (int64_t)c * f.stride + i, inv * v[c]);
+    f.nrm[h][i] = m;
+  } else {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) st(b + (int64_t)c * f.stride + i, v[c]);
+  }
+}
+
+template <typename S, typename R = typename Prec<S>::R>
+TP_DEV void load_spinor(const SpinorF<S>& f, int64_t i, cx<R>* v) {
+  load_half<S, R>(f, 0, i, v);
+  load_half<S, R>(f, 1, i, v + 6);
+}
+template <typename S, typename R = typename Prec<S>::R>
+TP_DEV void store_spinor(const SpinorF<S>& f, int64_t i, const cx<R>* v) {
+  store_half<S, R>(f, 0, i, v);
+  store_half<S, R>(f, 1, i, v + 6);
+}
+
+// Gauge links of one parity and direction: planes [9][stride].
+template <typename L>
+struct LinkF {
+  const L* p;
+  int64_t stride;
+};
+template <typename R, typename L> TP_DEV su3<R> load_su3(const LinkF<L>& f, int64_t i) {
+  su3<R> u;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) u.e[k] = ld<R, L>(f.p + (int64_t)k * f.stride + i);
+  return u;
+}
+
+// ---- Dirac-Pauli spin structure --------------------------------------------------------
+// gamma_t = diag(1,1,-1,-1); gamma_k = [[0, -i s_k], [i s_k, 0]].
+// (1 -+ gamma_k) psi = (h, -+ i s_k h) with h = psi_up +- i s_k psi_lo, so a
+// projected hop needs two colour matvecs on h and a reconstruction.
+// i s_x (a, b) = (i b, i a);  i s_y (a, b) = (b, -a);  i s_z (a, b) = (i a, -i b).
+template <int K, typename R> TP_DEV void is_k(const cx<R>* a, const cx<R>* b, cx<R>* oa, cx<R>* ob) {
+  // (oa, ob) = i sigma_K (a, b), each a colour vector (3 components)
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if constexpr (K == 0) { oa[c] = ti(b[c]); ob[c] = ti(a[c]); }
+    else if constexpr (K == 1) { oa[c] = b[c]; ob[c] = -a[c]; }
+    else { oa[c] = ti(a[c]); ob[c] = tmi(b[c]); }
+  }
+}
+
+// Half spinor for the forward hop in spatial direction K: h = psi_up + i s_K psi_lo.
+template <int K, typename R> TP_DEV void proj_minus(const cx<R>* psi, cx<R>* h) {
+  cx<R> a[3], b[3];
+  is_k<K, R>(psi + 6, psi + 9, a, b);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) { h[c] = psi[c] + a[c]; h[3 + c] = psi[3 + c] + b[c]; }
+}
+// Backward hop: h = psi_up - i s_K psi_lo.
+template <int K, typename R> TP_DEV void proj_plus(const cx<R>* psi, cx<R>* h) {
+  cx<R> a[3], b[3];
+  is_k<K, R>(psi + 6, psi + 9, a, b);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) { h[c] = psi[c] - a[c]; h[3 + c] = psi[3 + c] - b[c]; }
+}
+// out += w * (1 - gamma_K)/2-reconstruction of the transported half spinor g:
+// upper += g, lower += -i s_K g   (forward hop), times the overall factor w.
+template <int K, typename R> TP_DEV void recon_minus(cx<R>* out, const cx<R>* g, R w) {
+  cx<R> a[3], b[3];
+  is_k<K, R>(g, g + 3, a, b);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    out[c] += w * g[c];
+    out[3 + c] += w * g[3 + c];
+    out[6 + c] -= w * a[c];
+    out[9 + c] -= w * b[c];
+  }
+}
+// Backward: upper += g, lower += +i s_K g.
+template <int K, typename R> TP_DEV void recon_plus(cx<R>* out, const cx<R>* g, R w) {
+  cx<R> a[3], b[3];
+  is_k<K, R>(g, g + 3, a, b);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    out[c] += w * g[c];
+    out[3 + c] += w * g[3 + c];
+    out[6 + c] += w * a[c];
+    out[9 + c] += w * b[c];
+  }
+}
+
+// ---- clover blocks -------------------------------------------------------------------------
+// A commutes with gamma5 = [[0,-1],[-1,0]] and is stored as two hermitian 6x6 blocks
+// acting on u+ = psi_up - psi_lo and u- = psi_up + psi_lo (index spin_in_pair*3 + colour),
+// pre-multiplied by 1/2 so that
+//   (A psi)_up = B+ u+ + B- u-,   (A psi)_lo = B- u- - B+ u+.
+// Per block: 18 complex slots: slots 0..2 hold the six real diagonal entries in
+// pairs, slots 3..17 the strictly lower triangle in row-major order.  Planes [36][stride].
+template <typename R, typename L>
+TP_DEV void herm6_apply(const L* base, int64_t stride, int64_t i, const cx<R>* v, cx<R>* out) {
+  R d[6];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    cx<R> t = ld<R, L>(base + (int64_t)k * stride + i);
+    d[2 * k] = t.re;
+    d[2 * k + 1] = t.im;
+  }
+#pragma unroll
+  for (int r = 0; r < 6; ++r) out[r] = d[r] * v[r];
+  int slot = 3;
+#pragma unroll
+  for (int r = 1; r < 6; ++r) {
+#pragma unroll
+    for (int c = 0; c < r; ++c) {
+      cx<R> l = ld<R, L>(base + (int64_t)slot * stride + i);
+      out[r] += cmul(l, v[c]);
+      out[c] += cmulc(l, v[r]);
+      ++slot;
+    }
+  }
+}
+
+template <typename R, typename L>
+TP_DEV void clover_apply(const L* cl, int64_t stride, int64_t i, const cx<R>* psi, cx<R>* out) {
+  cx<R> up[6], um[6], bp[6], bm[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) { up[c] = psi[c] - psi[6 + c]; um[c] = psi[c] + psi[6 + c]; }
+  herm6_apply<R, L>(cl, stride, i, up, bp);
+  herm6_apply<R, L>(cl + 18 * stride, stride, i, um, bm);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) { out[c] = bp[c] + bm[c]; out[6 + c] = bm[c] - bp[c]; }
+}
+
+// ---- lattice geometry ----------------------------------------------------------------------
+// p3 ("line") layout: parity p = (x+y+z)&1; index within a parity = t*Vs2 + s with
+// s = (x + Lx*(y + Ly*z)) >> 1.  A time line (fixed s) stays inside one parity.
+// p4 layout: parity p = (x+y+z+t)&1; index = (x + Lx*(y + Ly*(z + Lz*t))) >> 1.
+struct Geom {
+  int Lx, Ly, Lz, Lt;
+  int Lxh, Vs2;
+  int64_t V2;
+};
+
+struct C3 { int x, y, z; };
+TP_DEV C3 p3_coords(const Geom& g, int p, int s) {
+  int xh = s % g.Lxh;
+  int r = s / g.Lxh;
+  int y = r % g.Ly;
+  int z = r / g.Ly;
+  int x = 2 * xh + ((y + z + p) & 1);
+  return {x, y, z};
+}
+TP_DEV int p3_index(const Geom& g, int x, int y, int z) { return (x + g.Lx * (y + g.Ly * z)) >> 1; }

@@ -1,0 +1,261 @@
+// Host-side internals of the tprec library: handle structures, internal field
+// descriptors, kernel launcher declarations and error plumbing.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <initializer_list>
+#include <string>
+#include <vector>
+
+#include "tp_device.h"
+#include "../../include/tprec.h"
+
+// ---------------------------------------------------------------- errors
+void tp_set_error(const std::string& msg);
+struct TpError {
+  tp_status code;
+  std::string msg;
+};
+#define TP_THROW(code, msg) throw TpError{code, msg}
+#define HIP_CHECK(expr)                                                                   \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw TpError{e_ == hipErrorOutOfMemory ? TP_ENOMEM : TP_EHIP,                      \
+                    std::string(#expr) + ": " + hipGetErrorString(e_)};                   \
+  } while (0)
+#define LAUNCH_CHECK() HIP_CHECK(hipGetLastError())
+
+// ---------------------------------------------------------------- profiling ids
+enum KernelId {
+  KID_PACK = 0,
+  KID_SITE_P3,      // M / D_s / clover / residual on the p3 layout
+  KID_SCHUR4D_EO,   // (A+mu)^-1 D_w^eo
+  KID_SCHUR4D_OE,   // (A+mu) psi_o - D_w^oe t_e
+  KID_LINE_CR,      // C_R / C_L / T^-1 scans without a stencil
+  KID_ILU_K2A,      // D_s + C_L + C_R + clover (even parity)
+  KID_ILU_K2B,      // C_L y and C_R C_L q (even parity)
+  KID_ILU_K3,       // D_s + clover + C_L + axpy (odd parity)
+  KID_LINE_STENCIL, // other stencil + scan line kernels (Wilson, temporal)
+  KID_BLAS,
+  KID_REDUCE,
+  KID_FORCE,
+  KID_COUNT
+};
+extern const char* const kKernelNames[KID_COUNT];
+
+// ---------------------------------------------------------------- internal fields
+// A spinor field in an internal layout (p3 or p4), both parities:
+// data [2 parity][12 component][V2] of the storage type of `prec`,
+// nrm [2 parity][2 half][V2] FP32 scales for TP_F16N (else null).
+struct Field {
+  int prec = TP_F64;
+  void* data = nullptr;
+  float* nrm = nullptr;
+  int64_t V2 = 0;
+  bool owned = false;
+
+  size_t elem_bytes() const { return prec == TP_F64 ? 16 : (prec == TP_F32 ? 8 : 4); }
+  template <typename S>
+  SpinorF<S> par(int p) const {
+    S* b = static_cast<S*>(data) + (int64_t)p * 12 * V2;
+    SpinorF<S> f;
+    f.p[0] = b;
+    f.p[1] = b + 6 * V2;
+    f.nrm[0] = nrm ? nrm + (int64_t)(2 * p) * V2 : nullptr;
+    f.nrm[1] = nrm ? nrm + (int64_t)(2 * p + 1) * V2 : nullptr;
+    f.stride = V2;
+    return f;
+  }
+};
+
+// Geometry helpers shared by host launchers.
+struct Lattice {
+  int L[4];        // Lx, Ly, Lz, Lt
+  int64_t V, V2;   // volume, half volume
+  int Vs, Vs2;     // spatial volume, half
+  Geom g;
+};
+
+// ---------------------------------------------------------------- handles
+struct ProfSlot {
+  int64_t launches = 0;
+  double ms = 0;
+  double bytes = 0;
+};
+
+struct tp_ctx_s {
+  Lattice lat;
+  int bc = -1;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool prof = false;
+  ProfSlot prof_slots[KID_COUNT];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  struct EvRec { int kid; double bytes; bool done; };
+  std::vector<EvRec> ev_pending;  // per used event pair
+  size_t ev_used = 0;
+  // reduction scratch
+  double* red_partial = nullptr;  // [kRedBlocks][8]
+  double* red_result = nullptr;   // [8]
+  double* red_host = nullptr;     // pinned [8]
+};
+
+struct tp_gauge_s {
+  tp_ctx ctx = nullptr;
+  double2* canon = nullptr;  // device copy of the canonical links [4][V][9]
+  double2* u3_d = nullptr;   // p3 layout [4 dir][2 par][9][V2], time phase folded
+  float2* u3_f = nullptr;
+  double2* u4_d = nullptr;   // p4 layout [4 dir][2 par][9][V2], time phase folded
+  float2* u4_f = nullptr;
+  double2* w_d = nullptr;    // p3 layout W(t) = U(t)...U(Lt-1) [2 par][9][V2]
+  float2* w_f = nullptr;
+  double2* poly = nullptr;   // W(0) per line [2 par][9][Vs2]
+};
+
+struct tp_clover_s {
+  tp_gauge g = nullptr;
+  double cs = 0, ct = 0;
+  double2* a3_d = nullptr;  // p3 layout chiral blocks of A/2 [2 par][36][V2]
+  float2* a3_f = nullptr;
+  double2* a4_d = nullptr;  // p4 layout chiral blocks of A/2 [2 par][36][V2]
+  float2* a4_f = nullptr;
+};
+
+struct Workspace;
+
+struct tp_op_s {
+  tp_gauge g = nullptr;
+  tp_clover c = nullptr;
+  double m0 = 0, gf = 1, mu = 1;
+  double2* gclos = nullptr;  // per line G = (I - mu^-Lt P)^-1 P / mu  [2 par][9][Vs2]
+  double2* a4_mu = nullptr;     // p4 (A+mu)/2 chiral blocks [2][36][V2]
+  double2* a4_inv = nullptr;    // p4 (A+mu)^-1 / 2 chiral blocks [2][36][V2]
+  float2* a4_mu_f = nullptr;
+  float2* a4_inv_f = nullptr;
+  double2* a3_mu = nullptr;     // p3 (A+mu)/2 and (A+mu)^-1/2 for apply checks
+  double2* a3_inv = nullptr;
+  float2* a3_mu_f = nullptr;
+  float2* a3_inv_f = nullptr;
+  double* mupow_d = nullptr;    // mu^-k, k = 0..Lt
+  float* mupow_f = nullptr;
+  Workspace* ws = nullptr;
+};
+
+// ---------------------------------------------------------------- memory helpers
+void* dev_alloc(size_t bytes);
+void dev_free(void* p);
+Field field_alloc(const Lattice& lat, int prec);
+void field_free(Field& f);
+
+// ---------------------------------------------------------------- profiling helpers
+struct ProfScope {
+  tp_ctx ctx;
+  int kid;
+  double bytes;
+  size_t slot;
+  bool on;
+  ProfScope(tp_ctx c, int k, double b);
+  ~ProfScope();
+};
+void prof_flush(tp_ctx ctx);
+
+// ---------------------------------------------------------------- launchers (layout / setup)
+// pack canonical c128 spinor (device) into an internal field; layout4 selects p4.
+void launch_pack(tp_ctx ctx, const double2* canon, Field& dst, bool layout4, bool gamma5);
+void launch_unpack(tp_ctx ctx, const Field& src, double2* canon, bool layout4, bool gamma5);
+void launch_pack_links(tp_ctx ctx, tp_gauge g);
+void launch_wline(tp_ctx ctx, tp_gauge g);
+void launch_closure(tp_ctx ctx, tp_op op, double* cond_out /*device [2*Vs2]*/);
+void launch_clover_build(tp_ctx ctx, tp_clover c, const double sig[6][2][2][2][2]);
+void launch_clover_derived(tp_ctx ctx, tp_op op, int* bad /*device counter*/);
+void launch_plaquette(tp_ctx ctx, tp_gauge g, double* out2 /*device partial sums*/);
+
+// ---------------------------------------------------------------- launchers (operators)
+// p3 site kernel: dst = c_mu*src + c_A*(A src) + c_t*(D_t src) + c_s*(D_s src) + c_in*in2,
+// for parities [par0, par0+npar); optional |dst|^2 into the reduction scratch.
+struct SiteCoef {
+  double c_mu, c_A, c_t, c_s, c_in;
+};
+// Returns the number of reduction partials written (0 unless want_norm).
+int launch_site_p3(tp_op op, int prec, const Field& src, Field& dst, const Field* in2,
+                   SiteCoef cf, int clover_kind /*0 none,1 A,2 (A+mu),3 (A+mu)^-1*/,
+                   int par0, int npar, bool want_norm);
+
+// 4D Schur pieces on the p4 layout (FP64 and FP32 storage).
+//   mode 0: dst_e = (A+mu)^-1 (c_h D_w^eo src_o)              [clover after hop]
+//   mode 1: dst_o = (A+mu) src_o + c_h D_w^oe t_e             [clover on self]
+//   mode 2: dst_p = c_in*in2_p + c_h D_w src_(1-p)            [plain hop + axpy]
+//   mode 3: dst_p = (A+mu)^-1 (in2_p + c_h D_w src_(1-p))     [reconstruction]
+//   mode 4: dst_p = clover(in2_p) with clover_kind             [site only]
+void launch_schur4d(tp_op op, int prec, int mode, int out_par, const Field* src, Field& dst,
+                    const Field* in2, double c_h, double c_in, int clover_kind);
+
+// Line (time-line scan) kernels on the p3 layout.
+enum LineMode { LM_CL = 0, LM_CR = 1, LM_CRCL = 2, LM_TINV = 3, LM_TDINV = 4 };
+struct LineIO;
+// Plain scans: dst = mode(src) on parity par (pass-through halves copied).
+void launch_line_plain(tp_op op, int prec, int mode, int par, const Field& src, Field& dst);
+// Stencil-prologue scan:
+//   v = c_s * D_s(nb, from parity 1-par) + c_A * A(self) + c_self * self
+//   r = mode(v);  dst = c_out * r + c_base * base
+// nb / self / base are fields (self and base on parity par); any may be null.
+struct LineStencilArgs {
+  const Field* nb_up;   // upper half of the neighbour field (parity 1-par)
+  const Field* nb_lo;   // lower half of the neighbour field
+  const Field* self;    // operand of A / self term on parity par (may be null)
+  const Field* base;    // added to the output (may be null)
+  double c_s, c_A, c_self, c_out, c_base;
+};
+void launch_line_stencil(tp_op op, int prec, int mode, int par, const LineStencilArgs& a,
+                         Field& dst);
+// ILU pieces (clover temporal + 3D Schur), see ops.cpp for the sequence.
+void launch_ilu_k1(tp_op op, int prec, const Field& psi, Field& aup);
+void launch_ilu_k2a(tp_op op, int prec, const Field& psi, const Field& aup, Field& y, Field& q);
+void launch_ilu_k2b(tp_op op, int prec, const Field& psi, const Field& y, const Field& q,
+                    Field& chi, Field& n);
+void launch_ilu_k3(tp_op op, int prec, const Field& psi, const Field& aup, const Field& n,
+                   Field& chi);
+
+// ---------------------------------------------------------------- BLAS
+constexpr int kRedBlocks = 1024;
+// Generic unit-wise BLAS on fields over parities [par0, par0+npar).
+enum BlasOp {
+  B_ZERO,         // y = 0
+  B_COPY,         // y = x                          (same precision)
+  B_CONVERT,      // y = x                          (any precisions)
+  B_AXPY,         // y = y + a x                    (a complex)
+  B_XPAY,         // y = x + a y
+  B_AXPBYPCZ,     // z = a x + b y + c z            (p update of BiCGStab: p = r + beta (p - w v))
+  B_NORM2,        // |x|^2
+  B_DOT,          // <x, y>
+  B_DOT_NORM,     // <x, y>, |y|^2
+  B_CAXPY_NORM,   // y = y + a x ; |y|^2            (s = r - alpha v)
+  B_DOT2_TS,      // <t, s>, |t|^2
+  B_BICG_UPDATE,  // x += a p + b s ; r = s - b t ; <rhat, r>, |r|^2
+  B_G5,           // y = gamma5 x
+  B_MIXED_ACC     // y(F64) += x(any)
+};
+struct BlasArgs {
+  double a[2], b[2], c[2];  // complex coefficients
+};
+// fs: up to six fields (see each op); returns reduction values (up to 4 doubles)
+// synchronously in red_out when the op reduces.
+void blas(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<const Field*> fs,
+          BlasArgs k = BlasArgs{}, double* red_out = nullptr);
+// Sum of the first nblocks per-block partials written by a site kernel with want_norm.
+double finish_norm(tp_ctx ctx, int nblocks);
+
+// ---------------------------------------------------------------- force
+void launch_force(tp_op op, const Field& x, const Field& lam, double2* grad, bool projected);
+
+// ---------------------------------------------------------------- composite operators (ops.cpp)
+void op_apply_M(tp_op op, int prec, const Field& src, Field& dst, bool dagger);
+void op_apply_prec(tp_op op, int scheme, int prec, const Field& src, Field& dst, bool dagger);
+void op_prepare(tp_op op, int scheme, int prec, const Field& eta, Field& et);
+void op_reconstruct(tp_op op, int scheme, int prec, const Field& y, Field& x);
+bool scheme_layout4(int scheme);
+// Workspace vectors (allocated lazily, owned by the op).
+Field& ws_get(tp_op op, int prec, int slot);
+void ws_free(tp_op op);

@@ -59,27 +59,83 @@ def su3_algebra(omega: np.ndarray) -> np.ndarray:
     return np.einsum("...a,aij->...ij", omega, gell_mann()) * 0.5
 
 
-def _expi(h: np.ndarray, eps) -> np.ndarray:
-    """exp(i eps h) for hermitian h [..., 3, 3] via its eigendecomposition."""
-    w, v = np.linalg.eigh(h)
-    ph = np.exp(1j * np.asarray(eps)[..., None] * w)
-    return np.einsum("...ij,...j,...kj->...ik", v, ph, v.conj())
+def expi_eigh(q: np.ndarray) -> np.ndarray:
+    """exp(i q) for hermitian q [..., 3, 3] via its eigendecomposition (reference form)."""
+    w, v = np.linalg.eigh(q)
+    return np.einsum("...ij,...j,...kj->...ik", v, np.exp(1j * w), v.conj())
+
+
+def expi_su3(q: np.ndarray) -> np.ndarray:
+    """exp(i q) for traceless hermitian q [..., 3, 3] in closed form.
+
+    Cayley-Hamilton: exp(iQ) = f0 + f1 Q + f2 Q^2 with the coefficients of
+    Morningstar and Peardon (Phys. Rev. D69 (2004) 054501, the stout-link
+    exponential), written from c0 = det Q = tr(Q^3)/3 and c1 = tr(Q^2)/2; a
+    negative c0 is mapped to |c0| with f_j(-c0) = (-1)^j conj(f_j(c0)), which
+    keeps the denominator 9u^2 - w^2 >= 2 c1 away from zero.
+    """
+    q2 = q @ q
+    c0 = np.einsum("...ij,...ji->...", q, q2).real / 3.0
+    c1 = np.einsum("...ii->...", q2).real / 2.0
+    neg = c0 < 0
+    c1s = np.maximum(c1, 1e-300)
+    c0max = 2.0 * (c1s / 3.0) ** 1.5
+    theta = np.arccos(np.clip(np.abs(c0) / c0max, 0.0, 1.0))
+    u = np.sqrt(c1s / 3.0) * np.cos(theta / 3.0)
+    w = np.sqrt(c1s) * np.sin(theta / 3.0)
+    small = np.abs(w) < 0.05
+    ws = np.where(small, 1.0, w)
+    xi0 = np.where(small, 1 - w * w / 6 * (1 - w * w / 20 * (1 - w * w / 42)), np.sin(ws) / ws)
+    e2iu = np.exp(2j * u)
+    emiu = np.exp(-1j * u)
+    cw = np.cos(w)
+    uu,ww = u * u, w * w
+    den = 9 * uu - ww
+    f0 = ((uu - ww) * e2iu + emiu * (8 * uu * cw + 2j * u * (3 * uu + ww) * xi0)) / den
+    f1 = (2 * u * e2iu - emiu * (2 * u * cw - 1j * (3 * uu - ww) * xi0)) / den
+    f2 = (e2iu - emiu * (cw + 3j * u * xi0)) / den
+    f0 = np.where(neg, np.conj(f0), f0)
+    f1 = np.where(neg, -np.conj(f1), f1)
+    f2 = np.where(neg, np.conj(f2), f2)
+    out = f1[..., None, None] * q + f2[..., None, None] * q2
+    out[..., 0, 0] += f0
+    out[..., 1, 1] += f0
+    out[..., 2, 2] += f0
+    return out
 
 
 def make_links(dims, eps_s: float, eps_t: float, seed: int) -> np.ndarray:
     """SU(3) links U_mu(x) = exp(i eps_mu H_mu(x)), canonical [4][Lt][Lz][Ly][Lx][3][3].
 
-    dims = (Lx, Ly, Lz, Lt).  The eight algebra coefficients of every link are
-    drawn in one call of numpy's PCG64 generator, shape (4, Lt, Lz, Ly, Lx, 8).
+    dims = (Lx, Ly, Lz, Lt).  The eight algebra coefficients of every link come
+    from one numpy PCG64 stream in C order of shape (4, Lt, Lz, Ly, Lx, 8), drawn
+    in time-slab chunks whose exponentials are evaluated on a thread pool.
     """
+    from concurrent.futures import ThreadPoolExecutor
+    import os
+
     lx, ly, lz, lt = dims
     rng = np.random.default_rng(seed)
-    omega = rng.standard_normal((4, lt, lz, ly, lx, 8))
-    h = su3_algebra(omega)
-    eps = np.empty((4, lt, lz, ly, lx))
-    eps[:3] = eps_s
-    eps[3] = eps_t
-    return np.ascontiguousarray(_expi(h, eps))
+    out = np.empty((4, lt, lz, ly, lx, 3, 3), dtype=np.complex128)
+    chunk = max(1, (1 << 19) // (lz * ly * lx))
+
+    def work(mu, t0, t1, omega, eps):
+        out[mu, t0:t1] = expi_su3(eps * su3_algebra(omega))
+
+    nthreads = max(1, min(16, os.cpu_count() or 1))
+    with ThreadPoolExecutor(nthreads) as ex:
+        futs = []
+        for mu in range(4):
+            eps = eps_t if mu == 3 else eps_s
+            for t0 in range(0, lt, chunk):
+                t1 = min(lt, t0 + chunk)
+                omega = rng.standard_normal((t1 - t0, lz, ly, lx, 8))
+                futs.append(ex.submit(work, mu, t0, t1, omega, eps))
+                if len(futs) > 4 * nthreads:  # bound the memory held by pending chunks
+                    futs.pop(0).result()
+        for f in futs:
+            f.result()
+    return out
 
 
 def unit_links(dims) -> np.ndarray:

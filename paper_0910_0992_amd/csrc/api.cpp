@@ -14,9 +14,8 @@ tp_status op_solve(tp_op op, const tp_solve_params& P, Field& x64, const Field& 
                    tp_solve_info& info);
 
 const char* const kKernelNames[KID_COUNT] = {
-    "pack_unpack",     "site_p3",        "schur4d_eo_clover_inv", "schur4d_oe_clover",
-    "line_scan_plain", "ilu_k2a",        "ilu_k2b",               "ilu_k3",
-    "line_scan_stencil", "blas",         "reduce_finish",         "force"};
+    "pack_unpack", "site_p3",  "schur4d_eo_clover_inv", "schur4d_oe_clover", "line_scan",
+    "ilu_mid",     "hop_site", "blas",                  "reduce_finish",     "force"};
 
 namespace {
 thread_local std::string g_last_error;
@@ -209,9 +208,10 @@ tp_status apply_wrap(tp_op op, int prec, void* dst, const void* src, bool l4, bo
     if (l4 && ctx->lat.L[3] % 2) TP_THROW(TP_EDIMS, "SCHUR4D needs an even time extent");
     Field& a = tmp_field(op, prec, 0);
     Field& b = tmp_field(op, prec, 1);
-    launch_pack(ctx, static_cast<const double2*>(src), a, l4, g5);
+    const double2* w = l4 ? nullptr : op->g->w_d;  // p3 operators act in the axial frame
+    launch_pack(ctx, static_cast<const double2*>(src), a, l4, g5, w);
     f(a, b);
-    launch_unpack(ctx, b, static_cast<double2*>(dst), l4, g5);
+    launch_unpack(ctx, b, static_cast<double2*>(dst), l4, g5, w);
   });
 }
 
@@ -315,10 +315,11 @@ tp_status tp_gauge_create(tp_ctx ctx, const void* links, int32_t where, tp_gauge
       g->u4_d = static_cast<double2*>(dev_alloc(lb));
       g->u4_f = static_cast<float2*>(dev_alloc(lb / 2));
       g->w_d = static_cast<double2*>(dev_alloc(size_t(2) * 9 * L.V2 * sizeof(double2)));
-      g->w_f = static_cast<float2*>(dev_alloc(size_t(2) * 9 * L.V2 * sizeof(float2)));
       g->poly = static_cast<double2*>(dev_alloc(size_t(2) * 9 * L.Vs2 * sizeof(double2)));
-      launch_pack_links(ctx, g);
+      g->canon_ax = static_cast<double2*>(dev_alloc(lb));
       launch_wline(ctx, g);
+      launch_axial_links(ctx, g);
+      launch_pack_links(ctx, g);
       HIP_CHECK(hipStreamSynchronize(ctx->stream));
     } catch (...) {
       tp_gauge_destroy(g);
@@ -339,7 +340,7 @@ tp_status tp_gauge_destroy(tp_gauge g) {
     dev_free(g->u4_d);
     dev_free(g->u4_f);
     dev_free(g->w_d);
-    dev_free(g->w_f);
+    dev_free(g->canon_ax);
     dev_free(g->poly);
     delete g;
   });
@@ -533,22 +534,25 @@ tp_status tp_apply_clover(tp_op op, int32_t prec, void* dst, const void* src, in
   });
 }
 
+static void line_both(tp_op op, int prec, int mode, Field& a, Field& b) {
+  LineIO io;
+  io.in_up = io.in_lo = &a;
+  for (int p = 0; p < 2; ++p) launch_line(op, prec, mode, p, io, b);
+}
+
 tp_status tp_apply_Tinv(tp_op op, int32_t prec, void* dst, const void* src, int32_t dagger) {
-  return apply_wrap(op, prec, dst, src, false, false, [&](Field& a, Field& b) {
-    for (int p = 0; p < 2; ++p) launch_line_plain(op, prec, dagger ? LM_TDINV : LM_TINV, p, a, b);
-  });
+  return apply_wrap(op, prec, dst, src, false, false,
+                    [&](Field& a, Field& b) { line_both(op, prec, dagger ? LM_TDINV : LM_TINV, a, b); });
 }
 
 tp_status tp_apply_CL(tp_op op, int32_t prec, void* dst, const void* src) {
-  return apply_wrap(op, prec, dst, src, false, false, [&](Field& a, Field& b) {
-    for (int p = 0; p < 2; ++p) launch_line_plain(op, prec, LM_CL, p, a, b);
-  });
+  return apply_wrap(op, prec, dst, src, false, false,
+                    [&](Field& a, Field& b) { line_both(op, prec, LM_CL, a, b); });
 }
 
 tp_status tp_apply_CR(tp_op op, int32_t prec, void* dst, const void* src) {
-  return apply_wrap(op, prec, dst, src, false, false, [&](Field& a, Field& b) {
-    for (int p = 0; p < 2; ++p) launch_line_plain(op, prec, LM_CR, p, a, b);
-  });
+  return apply_wrap(op, prec, dst, src, false, false,
+                    [&](Field& a, Field& b) { line_both(op, prec, LM_CR, a, b); });
 }
 
 tp_status tp_apply_prec(tp_op op, int32_t scheme, int32_t prec, void* dst, const void* src,
@@ -604,10 +608,11 @@ tp_status tp_solve(tp_op op, const tp_solve_params* params, void* x, const void*
     if (l4 && ctx->lat.L[3] % 2) TP_THROW(TP_EDIMS, "SCHUR4D needs an even time extent");
     Field& eta64 = ws_get(op, TP_F64, 60);
     Field& x64 = ws_get(op, TP_F64, 61);
-    launch_pack(ctx, static_cast<const double2*>(eta), eta64, l4, false);
-    if (P.use_x0) launch_pack(ctx, static_cast<const double2*>(x), x64, l4, false);
+    const double2* w = l4 ? nullptr : op->g->w_d;  // p3 schemes solve in the axial frame
+    launch_pack(ctx, static_cast<const double2*>(eta), eta64, l4, false, w);
+    if (P.use_x0) launch_pack(ctx, static_cast<const double2*>(x), x64, l4, false, w);
     st = op_solve(op, P, x64, eta64, *info);
-    launch_unpack(ctx, x64, static_cast<double2*>(x), l4, false);
+    launch_unpack(ctx, x64, static_cast<double2*>(x), l4, false, w);
     HIP_CHECK(hipStreamSynchronize(ctx->stream));
     prof_flush(ctx);
     if (st != TP_OK)
@@ -628,8 +633,8 @@ tp_status tp_force(tp_op op, const void* x, const void* lambda, void* grad, int3
     set_device(ctx);
     Field& a = tmp_field(op, TP_F64, 0);
     Field& b = tmp_field(op, TP_F64, 1);
-    launch_pack(ctx, static_cast<const double2*>(x), a, false, false);
-    launch_pack(ctx, static_cast<const double2*>(lambda), b, false, false);
+    launch_pack(ctx, static_cast<const double2*>(x), a, false, false, nullptr);
+    launch_pack(ctx, static_cast<const double2*>(lambda), b, false, false, nullptr);
     launch_force(op, a, b, static_cast<double2*>(grad), projected != 0);
   });
 }

@@ -1,31 +1,30 @@
 // Time-line kernels: the exact inverse of the temporal matrix T (and T^dagger)
-// inside C_L, C_R, fused with the spatial hop and the clover term.
+// inside C_L, C_R, and the fused middle step of the 3D ILU operator.
 //
 // Sec. II.A inverts T = mu - U_t(t) delta_{t+1,t'} (with the boundary corner)
 // per spatial site by Sherman-Morrison-Woodbury: an open back-substitution
-// plus a rank-3 correction built from partial Polyakov loops X(t).  Here the
-// same exact inverse is evaluated in the frame rotated by
-// W(t) = U_t(t) U_t(t+1) ... U_t(Lt-1) (the product the closed form of X
-// contains; W(0) = P, the Polyakov loop with the boundary phase):
-//   psi(t) = W(t) r(t)  turns  T psi = eta  into
-//   mu r(t) - r(t+1) = xi(t) := W(t)^dag eta(t)   (t < Lt-1),
-//   mu r(Lt-1) - P r(0) = xi(Lt-1),
-// whose solution is the scalar discounted suffix sum
-//   sigma(t) = (xi(t) + sigma(t+1)) / mu,  sigma(Lt) = 0,
-//   r(t) = sigma(t) + mu^-(Lt-1-t) delta,  delta = (I - mu^-Lt P)^-1 P sigma(0) / mu.
-// T^dagger mirrors it with a prefix sum and delta' = G^dagger rho(Lt-1).
-// This is the axial-gauge form of Sec. II.C applied on the fly.  Because the
-// recurrence has a scalar coefficient, a line splits into chunks whose
-// partial sums combine exactly through LDS (carry = mu^-k times the neighbour
-// chunk's head), so every time slice of a line gets its own thread.  The
-// closure G = (I - mu^-Lt P)^-1 P / mu is FP64 and applied in FP64.
+// plus a rank-3 correction built from partial Polyakov loops X(t).  The p3
+// operators here live in the axial gauge of Sec. II.C / App. C, fixed once per
+// gauge field with Omega(x) = W(x)^dag, W(t) = U_t(t) U_t(t+1) ... U_t(Lt-1):
+// every interior time link is the identity and U_t(Lt-1) = P, the Polyakov
+// loop with the boundary phase.  T psi = eta then reads
+//   mu psi(t) - psi(t+1) = eta(t)   (t < Lt-1),   mu psi(Lt-1) - P psi(0) = eta(Lt-1),
+// whose exact solution is the scalar discounted suffix sum
+//   sigma(t) = (eta(t) + sigma(t+1)) / mu,  sigma(Lt) = 0,
+//   psi(t) = sigma(t) + mu^-(Lt-1-t) delta,  delta = (I - mu^-Lt P)^-1 P sigma(0) / mu,
+// i.e. the SMW back-substitution with X(t) = -b mu^-(Lt-t) P.  T^dagger mirrors
+// it with a prefix sum and delta' = G^dagger rho(Lt-1).  No link is read by a
+// scan.  Because the recurrence has a scalar coefficient, a line splits into
+// chunks whose partial sums combine exactly through LDS (carry = mu^-k times
+// the neighbour chunk's head).  The closure G = (I - mu^-Lt P)^-1 P / mu is FP64
+// and applied in FP64.
 //
-// Workgroup = LPB consecutive lines x NCH chunks of CH consecutive time
-// slices; lanes run over lines first, so a wavefront reads LPB consecutive
-// sites per time slice.
+// Workgroup = LPB lines (whole tiles of 4 lines) x NCH chunks of CH consecutive
+// time slices.  Threads are numbered in memory order of the tiled p3 layout
+// (line-in-tile fastest, then chunk, then tile), so loads and stores are
+// contiguous across a wavefront.
 #pragma once
 #include "tp_internal.h"
-#include "tp_hop.h"
 
 namespace {
 
@@ -40,108 +39,99 @@ struct ScanCtx {
   int64_t gstride;
 };
 
-// v: per time slice of the chunk, NV complex values (NV/3 colour vectors) that are
-// already rotated by W^dagger.  On return v holds r(t) (still in the rotated frame).
+// v: per time slice of the chunk, NV complex values (NV/3 colour vectors); on return
+// v holds the scan result (T^-1 for BWD, T^dagger^-1 otherwise) on those values.
+// Groups of 6 values (two colour vectors) are finished one at a time, so only one
+// group's carries are live.
 template <typename R, int CH, int NV, bool BWD>
 TP_DEV void scan_core(cx<R> (&v)[CH][NV], cx<R>* lds, const ScanCtx<R>& sc) {
-  cx<R> X[NV];
-#pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    cx<R> acc = czero<R>();
-    if constexpr (BWD) {
-#pragma unroll
-      for (int k = CH - 1; k >= 0; --k) {
-        acc = sc.inv_mu * (v[k][c] + acc);
-        v[k][c] = acc;
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < CH; ++k) {
-        acc = sc.inv_mu * (v[k][c] + acc);
-        v[k][c] = acc;
-      }
-    }
-    X[c] = acc;
-  }
-  cx<R> C[NV], Z[NV];
   const int me = (sc.j * sc.LPB + sc.l) * 6;
 #pragma unroll
   for (int g = 0; g < NV / 6; ++g) {
+    // chunk-local recurrence
+    cx<R> X[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      cx<R> acc = czero<R>();
+      if constexpr (BWD) {
+#pragma unroll
+        for (int k = CH - 1; k >= 0; --k) {
+          acc = sc.inv_mu * (v[k][6 * g + c] + acc);
+          v[k][6 * g + c] = acc;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          acc = sc.inv_mu * (v[k][6 * g + c] + acc);
+          v[k][6 * g + c] = acc;
+        }
+      }
+      X[c] = acc;
+    }
+    // combine chunk heads (backward) / tails (forward) across the line
     R fd = sc.f;
     for (int d = 1; d < sc.NCH; d <<= 1) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) lds[me + c] = X[6 * g + c];
+      for (int c = 0; c < 6; ++c) lds[me + c] = X[c];
       __syncthreads();
       int jj = BWD ? sc.j + d : sc.j - d;
       if (jj >= 0 && jj < sc.NCH) {
         const int o = (jj * sc.LPB + sc.l) * 6;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) X[6 * g + c] += fd * lds[o + c];
+        for (int c = 0; c < 6; ++c) X[c] += fd * lds[o + c];
       }
       __syncthreads();
       fd = fd * fd;
     }
 #pragma unroll
-    for (int c = 0; c < 6; ++c) lds[me + c] = X[6 * g + c];
+    for (int c = 0; c < 6; ++c) lds[me + c] = X[c];
     __syncthreads();
     int jc = BWD ? sc.j + 1 : sc.j - 1;
     bool has = jc >= 0 && jc < sc.NCH;
-    const int oc = (has ? jc : 0) * sc.LPB * 6 + sc.l * 6;
+    const int oc = ((has ? jc : 0) * sc.LPB + sc.l) * 6;
     const int oz = ((BWD ? 0 : sc.NCH - 1) * sc.LPB + sc.l) * 6;
+    cx<R> C[6], D[6];
+    cx<double> Z[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      C[6 * g + c] = has ? lds[oc + c] : czero<R>();
-      Z[6 * g + c] = lds[oz + c];
+      C[c] = has ? lds[oc + c] : czero<R>();
+      cx<R> z = lds[oz + c];
+      Z[c] = cx<double>{double(z.re), double(z.im)};
     }
     __syncthreads();
-  }
-  // closure in FP64: delta = G z (backward) or G^dagger z (forward), per colour vector
-  cx<R> D[NV];
-  if (sc.active) {
-    cx<double> G[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      double2 e = sc.G[(int64_t)k * sc.gstride + sc.s];
-      G[k] = cx<double>{e.x, e.y};
-    }
-#pragma unroll
-    for (int q = 0; q < NV / 3; ++q) {
+    // closure in FP64: delta = G z (backward) or G^dagger z (forward), per colour vector
+    if (sc.active) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        cx<double> acc = czero<double>();
+        cx<double> acc0 = czero<double>(), acc1 = czero<double>();
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-          cx<double> z = cx<double>{double(Z[3 * q + b].re), double(Z[3 * q + b].im)};
-          if constexpr (BWD) acc += cmul(G[3 * a + b], z);
-          else acc += cmulc(G[3 * b + a], z);
+          int k = BWD ? 3 * a + b : 3 * b + a;
+          double2 e = sc.G[(int64_t)k * sc.gstride + sc.s];
+          cx<double> gk = cx<double>{e.x, e.y};
+          if constexpr (BWD) {
+            acc0 += cmul(gk, Z[b]);
+            acc1 += cmul(gk, Z[3 + b]);
+          } else {
+            acc0 += cmulc(gk, Z[b]);
+            acc1 += cmulc(gk, Z[3 + b]);
+          }
         }
-        D[3 * q + a] = cx<R>{R(acc.re), R(acc.im)};
+        D[a] = cx<R>{R(acc0.re), R(acc0.im)};
+        D[3 + a] = cx<R>{R(acc1.re), R(acc1.im)};
       }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) D[c] = czero<R>();
     }
-  } else {
 #pragma unroll
-    for (int c = 0; c < NV; ++c) D[c] = czero<R>();
-  }
+    for (int k = 0; k < CH; ++k) {
+      int t = sc.t0 + k;
+      R ca = BWD ? sc.mupow[CH - k] : sc.mupow[k + 1];
+      R cb = BWD ? sc.mupow[sc.Lt - 1 - t] : sc.mupow[t];
 #pragma unroll
-  for (int k = 0; k < CH; ++k) {
-    int t = sc.t0 + k;
-    R ca = BWD ? sc.mupow[CH - k] : sc.mupow[k + 1];
-    R cb = BWD ? sc.mupow[sc.Lt - 1 - t] : sc.mupow[t];
-#pragma unroll
-    for (int c = 0; c < NV; ++c) v[k][c] += ca * C[c] + cb * D[c];
-  }
-}
-
-// v[3q..3q+2] <- W^dag v (dag = true) or W v, for NV/3 colour vectors.
-template <typename R, int NV, bool DAG>
-TP_DEV void rotate(const su3<R>& w, cx<R>* v) {
-#pragma unroll
-  for (int q = 0; q < NV / 3; ++q) {
-    cx<R> o[3];
-    if constexpr (DAG) mvd(w, v + 3 * q, o);
-    else mv(w, v + 3 * q, o);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) v[3 * q + a] = o[a];
+      for (int c = 0; c < 6; ++c) v[k][6 * g + c] += ca * C[c] + cb * D[c];
+    }
   }
 }
 
@@ -159,13 +149,11 @@ template <> struct ModeT<LM_TDINV> { static constexpr int nb = 0, nf = 12; stati
 
 template <typename S>
 struct LineArgs {
-  SpinorF<S> in, out, nb, self, base;
-  LinkF<typename Prec<S>::L> w;     // W(t) of this parity
-  LinkF<typename Prec<S>::L> u[2][4];
+  SpinorF<S> in, out, aux, self, base;
   const typename Prec<S>::L* clov;  // A/2 blocks of this parity
   const double2* G;
   const typename Prec<S>::R* mupow;
-  double inv_mu, f, c_s, c_A, c_self, c_out, c_base;
+  double inv_mu, f, c_out, c_base;
   Geom g;
   int par, LPB, NCH;
 };
@@ -174,8 +162,10 @@ template <typename S>
 TP_DEV ScanCtx<typename Prec<S>::R> make_ctx(const LineArgs<S>& a, int CH) {
   using R = typename Prec<S>::R;
   ScanCtx<R> sc;
-  sc.l = threadIdx.x % a.LPB;
-  sc.j = threadIdx.x / a.LPB;
+  const int tid = threadIdx.x;
+  const int rest = tid / kTile;
+  sc.j = rest % a.NCH;
+  sc.l = (rest / a.NCH) * kTile + (tid % kTile);
   sc.LPB = a.LPB;
   sc.NCH = a.NCH;
   sc.t0 = sc.j * CH;
@@ -214,15 +204,11 @@ template <int MODE> TP_DEV constexpr bool passes(int h) {
   return h == 0 ? !(M::up_b || M::up_f) : !(M::lo_b || M::lo_f);
 }
 
-// Generic line kernel.
-//   STEN: v = c_s D_s(nb) [+ c_A A(self)] [+ c_self self]   else v = in
-//   r = MODE(v) on the scanned halves, v on the pass-through halves
-//   out = c_out r + c_base base (BASE) or r
-//   PASS = false: pass-through halves are not written (in-place or half outputs).
-template <typename S, int CH, int MODE, bool STEN, bool CLOV, bool SELF, bool BASE, bool PASS>
+// out = c_out MODE(in) + c_base base  (BASE), else c_out MODE(in).
+// Halves that MODE does not scan pass through (PASS), or are left untouched.
+template <typename S, int CH, int MODE, bool BASE, bool PASS>
 __global__ void __launch_bounds__(1024) k_line(LineArgs<S> a) {
   using R = typename Prec<S>::R;
-  using Lt = typename Prec<S>::L;
   using M = ModeT<MODE>;
   extern __shared__ char smem_raw[];
   cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
@@ -232,38 +218,14 @@ __global__ void __launch_bounds__(1024) k_line(LineArgs<S> a) {
   const R cout = R(a.c_out), cbase = R(a.c_base);
 #pragma unroll
   for (int k = 0; k < CH; ++k) {
-    const int t = sc.t0 + k;
-    const int64_t i = (int64_t)t * a.g.Vs2 + s;
+    const int64_t i = p3_idx(a.g, sc.t0 + k, s);
     cx<R> v[12];
     if (sc.active) {
-      if constexpr (STEN) {
-#pragma unroll
-        for (int c = 0; c < 12; ++c) v[c] = czero<R>();
-        hop_space_p3<S, R, Lt>(a.nb, a.u[a.par], a.u[1 - a.par], a.g, a.par, t, s, R(0.5 * a.c_s), v);
-        if constexpr (CLOV || SELF) {
-          cx<R> x[12];
-          load_spinor<S, R>(a.self, i, x);
-          if constexpr (CLOV) {
-            cx<R> ax[12];
-            clover_apply<R, Lt>(a.clov, a.g.V2, i, x, ax);
-            R ca = R(a.c_A);
-#pragma unroll
-            for (int c = 0; c < 12; ++c) v[c] += ca * ax[c];
-          }
-          if constexpr (SELF) {
-            R cs = R(a.c_self);
-#pragma unroll
-            for (int c = 0; c < 12; ++c) v[c] += cs * x[c];
-          }
-        }
-      } else {
-        if constexpr (M::up_b || M::up_f || (PASS && passes<MODE>(0))) load_half<S, R>(a.in, 0, i, v);
-        if constexpr (M::lo_b || M::lo_f || (PASS && passes<MODE>(1))) load_half<S, R>(a.in, 1, i, v + 6);
-      }
-      // pass-through halves go straight to the output
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        if (PASS && passes<MODE>(h)) {
+        const bool scanned = !passes<MODE>(h);
+        if (scanned || PASS) load_half<S, R>(a.in, h, i, v + 6 * h);
+        if (PASS && !scanned) {
           cx<R> o[6];
           if constexpr (BASE) {
             cx<R> bb[6];
@@ -277,15 +239,7 @@ __global__ void __launch_bounds__(1024) k_line(LineArgs<S> a) {
           store_half<S, R>(a.out, h, i, o);
         }
       }
-      su3<R> w = load_su3<R, Lt>(a.w, i);
-      if constexpr (M::nb > 0) {
-        split<MODE, R>(v, vb[k], vf[k]);
-        rotate<R, M::nb, true>(w, vb[k]);
-      }
-      if constexpr (M::nf > 0) {
-        if constexpr (M::nb == 0) split<MODE, R>(v, vb[k], vf[k]);
-        rotate<R, M::nf, true>(w, vf[k]);
-      }
+      split<MODE, R>(v, vb[k], vf[k]);
     } else {
 #pragma unroll
       for (int c = 0; c < Arr<M::nb>::n; ++c) vb[k][c] = czero<R>();
@@ -298,11 +252,7 @@ __global__ void __launch_bounds__(1024) k_line(LineArgs<S> a) {
   if (!sc.active) return;
 #pragma unroll
   for (int k = 0; k < CH; ++k) {
-    const int t = sc.t0 + k;
-    const int64_t i = (int64_t)t * a.g.Vs2 + s;
-    su3<R> w = load_su3<R, Lt>(a.w, i);
-    if constexpr (M::nb > 0) rotate<R, M::nb, false>(w, vb[k]);
-    if constexpr (M::nf > 0) rotate<R, M::nf, false>(w, vf[k]);
+    const int64_t i = p3_idx(a.g, sc.t0 + k, s);
     cx<R> v[12];
     merge<MODE, R>(v, vb[k], vf[k]);
 #pragma unroll
@@ -323,118 +273,78 @@ __global__ void __launch_bounds__(1024) k_line(LineArgs<S> a) {
   }
 }
 
-// ILU step K2a (even parity): u = D_s^eo a_o / gamma_f (a_o = (aup, psi_o lower)),
-//   w = C_R (C_L u + psi_e) = (T^dag^-1 (u_up + psi_up), T^-1 u_lo + psi_lo),
-//   y = A w.   Writes y and u.
+// Middle step of the 3D ILU operator on the even parity, all scans of one line in one
+// workgroup.  in = psi_e, aux = u = D_s^eo a_o / gamma_f:
+//   b   = T^-1 u_lo,  f = T^dag^-1 (u_up + psi_up)
+//   y   = A w,  w = C_R (C_L u + psi_e) = (f, b + psi_lo)
+//   chi_e = psi_e + C_L y = (psi_up + y_up, psi_lo + T^-1 y_lo)               -> out
+//   n_e = C_R C_L (y - u) = (T^dag^-1 (y_up - u_up), T^-1 y_lo - b)          -> base
 template <typename S, int CH>
-__global__ void __launch_bounds__(1024) k_ilu_k2a(LineArgs<S> a) {
+__global__ void __launch_bounds__(1024) k_ilu_mid(LineArgs<S> a) {
   using R = typename Prec<S>::R;
-  using Lt = typename Prec<S>::L;
+  using Lk = typename Prec<S>::L;
   extern __shared__ char smem_raw[];
   cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
   ScanCtx<R> sc = make_ctx<S>(a, CH);
   const int s = sc.active ? sc.s : 0;
-  cx<R> vb[CH][6], vf[CH][6], pl[CH][6];
+  cx<R> b[CH][6], f[CH][6], uup[CH][6];
 #pragma unroll
   for (int k = 0; k < CH; ++k) {
-    const int t = sc.t0 + k;
-    const int64_t i = (int64_t)t * a.g.Vs2 + s;
+    const int64_t i = p3_idx(a.g, sc.t0 + k, s);
     if (sc.active) {
-      cx<R> u[12], ps[6];
-#pragma unroll
-      for (int c = 0; c < 12; ++c) u[c] = czero<R>();
-      hop_space_p3<S, R, Lt>(a.nb, a.u[a.par], a.u[1 - a.par], a.g, a.par, t, s, R(0.5 * a.c_s), u);
-      store_spinor<S, R>(a.base, i, u);  // u, consumed by K2b
+      cx<R> ps[6];
+      load_half<S, R>(a.aux, 0, i, uup[k]);
+      load_half<S, R>(a.aux, 1, i, b[k]);
       load_half<S, R>(a.in, 0, i, ps);
-      load_half<S, R>(a.in, 1, i, pl[k]);
-      su3<R> w = load_su3<R, Lt>(a.w, i);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) { vf[k][c] = u[c] + ps[c]; vb[k][c] = u[6 + c]; }
-      rotate<R, 6, true>(w, vb[k]);
-      rotate<R, 6, true>(w, vf[k]);
+      for (int c = 0; c < 6; ++c) f[k][c] = uup[k][c] + ps[c];
     } else {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) { vb[k][c] = czero<R>(); vf[k][c] = czero<R>(); pl[k][c] = czero<R>(); }
+      for (int c = 0; c < 6; ++c) { b[k][c] = czero<R>(); f[k][c] = czero<R>(); uup[k][c] = czero<R>(); }
     }
   }
-  scan_core<R, CH, 6, true>(vb, lds, sc);
-  scan_core<R, CH, 6, false>(vf, lds, sc);
+  scan_core<R, CH, 6, true>(b, lds, sc);
+  scan_core<R, CH, 6, false>(f, lds, sc);
+  // y = A w; write chi_up; second-phase inputs y_lo (backward) and y_up - u_up (forward)
+#pragma unroll
+  for (int k = 0; k < CH; ++k) {
+    const int64_t i = p3_idx(a.g, sc.t0 + k, s);
+    if (sc.active) {
+      cx<R> w[12], y[12], pl[6], ps[6];
+      load_half<S, R>(a.in, 1, i, pl);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) { w[c] = f[k][c]; w[6 + c] = b[k][c] + pl[c]; }
+      clover_apply<R, Lk>(a.clov, a.g.V2, i, w, y);
+      load_half<S, R>(a.in, 0, i, ps);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) ps[c] += y[c];
+      store_half<S, R>(a.out, 0, i, ps);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        f[k][c] = y[c] - uup[k][c];
+        uup[k][c] = y[6 + c];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) { f[k][c] = czero<R>(); uup[k][c] = czero<R>(); }
+    }
+  }
+  scan_core<R, CH, 6, true>(uup, lds, sc);   // T^-1 y_lo
+  scan_core<R, CH, 6, false>(f, lds, sc);    // T^dag^-1 (y_up - u_up)
   if (!sc.active) return;
 #pragma unroll
   for (int k = 0; k < CH; ++k) {
-    const int t = sc.t0 + k;
-    const int64_t i = (int64_t)t * a.g.Vs2 + s;
-    su3<R> w = load_su3<R, Lt>(a.w, i);
-    rotate<R, 6, false>(w, vb[k]);
-    rotate<R, 6, false>(w, vf[k]);
-    cx<R> x[12], y[12];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) { x[c] = vf[k][c]; x[6 + c] = vb[k][c] + pl[k][c]; }
-    clover_apply<R, Lt>(a.clov, a.g.V2, i, x, y);
-    store_spinor<S, R>(a.out, i, y);
-  }
-}
-
-// ILU step K2b (even parity): chi_e = psi_e + C_L y = (psi_up + y_up, psi_lo + T^-1 y_lo),
-//   n_e = C_R C_L (y - u) = (T^dag^-1 (y_up - u_up), T^-1 (y_lo - u_lo)).
-// in = psi_e, self = y, nb = u (same parity), out = chi_e, base = n_e.
-template <typename S, int CH>
-__global__ void __launch_bounds__(1024) k_ilu_k2b(LineArgs<S> a) {
-  using R = typename Prec<S>::R;
-  using Lt = typename Prec<S>::L;
-  extern __shared__ char smem_raw[];
-  cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
-  ScanCtx<R> sc = make_ctx<S>(a, CH);
-  const int s = sc.active ? sc.s : 0;
-  cx<R> vb[CH][12], vf[CH][6], pl[CH][6];
-#pragma unroll
-  for (int k = 0; k < CH; ++k) {
-    const int t = sc.t0 + k;
-    const int64_t i = (int64_t)t * a.g.Vs2 + s;
-    if (sc.active) {
-      cx<R> y[12], u[12], ps[6], o[6];
-      load_spinor<S, R>(a.self, i, y);
-      load_spinor<S, R>(a.nb, i, u);
-      load_half<S, R>(a.in, 0, i, ps);
-      load_half<S, R>(a.in, 1, i, pl[k]);
-#pragma unroll
-      for (int c = 0; c < 6; ++c) o[c] = ps[c] + y[c];
-      store_half<S, R>(a.out, 0, i, o);
-      su3<R> w = load_su3<R, Lt>(a.w, i);
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        vb[k][c] = y[6 + c];
-        vb[k][6 + c] = y[6 + c] - u[6 + c];
-        vf[k][c] = y[c] - u[c];
-      }
-      rotate<R, 12, true>(w, vb[k]);
-      rotate<R, 6, true>(w, vf[k]);
-    } else {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        vb[k][c] = czero<R>(); vb[k][6 + c] = czero<R>(); vf[k][c] = czero<R>(); pl[k][c] = czero<R>();
-      }
-    }
-  }
-  scan_core<R, CH, 12, true>(vb, lds, sc);
-  scan_core<R, CH, 6, false>(vf, lds, sc);
-  if (!sc.active) return;
-#pragma unroll
-  for (int k = 0; k < CH; ++k) {
-    const int t = sc.t0 + k;
-    const int64_t i = (int64_t)t * a.g.Vs2 + s;
-    su3<R> w = load_su3<R, Lt>(a.w, i);
-    rotate<R, 12, false>(w, vb[k]);
-    rotate<R, 6, false>(w, vf[k]);
-    cx<R> o[6], n[12];
+    const int64_t i = p3_idx(a.g, sc.t0 + k, s);
+    cx<R> pl[6], n[6];
+    load_half<S, R>(a.in, 1, i, pl);
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      o[c] = pl[k][c] + vb[k][c];
-      n[c] = vf[k][c];
-      n[6 + c] = vb[k][6 + c];
+      pl[c] += uup[k][c];
+      n[c] = uup[k][c] - b[k][c];
     }
-    store_half<S, R>(a.out, 1, i, o);
-    store_spinor<S, R>(a.base, i, n);
+    store_half<S, R>(a.out, 1, i, pl);
+    store_half<S, R>(a.base, 0, i, f[k]);
+    store_half<S, R>(a.base, 1, i, n);
   }
 }
 
@@ -443,15 +353,15 @@ struct Shape {
   int CH, NCH, LPB;
 };
 
-// Pick CH (time slices per thread) from `allowed`, NCH = Lt/CH chunks, and LPB lines so
-// that LPB * NCH <= max_threads with LPB as close to lpb_target as possible.
+// Pick CH (time slices per thread) from `allowed`, NCH = Lt/CH chunks, and LPB lines
+// (a multiple of the 4-line tile) so that LPB * NCH <= max_threads.
 Shape pick_shape(int Lt, int lpb_target, int max_threads, std::initializer_list<int> allowed) {
   for (int ch : allowed) {
     if (Lt % ch) continue;
     int nch = Lt / ch;
-    if (nch > max_threads) continue;
+    if (nch * kTile > max_threads) continue;
     int lpb = lpb_target;
-    while (lpb > 1 && lpb * nch > max_threads) lpb >>= 1;
+    while (lpb > kTile && lpb * nch > max_threads) lpb >>= 1;
     return Shape{ch, nch, lpb};
   }
   TP_THROW(TP_EDIMS, "time extent not supported by the line kernels");
@@ -463,17 +373,6 @@ LineArgs<S> base_args(tp_op op, int par) {
   const Lattice& L = ctx->lat;
   LineArgs<S> a{};
   using Lk = typename Prec<S>::L;
-  const Lk* w;
-  const Lk* u3;
-  if constexpr (sizeof(Lk) == 16) { w = (const Lk*)op->g->w_d; u3 = (const Lk*)op->g->u3_d; }
-  else { w = (const Lk*)op->g->w_f; u3 = (const Lk*)op->g->u3_f; }
-  a.w.p = w + (int64_t)par * 9 * L.V2;
-  a.w.stride = L.V2;
-  for (int p = 0; p < 2; ++p)
-    for (int d = 0; d < 4; ++d) {
-      a.u[p][d].p = u3 + (int64_t)(d * 2 + p) * 9 * L.V2;
-      a.u[p][d].stride = L.V2;
-    }
   a.clov = nullptr;
   if (op->c) {
     if constexpr (sizeof(Lk) == 16) a.clov = (const Lk*)op->c->a3_d + (int64_t)par * 36 * L.V2;
@@ -499,8 +398,6 @@ SpinorF<S> pv(const Field* f, int p) {
 
 template <typename S>
 constexpr int max_threads() { return sizeof(typename Prec<S>::R) == 8 ? 512 : 1024; }
-template <typename S>
-constexpr int lpb_target() { return sizeof(typename Prec<S>::R) == 8 ? 8 : 16; }
 
 template <typename S, typename K>
 void go(tp_op op, K kern, LineArgs<S>& a, Shape sh) {
@@ -525,148 +422,56 @@ void go(tp_op op, K kern, LineArgs<S>& a, Shape sh) {
   }
 
 template <typename S, int MODE>
-void line_plain_t(tp_op op, int par, const Field& src, Field& dst, bool pass) {
+void line_t(tp_op op, int par, const LineIO& io, Field& dst) {
   LineArgs<S> a = base_args<S>(op, par);
-  a.in = pv<S>(&src, par);
+  SpinorF<S> up = pv<S>(io.in_up, par), lo = pv<S>(io.in_lo, par);
+  a.in = up;
+  a.in.p[1] = lo.p[1];
+  a.in.nrm[1] = lo.nrm[1];
   a.out = pv<S>(&dst, par);
-  a.c_out = 1.0;
-  constexpr bool heavy = ModeT<MODE>::nb + ModeT<MODE>::nf > 6;
-  Shape sh = heavy ? pick_shape(op->g->ctx->lat.L[3], lpb_target<S>(), max_threads<S>(), {2, 1, 4})
-                   : pick_shape(op->g->ctx->lat.L[3], lpb_target<S>(), max_threads<S>(), {4, 2, 1});
-  if (pass) {
-    TP_CH_DISPATCH(sh.CH, go<S>(op, k_line<S, CH, MODE, false, false, false, false, true>, a, sh))
+  a.base = pv<S>(io.base, par);
+  a.c_out = io.c_out;
+  a.c_base = io.c_base;
+  Shape sh = pick_shape(op->g->ctx->lat.L[3], 16, max_threads<S>(), {1, 2, 4});
+  if (io.base) {
+    if (io.pass) { TP_CH_DISPATCH(sh.CH, go<S>(op, k_line<S, CH, MODE, true, true>, a, sh)) }
+    else { TP_CH_DISPATCH(sh.CH, go<S>(op, k_line<S, CH, MODE, true, false>, a, sh)) }
   } else {
-    TP_CH_DISPATCH(sh.CH, go<S>(op, k_line<S, CH, MODE, false, false, false, false, false>, a, sh))
+    if (io.pass) { TP_CH_DISPATCH(sh.CH, go<S>(op, k_line<S, CH, MODE, false, true>, a, sh)) }
+    else { TP_CH_DISPATCH(sh.CH, go<S>(op, k_line<S, CH, MODE, false, false>, a, sh)) }
   }
 }
 
 template <typename S>
-void line_plain_s(tp_op op, int mode, int par, const Field& src, Field& dst) {
+void line_s(tp_op op, int mode, int par, const LineIO& io, Field& dst) {
   switch (mode) {
-    case LM_CL: line_plain_t<S, LM_CL>(op, par, src, dst, src.data != dst.data); break;
-    case LM_CR: line_plain_t<S, LM_CR>(op, par, src, dst, src.data != dst.data); break;
-    case LM_CRCL: line_plain_t<S, LM_CRCL>(op, par, src, dst, src.data != dst.data); break;
-    case LM_TINV: line_plain_t<S, LM_TINV>(op, par, src, dst, src.data != dst.data); break;
-    default: line_plain_t<S, LM_TDINV>(op, par, src, dst, src.data != dst.data); break;
-  }
-}
-
-template <typename S, int MODE, bool CLOV, bool SELF, bool BASE>
-void line_sten_t4(tp_op op, LineArgs<S>& a, Shape sh) {
-  TP_CH_DISPATCH(sh.CH, go<S>(op, k_line<S, CH, MODE, true, CLOV, SELF, BASE, true>, a, sh))
-}
-
-template <typename S, int MODE>
-void line_sten_t(tp_op op, int par, const LineStencilArgs& s, Field& dst) {
-  const Lattice& L = op->g->ctx->lat;
-  LineArgs<S> a = base_args<S>(op, par);
-  SpinorF<S> up = pv<S>(s.nb_up, 1 - par), lo = pv<S>(s.nb_lo, 1 - par);
-  a.nb = up;
-  a.nb.p[1] = lo.p[1];
-  a.nb.nrm[1] = lo.nrm[1];
-  a.self = pv<S>(s.self, par);
-  a.base = pv<S>(s.base, par);
-  a.out = pv<S>(&dst, par);
-  a.c_s = s.c_s;
-  a.c_A = s.c_A;
-  a.c_self = s.c_self;
-  a.c_out = s.c_out;
-  a.c_base = s.c_base;
-  bool clov = s.self && s.c_A != 0.0 && a.clov != nullptr;
-  bool self = s.self && s.c_self != 0.0;
-  bool base = s.base != nullptr;
-  Shape sh = pick_shape(L.L[3], lpb_target<S>(), max_threads<S>(), {2, 1, 4});
-  if (clov) {
-    if (base) line_sten_t4<S, MODE, true, false, true>(op, a, sh);
-    else line_sten_t4<S, MODE, true, false, false>(op, a, sh);
-  } else if (self) {
-    if (base) line_sten_t4<S, MODE, false, true, true>(op, a, sh);
-    else line_sten_t4<S, MODE, false, true, false>(op, a, sh);
-  } else {
-    if (base) line_sten_t4<S, MODE, false, false, true>(op, a, sh);
-    else line_sten_t4<S, MODE, false, false, false>(op, a, sh);
+    case LM_CL: line_t<S, LM_CL>(op, par, io, dst); break;
+    case LM_CR: line_t<S, LM_CR>(op, par, io, dst); break;
+    case LM_CRCL: line_t<S, LM_CRCL>(op, par, io, dst); break;
+    case LM_TINV: line_t<S, LM_TINV>(op, par, io, dst); break;
+    default: line_t<S, LM_TDINV>(op, par, io, dst); break;
   }
 }
 
 template <typename S>
-void line_sten_s(tp_op op, int mode, int par, const LineStencilArgs& s, Field& dst) {
-  switch (mode) {
-    case LM_CL: line_sten_t<S, LM_CL>(op, par, s, dst); break;
-    case LM_CR: line_sten_t<S, LM_CR>(op, par, s, dst); break;
-    case LM_CRCL: line_sten_t<S, LM_CRCL>(op, par, s, dst); break;
-    default: TP_THROW(TP_EINVAL, "stencil line mode");
-  }
-}
-
-template <typename S>
-void k2a_t(tp_op op, const Field& psi, const Field& aup, Field& y, Field& u) {
-  const Lattice& L = op->g->ctx->lat;
-  LineArgs<S> a = base_args<S>(op, 0);
-  SpinorF<S> up = pv<S>(&aup, 1), lo = pv<S>(&psi, 1);
-  a.nb = up;
-  a.nb.p[1] = lo.p[1];
-  a.nb.nrm[1] = lo.nrm[1];
-  a.in = pv<S>(&psi, 0);
-  a.out = pv<S>(&y, 0);
-  a.base = pv<S>(&u, 0);
-  a.c_s = 1.0 / op->gf;
-  Shape sh = pick_shape(L.L[3], lpb_target<S>(), max_threads<S>(), {2, 1, 4});
-  TP_CH_DISPATCH(sh.CH, go<S>(op, k_ilu_k2a<S, CH>, a, sh))
-}
-
-template <typename S>
-void k2b_t(tp_op op, const Field& psi, const Field& y, const Field& u, Field& chi, Field& n) {
+void mid_t(tp_op op, const Field& psi, const Field& u, Field& chi, Field& n) {
   const Lattice& L = op->g->ctx->lat;
   LineArgs<S> a = base_args<S>(op, 0);
   a.in = pv<S>(&psi, 0);
-  a.self = pv<S>(&y, 0);
-  a.nb = pv<S>(&u, 0);
+  a.aux = pv<S>(&u, 0);
   a.out = pv<S>(&chi, 0);
   a.base = pv<S>(&n, 0);
-  Shape sh = pick_shape(L.L[3], lpb_target<S>(), max_threads<S>(), {2, 1, 4});
-  TP_CH_DISPATCH(sh.CH, go<S>(op, k_ilu_k2b<S, CH>, a, sh))
-}
-
-
-template <typename S>
-void k3_t(tp_op op, const Field& psi, const Field& aup, const Field& n, Field& chi) {
-  const Lattice& L = op->g->ctx->lat;
-  LineArgs<S> a = base_args<S>(op, 1);
-  a.nb = pv<S>(&n, 0);
-  a.self = pv<S>(&psi, 1);
-  SpinorF<S> au = pv<S>(&aup, 1);
-  a.self.p[0] = au.p[0];
-  a.self.nrm[0] = au.nrm[0];
-  a.base = pv<S>(&psi, 1);
-  a.out = pv<S>(&chi, 1);
-  a.c_s = 1.0 / op->gf;
-  a.c_A = 1;
-  a.c_out = 1;
-  a.c_base = 1;
-  Shape sh = pick_shape(L.L[3], lpb_target<S>(), max_threads<S>(), {2, 1, 4});
-  if (op->c) line_sten_t4<S, LM_CL, true, false, true>(op, a, sh);
-  else line_sten_t4<S, LM_CL, false, false, true>(op, a, sh);
+  Shape sh = pick_shape(L.L[3], 16, max_threads<S>(), {1, 2, 4});
+  TP_CH_DISPATCH(sh.CH, go<S>(op, k_ilu_mid<S, CH>, a, sh))
 }
 
 }  // namespace
 
 #define TP_CAT2(a, b) a##b
 #define TP_CAT(a, b) TP_CAT2(a, b)
-void TP_CAT(line_plain_, TP_LINE_SUFFIX)(tp_op op, int mode, int par, const Field& src, Field& dst) {
-  line_plain_s<TP_LINE_S>(op, mode, par, src, dst);
+void TP_CAT(line_, TP_LINE_SUFFIX)(tp_op op, int mode, int par, const LineIO& io, Field& dst) {
+  line_s<TP_LINE_S>(op, mode, par, io, dst);
 }
-void TP_CAT(line_half_cr_, TP_LINE_SUFFIX)(tp_op op, const Field& src, Field& dst) {
-  line_plain_t<TP_LINE_S, LM_CR>(op, 1, src, dst, false);
-}
-void TP_CAT(line_sten_, TP_LINE_SUFFIX)(tp_op op, int mode, int par, const LineStencilArgs& s, Field& dst) {
-  line_sten_s<TP_LINE_S>(op, mode, par, s, dst);
-}
-void TP_CAT(ilu_k2a_, TP_LINE_SUFFIX)(tp_op op, const Field& psi, const Field& aup, Field& y, Field& u) {
-  k2a_t<TP_LINE_S>(op, psi, aup, y, u);
-}
-void TP_CAT(ilu_k2b_, TP_LINE_SUFFIX)(tp_op op, const Field& psi, const Field& y, const Field& u, Field& chi, Field& n) {
-  k2b_t<TP_LINE_S>(op, psi, y, u, chi, n);
-}
-void TP_CAT(ilu_k3_, TP_LINE_SUFFIX)(tp_op op, const Field& psi, const Field& aup, const Field& n, Field& chi) {
-  k3_t<TP_LINE_S>(op, psi, aup, n, chi);
+void TP_CAT(ilu_mid_, TP_LINE_SUFFIX)(tp_op op, const Field& psi, const Field& u, Field& chi, Field& n) {
+  mid_t<TP_LINE_S>(op, psi, u, chi, n);
 }

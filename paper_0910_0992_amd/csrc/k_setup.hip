@@ -24,13 +24,33 @@ TP_DEV void site_pi(const Geom& g, bool l4, int x, int y, int z, int t, int& p, 
     i = (f3 + (int64_t)g.Lx * g.Ly * g.Lz * t) >> 1;
   } else {
     p = (x + y + z) & 1;
-    i = (int64_t)t * g.Vs2 + (f3 >> 1);
+    i = p3_idx(g, t, int(f3 >> 1));
+  }
+}
+
+// psi(colour) <- W^dag psi (to_axial) or W psi (from the axial frame), all four spins, FP64.
+TP_DEV void rotate_spinor(const double2* __restrict__ w, int p, int64_t i, int64_t V2, bool dag,
+                          cx<double>* v) {
+  const double2* b = w + (int64_t)p * 9 * V2 + i;
+  su3<double> W;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    double2 e = b[(int64_t)k * V2];
+    W.e[k] = cx<double>{e.x, e.y};
+  }
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp) {
+    cx<double> o[3];
+    if (dag) mvd(W, v + 3 * sp, o);
+    else mv(W, v + 3 * sp, o);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[3 * sp + c] = o[c];
   }
 }
 
 template <typename S>
 __global__ void k_pack(const double2* __restrict__ canon, SpinorF<S> f0, SpinorF<S> f1, Geom g,
-                       int64_t V, bool l4, bool g5) {
+                       int64_t V, bool l4, bool g5, const double2* __restrict__ w) {
   using R = typename Prec<S>::R;
   int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= V) return;
@@ -39,13 +59,14 @@ __global__ void k_pack(const double2* __restrict__ canon, SpinorF<S> f0, SpinorF
   int p;
   int64_t i;
   site_pi(g, l4, x, y, z, t, p, i);
-  cx<R> v[12];
+  cx<double> d[12];
   const double2* src = canon + n * 12;
 #pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    double2 d = src[c];
-    v[c] = cx<R>{R(d.x), R(d.y)};
-  }
+  for (int c = 0; c < 12; ++c) d[c] = cx<double>{src[c].x, src[c].y};
+  if (w) rotate_spinor(w, p, i, g.V2, true, d);
+  cx<R> v[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = cx<R>{R(d[c].re), R(d[c].im)};
   if (g5) {  // gamma5 = [[0,-1],[-1,0]] in the Dirac-Pauli basis
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
@@ -59,7 +80,7 @@ __global__ void k_pack(const double2* __restrict__ canon, SpinorF<S> f0, SpinorF
 
 template <typename S>
 __global__ void k_unpack(double2* __restrict__ canon, SpinorF<S> f0, SpinorF<S> f1, Geom g,
-                         int64_t V, bool l4, bool g5) {
+                         int64_t V, bool l4, bool g5, const double2* __restrict__ w) {
   using R = typename Prec<S>::R;
   int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= V) return;
@@ -78,28 +99,30 @@ __global__ void k_unpack(double2* __restrict__ canon, SpinorF<S> f0, SpinorF<S> 
       v[6 + c] = -a;
     }
   }
+  cx<double> d[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) d[c] = cx<double>{double(v[c].re), double(v[c].im)};
+  if (w) rotate_spinor(w, p, i, g.V2, false, d);
   double2* dst = canon + n * 12;
 #pragma unroll
-  for (int c = 0; c < 12; ++c) dst[c] = make_double2(double(v[c].re), double(v[c].im));
+  for (int c = 0; c < 12; ++c) dst[c] = make_double2(d[c].re, d[c].im);
 }
 
-// links: canon [4][V][9] -> p3 FP64/FP32 and p4 FP64, phase b folded into U_t(Lt-1)
-__global__ void k_pack_links(const double2* __restrict__ canon, double2* u3d, float2* u3f,
-                             double2* u4d, float2* u4f, Geom g, int64_t V, double b) {
+// links: canon [4][V][9] -> p4 FP64/FP32 (the 4D even-odd baseline), phase b folded
+// into U_t(Lt-1)
+__global__ void k_pack_links4(const double2* __restrict__ canon, double2* u4d, float2* u4f, Geom g,
+                              int64_t V, double b) {
   int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int mu = blockIdx.y;
   if (n >= V) return;
   int x, y, z, t;
   canon_coords(n, g, x, y, z, t);
   double ph = (mu == 3 && t == g.Lt - 1) ? b : 1.0;
-  int p3, p4;
-  int64_t i3, i4;
-  site_pi(g, false, x, y, z, t, p3, i3);
+  int p4;
+  int64_t i4;
   site_pi(g, true, x, y, z, t, p4, i4);
   const double2* src = canon + ((int64_t)mu * V + n) * 9;
   int64_t V2 = V / 2;
-  double2* d3 = u3d + ((int64_t)(mu * 2 + p3) * 9) * V2 + i3;
-  float2* f3 = u3f + ((int64_t)(mu * 2 + p3) * 9) * V2 + i3;
   double2* d4 = u4d + ((int64_t)(mu * 2 + p4) * 9) * V2 + i4;
   float2* f4 = u4f + ((int64_t)(mu * 2 + p4) * 9) * V2 + i4;
 #pragma unroll
@@ -107,8 +130,6 @@ __global__ void k_pack_links(const double2* __restrict__ canon, double2* u3d, fl
     double2 e = src[k];
     e.x *= ph;
     e.y *= ph;
-    d3[(int64_t)k * V2] = e;
-    f3[(int64_t)k * V2] = make_float2(float(e.x), float(e.y));
     d4[(int64_t)k * V2] = e;
     f4[(int64_t)k * V2] = make_float2(float(e.x), float(e.y));
   }
@@ -126,38 +147,81 @@ TP_DEV void mm3(const cx<double>* a, const cx<double>* b, cx<double>* c) {
     }
 }
 
-// W(t) = U'(t) U'(t+1) ... U'(Lt-1) per time line (U' has the phase folded in).
-// One thread per line: an Lt-step product, run once per gauge field.
-__global__ void k_wline(const double2* __restrict__ u3d, double2* wd, float2* wf, double2* poly,
-                        Geom g) {
+// W(t) = U'(t) U'(t+1) ... U'(Lt-1) per time line, U' the time links with the phase b
+// folded into U'(Lt-1).  One thread per line: an Lt-step product, run once per gauge field.
+__global__ void k_wline(const double2* __restrict__ canon, double2* wd, double2* poly, Geom g,
+                        int64_t V, double b) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   int p = blockIdx.y;
   if (s >= g.Vs2) return;
   int64_t V2 = g.V2;
-  const double2* ut = u3d + ((int64_t)(3 * 2 + p) * 9) * V2;
+  C3 q = p3_coords(g, p, s);
+  int64_t f3 = (int64_t)q.x + (int64_t)g.Lx * (q.y + (int64_t)g.Ly * q.z);
+  int64_t Vs = (int64_t)g.Lx * g.Ly * g.Lz;
   double2* w = wd + (int64_t)p * 9 * V2;
-  float2* w32 = wf + (int64_t)p * 9 * V2;
   cx<double> acc[9], u[9], nw[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) acc[k] = cx<double>{(k % 4 == 0) ? 1.0 : 0.0, 0.0};
   for (int t = g.Lt - 1; t >= 0; --t) {
-    int64_t i = (int64_t)t * g.Vs2 + s;
+    int64_t i = p3_idx(g, t, s);
+    const double2* src = canon + ((int64_t)3 * V + f3 + Vs * t) * 9;
+    double ph = t == g.Lt - 1 ? b : 1.0;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      double2 e = ut[(int64_t)k * V2 + i];
-      u[k] = cx<double>{e.x, e.y};
-    }
+    for (int k = 0; k < 9; ++k) u[k] = cx<double>{ph * src[k].x, ph * src[k].y};
     mm3(u, acc, nw);
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       acc[k] = nw[k];
       w[(int64_t)k * V2 + i] = make_double2(nw[k].re, nw[k].im);
-      w32[(int64_t)k * V2 + i] = make_float2(float(nw[k].re), float(nw[k].im));
     }
   }
   double2* pl = poly + (int64_t)p * 9 * g.Vs2;
 #pragma unroll
   for (int k = 0; k < 9; ++k) pl[(int64_t)k * g.Vs2 + s] = make_double2(acc[k].re, acc[k].im);
+}
+
+// Axial-gauge links U^ax_mu(x) = W(x)^dag U'_mu(x) W(x+mu) with Omega = W^dag (Sec. II.C,
+// App. C): every time link becomes the identity except U^ax_t(Lt-1) = W(0) = P.
+// Writes the p3 layout (F64, F32) and a canonical copy for the clover build.
+__global__ void k_axial_links(const double2* __restrict__ canon, const double2* __restrict__ wd,
+                              double2* u3d, float2* u3f, double2* canon_ax, Geom g, int64_t V,
+                              double b) {
+  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int mu = blockIdx.y;
+  if (n >= V) return;
+  int x, y, z, t;
+  canon_coords(n, g, x, y, z, t);
+  int xs[4] = {x, y, z, t};
+  int ls[4] = {g.Lx, g.Ly, g.Lz, g.Lt};
+  xs[mu] = xs[mu] + 1 == ls[mu] ? 0 : xs[mu] + 1;
+  int pa, pb;
+  int64_t ia, ib;
+  site_pi(g, false, x, y, z, t, pa, ia);
+  site_pi(g, false, xs[0], xs[1], xs[2], xs[3], pb, ib);
+  int64_t V2 = V / 2;
+  cx<double> U[9], Wa[9], Wb[9], T1[9], T2[9];
+  double ph = (mu == 3 && t == g.Lt - 1) ? b : 1.0;
+  const double2* src = canon + ((int64_t)mu * V + n) * 9;
+  for (int k = 0; k < 9; ++k) {
+    U[k] = cx<double>{ph * src[k].x, ph * src[k].y};
+    double2 ea = wd[((int64_t)pa * 9 + k) * V2 + ia];
+    double2 eb = wd[((int64_t)pb * 9 + k) * V2 + ib];
+    Wa[k] = cx<double>{ea.x, -ea.y};  // conj, transposed below
+    Wb[k] = cx<double>{eb.x, eb.y};
+  }
+  cx<double> Wad[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) Wad[3 * r + c] = Wa[3 * c + r];
+  mm3(Wad, U, T1);
+  mm3(T1, Wb, T2);
+  double2* d3 = u3d + ((int64_t)(mu * 2 + pa) * 9) * V2 + ia;
+  float2* f3 = u3f + ((int64_t)(mu * 2 + pa) * 9) * V2 + ia;
+  double2* ca = canon_ax + ((int64_t)mu * V + n) * 9;
+  for (int k = 0; k < 9; ++k) {
+    d3[(int64_t)k * V2] = make_double2(T2[k].re, T2[k].im);
+    f3[(int64_t)k * V2] = make_float2(float(T2[k].re), float(T2[k].im));
+    ca[k] = make_double2(T2[k].re, T2[k].im);
+  }
 }
 
 TP_DEV bool inv3(const cx<double>* m, cx<double>* r) {
@@ -336,10 +400,10 @@ __global__ void k_clover_build(const double2* __restrict__ canon, double2* a3d, 
   site_pi(g, true, x, y, z, t, p4, i4);
   int64_t V2 = V / 2;
   for (int c = 0; c < 2; ++c) {
-    double2* d3 = a3d + ((int64_t)p3 * 36 + 18 * c) * V2;
-    float2* f3 = a3f + ((int64_t)p3 * 36 + 18 * c) * V2;
-    double2* d4 = a4d + ((int64_t)p4 * 36 + 18 * c) * V2;
-    float2* f4 = a4f + ((int64_t)p4 * 36 + 18 * c) * V2;
+    double2* d3 = a3d ? a3d + ((int64_t)p3 * 36 + 18 * c) * V2 : nullptr;
+    float2* f3 = a3f ? a3f + ((int64_t)p3 * 36 + 18 * c) * V2 : nullptr;
+    double2* d4 = a4d ? a4d + ((int64_t)p4 * 36 + 18 * c) * V2 : nullptr;
+    float2* f4 = a4f ? a4f + ((int64_t)p4 * 36 + 18 * c) * V2 : nullptr;
     store_herm6(B[c], d3, f3, V2, i3, d4, i4, f4);
   }
 }
@@ -471,51 +535,58 @@ __global__ void k_plaquette(const double2* __restrict__ canon, Geom g, int64_t V
 inline unsigned nblk(int64_t n, int64_t b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
 template <typename S>
-void pack_t(tp_ctx ctx, const double2* canon, Field& dst, bool l4, bool g5) {
+void pack_t(tp_ctx ctx, const double2* canon, Field& dst, bool l4, bool g5, const double2* w) {
   const Lattice& L = ctx->lat;
   hipLaunchKernelGGL(k_pack<S>, dim3(nblk(L.V)), dim3(kBlock), 0, ctx->stream, canon,
-                     dst.template par<S>(0), dst.template par<S>(1), L.g, L.V, l4, g5);
+                     dst.template par<S>(0), dst.template par<S>(1), L.g, L.V, l4, g5, w);
   LAUNCH_CHECK();
 }
 template <typename S>
-void unpack_t(tp_ctx ctx, const Field& src, double2* canon, bool l4, bool g5) {
+void unpack_t(tp_ctx ctx, const Field& src, double2* canon, bool l4, bool g5, const double2* w) {
   const Lattice& L = ctx->lat;
   hipLaunchKernelGGL(k_unpack<S>, dim3(nblk(L.V)), dim3(kBlock), 0, ctx->stream, canon,
-                     src.template par<S>(0), src.template par<S>(1), L.g, L.V, l4, g5);
+                     src.template par<S>(0), src.template par<S>(1), L.g, L.V, l4, g5, w);
   LAUNCH_CHECK();
 }
 
 }  // namespace
 
-void launch_pack(tp_ctx ctx, const double2* canon, Field& dst, bool l4, bool g5) {
-  ProfScope ps(ctx, KID_PACK, double(ctx->lat.V) * (192 + 12 * dst.elem_bytes()));
+void launch_pack(tp_ctx ctx, const double2* canon, Field& dst, bool l4, bool g5, const double2* w) {
+  ProfScope ps(ctx, KID_PACK, double(ctx->lat.V) * (192 + 12 * dst.elem_bytes() + (w ? 144 : 0)));
   switch (dst.prec) {
-    case TP_F64: pack_t<double2>(ctx, canon, dst, l4, g5); break;
-    case TP_F32: pack_t<float2>(ctx, canon, dst, l4, g5); break;
-    default: pack_t<__half2>(ctx, canon, dst, l4, g5); break;
+    case TP_F64: pack_t<double2>(ctx, canon, dst, l4, g5, w); break;
+    case TP_F32: pack_t<float2>(ctx, canon, dst, l4, g5, w); break;
+    default: pack_t<__half2>(ctx, canon, dst, l4, g5, w); break;
   }
 }
 
-void launch_unpack(tp_ctx ctx, const Field& src, double2* canon, bool l4, bool g5) {
-  ProfScope ps(ctx, KID_PACK, double(ctx->lat.V) * (192 + 12 * src.elem_bytes()));
+void launch_unpack(tp_ctx ctx, const Field& src, double2* canon, bool l4, bool g5, const double2* w) {
+  ProfScope ps(ctx, KID_PACK, double(ctx->lat.V) * (192 + 12 * src.elem_bytes() + (w ? 144 : 0)));
   switch (src.prec) {
-    case TP_F64: unpack_t<double2>(ctx, src, canon, l4, g5); break;
-    case TP_F32: unpack_t<float2>(ctx, src, canon, l4, g5); break;
-    default: unpack_t<__half2>(ctx, src, canon, l4, g5); break;
+    case TP_F64: unpack_t<double2>(ctx, src, canon, l4, g5, w); break;
+    case TP_F32: unpack_t<float2>(ctx, src, canon, l4, g5, w); break;
+    default: unpack_t<__half2>(ctx, src, canon, l4, g5, w); break;
   }
 }
 
 void launch_pack_links(tp_ctx ctx, tp_gauge g) {
   const Lattice& L = ctx->lat;
-  hipLaunchKernelGGL(k_pack_links, dim3(nblk(L.V), 4), dim3(kBlock), 0, ctx->stream, g->canon,
-                     g->u3_d, g->u3_f, g->u4_d, g->u4_f, L.g, L.V, double(ctx->bc));
+  hipLaunchKernelGGL(k_pack_links4, dim3(nblk(L.V), 4), dim3(kBlock), 0, ctx->stream, g->canon,
+                     g->u4_d, g->u4_f, L.g, L.V, double(ctx->bc));
   LAUNCH_CHECK();
 }
 
 void launch_wline(tp_ctx ctx, tp_gauge g) {
   const Lattice& L = ctx->lat;
-  hipLaunchKernelGGL(k_wline, dim3((L.Vs2 + 63) / 64, 2), dim3(64), 0, ctx->stream, g->u3_d,
-                     g->w_d, g->w_f, g->poly, L.g);
+  hipLaunchKernelGGL(k_wline, dim3((L.Vs2 + 63) / 64, 2), dim3(64), 0, ctx->stream, g->canon,
+                     g->w_d, g->poly, L.g, L.V, double(ctx->bc));
+  LAUNCH_CHECK();
+}
+
+void launch_axial_links(tp_ctx ctx, tp_gauge g) {
+  const Lattice& L = ctx->lat;
+  hipLaunchKernelGGL(k_axial_links, dim3(nblk(L.V, 64), 4), dim3(64), 0, ctx->stream, g->canon,
+                     g->w_d, g->u3_d, g->u3_f, g->canon_ax, L.g, L.V, double(ctx->bc));
   LAUNCH_CHECK();
 }
 
@@ -528,14 +599,19 @@ void launch_closure(tp_ctx ctx, tp_op op, double* cond) {
 }
 
 void launch_clover_build(tp_ctx ctx, tp_clover c, const double sig[6][2][2][2][2]) {
+  // p3 blocks from the axial-gauge links (the frame of every p3 operator), p4 blocks
+  // from the original links (the 4D even-odd baseline)
   const Lattice& L = ctx->lat;
   SigTab t;
   for (int p = 0; p < 6; ++p)
     for (int ch = 0; ch < 2; ++ch)
       for (int r = 0; r < 2; ++r)
         for (int q = 0; q < 2; ++q) t.s[p][ch][r][q] = make_double2(sig[p][ch][r][q][0], sig[p][ch][r][q][1]);
+  hipLaunchKernelGGL(k_clover_build, dim3(nblk(L.V, 64)), dim3(64), 0, ctx->stream, c->g->canon_ax,
+                     c->a3_d, c->a3_f, (double2*)nullptr, (float2*)nullptr, L.g, L.V, t);
+  LAUNCH_CHECK();
   hipLaunchKernelGGL(k_clover_build, dim3(nblk(L.V, 64)), dim3(64), 0, ctx->stream, c->g->canon,
-                     c->a3_d, c->a3_f, c->a4_d, c->a4_f, L.g, L.V, t);
+                     (double2*)nullptr, (float2*)nullptr, c->a4_d, c->a4_f, L.g, L.V, t);
   LAUNCH_CHECK();
 }
 

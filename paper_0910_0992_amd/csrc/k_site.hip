@@ -11,7 +11,9 @@ constexpr int kBlock = 256;
 
 template <typename S>
 struct SiteArgsP3 {
-  SpinorF<S> src[2], dst[2], in2[2];
+  // for output parity p: self[p] (parity p operand of mu, A, D_t), nb[p] (parity 1-p
+  // operand of D_s), in2[p]
+  SpinorF<S> self[2], nb[2], dst[2], in2[2];
   LinkF<typename Prec<S>::L> u[2][4];  // [parity][direction]
   const typename Prec<S>::L* clov[2];
   double c_mu, c_A, c_t, c_s, c_in;
@@ -31,14 +33,14 @@ __global__ void __launch_bounds__(kBlock) k_site_p3(SiteArgsP3<S> a) {
        n += (int64_t)gridDim.x * blockDim.x) {
     int p = a.par0 + int(n / a.g.V2);
     int64_t i = n % a.g.V2;
-    int t = int(i / a.g.Vs2);
-    int s = int(i % a.g.Vs2);
+    int t, s;
+    p3_ts(a.g, i, t, s);
     cx<R> out[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) out[c] = czero<R>();
     if (a.c_mu != 0.0 || CLOV) {
       cx<R> psi[12];
-      load_spinor<S, R>(a.src[p], i, psi);
+      load_spinor<S, R>(a.self[p], i, psi);
       R cm = R(a.c_mu);
 #pragma unroll
       for (int c = 0; c < 12; ++c) out[c] = cm * psi[c];
@@ -51,10 +53,10 @@ __global__ void __launch_bounds__(kBlock) k_site_p3(SiteArgsP3<S> a) {
       }
     }
     if constexpr (DT) {
-      hop_time_p3<S, R, Lt>(a.src[p], a.u[p][3], a.g, t, s, R(a.c_t), out);
+      hop_time_p3<S, R, Lt>(a.self[p], a.u[p][3], a.g, t, s, R(a.c_t), out);
     }
     if constexpr (DS) {
-      hop_space_p3<S, R, Lt>(a.src[1 - p], a.u[p], a.u[1 - p], a.g, p, t, s, R(0.5 * a.c_s), out);
+      hop_space_p3<S, R, Lt>(a.nb[p], a.u[p], a.u[1 - p], a.g, p, t, s, R(0.5 * a.c_s), out);
     }
     if constexpr (IN2) {
       cx<R> e[12];
@@ -174,7 +176,7 @@ __global__ void k_force(SpinorF<double2> x0, SpinorF<double2> x1, SpinorF<double
   xs[mu] = xs[mu] + 1 == ls[mu] ? 0 : xs[mu] + 1;
   auto p3 = [&](int X, int Y, int Z, int T, int& p, int64_t& i) {
     p = (X + Y + Z) & 1;
-    i = (int64_t)T * g.Vs2 + ((X + g.Lx * (Y + g.Ly * Z)) >> 1);
+    i = p3_idx(g, T, (X + g.Lx * (Y + g.Ly * Z)) >> 1);
   };
   int pa, pb;
   int64_t ia, ib;
@@ -301,13 +303,23 @@ void site_in2(tp_op op, SiteArgsP3<S>& a, int64_t nb, bool in2, bool norm) {
 }
 
 template <typename S>
-int site_t(tp_op op, const Field& src, Field& dst, const Field* in2, SiteCoef cf, int ck, int par0,
-           int npar, bool norm) {
+SpinorF<S> halves(const Field* up, const Field* lo, int p) {
+  SpinorF<S> a = view<S>(up, p), b = view<S>(lo, p);
+  a.p[1] = b.p[1];
+  a.nrm[1] = b.nrm[1];
+  if (!up) a.stride = b.stride;
+  return a;
+}
+
+template <typename S>
+int site_t(tp_op op, const SiteIO& io, Field& dst, SiteCoef cf, int ck, int par0, int npar, bool norm) {
   tp_ctx ctx = op->g->ctx;
   const Lattice& L = ctx->lat;
+  const Field* in2 = io.in2;
   SiteArgsP3<S> a;
   for (int p = 0; p < 2; ++p) {
-    a.src[p] = view<S>(&src, p);
+    a.self[p] = halves<S>(io.self_up, io.self_lo, p);
+    a.nb[p] = halves<S>(io.nb_up, io.nb_lo, 1 - p);
     a.dst[p] = view<S>(&dst, p);
     a.in2[p] = view<S>(in2, p);
   }
@@ -379,20 +391,30 @@ void schur4d_t(tp_op op, int mode, int p, const Field* src, Field& dst, const Fi
 
 }  // namespace
 
-int launch_site_p3(tp_op op, int prec, const Field& src, Field& dst, const Field* in2, SiteCoef cf,
-                   int ck, int par0, int npar, bool norm) {
+int launch_site(tp_op op, int prec, const SiteIO& io, Field& dst, SiteCoef cf, int ck, int par0,
+                int npar, bool norm) {
   tp_ctx ctx = op->g->ctx;
   const Lattice& L = ctx->lat;
-  double S = double(src.elem_bytes()) * 12;
-  double Lb = prec == TP_F64 ? 144 : 72;
-  double bytes = double(npar) * L.V2 * (2 * S + (cf.c_s != 0 ? S + 6 * Lb : 0) +
-                                        (cf.c_t != 0 ? 2 * Lb : 0) + (ck ? 4 * Lb : 0) + (in2 ? S : 0));
-  ProfScope ps(ctx, KID_SITE_P3, bytes);
+  double S = spinor_bytes(prec), Lb = link_bytes(prec), C = clov_bytes(prec);
+  bool self = cf.c_mu != 0 || (ck && cf.c_A != 0);
+  double bytes = double(npar) * L.V2 *
+                 (S + (self ? S : 0) + (cf.c_s != 0 ? S + 6 * Lb : 0) + (cf.c_t != 0 ? S + 2 * Lb : 0) +
+                  (ck && cf.c_A != 0 ? C : 0) + (io.in2 ? S : 0));
+  // the time-line pipeline's stencils are accounted separately from M / residual applies
+  ProfScope ps(ctx, cf.c_t != 0 || io.in2 ? KID_SITE_P3 : KID_HOP, bytes);
   switch (prec) {
-    case TP_F64: return site_t<double2>(op, src, dst, in2, cf, ck, par0, npar, norm);
-    case TP_F32: return site_t<float2>(op, src, dst, in2, cf, ck, par0, npar, norm);
-    default: return site_t<__half2>(op, src, dst, in2, cf, ck, par0, npar, norm);
+    case TP_F64: return site_t<double2>(op, io, dst, cf, ck, par0, npar, norm);
+    case TP_F32: return site_t<float2>(op, io, dst, cf, ck, par0, npar, norm);
+    default: return site_t<__half2>(op, io, dst, cf, ck, par0, npar, norm);
   }
+}
+
+int launch_site_p3(tp_op op, int prec, const Field& src, Field& dst, const Field* in2, SiteCoef cf,
+                   int ck, int par0, int npar, bool norm) {
+  SiteIO io;
+  io.self_up = io.self_lo = io.nb_up = io.nb_lo = &src;
+  io.in2 = in2;
+  return launch_site(op, prec, io, dst, cf, ck, par0, npar, norm);
 }
 
 void launch_schur4d(tp_op op, int prec, int mode, int p, const Field* src, Field& dst, const Field* in2,

@@ -6,14 +6,16 @@
 //   TEMPORAL        Mt = C_L M C_R = 1 + C_L (A - D_s/gamma_f) C_R   (eq:ContaminatedUnprec)
 //   TEMPORAL_SCHUR  p3 parity: Mt3 = S_L M S_R.  Wilson: diag(1, 1 - Dbar^oe Dbar^eo/gamma_f^2)
 //                   (eq:TPrecFull); clover: eq:TPrecPartial (3D ILU), applied as
-//                     a_o  = C_R^o psi_o                                  (K1)
-//                     u    = D_s^eo a_o / gamma_f                          (K2a)
-//                     y    = A^ee C_R^e (C_L^e u + psi_e)                  (K2a)
-//                     chi_e = psi_e + C_L^e y                              (K2b)
-//                     n_e  = C_R^e C_L^e (y - u)                           (K2b)
-//                     chi_o = psi_o + C_L^o [A^oo a_o + D_s^oe n_e / gamma_f]  (K3)
+//                     a_o   = C_R^o psi_o                          (scan, upper half only)
+//                     u     = D_s^eo a_o / gamma_f                 (site hop)
+//                     y     = A^ee C_R^e (C_L^e u + psi_e)         \
+//                     chi_e = psi_e + C_L^e y                      } (fused scans + clover)
+//                     n_e   = C_R^e C_L^e (y - u)                  /
+//                     v     = A^oo a_o + D_s^oe n_e / gamma_f      (site hop + clover)
+//                     chi_o = psi_o + C_L^o v                      (scan)
 //                   which is the appendix's ILU sequence with t1 = C_L u, t2 = C_L y,
 //                   C_R(t2 - t1) = C_R C_L (y - u) and the Dbar/Abar products expanded.
+// All p3 operators act in the axial gauge (interior time links = 1), see k_line_impl.h.
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -50,7 +52,7 @@ namespace {
 
 // workspace slot numbers
 enum {
-  W_T1 = 0, W_T2, W_T3, W_T4, W_G5A, W_G5B, W_PREP,
+  W_T1 = 0, W_T2, W_T3, W_T4, W_G5A, W_G5B, W_PREP, W_PREP2,
   // solver vectors
   W_R = 16, W_RHAT, W_P, W_V, W_S, W_T, W_X, W_B, W_Y, W_Z, W_D,
   W_X64 = 40, W_R64, W_ETA64, W_TMP64
@@ -69,54 +71,62 @@ void schur4d_odd(tp_op op, int prec, const Field& src, Field& dst) {
   launch_schur4d(op, prec, 1, 1, &t, dst, &src, -1.0, 0.0, 2);
 }
 
+LineIO lio(const Field* in, const Field* base = nullptr, bool pass = true) {
+  LineIO io;
+  io.in_up = io.in_lo = in;
+  io.base = base;
+  io.pass = pass;
+  return io;
+}
+SiteIO sio_nb(const Field* nb_up, const Field* nb_lo) {
+  SiteIO io;
+  io.nb_up = nb_up;
+  io.nb_lo = nb_lo;
+  return io;
+}
+
 // Wilson S_o on the odd p3 parity: dst_o = src_o - C_L D_s (C_R C_L) D_s C_R src_o / gamma_f^2
 void wilson_so_odd(tp_op op, int prec, const Field& src, Field& dst) {
   Field& aup = ws_get(op, prec, W_T1);
-  Field& m = ws_get(op, prec, W_T2);
-  launch_ilu_k1(op, prec, src, aup);
-  LineStencilArgs s2{};
-  s2.nb_up = &aup;
-  s2.nb_lo = &src;
-  s2.c_s = 1.0;
-  s2.c_out = 1.0;
-  launch_line_stencil(op, prec, LM_CRCL, 0, s2, m);
-  LineStencilArgs s3{};
-  s3.nb_up = &m;
-  s3.nb_lo = &m;
-  s3.base = &src;
-  s3.c_s = -1.0 / (op->gf * op->gf);
-  s3.c_out = 1.0;
-  s3.c_base = 1.0;
-  launch_line_stencil(op, prec, LM_CL, 1, s3, dst);
+  Field& u = ws_get(op, prec, W_T2);
+  Field& m = ws_get(op, prec, W_T3);
+  Field& v = ws_get(op, prec, W_T4);
+  launch_line(op, prec, LM_CR, 1, lio(&src, nullptr, false), aup);          // a_o upper
+  launch_site(op, prec, sio_nb(&aup, &src), u, SiteCoef{0, 0, 0, 1.0, 0}, 0, 0, 1, false);
+  launch_line(op, prec, LM_CRCL, 0, lio(&u), m);
+  launch_site(op, prec, sio_nb(&m, &m), v,
+              SiteCoef{0, 0, 0, -1.0 / (op->gf * op->gf), 0}, 0, 1, 1, false);
+  launch_line(op, prec, LM_CL, 1, lio(&v, &src), dst);
 }
 
 void ilu_full(tp_op op, int prec, const Field& src, Field& dst) {
   Field& aup = ws_get(op, prec, W_T1);
-  Field& y = ws_get(op, prec, W_T2);
-  Field& u = ws_get(op, prec, W_T3);
-  Field& n = ws_get(op, prec, W_T4);
-  launch_ilu_k1(op, prec, src, aup);
-  launch_ilu_k2a(op, prec, src, aup, y, u);
-  launch_ilu_k2b(op, prec, src, y, u, dst, n);
-  launch_ilu_k3(op, prec, src, aup, n, dst);
+  Field& u = ws_get(op, prec, W_T2);
+  Field& n = ws_get(op, prec, W_T3);
+  Field& v = ws_get(op, prec, W_T4);
+  const double ig = 1.0 / op->gf;
+  launch_line(op, prec, LM_CR, 1, lio(&src, nullptr, false), aup);          // a_o upper
+  launch_site(op, prec, sio_nb(&aup, &src), u, SiteCoef{0, 0, 0, ig, 0}, 0, 0, 1, false);
+  launch_ilu_mid(op, prec, src, u, dst, n);                                 // chi_e, n_e
+  SiteIO io3;
+  io3.self_up = &aup;
+  io3.self_lo = &src;
+  io3.nb_up = io3.nb_lo = &n;
+  launch_site(op, prec, io3, v, SiteCoef{0, 1.0, 0, ig, 0}, 1, 1, 1, false);
+  launch_line(op, prec, LM_CL, 1, lio(&v, &src), dst);                      // chi_o
 }
 
 void temporal_full(tp_op op, int prec, const Field& src, Field& dst) {
+  // C_L M C_R = 1 + C_L (A - D_s / gamma_f) C_R
   Field& a = ws_get(op, prec, W_T1);
-  launch_line_plain(op, prec, LM_CR, 0, src, a);
-  launch_line_plain(op, prec, LM_CR, 1, src, a);
-  for (int p = 0; p < 2; ++p) {
-    LineStencilArgs s{};
-    s.nb_up = &a;
-    s.nb_lo = &a;
-    s.self = &a;
-    s.base = &src;
-    s.c_s = -1.0 / op->gf;
-    s.c_A = 1.0;
-    s.c_out = 1.0;
-    s.c_base = 1.0;
-    launch_line_stencil(op, prec, LM_CL, p, s, dst);
-  }
+  Field& v = ws_get(op, prec, W_T2);
+  launch_line(op, prec, LM_CR, 0, lio(&src), a);
+  launch_line(op, prec, LM_CR, 1, lio(&src), a);
+  SiteIO io;
+  io.self_up = io.self_lo = io.nb_up = io.nb_lo = &a;
+  launch_site(op, prec, io, v, SiteCoef{0, 1.0, 0, -1.0 / op->gf, 0}, op->c ? 1 : 0, 0, 2, false);
+  launch_line(op, prec, LM_CL, 0, lio(&v, &src), dst);
+  launch_line(op, prec, LM_CL, 1, lio(&v, &src), dst);
 }
 
 void apply_M_noalias(tp_op op, int prec, const Field& src, Field& dst) {
@@ -225,22 +235,19 @@ void op_prepare(tp_op op, int scheme, int prec, const Field& eta, Field& et) {
       break;
     }
     case TP_TEMPORAL:
-      launch_line_plain(op, prec, LM_CL, 0, eta, et);
-      launch_line_plain(op, prec, LM_CL, 1, eta, et);
+      launch_line(op, prec, LM_CL, 0, lio(&eta), et);
+      launch_line(op, prec, LM_CL, 1, lio(&eta), et);
       break;
     case TP_TEMPORAL_SCHUR: {
       // eta~_e = C_L^e eta_e ; eta~_o = C_L^o [eta_o + D_s^oe C_R^e C_L^e eta_e / gamma_f]
       Field& t = ws_get(op, prec, W_PREP);
-      launch_line_plain(op, prec, LM_CL, 0, eta, et);
-      launch_line_plain(op, prec, LM_CRCL, 0, eta, t);
-      LineStencilArgs s{};
-      s.nb_up = &t;
-      s.nb_lo = &t;
-      s.self = &eta;
-      s.c_s = 1.0 / op->gf;
-      s.c_self = 1.0;
-      s.c_out = 1.0;
-      launch_line_stencil(op, prec, LM_CL, 1, s, et);
+      Field& v = ws_get(op, prec, W_PREP2);
+      launch_line(op, prec, LM_CL, 0, lio(&eta), et);
+      launch_line(op, prec, LM_CRCL, 0, lio(&eta), t);
+      SiteIO io = sio_nb(&t, &t);
+      io.in2 = &eta;
+      launch_site(op, prec, io, v, SiteCoef{0, 0, 0, 1.0 / op->gf, 1.0}, 0, 1, 1, false);
+      launch_line(op, prec, LM_CL, 1, lio(&v), et);
       break;
     }
     default:
@@ -263,22 +270,17 @@ void op_reconstruct(tp_op op, int scheme, int prec, const Field& y, Field& x) {
       break;
     }
     case TP_TEMPORAL:
-      launch_line_plain(op, prec, LM_CR, 0, y, x);
-      launch_line_plain(op, prec, LM_CR, 1, y, x);
+      launch_line(op, prec, LM_CR, 0, lio(&y), x);
+      launch_line(op, prec, LM_CR, 1, lio(&y), x);
       break;
     case TP_TEMPORAL_SCHUR: {
       // x_o = C_R^o y_o ; x_e = C_R^e [y_e + C_L^e D_s^eo x_o / gamma_f]
-      Field& t = ws_get(op, prec, W_PREP);
-      launch_line_plain(op, prec, LM_CR, 1, y, x);
-      LineStencilArgs s{};
-      s.nb_up = &x;
-      s.nb_lo = &x;
-      s.base = &y;
-      s.c_s = 1.0 / op->gf;
-      s.c_out = 1.0;
-      s.c_base = 1.0;
-      launch_line_stencil(op, prec, LM_CL, 0, s, t);
-      launch_line_plain(op, prec, LM_CR, 0, t, x);
+      Field& v = ws_get(op, prec, W_PREP);
+      Field& t = ws_get(op, prec, W_PREP2);
+      launch_line(op, prec, LM_CR, 1, lio(&y), x);
+      launch_site(op, prec, sio_nb(&x, &x), v, SiteCoef{0, 0, 0, 1.0 / op->gf, 0}, 0, 0, 1, false);
+      launch_line(op, prec, LM_CL, 0, lio(&v, &y), t);
+      launch_line(op, prec, LM_CR, 0, lio(&t), x);
       break;
     }
     default:

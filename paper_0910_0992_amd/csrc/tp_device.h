@@ -249,8 +249,12 @@ TP_DEV void clover_apply(const L* cl, int64_t stride, int64_t i, const cx<R>* ps
 }
 
 // ---- lattice geometry ----------------------------------------------------------------------
-// p3 ("line") layout: parity p = (x+y+z)&1; index within a parity = t*Vs2 + s with
-// s = (x + Lx*(y + Ly*z)) >> 1.  A time line (fixed s) stays inside one parity.
+// p3 ("line") layout: parity p = (x+y+z)&1; spatial index s = (x + Lx*(y + Ly*z)) >> 1;
+// a time line (fixed s) stays inside one parity.  Lines are grouped in tiles of 4 and
+// a tile stores all its time slices contiguously:
+//   index(t, s) = ((s / 4) * Lt + t) * 4 + s % 4,
+// so a workgroup that owns whole lines reads and writes contiguous memory in thread
+// order.  Vs/2 is always a multiple of 4 (every spatial extent is even).
 // p4 layout: parity p = (x+y+z+t)&1; index = (x + Lx*(y + Ly*(z + Lz*t))) >> 1.
 struct Geom {
   int Lx, Ly, Lz, Lt;
@@ -268,3 +272,13 @@ TP_DEV C3 p3_coords(const Geom& g, int p, int s) {
   return {x, y, z};
 }
 TP_DEV int p3_index(const Geom& g, int x, int y, int z) { return (x + g.Lx * (y + g.Ly * z)) >> 1; }
+constexpr int kTile = 4;
+TP_HD int64_t p3_idx(const Geom& g, int t, int s) {
+  return ((int64_t)(s >> 2) * g.Lt + t) * kTile + (s & 3);
+}
+TP_HD void p3_ts(const Geom& g, int64_t i, int& t, int& s) {
+  int64_t tile = i / ((int64_t)kTile * g.Lt);
+  int r = int(i - tile * kTile * g.Lt);
+  t = r >> 2;
+  s = int(tile * kTile) + (r & 3);
+}

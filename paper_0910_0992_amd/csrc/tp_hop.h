@@ -11,8 +11,8 @@ TP_DEV void hop_time_p3(const SpinorF<S>& f, const LinkF<Lt>& ut, const Geom& g,
                         cx<R>* out) {
   int tf = t + 1 == g.Lt ? 0 : t + 1;
   int tb = t == 0 ? g.Lt - 1 : t - 1;
-  int64_t i = (int64_t)t * g.Vs2 + s;
-  int64_t jf = (int64_t)tf * g.Vs2 + s, jb = (int64_t)tb * g.Vs2 + s;
+  int64_t i = p3_idx(g, t, s);
+  int64_t jf = p3_idx(g, tf, s), jb = p3_idx(g, tb, s);
   cx<R> v[6], w[6];
   load_half<S, R>(f, 1, jf, v);
   su3<R> U = load_su3<R, Lt>(ut, i);
@@ -53,17 +53,16 @@ template <typename S, typename R, typename Lt>
 TP_DEV void hop_space_p3(const SpinorF<S>& nb, const LinkF<Lt>* u_here, const LinkF<Lt>* u_there,
                          const Geom& g, int p, int t, int s, R c, cx<R>* out) {
   C3 q = p3_coords(g, p, s);
-  int64_t tb = (int64_t)t * g.Vs2;
-  int64_t i = tb + s;
+  int64_t i = p3_idx(g, t, s);
   int xp = q.x + 1 == g.Lx ? 0 : q.x + 1, xm = q.x == 0 ? g.Lx - 1 : q.x - 1;
   int yp = q.y + 1 == g.Ly ? 0 : q.y + 1, ym = q.y == 0 ? g.Ly - 1 : q.y - 1;
   int zp = q.z + 1 == g.Lz ? 0 : q.z + 1, zm = q.z == 0 ? g.Lz - 1 : q.z - 1;
-  hop_dir<0, S, R, Lt>(nb, u_here[0], i, tb + p3_index(g, xp, q.y, q.z), u_there[0],
-                       tb + p3_index(g, xm, q.y, q.z), c, out);
-  hop_dir<1, S, R, Lt>(nb, u_here[1], i, tb + p3_index(g, q.x, yp, q.z), u_there[1],
-                       tb + p3_index(g, q.x, ym, q.z), c, out);
-  hop_dir<2, S, R, Lt>(nb, u_here[2], i, tb + p3_index(g, q.x, q.y, zp), u_there[2],
-                       tb + p3_index(g, q.x, q.y, zm), c, out);
+  hop_dir<0, S, R, Lt>(nb, u_here[0], i, p3_idx(g, t, p3_index(g, xp, q.y, q.z)), u_there[0],
+                       p3_idx(g, t, p3_index(g, xm, q.y, q.z)), c, out);
+  hop_dir<1, S, R, Lt>(nb, u_here[1], i, p3_idx(g, t, p3_index(g, q.x, yp, q.z)), u_there[1],
+                       p3_idx(g, t, p3_index(g, q.x, ym, q.z)), c, out);
+  hop_dir<2, S, R, Lt>(nb, u_here[2], i, p3_idx(g, t, p3_index(g, q.x, q.y, zp)), u_there[2],
+                       p3_idx(g, t, p3_index(g, q.x, q.y, zm)), c, out);
 }
 
 // p4 layout: out += c_t * D_t psi + c_sp * D_s psi at site i of parity p;

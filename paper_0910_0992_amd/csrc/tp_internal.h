@@ -33,11 +33,9 @@ enum KernelId {
   KID_SITE_P3,      // M / D_s / clover / residual on the p3 layout
   KID_SCHUR4D_EO,   // (A+mu)^-1 D_w^eo
   KID_SCHUR4D_OE,   // (A+mu) psi_o - D_w^oe t_e
-  KID_LINE_CR,      // C_R / C_L / T^-1 scans without a stencil
-  KID_ILU_K2A,      // D_s + C_L + C_R + clover (even parity)
-  KID_ILU_K2B,      // C_L y and C_R C_L q (even parity)
-  KID_ILU_K3,       // D_s + clover + C_L + axpy (odd parity)
-  KID_LINE_STENCIL, // other stencil + scan line kernels (Wilson, temporal)
+  KID_LINE_CR,      // C_R / C_L / C_R C_L / T^-1 scans
+  KID_ILU_MID,      // fused scans + clover of the 3D ILU operator (even parity)
+  KID_HOP,          // D_s / clover site kernels feeding the scans
   KID_BLAS,
   KID_REDUCE,
   KID_FORCE,
@@ -105,12 +103,14 @@ struct tp_ctx_s {
 struct tp_gauge_s {
   tp_ctx ctx = nullptr;
   double2* canon = nullptr;  // device copy of the canonical links [4][V][9]
-  double2* u3_d = nullptr;   // p3 layout [4 dir][2 par][9][V2], time phase folded
+  // p3 layout [4 dir][2 par][9][V2] in the axial gauge W(x)^dag U(x) W(x+mu): interior
+  // time links are the identity, U_t(Lt-1) = P (Polyakov loop with the phase b)
+  double2* u3_d = nullptr;
   float2* u3_f = nullptr;
   double2* u4_d = nullptr;   // p4 layout [4 dir][2 par][9][V2], time phase folded
   float2* u4_f = nullptr;
-  double2* w_d = nullptr;    // p3 layout W(t) = U(t)...U(Lt-1) [2 par][9][V2]
-  float2* w_f = nullptr;
+  double2* w_d = nullptr;    // p3 layout W(t) = U(t)...U(Lt-1) [2 par][9][V2], FP64
+  double2* canon_ax = nullptr;  // axial-gauge links, canonical order (clover build)
   double2* poly = nullptr;   // W(0) per line [2 par][9][Vs2]
 };
 
@@ -162,11 +162,15 @@ struct ProfScope {
 void prof_flush(tp_ctx ctx);
 
 // ---------------------------------------------------------------- launchers (layout / setup)
-// pack canonical c128 spinor (device) into an internal field; layout4 selects p4.
-void launch_pack(tp_ctx ctx, const double2* canon, Field& dst, bool layout4, bool gamma5);
-void launch_unpack(tp_ctx ctx, const Field& src, double2* canon, bool layout4, bool gamma5);
-void launch_pack_links(tp_ctx ctx, tp_gauge g);
-void launch_wline(tp_ctx ctx, tp_gauge g);
+// pack canonical c128 spinor (device) into an internal field; layout4 selects p4; w (p3
+// only) rotates into the axial frame, psi -> W^dag psi (unpack: psi -> W psi).
+void launch_pack(tp_ctx ctx, const double2* canon, Field& dst, bool layout4, bool gamma5,
+                 const double2* w);
+void launch_unpack(tp_ctx ctx, const Field& src, double2* canon, bool layout4, bool gamma5,
+                   const double2* w);
+void launch_pack_links(tp_ctx ctx, tp_gauge g);   // p4 layout (original frame)
+void launch_wline(tp_ctx ctx, tp_gauge g);        // W(t), P from the canonical links
+void launch_axial_links(tp_ctx ctx, tp_gauge g);  // p3 layout, axial frame
 void launch_closure(tp_ctx ctx, tp_op op, double* cond_out /*device [2*Vs2]*/);
 void launch_clover_build(tp_ctx ctx, tp_clover c, const double sig[6][2][2][2][2]);
 void launch_clover_derived(tp_ctx ctx, tp_op op, int* bad /*device counter*/);
@@ -194,29 +198,37 @@ void launch_schur4d(tp_op op, int prec, int mode, int out_par, const Field* src,
 
 // Line (time-line scan) kernels on the p3 layout.
 enum LineMode { LM_CL = 0, LM_CR = 1, LM_CRCL = 2, LM_TINV = 3, LM_TDINV = 4 };
-struct LineIO;
-// Plain scans: dst = mode(src) on parity par (pass-through halves copied).
-void launch_line_plain(tp_op op, int prec, int mode, int par, const Field& src, Field& dst);
-// Stencil-prologue scan:
-//   v = c_s * D_s(nb, from parity 1-par) + c_A * A(self) + c_self * self
-//   r = mode(v);  dst = c_out * r + c_base * base
-// nb / self / base are fields (self and base on parity par); any may be null.
-struct LineStencilArgs {
-  const Field* nb_up;   // upper half of the neighbour field (parity 1-par)
-  const Field* nb_lo;   // lower half of the neighbour field
-  const Field* self;    // operand of A / self term on parity par (may be null)
-  const Field* base;    // added to the output (may be null)
-  double c_s, c_A, c_self, c_out, c_base;
+// dst = c_out MODE(in) + c_base base on parity par.  The input's halves may come from
+// different fields; halves that MODE does not scan pass through when `pass`, else they
+// are not written.
+struct LineIO {
+  const Field* in_up = nullptr;
+  const Field* in_lo = nullptr;
+  const Field* base = nullptr;
+  double c_out = 1.0, c_base = 1.0;
+  bool pass = true;
 };
-void launch_line_stencil(tp_op op, int prec, int mode, int par, const LineStencilArgs& a,
-                         Field& dst);
-// ILU pieces (clover temporal + 3D Schur), see ops.cpp for the sequence.
-void launch_ilu_k1(tp_op op, int prec, const Field& psi, Field& aup);
-void launch_ilu_k2a(tp_op op, int prec, const Field& psi, const Field& aup, Field& y, Field& q);
-void launch_ilu_k2b(tp_op op, int prec, const Field& psi, const Field& y, const Field& q,
-                    Field& chi, Field& n);
-void launch_ilu_k3(tp_op op, int prec, const Field& psi, const Field& aup, const Field& n,
-                   Field& chi);
+void launch_line(tp_op op, int prec, int mode, int par, const LineIO& io, Field& dst);
+// Fused middle step of the 3D ILU operator (even parity): from psi_e and
+// u = D_s^eo a_o / gamma_f, chi_e = psi_e + C_L y and n_e = C_R C_L (y - u) with
+// y = A C_R (C_L u + psi_e).
+void launch_ilu_mid(tp_op op, int prec, const Field& psi, const Field& u, Field& chi, Field& n);
+
+// Site kernel with operands assembled from half fields: for output parity p,
+//   dst = c_mu self + c_A A self + c_t D_t self + c_s D_s nb + c_in in2,
+// self (and in2) read on parity p, nb on parity 1-p.
+struct SiteIO {
+  const Field* self_up = nullptr;
+  const Field* self_lo = nullptr;
+  const Field* nb_up = nullptr;
+  const Field* nb_lo = nullptr;
+  const Field* in2 = nullptr;
+};
+int launch_site(tp_op op, int prec, const SiteIO& io, Field& dst, SiteCoef cf, int clover_kind,
+                int par0, int npar, bool want_norm);
+double spinor_bytes(int prec);
+double link_bytes(int prec);
+double clov_bytes(int prec);
 
 // ---------------------------------------------------------------- BLAS
 constexpr int kRedBlocks = 1024;

@@ -73,4 +73,4 @@ def test_null_handles_rejected(lib):
 def test_kernel_profile_names(lib):
     n = lib.tp_prof_count()
     names = [lib.tp_prof_name(k).decode() for k in range(n)]
-    assert "ilu_k2a" in names and "site_p3" in names and len(set(names)) == n
+    assert "ilu_mid" in names and "line_scan" in names and len(set(names)) == n

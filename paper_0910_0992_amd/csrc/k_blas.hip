@@ -7,6 +7,10 @@
 namespace {
 
 constexpr int kBlock = 256;
+// Grid of the level-1 kernels: 4 workgroups per CU; enough loads in flight to stream HBM
+// and few partials to sum.
+constexpr int kBlasBlocks = 1024;
+static_assert(kBlasBlocks <= kRedBlocks, "partials buffer too small");
 
 template <typename S>
 struct BlasK {
@@ -17,8 +21,8 @@ struct BlasK {
   double* partial;
 };
 
-TP_DEV void block_reduce(double (&acc)[4], int nred, double* partial) {
-  __shared__ double sh[kBlock / 64][4];
+TP_DEV void block_reduce(double (&acc)[8], int nred, double* partial) {
+  __shared__ double sh[kBlock / 64][8];
   for (int k = 0; k < nred; ++k) {
     double v = acc[k];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -34,10 +38,20 @@ TP_DEV void block_reduce(double (&acc)[4], int nred, double* partial) {
 
 template <typename R> TP_DEV cx<R> cc(const double* z) { return cx<R>{R(z[0]), R(z[1])}; }
 
+// acc[0..1] += <x, y> = sum conj(x) y over one half spinor, in FP64.
+template <typename R>
+TP_DEV void dot_acc(const cx<R>* x, const cx<R>* y, double* acc) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    acc[0] += double(x[c].re) * double(y[c].re) + double(x[c].im) * double(y[c].im);
+    acc[1] += double(x[c].re) * double(y[c].im) - double(x[c].im) * double(y[c].re);
+  }
+}
+
 template <typename S, int OP>
 __global__ void __launch_bounds__(kBlock) k_blas(BlasK<S> k) {
   using R = typename Prec<S>::R;
-  double acc[4] = {0, 0, 0, 0};
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const cx<R> A = cc<R>(k.a), B = cc<R>(k.b), C = cc<R>(k.c);
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < k.n;
        u += (int64_t)gridDim.x * blockDim.x) {
@@ -61,12 +75,6 @@ __global__ void __launch_bounds__(kBlock) k_blas(BlasK<S> k) {
       load_half<S, R>(k.f[1][p], h, i, y);
       for (int c = 0; c < 6; ++c) y[c] = x[c] + cmul(A, y[c]);
       store_half<S, R>(k.f[1][p], h, i, y);
-    } else if constexpr (OP == B_AXPBYPCZ) {
-      load_half<S, R>(k.f[0][p], h, i, x);
-      load_half<S, R>(k.f[1][p], h, i, y);
-      load_half<S, R>(k.f[2][p], h, i, z);
-      for (int c = 0; c < 6; ++c) z[c] = cmul(A, x[c]) + cmul(B, y[c]) + cmul(C, z[c]);
-      store_half<S, R>(k.f[2][p], h, i, z);
     } else if constexpr (OP == B_NORM2) {
       load_half<S, R>(k.f[0][p], h, i, x);
       for (int c = 0; c < 6; ++c) acc[0] += double(norm2(x[c]));
@@ -86,39 +94,50 @@ __global__ void __launch_bounds__(kBlock) k_blas(BlasK<S> k) {
         acc[0] += double(norm2(y[c]));
       }
       store_half<S, R>(k.f[1][p], h, i, y);
-    } else if constexpr (OP == B_DOT2_TS) {
+    } else if constexpr (OP == B_AXPYZ_NORM) {
+      load_half<S, R>(k.f[0][p], h, i, x);
+      load_half<S, R>(k.f[1][p], h, i, y);
+      for (int c = 0; c < 6; ++c) {
+        y[c] += cmul(A, x[c]);
+        acc[0] += double(norm2(y[c]));
+      }
+      store_half<S, R>(k.f[2][p], h, i, y);
+    } else if constexpr (OP == B_DOT4_TS) {
       load_half<S, R>(k.f[0][p], h, i, x);  // t
       load_half<S, R>(k.f[1][p], h, i, y);  // s
-      for (int c = 0; c < 6; ++c) {
-        acc[0] += double(x[c].re) * double(y[c].re) + double(x[c].im) * double(y[c].im);
-        acc[1] += double(x[c].re) * double(y[c].im) - double(x[c].im) * double(y[c].re);
-        acc[2] += double(norm2(x[c]));
-      }
-    } else if constexpr (OP == B_BICG_UPDATE) {
-      // f0 = x, f1 = p, f2 = s, f3 = t, f4 = r (out), f5 = rhat
+      load_half<S, R>(k.f[2][p], h, i, z);  // rhat
+      dot_acc(x, y, acc);
+      for (int c = 0; c < 6; ++c) acc[2] += double(norm2(x[c]));
+      dot_acc(z, y, acc + 3);
+      dot_acc(z, x, acc + 5);
+    } else if constexpr (OP == B_BICG_FUSED) {
+      // f0 = x, f1 = p, f2 = s, f3 = t, f4 = v, f5 = r (out); A = alpha, B = omega, C = beta
       load_half<S, R>(k.f[0][p], h, i, x);
       load_half<S, R>(k.f[1][p], h, i, y);
       load_half<S, R>(k.f[2][p], h, i, z);
       load_half<S, R>(k.f[3][p], h, i, w);
-      load_half<S, R>(k.f[5][p], h, i, v);
+      load_half<S, R>(k.f[4][p], h, i, v);
+      const cx<R> BC = cmul(B, C);
       for (int c = 0; c < 6; ++c) {
         x[c] += cmul(A, y[c]) + cmul(B, z[c]);
-        z[c] = z[c] - cmul(B, w[c]);  // r = s - omega t
-        acc[0] += double(v[c].re) * double(z[c].re) + double(v[c].im) * double(z[c].im);
-        acc[1] += double(v[c].re) * double(z[c].im) - double(v[c].im) * double(z[c].re);
-        acc[2] += double(norm2(z[c]));
+        z[c] = z[c] - cmul(B, w[c]);                  // r = s - omega t
+        y[c] = z[c] + cmul(C, y[c]) - cmul(BC, v[c]);  // p = r + beta (p - omega v)
+        acc[0] += double(norm2(z[c]));
       }
       store_half<S, R>(k.f[0][p], h, i, x);
-      store_half<S, R>(k.f[4][p], h, i, z);
+      store_half<S, R>(k.f[5][p], h, i, z);
+      store_half<S, R>(k.f[1][p], h, i, y);
     } else if constexpr (OP == B_G5) {
       load_half<S, R>(k.f[0][p], h, i, x);
       for (int c = 0; c < 6; ++c) x[c] = -x[c];
       store_half<S, R>(k.f[1][p], 1 - h, i, x);
     }
   }
-  constexpr int nred = (OP == B_NORM2 || OP == B_CAXPY_NORM) ? 1
-                     : (OP == B_DOT) ? 2
-                     : (OP == B_DOT_NORM || OP == B_DOT2_TS || OP == B_BICG_UPDATE) ? 3 : 0;
+  constexpr int nred =
+      (OP == B_NORM2 || OP == B_CAXPY_NORM || OP == B_AXPYZ_NORM || OP == B_BICG_FUSED) ? 1
+      : (OP == B_DOT) ? 2
+      : (OP == B_DOT_NORM) ? 3
+      : (OP == B_DOT4_TS) ? 7 : 0;
   if constexpr (nred > 0) block_reduce(acc, nred, k.partial);
 }
 
@@ -181,7 +200,7 @@ int blas_go(tp_ctx ctx, int par0, int npar, const Field* const* fs, BlasArgs k) 
   a.n = (int64_t)npar * 2 * a.V2;
   a.partial = ctx->red_partial;
   int64_t nb = (a.n + kBlock - 1) / kBlock;
-  if (nb > kRedBlocks) nb = kRedBlocks;
+  if (nb > kBlasBlocks) nb = kBlasBlocks;
   hipLaunchKernelGGL((k_blas<S, OP>), dim3((unsigned)nb), dim3(kBlock), 0, ctx->stream, a);
   LAUNCH_CHECK();
   return int(nb);
@@ -250,9 +269,9 @@ void blas(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<const
   {
     double passes = 2;
     switch (op) {
-      case B_AXPY: case B_XPAY: case B_DOT_NORM: case B_CAXPY_NORM: case B_DOT2_TS: passes = 3; break;
-      case B_AXPBYPCZ: passes = 4; break;
-      case B_BICG_UPDATE: passes = 7; break;
+      case B_AXPY: case B_XPAY: case B_DOT_NORM: case B_CAXPY_NORM: case B_AXPYZ_NORM: passes = 3; break;
+      case B_DOT4_TS: passes = 3; break;
+      case B_BICG_FUSED: passes = 8; break;
       case B_NORM2: passes = 1; break;
       case B_ZERO: passes = 1; break;
       default: break;
@@ -263,16 +282,13 @@ void blas(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<const
       case B_COPY: nb = blas_prec<B_COPY>(ctx, prec, par0, npar, fs, k); break;
       case B_AXPY: nb = blas_prec<B_AXPY>(ctx, prec, par0, npar, fs, k); break;
       case B_XPAY: nb = blas_prec<B_XPAY>(ctx, prec, par0, npar, fs, k); break;
-      case B_AXPBYPCZ: nb = blas_prec<B_AXPBYPCZ>(ctx, prec, par0, npar, fs, k); break;
       case B_NORM2: nb = blas_prec<B_NORM2>(ctx, prec, par0, npar, fs, k); nred = 1; break;
       case B_DOT: nb = blas_prec<B_DOT>(ctx, prec, par0, npar, fs, k); nred = 2; break;
       case B_DOT_NORM: nb = blas_prec<B_DOT_NORM>(ctx, prec, par0, npar, fs, k); nred = 3; break;
       case B_CAXPY_NORM: nb = blas_prec<B_CAXPY_NORM>(ctx, prec, par0, npar, fs, k); nred = 1; break;
-      case B_DOT2_TS: nb = blas_prec<B_DOT2_TS>(ctx, prec, par0, npar, fs, k); nred = 3; break;
-      case B_BICG_UPDATE:  // fields: x, p, s, t, r, rhat
-        nb = blas_prec<B_BICG_UPDATE>(ctx, prec, par0, npar, fs, k);
-        nred = 3;
-        break;
+      case B_AXPYZ_NORM: nb = blas_prec<B_AXPYZ_NORM>(ctx, prec, par0, npar, fs, k); nred = 1; break;
+      case B_DOT4_TS: nb = blas_prec<B_DOT4_TS>(ctx, prec, par0, npar, fs, k); nred = 7; break;
+      case B_BICG_FUSED: nb = blas_prec<B_BICG_FUSED>(ctx, prec, par0, npar, fs, k); nred = 1; break;
       case B_G5: nb = blas_prec<B_G5>(ctx, prec, par0, npar, fs, k); break;
       default: TP_THROW(TP_EINVAL, "blas op");
     }

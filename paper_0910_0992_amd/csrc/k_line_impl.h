@@ -30,14 +30,98 @@ namespace {
 
 template <typename R>
 struct ScanCtx {
-  int l, j, LPB, NCH, t0, Lt;
+  int l, j, LPB, NCH, t0, Lt, CH;
   int s;
+  int tile;     // tile of 4 lines within the workgroup
   bool active;
+  bool fast;    // NCH % 16 == 0: wavefront-shuffle scan (each wave = 16 chunks x 4 lines)
   R inv_mu, f;  // 1/mu and mu^-CH
   const R* mupow;  // mu^-k, k = 0..Lt
   const double2* G;  // closure planes [9][Vs2] of this parity
   int64_t gstride;
 };
+
+template <typename R> TP_DEV cx<R> shdown(cx<R> v, int d) {
+  return cx<R>{__shfl_down(v.re, d, 64), __shfl_down(v.im, d, 64)};
+}
+template <typename R> TP_DEV cx<R> shup(cx<R> v, int d) {
+  return cx<R>{__shfl_up(v.re, d, 64), __shfl_up(v.im, d, 64)};
+}
+
+// Exclusive carries of the chunk heads X (6 values) across a line, fast path.  A wave
+// holds 16 consecutive chunks of 4 lines (lane = (j % 16) * 4 + line).
+//   level 1: inclusive suffix (BWD) / prefix (FWD) within the 16-chunk segment by shuffles;
+//   level 2: the segment totals of each line are scanned by the tile's first wave
+//            (lane = segment * 4 + line), factor f^16;
+//   level 3: carry C_j = exclusive in-segment value + f^(distance) * next segment's total.
+// Z = the line's total at chunk 0 (BWD) or at the last chunk (FWD).
+template <typename R, bool BWD>
+TP_DEV void combine_fast(cx<R> (&X)[6], cx<R> (&C)[6], cx<R> (&Z)[6], cx<R>* lds, const ScanCtx<R>& sc) {
+  const int jw = sc.j & 15;
+  const int lt = sc.l & 3;
+  R fd = sc.f;
+#pragma unroll
+  for (int d = 1; d < 16; d <<= 1) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      cx<R> y = BWD ? shdown(X[c], 4 * d) : shup(X[c], 4 * d);
+      bool ok = BWD ? (jw + d < 16) : (jw - d >= 0);
+      if (ok) X[c] += fd * y;
+    }
+    fd = fd * fd;
+  }
+  // exclusive within the segment
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    cx<R> y = BWD ? shdown(X[c], 4) : shup(X[c], 4);
+    bool ok = BWD ? (jw < 15) : (jw > 0);
+    C[c] = ok ? y : czero<R>();
+  }
+  const int nseg = sc.NCH >> 4;
+  const int seg = sc.j >> 4;
+  cx<R>* tab = lds + (sc.tile * 16) * kTile * 6;  // [segment][line][6] for this tile
+  if (jw == (BWD ? 0 : 15)) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) tab[(seg * kTile + lt) * 6 + c] = X[c];
+  }
+  __syncthreads();
+  // the tile's first wave (j < 16, uniform per wave) scans the segment totals;
+  // lane = segment * 4 + line
+  const int sg = sc.j;
+  cx<R> T[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) T[c] = czero<R>();
+  if (sc.j < 16) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) T[c] = sg < nseg ? tab[(sg * kTile + lt) * 6 + c] : czero<R>();
+    R Fd = sc.mupow[16 * sc.CH];
+    for (int d = 1; d < nseg; d <<= 1) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        cx<R> y = BWD ? shdown(T[c], 4 * d) : shup(T[c], 4 * d);
+        bool ok = BWD ? (sg + d < nseg) : (sg - d >= 0);
+        if (ok) T[c] += Fd * y;
+      }
+      Fd = Fd * Fd;
+    }
+  }
+  __syncthreads();  // every segment total has been read
+  if (sc.j < 16 && sg < nseg) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) tab[(sg * kTile + lt) * 6 + c] = T[c];
+  }
+  __syncthreads();
+  const int nxt = BWD ? seg + 1 : seg - 1;
+  const bool hasn = BWD ? (nxt < nseg) : (nxt >= 0);
+  const R w = sc.mupow[sc.CH * (BWD ? (15 - jw) : jw)];
+  const int zs = BWD ? 0 : nseg - 1;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    if (hasn) C[c] += w * tab[(nxt * kTile + lt) * 6 + c];
+    Z[c] = tab[(zs * kTile + lt) * 6 + c];
+  }
+  __syncthreads();  // the table is reused by the next group
+}
 
 // v: per time slice of the chunk, NV complex values (NV/3 colour vectors); on return
 // v holds the scan result (T^-1 for BWD, T^dagger^-1 otherwise) on those values.
@@ -68,7 +152,18 @@ TP_DEV void scan_core(cx<R> (&v)[CH][NV], cx<R>* lds, const ScanCtx<R>& sc) {
       }
       X[c] = acc;
     }
-    // combine chunk heads (backward) / tails (forward) across the line
+    cx<R> C[6], D[6];
+    cx<double> Z[6];
+    if (sc.fast) {
+      cx<R> Cr[6], Zr[6];
+      combine_fast<R, BWD>(X, Cr, Zr, lds, sc);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        C[c] = Cr[c];
+        Z[c] = cx<double>{double(Zr[c].re), double(Zr[c].im)};
+      }
+    } else {
+    // combine chunk heads (backward) / tails (forward) across the line (Hillis-Steele)
     R fd = sc.f;
     for (int d = 1; d < sc.NCH; d <<= 1) {
 #pragma unroll
@@ -90,8 +185,6 @@ TP_DEV void scan_core(cx<R> (&v)[CH][NV], cx<R>* lds, const ScanCtx<R>& sc) {
     bool has = jc >= 0 && jc < sc.NCH;
     const int oc = ((has ? jc : 0) * sc.LPB + sc.l) * 6;
     const int oz = ((BWD ? 0 : sc.NCH - 1) * sc.LPB + sc.l) * 6;
-    cx<R> C[6], D[6];
-    cx<double> Z[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       C[c] = has ? lds[oc + c] : czero<R>();
@@ -99,6 +192,7 @@ TP_DEV void scan_core(cx<R> (&v)[CH][NV], cx<R>* lds, const ScanCtx<R>& sc) {
       Z[c] = cx<double>{double(z.re), double(z.im)};
     }
     __syncthreads();
+    }
     // closure in FP64: delta = G z (backward) or G^dagger z (forward), per colour vector
     if (sc.active) {
 #pragma unroll
@@ -165,7 +259,10 @@ TP_DEV ScanCtx<typename Prec<S>::R> make_ctx(const LineArgs<S>& a, int CH) {
   const int tid = threadIdx.x;
   const int rest = tid / kTile;
   sc.j = rest % a.NCH;
-  sc.l = (rest / a.NCH) * kTile + (tid % kTile);
+  sc.tile = rest / a.NCH;
+  sc.l = sc.tile * kTile + (tid % kTile);
+  sc.CH = CH;
+  sc.fast = (a.NCH % 16) == 0;
   sc.LPB = a.LPB;
   sc.NCH = a.NCH;
   sc.t0 = sc.j * CH;

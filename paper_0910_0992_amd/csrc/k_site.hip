@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(kBlock) k_site_p3(SiteArgsP3<S> a) {
   for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < a.n;
        n += (int64_t)gridDim.x * blockDim.x) {
     int p = a.par0 + int(n / a.g.V2);
-    int64_t i = n % a.g.V2;
+    const int64_t i = n % a.g.V2;
     int t, s;
     p3_ts(a.g, i, t, s);
     cx<R> out[12];

@@ -315,7 +315,7 @@ KrylovResult bicgstab(const KrylovOp& A, const Field& b, Field& y, double eps, i
   Field& s = ws_get(A.op, pr, W_S);
   Field& t = ws_get(A.op, pr, W_T);
   KrylovResult res;
-  double red[4];
+  double red[8];
   blas(ctx, B_ZERO, p0, np, {nullptr, &y});
   blas(ctx, B_COPY, p0, np, {&b, &r});
   blas(ctx, B_COPY, p0, np, {&b, &rh});
@@ -345,8 +345,7 @@ KrylovResult bicgstab(const KrylovOp& A, const Field& b, Field& y, double eps, i
     // alpha = rho / <rhat, v>
     double al_r = (rho_r * red[0] + rho_i * red[1]) / den;
     double al_i = (rho_i * red[0] - rho_r * red[1]) / den;
-    blas(ctx, B_COPY, p0, np, {&r, &s});
-    blas(ctx, B_CAXPY_NORM, p0, np, {&v, &s}, cplx(-al_r, -al_i), red);
+    blas(ctx, B_AXPYZ_NORM, p0, np, {&v, &r, &s}, cplx(-al_r, -al_i), red);
     double s2 = red[0];
     res.iters++;
     if (s2 <= tgt2) {
@@ -357,25 +356,31 @@ KrylovResult bicgstab(const KrylovOp& A, const Field& b, Field& y, double eps, i
     }
     A.apply(s, t, false);
     res.applies++;
-    blas(ctx, B_DOT2_TS, p0, np, {&t, &s}, BlasArgs{}, red);
-    if (red[2] == 0.0 || !isfinite(red[2])) { res.breakdown = true; break; }
+    // <t,s>, |t|^2, <rhat,s>, <rhat,t>: omega, and rho_new = <rhat, s - omega t> before r exists,
+    // so the x, r and p updates share one pass over the fields
+    blas(ctx, B_DOT4_TS, p0, np, {&t, &s, &rh}, BlasArgs{}, red);
     double om_r = red[0] / red[2], om_i = red[1] / red[2];
-    blas(ctx, B_BICG_UPDATE, p0, np, {&y, &p, &s, &t, &r, &rh}, cplx(al_r, al_i, om_r, om_i), red);
-    double rn_r = red[0], rn_i = red[1];
-    r2 = red[2];
+    double rn_r = red[3] - (om_r * red[5] - om_i * red[6]);
+    double rn_i = red[4] - (om_r * red[6] + om_i * red[5]);
+    // beta = (rho_new / rho) (alpha / omega)
+    double rr = rho_r * rho_r + rho_i * rho_i;
+    double oo = om_r * om_r + om_i * om_i;
+    if (red[2] == 0.0 || !isfinite(oo) || oo == 0.0 || rr == 0.0) {
+      // keep the half step: y + alpha p has residual s
+      blas(ctx, B_AXPY, p0, np, {&p, &y}, cplx(al_r, al_i));
+      r2 = s2;
+      res.breakdown = true;
+      break;
+    }
+    double q_r = (rn_r * rho_r + rn_i * rho_i) / rr, q_i = (rn_i * rho_r - rn_r * rho_i) / rr;
+    double w_r = (al_r * om_r + al_i * om_i) / oo, w_i = (al_i * om_r - al_r * om_i) / oo;
+    double be_r = q_r * w_r - q_i * w_i, be_i = q_r * w_i + q_i * w_r;
+    blas(ctx, B_BICG_FUSED, p0, np, {&y, &p, &s, &t, &v, &r}, cplx(al_r, al_i, om_r, om_i, be_r, be_i),
+         red);
+    r2 = red[0];
     if (!isfinite(r2)) { res.breakdown = true; break; }
     if (r2 < best2) { best2 = r2; best_it = res.iters; }
     if (r2 <= tgt2) { res.converged = true; break; }
-    // beta = (rho_new / rho) (alpha / omega)
-    double rr = rho_r * rho_r + rho_i * rho_i;
-    double q_r = (rn_r * rho_r + rn_i * rho_i) / rr, q_i = (rn_i * rho_r - rn_r * rho_i) / rr;
-    double oo = om_r * om_r + om_i * om_i;
-    if (oo == 0.0 || rr == 0.0) { res.breakdown = true; break; }
-    double w_r = (al_r * om_r + al_i * om_i) / oo, w_i = (al_i * om_r - al_r * om_i) / oo;
-    double be_r = q_r * w_r - q_i * w_i, be_i = q_r * w_i + q_i * w_r;
-    // p = r + beta (p - omega v) = r - beta omega v + beta p
-    double bo_r = be_r * om_r - be_i * om_i, bo_i = be_r * om_i + be_i * om_r;
-    blas(ctx, B_AXPBYPCZ, p0, np, {&r, &v, &p}, cplx(1, 0, -bo_r, -bo_i, be_r, be_i));
     rho_r = rn_r;
     rho_i = rn_i;
     if (rho_r * rho_r + rho_i * rho_i < 1e-60 * bn2 * bn2) {
@@ -400,7 +405,7 @@ KrylovResult cgnr(const KrylovOp& A, const Field& b, Field& y, double eps, int m
   Field& p = ws_get(A.op, pr, W_P);
   Field& w = ws_get(A.op, pr, W_V);
   KrylovResult res;
-  double red[4];
+  double red[8];
   blas(ctx, B_ZERO, p0, np, {nullptr, &y});
   blas(ctx, B_COPY, p0, np, {&b, &r});
   double bn2 = nrm2(ctx, A, b);
@@ -488,7 +493,7 @@ double true_residual(tp_op op, bool l4, const Field& x, const Field& eta, Field&
   }
   apply_M_p4(op, TP_F64, x, r);
   blas(ctx, B_XPAY, 0, 2, {&eta, &r}, cplx(-1, 0));
-  double red[4];
+  double red[8];
   blas(ctx, B_NORM2, 0, 2, {&r}, BlasArgs{}, red);
   return red[0];
 }
@@ -502,7 +507,7 @@ tp_status op_solve(tp_op op, const tp_solve_params& P, Field& x64, const Field& 
   bool l4 = scheme_layout4(P.scheme);
   int pr = P.prec;
   Field& r64 = ws_get(op, TP_F64, W_R64);
-  double red[4];
+  double red[8];
   blas(ctx, B_NORM2, 0, 2, {&eta64}, BlasArgs{}, red);
   double eta2 = red[0];
   if (!isfinite(eta2)) TP_THROW(TP_EINVAL, "source contains NaN or Inf");

@@ -231,7 +231,7 @@ double link_bytes(int prec);
 double clov_bytes(int prec);
 
 // ---------------------------------------------------------------- BLAS
-constexpr int kRedBlocks = 1024;
+constexpr int kRedBlocks = 4096;
 // Generic unit-wise BLAS on fields over parities [par0, par0+npar).
 enum BlasOp {
   B_ZERO,         // y = 0
@@ -239,20 +239,22 @@ enum BlasOp {
   B_CONVERT,      // y = x                          (any precisions)
   B_AXPY,         // y = y + a x                    (a complex)
   B_XPAY,         // y = x + a y
-  B_AXPBYPCZ,     // z = a x + b y + c z            (p update of BiCGStab: p = r + beta (p - w v))
   B_NORM2,        // |x|^2
   B_DOT,          // <x, y>
   B_DOT_NORM,     // <x, y>, |y|^2
-  B_CAXPY_NORM,   // y = y + a x ; |y|^2            (s = r - alpha v)
-  B_DOT2_TS,      // <t, s>, |t|^2
-  B_BICG_UPDATE,  // x += a p + b s ; r = s - b t ; <rhat, r>, |r|^2
+  B_CAXPY_NORM,   // y = y + a x ; |y|^2
+  B_AXPYZ_NORM,   // z = y + a x ; |z|^2            (s = r - alpha v)
+  B_DOT4_TS,      // <t, s>, |t|^2, <rhat, s>, <rhat, t>   (fields t, s, rhat)
+  B_BICG_FUSED,   // x += a p + b s ; r = s - b t ; p = r + c (p - b v) ; |r|^2
+                  //                                (fields x, p, s, t, v, r)
   B_G5,           // y = gamma5 x
   B_MIXED_ACC     // y(F64) += x(any)
 };
 struct BlasArgs {
   double a[2], b[2], c[2];  // complex coefficients
 };
-// fs: up to six fields (see each op); returns reduction values (up to 4 doubles)
+// fs: up to six fields (see each op); returns reduction values (up to 8 doubles, so
+// red_out must hold 8)
 // synchronously in red_out when the op reduces.
 void blas(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<const Field*> fs,
           BlasArgs k = BlasArgs{}, double* red_out = nullptr);

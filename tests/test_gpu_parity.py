@@ -5,8 +5,9 @@ Tolerances (relative l2 over the whole field):
   F32  3e-6 single kernels, 2e-5 composites   (FP32 rounding, ~2^-24 per op times depth)
   F16N 4e-3 single kernels, 1.5e-2 composites (FP16 storage, 2^-11 relative per stored half
        spinor, scaled by its largest component)
-Lattices span several workgroups (16 lines each), ragged line counts and time
-extents that are not powers of two.
+Lattices span several workgroups, ragged line counts, time extents that are not
+powers of two, and the scan's fast path (time extents that are multiples of 16,
+up to 16 wavefront segments of 16 chunks per line).
 """
 import numpy as np
 import pytest
@@ -27,6 +28,10 @@ CASES = {
     "clover_8x32": ((8, 8, 8, 32), 0.35, 0.12, 3.5, -0.05, 1.6, 1.0, -1),
     "clover_ragged": ((6, 4, 2, 10), 0.5, 0.3, 2.0, 0.1, 1.2, 0.9, -1),
     "clover_periodic": ((4, 6, 4, 12), 0.4, 0.2, 5.0, -0.05, 1.6, 1.0, 1),
+    # long lines: 16 wavefront segments of 16 chunks (the 256-slice benchmark shape)
+    "clover_long": ((4, 2, 2, 256), 0.4, 0.1, 6.0, -0.01, 1.6, 1.0, -1),
+    # 3 segments, many tiles per workgroup
+    "clover_lt48": ((6, 6, 4, 48), 0.35, 0.12, 3.5, -0.01, 1.6, 1.0, -1),
 }
 
 

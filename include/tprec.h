@@ -97,7 +97,12 @@ tp_status tp_ctx_set_stream(tp_ctx ctx, void* hip_stream);
  * Copies the canonical links (host or device pointer, per `where`) into the
  * library's layouts and prepares the per-time-line products used by T^-1:
  * W(t) = U_t(t) U_t(t+1) ... U_t(Lt-1) with the boundary phase folded into the
- * last link; W(0) is the Polyakov loop (Sec. II.A, the closed form of X). */
+ * last link; W(0) is the Polyakov loop (Sec. II.A, the closed form of X).
+ * Time links must be unitary (checked to 1e-10, else TP_EINVAL): the p3 operators
+ * work in the axial frame rotated by W^dag (Sec. II.C), a gauge rotation only for
+ * unitary W.  Spatial links may be any complex 3x3 matrices; when all of them are
+ * SU(3) to 1e-9, the FP32 and FP16 kernels read their first two rows and rebuild
+ * the third (FP64 kernels always read all nine entries). */
 tp_status tp_gauge_create(tp_ctx ctx, const void* links, int32_t where, tp_gauge* out);
 tp_status tp_gauge_destroy(tp_gauge g);
 /* Mean plaquette diagnostics: spatial and temporal (1/3 Re tr) averages. */

@@ -317,10 +317,22 @@ tp_status tp_gauge_create(tp_ctx ctx, const void* links, int32_t where, tp_gauge
       g->w_d = static_cast<double2*>(dev_alloc(size_t(2) * 9 * L.V2 * sizeof(double2)));
       g->poly = static_cast<double2*>(dev_alloc(size_t(2) * 9 * L.Vs2 * sizeof(double2)));
       g->canon_ax = static_cast<double2*>(dev_alloc(lb));
-      launch_wline(ctx, g);
-      launch_axial_links(ctx, g);
-      launch_pack_links(ctx, g);
-      HIP_CHECK(hipStreamSynchronize(ctx->stream));
+      int* flags = static_cast<int*>(dev_alloc(2 * sizeof(int)));
+      int hf[2] = {1, 1};
+      try {
+        HIP_CHECK(hipMemsetAsync(flags, 0, 2 * sizeof(int), ctx->stream));
+        launch_wline(ctx, g);
+        launch_axial_links(ctx, g, flags);
+        launch_pack_links(ctx, g);
+        HIP_CHECK(hipMemcpyAsync(hf, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_CHECK(hipStreamSynchronize(ctx->stream));
+      } catch (...) {
+        dev_free(flags);
+        throw;
+      }
+      dev_free(flags);
+      if (hf[1]) TP_THROW(TP_EINVAL, "time links must be unitary (U U^dag = 1 to 1e-10)");
+      g->su3_spatial = hf[0] == 0;
     } catch (...) {
       tp_gauge_destroy(g);
       throw;

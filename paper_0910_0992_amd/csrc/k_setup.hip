@@ -185,7 +185,7 @@ __global__ void k_wline(const double2* __restrict__ canon, double2* wd, double2*
 // Writes the p3 layout (F64, F32) and a canonical copy for the clover build.
 __global__ void k_axial_links(const double2* __restrict__ canon, const double2* __restrict__ wd,
                               double2* u3d, float2* u3f, double2* canon_ax, Geom g, int64_t V,
-                              double b) {
+                              double b, int* flags) {
   int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int mu = blockIdx.y;
   if (n >= V) return;
@@ -214,6 +214,28 @@ __global__ void k_axial_links(const double2* __restrict__ canon, const double2* 
     for (int c = 0; c < 3; ++c) Wad[3 * r + c] = Wa[3 * c + r];
   mm3(Wad, U, T1);
   mm3(T1, Wb, T2);
+  {
+    // spatial links: deviation of the axial-frame link from SU(3); time links: deviation of
+    // the input link from unitarity (the axial frame is a gauge rotation only for unitary W)
+    const cx<double>* m = mu < 3 ? T2 : U;
+    double dev = 0;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        cx<double> e = cx<double>{r == c ? -1.0 : 0.0, 0.0};
+        for (int k = 0; k < 3; ++k) e += cmul(m[3 * r + k], conj(m[3 * c + k]));
+        dev = fmax(dev, sqrt(norm2(e)));
+      }
+    if (mu < 3) {
+      cx<double> c0 = cmul(m[4], m[8]) - cmul(m[5], m[7]);
+      cx<double> c1 = cmul(m[5], m[6]) - cmul(m[3], m[8]);
+      cx<double> c2 = cmul(m[3], m[7]) - cmul(m[4], m[6]);
+      cx<double> det = cmul(m[0], c0) + cmul(m[1], c1) + cmul(m[2], c2);
+      dev = fmax(dev, sqrt(norm2(det - cx<double>{1.0, 0.0})));
+      if (!(dev <= 1e-9)) flags[0] = 1;
+    } else if (!(dev <= 1e-10)) {
+      flags[1] = 1;
+    }
+  }
   double2* d3 = u3d + ((int64_t)(mu * 2 + pa) * 9) * V2 + ia;
   float2* f3 = u3f + ((int64_t)(mu * 2 + pa) * 9) * V2 + ia;
   double2* ca = canon_ax + ((int64_t)mu * V + n) * 9;
@@ -583,10 +605,10 @@ void launch_wline(tp_ctx ctx, tp_gauge g) {
   LAUNCH_CHECK();
 }
 
-void launch_axial_links(tp_ctx ctx, tp_gauge g) {
+void launch_axial_links(tp_ctx ctx, tp_gauge g, int* flags) {
   const Lattice& L = ctx->lat;
   hipLaunchKernelGGL(k_axial_links, dim3(nblk(L.V, 64), 4), dim3(64), 0, ctx->stream, g->canon,
-                     g->w_d, g->u3_d, g->u3_f, g->canon_ax, L.g, L.V, double(ctx->bc));
+                     g->w_d, g->u3_d, g->u3_f, g->canon_ax, L.g, L.V, double(ctx->bc), flags);
   LAUNCH_CHECK();
 }
 

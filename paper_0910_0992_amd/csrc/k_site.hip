@@ -2,6 +2,8 @@
 // ("line") layout, the 4D even-odd Schur pieces on the p4 layout, and the
 // link-gradient kernel.  One thread per output site; spin projection in the
 // Dirac-Pauli basis (only two colour matvecs per hop direction).
+#include <type_traits>
+
 #include "tp_internal.h"
 #include "tp_hop.h"
 
@@ -23,7 +25,8 @@ struct SiteArgsP3 {
   double* partial;
 };
 
-template <typename S, bool DT, bool DS, bool CLOV, bool IN2, bool NORM>
+// DS: 0 = no spatial hop, 3 = spatial links read whole, 2 = read as two rows (SU(3))
+template <typename S, bool DT, int DS, bool CLOV, bool IN2, bool NORM>
 __global__ void __launch_bounds__(kBlock) k_site_p3(SiteArgsP3<S> a) {
   using R = typename Prec<S>::R;
   using Lt = typename Prec<S>::L;
@@ -55,8 +58,8 @@ __global__ void __launch_bounds__(kBlock) k_site_p3(SiteArgsP3<S> a) {
     if constexpr (DT) {
       hop_time_p3<S, R, Lt>(a.self[p], a.u[p][3], a.g, t, s, R(a.c_t), out);
     }
-    if constexpr (DS) {
-      hop_space_p3<S, R, Lt>(a.nb[p], a.u[p], a.u[1 - p], a.g, p, t, s, R(0.5 * a.c_s), out);
+    if constexpr (DS != 0) {
+      hop_space_p3<S, R, Lt, DS>(a.nb[p], a.u[p], a.u[1 - p], a.g, p, t, s, R(0.5 * a.c_s), out);
     }
     if constexpr (IN2) {
       cx<R> e[12];
@@ -283,7 +286,7 @@ template <> const float2* clover_base<__half2>(tp_op op, int kind, bool l4) {
   return clover_base<float2>(op, kind, l4);
 }
 
-template <typename S, bool DT, bool DS, bool CLOV, bool IN2, bool NORM>
+template <typename S, bool DT, int DS, bool CLOV, bool IN2, bool NORM>
 void site_go(tp_op op, SiteArgsP3<S>& a, int64_t nblocks) {
   tp_ctx ctx = op->g->ctx;
   hipLaunchKernelGGL((k_site_p3<S, DT, DS, CLOV, IN2, NORM>), dim3((unsigned)nblocks), dim3(kBlock), 0,
@@ -291,7 +294,7 @@ void site_go(tp_op op, SiteArgsP3<S>& a, int64_t nblocks) {
   LAUNCH_CHECK();
 }
 
-template <typename S, bool DT, bool DS, bool CLOV>
+template <typename S, bool DT, int DS, bool CLOV>
 void site_in2(tp_op op, SiteArgsP3<S>& a, int64_t nb, bool in2, bool norm) {
   if (in2) {
     if (norm) site_go<S, DT, DS, CLOV, true, true>(op, a, nb);
@@ -340,18 +343,31 @@ int site_t(tp_op op, const SiteIO& io, Field& dst, SiteCoef cf, int ck, int par0
   if (norm) nb = nb < kRedBlocks ? nb : kRedBlocks;
   bool dt = cf.c_t != 0.0, ds = cf.c_s != 0.0;
   bool i2 = in2 != nullptr;
+  // reduced-precision spatial hops read SU(3) links as two rows
+  constexpr bool kReduced = !std::is_same<S, double2>::value;
+  const bool two = kReduced && op->g->su3_spatial;
   if (dt && ds) {
-    if (clov) site_in2<S, true, true, true>(op, a, nb, i2, norm);
-    else site_in2<S, true, true, false>(op, a, nb, i2, norm);
+    if (two) {
+      if (clov) site_in2<S, true, kReduced ? 2 : 3, true>(op, a, nb, i2, norm);
+      else site_in2<S, true, kReduced ? 2 : 3, false>(op, a, nb, i2, norm);
+    } else {
+      if (clov) site_in2<S, true, 3, true>(op, a, nb, i2, norm);
+      else site_in2<S, true, 3, false>(op, a, nb, i2, norm);
+    }
   } else if (ds) {
-    if (clov) site_in2<S, false, true, true>(op, a, nb, i2, norm);
-    else site_in2<S, false, true, false>(op, a, nb, i2, norm);
+    if (two) {
+      if (clov) site_in2<S, false, kReduced ? 2 : 3, true>(op, a, nb, i2, norm);
+      else site_in2<S, false, kReduced ? 2 : 3, false>(op, a, nb, i2, norm);
+    } else {
+      if (clov) site_in2<S, false, 3, true>(op, a, nb, i2, norm);
+      else site_in2<S, false, 3, false>(op, a, nb, i2, norm);
+    }
   } else if (dt) {
-    if (clov) site_in2<S, true, false, true>(op, a, nb, i2, norm);
-    else site_in2<S, true, false, false>(op, a, nb, i2, norm);
+    if (clov) site_in2<S, true, 0, true>(op, a, nb, i2, norm);
+    else site_in2<S, true, 0, false>(op, a, nb, i2, norm);
   } else {
-    if (clov) site_in2<S, false, false, true>(op, a, nb, i2, norm);
-    else site_in2<S, false, false, false>(op, a, nb, i2, norm);
+    if (clov) site_in2<S, false, 0, true>(op, a, nb, i2, norm);
+    else site_in2<S, false, 0, false>(op, a, nb, i2, norm);
   }
   return norm ? int(nb) : 0;
 }
@@ -396,9 +412,11 @@ int launch_site(tp_op op, int prec, const SiteIO& io, Field& dst, SiteCoef cf, i
   tp_ctx ctx = op->g->ctx;
   const Lattice& L = ctx->lat;
   double S = spinor_bytes(prec), Lb = link_bytes(prec), C = clov_bytes(prec);
+  // spatial links read as two rows (12 reals) when they are SU(3) and the precision is reduced
+  double Ls = (prec != TP_F64 && op->g->su3_spatial) ? Lb * 2 / 3 : Lb;
   bool self = cf.c_mu != 0 || (ck && cf.c_A != 0);
   double bytes = double(npar) * L.V2 *
-                 (S + (self ? S : 0) + (cf.c_s != 0 ? S + 6 * Lb : 0) + (cf.c_t != 0 ? S + 2 * Lb : 0) +
+                 (S + (self ? S : 0) + (cf.c_s != 0 ? S + 6 * Ls : 0) + (cf.c_t != 0 ? S + 2 * Lb : 0) +
                   (ck && cf.c_A != 0 ? C : 0) + (io.in2 ? S : 0));
   // the time-line pipeline's stencils are accounted separately from M / residual applies
   ProfScope ps(ctx, cf.c_t != 0 || io.in2 ? KID_SITE_P3 : KID_HOP, bytes);

@@ -144,10 +144,24 @@ struct LinkF {
   const L* p;
   int64_t stride;
 };
-template <typename R, typename L> TP_DEV su3<R> load_su3(const LinkF<L>& f, int64_t i) {
+// ROWS = 3 reads all nine entries; ROWS = 2 reads the first two rows of an SU(3) link and
+// rebuilds the third: the rows are orthonormal with unit determinant, so the third row is
+// the complex conjugate of the cross product of the first two.
+template <typename R, typename L, int ROWS = 3>
+TP_DEV su3<R> load_su3(const LinkF<L>& f, int64_t i) {
   su3<R> u;
+  if constexpr (ROWS == 2) {
 #pragma unroll
-  for (int k = 0; k < 9; ++k) u.e[k] = ld<R, L>(f.p + (int64_t)k * f.stride + i);
+    for (int k = 0; k < 6; ++k) u.e[k] = ld<R, L>(f.p + (int64_t)k * f.stride + i);
+    const cx<R>* a = u.e;
+    const cx<R>* b = u.e + 3;
+    u.e[6] = conj(cmul(a[1], b[2]) - cmul(a[2], b[1]));
+    u.e[7] = conj(cmul(a[2], b[0]) - cmul(a[0], b[2]));
+    u.e[8] = conj(cmul(a[0], b[1]) - cmul(a[1], b[0]));
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u.e[k] = ld<R, L>(f.p + (int64_t)k * f.stride + i);
+  }
   return u;
 }
 

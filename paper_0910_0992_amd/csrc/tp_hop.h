@@ -29,19 +29,20 @@ TP_DEV void hop_time_p3(const SpinorF<S>& f, const LinkF<Lt>& ut, const Geom& g,
 }
 
 // One spatial direction K of the projected hop; c already includes the 1/2 of P+-.
-template <int K, typename S, typename R, typename Lt>
+// ROWS: stored rows of the links (2 = SU(3), third row rebuilt).
+template <int K, typename S, typename R, typename Lt, int ROWS = 3>
 TP_DEV void hop_dir(const SpinorF<S>& nb, const LinkF<Lt>& u_fwd, int64_t i_fwd_link,
                     int64_t jf, const LinkF<Lt>& u_bwd, int64_t jb, R c, cx<R>* out) {
   cx<R> psi[12], h[6], w[6];
   load_spinor<S, R>(nb, jf, psi);
   proj_minus<K, R>(psi, h);
-  su3<R> U = load_su3<R, Lt>(u_fwd, i_fwd_link);
+  su3<R> U = load_su3<R, Lt, ROWS>(u_fwd, i_fwd_link);
   mv(U, h, w);
   mv(U, h + 3, w + 3);
   recon_minus<K, R>(out, w, c);
   load_spinor<S, R>(nb, jb, psi);
   proj_plus<K, R>(psi, h);
-  su3<R> V = load_su3<R, Lt>(u_bwd, jb);
+  su3<R> V = load_su3<R, Lt, ROWS>(u_bwd, jb);
   mvd(V, h, w);
   mvd(V, h + 3, w + 3);
   recon_plus<K, R>(out, w, c);
@@ -49,7 +50,7 @@ TP_DEV void hop_dir(const SpinorF<S>& nb, const LinkF<Lt>& u_fwd, int64_t i_fwd_
 
 // out += c * D_s psi at p3 site (p, t, s): nb is the field on parity 1-p,
 // u_here[k] the links on parity p, u_there[k] those on parity 1-p.
-template <typename S, typename R, typename Lt>
+template <typename S, typename R, typename Lt, int ROWS = 3>
 TP_DEV void hop_space_p3(const SpinorF<S>& nb, const LinkF<Lt>* u_here, const LinkF<Lt>* u_there,
                          const Geom& g, int p, int t, int s, R c, cx<R>* out) {
   C3 q = p3_coords(g, p, s);
@@ -57,11 +58,11 @@ TP_DEV void hop_space_p3(const SpinorF<S>& nb, const LinkF<Lt>* u_here, const Li
   int xp = q.x + 1 == g.Lx ? 0 : q.x + 1, xm = q.x == 0 ? g.Lx - 1 : q.x - 1;
   int yp = q.y + 1 == g.Ly ? 0 : q.y + 1, ym = q.y == 0 ? g.Ly - 1 : q.y - 1;
   int zp = q.z + 1 == g.Lz ? 0 : q.z + 1, zm = q.z == 0 ? g.Lz - 1 : q.z - 1;
-  hop_dir<0, S, R, Lt>(nb, u_here[0], i, p3_idx(g, t, p3_index(g, xp, q.y, q.z)), u_there[0],
+  hop_dir<0, S, R, Lt, ROWS>(nb, u_here[0], i, p3_idx(g, t, p3_index(g, xp, q.y, q.z)), u_there[0],
                        p3_idx(g, t, p3_index(g, xm, q.y, q.z)), c, out);
-  hop_dir<1, S, R, Lt>(nb, u_here[1], i, p3_idx(g, t, p3_index(g, q.x, yp, q.z)), u_there[1],
+  hop_dir<1, S, R, Lt, ROWS>(nb, u_here[1], i, p3_idx(g, t, p3_index(g, q.x, yp, q.z)), u_there[1],
                        p3_idx(g, t, p3_index(g, q.x, ym, q.z)), c, out);
-  hop_dir<2, S, R, Lt>(nb, u_here[2], i, p3_idx(g, t, p3_index(g, q.x, q.y, zp)), u_there[2],
+  hop_dir<2, S, R, Lt, ROWS>(nb, u_here[2], i, p3_idx(g, t, p3_index(g, q.x, q.y, zp)), u_there[2],
                        p3_idx(g, t, p3_index(g, q.x, q.y, zm)), c, out);
 }
 

@@ -112,6 +112,8 @@ struct tp_gauge_s {
   double2* w_d = nullptr;    // p3 layout W(t) = U(t)...U(Lt-1) [2 par][9][V2], FP64
   double2* canon_ax = nullptr;  // axial-gauge links, canonical order (clover build)
   double2* poly = nullptr;   // W(0) per line [2 par][9][Vs2]
+  // every axial-frame spatial link is SU(3) to 1e-9: FP32/FP16 kernels read two rows
+  bool su3_spatial = false;
 };
 
 struct tp_clover_s {
@@ -170,7 +172,10 @@ void launch_unpack(tp_ctx ctx, const Field& src, double2* canon, bool layout4, b
                    const double2* w);
 void launch_pack_links(tp_ctx ctx, tp_gauge g);   // p4 layout (original frame)
 void launch_wline(tp_ctx ctx, tp_gauge g);        // W(t), P from the canonical links
-void launch_axial_links(tp_ctx ctx, tp_gauge g);  // p3 layout, axial frame
+// p3 layout, axial frame.  flags: two device ints zeroed by the caller; [0] is set when an
+// axial-frame spatial link deviates from SU(3) by more than 1e-9, [1] when a time link
+// deviates from unitarity by more than 1e-10
+void launch_axial_links(tp_ctx ctx, tp_gauge g, int* flags);
 void launch_closure(tp_ctx ctx, tp_op op, double* cond_out /*device [2*Vs2]*/);
 void launch_clover_build(tp_ctx ctx, tp_clover c, const double sig[6][2][2][2][2]);
 void launch_clover_derived(tp_ctx ctx, tp_op op, int* bad /*device counter*/);

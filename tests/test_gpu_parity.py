@@ -32,7 +32,19 @@ CASES = {
     "clover_long": ((4, 2, 2, 256), 0.4, 0.1, 6.0, -0.01, 1.6, 1.0, -1),
     # 3 segments, many tiles per workgroup
     "clover_lt48": ((6, 6, 4, 48), 0.35, 0.12, 3.5, -0.01, 1.6, 1.0, -1),
+    # U(3) spatial links (a random U(1) phase on each): not SU(3), so the reduced-precision
+    # kernels read all nine link entries instead of rebuilding the third row
+    "clover_u3_spatial": ((4, 4, 4, 16), 0.35, 0.12, 3.0, -0.05, 1.6, 1.0, -1, "u1_spatial"),
 }
+
+
+def _links(dims, es, et, variant):
+    U = synth.make_links(dims, es, et, 1000)
+    if variant == "u1_spatial":
+        rng = np.random.default_rng(77)
+        ph = np.exp(2j * np.pi * rng.random((3,) + tuple(reversed(dims)) + (1, 1)))
+        U[:3] *= ph
+    return U
 
 
 def _rel(a, b):
@@ -49,8 +61,8 @@ def _close(a, b, tol, what=""):
 @pytest.fixture(scope="module", params=list(CASES))
 def case(request):
     from paper_0910_0992_amd import Operator
-    dims, es, et, xi, m0, cs, ct, bc = CASES[request.param]
-    U = synth.make_links(dims, es, et, 1000)
+    dims, es, et, xi, m0, cs, ct, bc, *variant = CASES[request.param]
+    U = _links(dims, es, et, variant[0] if variant else None)
     c_s = cs / xi
     oop = OOp(U, m0, xi, float(bc), c_s, ct)
     gop = Operator(torch.from_numpy(U).cuda(), m0, xi, c_s, ct, bc)
@@ -171,3 +183,19 @@ def test_plaquette(case):
             acc += np.trace(l, axis1=-2, axis2=-1).real.mean() / 3
         want.append(acc / 3)
     assert abs(ps - want[0]) < 1e-12 and abs(pt - want[1]) < 1e-12
+
+
+def test_gauge_rejects_nonunitary_time_links():
+    """The p3 operators rotate by the time-line products W^dag, a gauge rotation only when
+    the time links are unitary; a non-unitary time link is refused at set-up."""
+    from paper_0910_0992_amd import Operator
+    from paper_0910_0992_amd._lib import TprecError
+    dims = (4, 4, 4, 8)
+    U = synth.make_links(dims, 0.3, 0.1, 5)
+    U[3, 2, 1, 0, 3] *= 1.01
+    with pytest.raises(TprecError, match="unitary"):
+        Operator(torch.from_numpy(U).cuda(), -0.05, 3.0, 0.5, 1.0, -1)
+    # an overall U(1) phase on the time links is still unitary and accepted
+    U = synth.make_links(dims, 0.3, 0.1, 5)
+    U[3] *= np.exp(0.3j)
+    Operator(torch.from_numpy(U).cuda(), -0.05, 3.0, 0.5, 1.0, -1).close()

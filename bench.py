@@ -22,6 +22,30 @@ sys.path.insert(0, ROOT)
 METRIC = "time-to-solution @1e-10 resid (mixed vs FP64 even-odd); operator HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE + WRITE_SIZE runs scaled
+# by a 1 GiB copy (FETCH x2.0000, WRITE x1.0000), for the sources whose hash is recorded; any
+# change to those sources makes the figure stale and it is reported as null.
+TRAFFIC = {
+    ("clover_32x256", "F32", "hop_site"): {
+        "bytes_per_launch": 4.412e9,
+        "sources": ["k_site.hip", "tp_hop.h", "tp_device.h"],
+        "sha256": "fd0490eba94d77609f2c42734cbef73169b81394f60a015bc33fd7824cb862d2",
+    },
+}
+
+
+def measured_traffic(workload, prec, kernel):
+    import hashlib
+
+    rec = TRAFFIC.get((workload, prec, kernel))
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        with open(os.path.join(ROOT, "paper_0910_0992_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return rec["bytes_per_launch"] if h.hexdigest() == rec["sha256"] else None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -31,9 +55,33 @@ def parse():
     ap.add_argument("--workload", default="clover_32x256")
     ap.add_argument("--prec", default="F32", help="inner precision of the mixed solve")
     ap.add_argument("--no-baseline", action="store_true", help="skip the FP64 even-odd solve")
+    ap.add_argument("--no-f16n", action="store_true", help="skip the FP16+norm mixed solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-prof", action="store_true", help="no per-kernel events in the timed region")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 1 GiB, five times: its FETCH_SIZE / WRITE_SIZE
+    counters per dispatch are the scale for the counters of the operator kernels."""
+    import torch
+
+    n = 1 << 28  # float32 elements = 1 GiB
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(5):
+        dst.copy_(src)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / 5
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "avg_ms": ms,
+                      "GBs": 8 * n / (ms * 1e-3) / 1e9}))
 
 
 def cpu_baseline(cfg, applies):
@@ -74,6 +122,9 @@ def cpu_baseline(cfg, applies):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
               "(the multi-GPU path is a design note only)", file=sys.stderr)
@@ -166,12 +217,22 @@ def main():
         bytes_per = d["bytes"] / d["launches"]
         gbs = bytes_per / (avg_ms * 1e-3) / 1e9
         res["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": gbs, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                           "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                           "traffic": measured_traffic(args.workload, args.prec, dom),
                            "avg_ms": avg_ms, "bytes_per_launch": bytes_per, "launches": d["launches"]}
         res["kernels"] = {k: {"launches": v["launches"], "avg_ms": v["ms"] / v["launches"],
                               "GBs": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None,
                               "share": v["ms"] / sum(s["ms"] for s in stats.values())}
                           for k, v in stats.items()}
+    if args.prec != "F16N" and not args.no_f16n:
+        htts, hinfos, _, xh = run("TEMPORAL_SCHUR", "F16N", 1, 1, False)
+        res["f16n_tts_s"] = htts
+        res["f16n_iters"] = hinfos[-1]["iters"]
+        res["f16n_outer_cycles"] = hinfos[-1]["outer_iters"]
+        res["f16n_true_rel_resid"] = hinfos[-1]["true_rel_resid"]
+        res["f16n_rel_diff_vs_f32_solution"] = (torch.linalg.vector_norm(xh - x) /
+                                                 torch.linalg.vector_norm(x)).item()
+        del xh
     if not args.no_baseline:
         btts, binfos, _, xb = run("SCHUR4D", "F64", max(1, args.steps - 1), min(args.warmup, 1), False)
         res["fp64_even_odd_tts_s"] = btts

@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--no-f16n", action="store_true", help="skip the FP16+norm mixed solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-prof", action="store_true", help="no per-kernel events in the timed region")
+    ap.add_argument("--schemes", action="store_true",
+                    help="only compare the four schemes in FP64 on the workload: BiCGStab iterations "
+                         "and time, CGNR iterations and the Lanczos condition number")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -120,8 +123,46 @@ def cpu_baseline(cfg, applies):
     }
 
 
+def compare_schemes(args):
+    """FP64 solves of the workload's Gaussian source with each scheme: BiCGStab (iterations,
+    time) and CGNR with the Lanczos estimate of kappa(A^dagger A) of the preconditioned
+    operator.  One JSON line."""
+    import torch
+
+    import synth
+    from paper_0910_0992_amd import Operator
+
+    cfg = synth.WORKLOADS[args.workload]
+    dims, xi = cfg["dims"], cfg["xi"]
+    U = synth.make_links(dims, cfg["eps_s"], cfg["eps_t"], cfg["seed"])
+    eta = torch.from_numpy(synth.make_source(dims, 2000)).cuda()
+    op = Operator(torch.from_numpy(U).cuda(), cfg["m0"], xi, cfg["csw_s"] / xi, cfg["csw_t"], -1)
+    del U
+    out = {}
+    for scheme in ("UNPREC", "SCHUR4D", "TEMPORAL", "TEMPORAL_SCHUR"):
+        op.solve(eta, scheme=scheme, solver="BICGSTAB", prec="F64", tol=1e-10)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, ib = op.solve(eta, scheme=scheme, solver="BICGSTAB", prec="F64", tol=1e-10)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        _, ic = op.solve(eta, scheme=scheme, solver="CGNR", prec="F64", tol=1e-10, estimate_kappa=True)
+        out[scheme] = {"bicgstab_iters": ib["iters"], "bicgstab_s": tb,
+                       "bicgstab_true_rel_resid": ib["true_rel_resid"], "cgnr_iters": ic["iters"],
+                       "kappa": ic["kappa_est"], "lambda_min": ic["lambda_min"],
+                       "lambda_max": ic["lambda_max"], "cgnr_true_rel_resid": ic["true_rel_resid"]}
+        print(f"[bench] {scheme}: BiCGStab {ib['iters']} its {tb:.3f} s, CGNR {ic['iters']} its, "
+              f"kappa {ic['kappa_est']:.1f}", file=sys.stderr, flush=True)
+    op.close()
+    print(json.dumps({"mode": "schemes", "workload": args.workload, "dims": dims, "xi": xi,
+                      "m0": cfg["m0"], "results": out}))
+
+
 def main():
     args = parse()
+    if args.schemes:
+        compare_schemes(args)
+        return
     if args.copy_calibration:
         copy_calibration()
         return

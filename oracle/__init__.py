@@ -27,6 +27,8 @@ Modules:
     schemes   parity masks and the four preconditioning schemes (Sec. II.B)
     krylov    CGNR, BiCGStab and the Lanczos condition-number estimate
     force     gradient of |M^-1 eta|^2 w.r.t. the links and the source
+    sampled   M at chosen sites and T^-1 on chosen time lines of a large lattice, from
+              the functions above called on a small window or a single line
 
 Parity status: every function is pinned by a test in ``tests/test_oracle_*.py``
 (free-field momentum space, brute-force dense inverses, gauge covariance,

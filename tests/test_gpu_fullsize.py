@@ -1,0 +1,198 @@
+"""GPU parity at the benchmark workloads' full sizes, in the launch configurations the
+benchmark uses, against the oracle evaluated at sampled sites and time lines
+(`oracle.sampled`), and against properties that hold at any size.
+
+* M (every precision) at 48 sampled sites, T^-1 and T^dagger^-1 on 8 sampled time lines;
+* the preconditioned operators: S_L M S_R y against prepare(M(reconstruct(y))) and
+  gamma5-hermiticity, at the full shape;
+* the benchmark solve (temporal+3D-ILU, mixed FP32): the oracle's residual at sampled
+  sites is bounded by the library's FP64 true residual, which must be <= 1e-10;
+* 24^3x128: the 12 spin-colour point sources at the origin, FP32 and FP16+norm inner
+  solves, each to 1e-10, against the FP64 even-odd solution;
+* 12^3x64: the gradient of |M^-1 eta|^2 against central finite differences
+  (h = 1e-6, 32 random su(3) directions) with FP64 solves to 1e-13.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import sampled
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"F64": 1e-12, "F32": 6e-6, "F16N": 8e-3}
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module", params=["clover_16x128", "clover_32x256"])
+def big(request):
+    from paper_0910_0992_amd import Operator
+    cfg = synth.WORKLOADS[request.param]
+    dims, xi = cfg["dims"], cfg["xi"]
+    print(f"[fullsize] {request.param} {dims}: generating links", flush=True)
+    U = synth.make_links(dims, cfg["eps_s"], cfg["eps_t"], cfg["seed"])
+    eta = synth.make_source(dims, 2000)
+    c_s, c_t = cfg["csw_s"] / xi, cfg["csw_t"]
+    gop = Operator(torch.from_numpy(U).cuda(), cfg["m0"], xi, c_s, c_t, -1)
+    rng = np.random.default_rng(7)
+    lx, ly, lz, lt = dims
+    sites = [(0, 0, 0, 0), (lx - 1, ly - 1, lz - 1, lt - 1), (3, 0, lz - 1, lt - 1), (0, 5, 2, 0)]
+    sites += [tuple(int(rng.integers(0, L)) for L in dims) for _ in range(44)]
+    lines = [(0, 0, 0), (lx - 1, ly - 1, lz - 1)] + [tuple(int(rng.integers(0, L)) for L in dims[:3])
+                                                    for _ in range(6)]
+    print(f"[fullsize] {request.param}: operator ready", flush=True)
+    yield dict(name=request.param, cfg=cfg, dims=dims, U=U, eta=eta, teta=torch.from_numpy(eta).cuda(),
+               gop=gop, m0=cfg["m0"], xi=xi, c_s=c_s, c_t=c_t, sites=sites, lines=lines)
+    gop.close()
+
+
+def _at(field, sites):
+    return np.stack([field[t, z, y, x] for (x, y, z, t) in sites])
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32", "F16N"])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_M_sampled_sites(big, prec, dagger):
+    b = big
+    got = _at(_np(b["gop"].apply_M(b["teta"], prec, dagger=dagger)), b["sites"])
+    ref = sampled.M_at_sites(b["U"], b["eta"], b["sites"], b["m0"], b["xi"], -1.0, b["c_s"], b["c_t"],
+                             dagger=dagger)
+    assert _rel(got, ref) < TOL[prec], (b["name"], prec, _rel(got, ref))
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32", "F16N"])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_Tinv_sampled_lines(big, prec, dagger):
+    b = big
+    out = _np(b["gop"].apply_Tinv(b["teta"], prec, dagger=dagger))
+    got = np.stack([out[:, z, y, x] for (x, y, z) in b["lines"]])
+    mu = b["m0"] + 1.0 + 3.0 / b["xi"]
+    ref = sampled.Tinv_on_lines(b["U"], b["eta"], b["lines"], mu, -1.0, dagger=dagger)
+    assert _rel(got, ref) < TOL[prec], (b["name"], prec, _rel(got, ref))
+
+
+@pytest.mark.parametrize("scheme", ["TEMPORAL", "TEMPORAL_SCHUR"])
+def test_prec_is_SL_M_SR(big, scheme):
+    """The fused preconditioned apply equals the composition of the separately
+    parity-checked maps: S_L M S_R y = prepare(M(reconstruct(y)))."""
+    g = big["gop"]
+    y = big["teta"]
+    a = _np(g.apply_prec(y, scheme, "F64"))
+    c = _np(g.prepare_source(g.apply_M(g.reconstruct(y, scheme, "F64"), "F64"), scheme, "F64"))
+    assert _rel(a, c) < 1e-12
+    a32 = _np(g.apply_prec(y, scheme, "F32"))
+    assert _rel(a32, c) < 2e-5
+
+
+@pytest.mark.parametrize("scheme", ["TEMPORAL_SCHUR", "SCHUR4D"])
+def test_prec_gamma5_hermiticity(big, scheme):
+    g = big["gop"]
+    phi = torch.from_numpy(synth.make_source(big["dims"], 2003)).cuda()
+    psi = big["teta"]
+    lhs = torch.vdot(phi.flatten(), g.apply_prec(psi, scheme, "F64").flatten()).item()
+    rhs = torch.vdot(g.apply_prec(phi, scheme, "F64", dagger=True).flatten(), psi.flatten()).item()
+    assert abs(lhs - rhs) < 1e-11 * abs(lhs), (lhs, rhs)
+
+
+def test_bench_solve_residual_sampled(big):
+    """The benchmark's solve; the oracle's residual on 48 sites cannot exceed the global one."""
+    b = big
+    x, info = b["gop"].solve(b["teta"], scheme="TEMPORAL_SCHUR", prec="F32", tol=1e-10)
+    assert info["true_rel_resid"] <= 1e-10, info
+    xs = _np(x)
+    r = _at(b["eta"], b["sites"]) - sampled.M_at_sites(b["U"], xs, b["sites"], b["m0"], b["xi"], -1.0,
+                                                      b["c_s"], b["c_t"])
+    assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(b["eta"]), (np.linalg.norm(r), info)
+
+
+def test_point_sources_24x128():
+    """The 12 unit spin-colour sources at the origin: each mixed solve reaches 1e-10 and
+    agrees with the FP64 even-odd solve."""
+    from paper_0910_0992_amd import Operator
+    cfg = synth.WORKLOADS["clover_24x128"]
+    dims, xi = cfg["dims"], cfg["xi"]
+    print(f"[fullsize] clover_24x128 {dims}: generating links", flush=True)
+    U = synth.make_links(dims, cfg["eps_s"], cfg["eps_t"], cfg["seed"])
+    g = Operator(torch.from_numpy(U).cuda(), cfg["m0"], xi, cfg["csw_s"] / xi, cfg["csw_t"], -1)
+    try:
+        sites = [(0, 0, 0, 0), (1, 0, 0, 0), (0, 0, 0, 1), (23, 23, 23, 127)]
+        for k in range(12):
+            eta = synth.make_point_source(dims, k // 3, k % 3)
+            te = torch.from_numpy(eta).cuda()
+            x64, i64 = g.solve(te, scheme="SCHUR4D", prec="F64", tol=1e-10)
+            assert i64["true_rel_resid"] <= 1e-10, i64
+            for prec in ("F32", "F16N"):
+                x, info = g.solve(te, scheme="TEMPORAL_SCHUR", prec=prec, tol=1e-10)
+                assert info["true_rel_resid"] <= 1e-10, (k, prec, info)
+                rel = (torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64)).item()
+                assert rel < 1e-7, (k, prec, rel)
+            if k % 4 == 0:
+                r = _at(eta, sites) - sampled.M_at_sites(U, _np(x), sites, cfg["m0"], xi, -1.0,
+                                                         cfg["csw_s"] / xi, cfg["csw_t"])
+                assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(eta)
+            print(f"[fullsize] point source {k}: FP64 {i64['iters']} its, mixed {info['iters']} its",
+                  flush=True)
+    finally:
+        g.close()
+
+
+def test_gradient_fd_12x64():
+    """d|M^-1 eta|^2 / dh for U -> exp(i h omega) U against the autograd link gradient, and
+    the source gradient.  The link gradient holds the SW term fixed, so the check runs at
+    csw = 0, where that is the whole derivative."""
+    from paper_0910_0992_amd import Operator
+    from paper_0910_0992_amd.api import SolveFn
+    cfg = synth.WORKLOADS["clover_12x64"]
+    dims, xi, m0 = cfg["dims"], cfg["xi"], cfg["m0"]
+    U = synth.make_links(dims, cfg["eps_s"], cfg["eps_t"], cfg["seed"])
+    eta = synth.make_source(dims, 2000)
+
+    def loss(Uh):
+        g = Operator(torch.from_numpy(Uh).cuda(), m0, xi, 0.0, 0.0, -1)
+        try:
+            x, info = g.solve(torch.from_numpy(eta).cuda(), scheme="TEMPORAL_SCHUR", prec="F64", tol=1e-13)
+            return torch.vdot(x.flatten(), x.flatten()).real.item()
+        finally:
+            g.close()
+
+    links = torch.from_numpy(U).cuda().requires_grad_(True)
+    te = torch.from_numpy(eta).cuda().requires_grad_(True)
+    x = SolveFn.apply(links, te, m0, xi, 0.0, 0.0, -1, "TEMPORAL_SCHUR", "F64", 1e-13)
+    L = torch.vdot(x.flatten(), x.flatten()).real
+    L.backward()
+    gU = _np(links.grad)
+    gE = _np(te.grad)
+    L0 = L.item()
+    assert abs(loss(U) - L0) < 1e-12 * L0
+    h = 1e-6
+    worst = 0.0
+    for k in range(32):
+        om = synth.make_algebra_field(dims, 4000 + k)
+        fd = (loss(synth.expi_su3(h * om) @ U) - loss(synth.expi_su3(-h * om) @ U)) / (2 * h)
+        an = np.vdot(gU, 1j * om @ U).real
+        worst = max(worst, abs(fd - an) / L0)
+        if k % 8 == 7:
+            print(f"[fullsize] FD direction {k}: worst relative deviation {worst:.2e}", flush=True)
+    assert worst < 5e-6, worst
+    d = synth.make_source(dims, 2001)
+    fd = (loss_eta(U, eta + h * d, m0, xi) - loss_eta(U, eta - h * d, m0, xi)) / (2 * h)
+    assert abs(fd - np.vdot(gE, d).real) < 5e-6 * L0
+
+
+def loss_eta(U, eta, m0, xi):
+    from paper_0910_0992_amd import Operator
+    g = Operator(torch.from_numpy(U).cuda(), m0, xi, 0.0, 0.0, -1)
+    try:
+        x, _ = g.solve(torch.from_numpy(eta).cuda(), scheme="TEMPORAL_SCHUR", prec="F64", tol=1e-13)
+        return torch.vdot(x.flatten(), x.flatten()).real.item()
+    finally:
+        g.close()

@@ -454,6 +454,7 @@ tp_status tp_op_create(tp_gauge g, tp_clover c, double m0, double gamma_f, tp_op
     try {
       if (!(op->mu > 0)) TP_THROW(TP_EINVAL, "mass term mu = m0 + 1 + 3/gamma_f must be positive");
       op->gclos = static_cast<double2*>(dev_alloc(size_t(2) * 9 * L.Vs2 * sizeof(double2)));
+      op->gclos_f = static_cast<float2*>(dev_alloc(size_t(2) * 9 * L.Vs2 * sizeof(float2)));
       size_t cb = size_t(2) * 36 * L.V2;
       op->a4_mu = static_cast<double2*>(dev_alloc(cb * sizeof(double2)));
       op->a4_inv = static_cast<double2*>(dev_alloc(cb * sizeof(double2)));
@@ -508,6 +509,7 @@ tp_status tp_op_destroy(tp_op op) {
     (void)hipStreamSynchronize(op->g->ctx->stream);
     ws_free(op);
     dev_free(op->gclos);
+    dev_free(op->gclos_f);
     dev_free(op->a4_mu);
     dev_free(op->a4_inv);
     dev_free(op->a4_mu_f);

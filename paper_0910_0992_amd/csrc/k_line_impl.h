@@ -16,8 +16,9 @@
 // it with a prefix sum and delta' = G^dagger rho(Lt-1).  No link is read by a
 // scan.  Because the recurrence has a scalar coefficient, a line splits into
 // chunks whose partial sums combine exactly through LDS (carry = mu^-k times
-// the neighbour chunk's head).  The closure G = (I - mu^-Lt P)^-1 P / mu is FP64
-// and applied in FP64.
+// the neighbour chunk's head).  The closure G = (I - mu^-Lt P)^-1 P / mu is formed
+// in FP64 at set-up (mu^-Lt is far below FP32 range on long lines) and applied in the
+// kernel's arithmetic precision.
 //
 // Workgroup = LPB lines (whole tiles of 4 lines) x NCH chunks of CH consecutive
 // time slices.  Threads are numbered in memory order of the tiled p3 layout
@@ -28,6 +29,10 @@
 
 namespace {
 
+template <typename R> struct Cplx2;
+template <> struct Cplx2<double> { using T = double2; };
+template <> struct Cplx2<float> { using T = float2; };
+
 template <typename R>
 struct ScanCtx {
   int l, j, LPB, NCH, t0, Lt, CH;
@@ -37,7 +42,7 @@ struct ScanCtx {
   bool fast;    // NCH % 16 == 0: wavefront-shuffle scan (each wave = 16 chunks x 4 lines)
   R inv_mu, f;  // 1/mu and mu^-CH
   const R* mupow;  // mu^-k, k = 0..Lt
-  const double2* G;  // closure planes [9][Vs2] of this parity
+  const typename Cplx2<R>::T* G;  // closure planes [9][Vs2] of this parity
   int64_t gstride;
 };
 
@@ -152,16 +157,9 @@ TP_DEV void scan_core(cx<R> (&v)[CH][NV], cx<R>* lds, const ScanCtx<R>& sc) {
       }
       X[c] = acc;
     }
-    cx<R> C[6], D[6];
-    cx<double> Z[6];
+    cx<R> C[6], D[6], Z[6];
     if (sc.fast) {
-      cx<R> Cr[6], Zr[6];
-      combine_fast<R, BWD>(X, Cr, Zr, lds, sc);
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        C[c] = Cr[c];
-        Z[c] = cx<double>{double(Zr[c].re), double(Zr[c].im)};
-      }
+      combine_fast<R, BWD>(X, C, Z, lds, sc);
     } else {
     // combine chunk heads (backward) / tails (forward) across the line (Hillis-Steele)
     R fd = sc.f;
@@ -188,21 +186,20 @@ TP_DEV void scan_core(cx<R> (&v)[CH][NV], cx<R>* lds, const ScanCtx<R>& sc) {
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       C[c] = has ? lds[oc + c] : czero<R>();
-      cx<R> z = lds[oz + c];
-      Z[c] = cx<double>{double(z.re), double(z.im)};
+      Z[c] = lds[oz + c];
     }
     __syncthreads();
     }
-    // closure in FP64: delta = G z (backward) or G^dagger z (forward), per colour vector
+    // closure: delta = G z (backward) or G^dagger z (forward), per colour vector
     if (sc.active) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        cx<double> acc0 = czero<double>(), acc1 = czero<double>();
+        cx<R> acc0 = czero<R>(), acc1 = czero<R>();
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
           int k = BWD ? 3 * a + b : 3 * b + a;
-          double2 e = sc.G[(int64_t)k * sc.gstride + sc.s];
-          cx<double> gk = cx<double>{e.x, e.y};
+          const auto e = sc.G[(int64_t)k * sc.gstride + sc.s];
+          cx<R> gk = cx<R>{R(e.x), R(e.y)};
           if constexpr (BWD) {
             acc0 += cmul(gk, Z[b]);
             acc1 += cmul(gk, Z[3 + b]);
@@ -211,8 +208,8 @@ TP_DEV void scan_core(cx<R> (&v)[CH][NV], cx<R>* lds, const ScanCtx<R>& sc) {
             acc1 += cmulc(gk, Z[3 + b]);
           }
         }
-        D[a] = cx<R>{R(acc0.re), R(acc0.im)};
-        D[3 + a] = cx<R>{R(acc1.re), R(acc1.im)};
+        D[a] = acc0;
+        D[3 + a] = acc1;
       }
     } else {
 #pragma unroll
@@ -245,11 +242,12 @@ template <typename S>
 struct LineArgs {
   SpinorF<S> in, out, aux, self, base;
   const typename Prec<S>::L* clov;  // A/2 blocks of this parity
-  const double2* G;
+  const typename Prec<S>::L* G;  // closure, FP64 or FP32
   const typename Prec<S>::R* mupow;
   double inv_mu, f, c_out, c_base;
   Geom g;
   int par, LPB, NCH;
+  int lds_table;  // complex elements of LDS used by the chunk combine (the rest follows it)
 };
 
 template <typename S>
@@ -376,12 +374,21 @@ __global__ void __launch_bounds__(1024) k_line(LineArgs<S> a) {
 //   y   = A w,  w = C_R (C_L u + psi_e) = (f, b + psi_lo)
 //   chi_e = psi_e + C_L y = (psi_up + y_up, psi_lo + T^-1 y_lo)               -> out
 //   n_e = C_R C_L (y - u) = (T^dag^-1 (y_up - u_up), T^-1 y_lo - b)          -> base
+// Threads per workgroup of the middle kernel: one slice per thread needs 1024-thread groups on
+// 256-slice lines; two or more slices per thread run in 512-thread groups with twice the
+// registers per thread.
+template <int CH> constexpr int mid_threads() { return CH == 1 ? 1024 : 512; }
+
 template <typename S, int CH>
-__global__ void __launch_bounds__(1024) k_ilu_mid(LineArgs<S> a) {
+__global__ void __launch_bounds__(mid_threads<CH>()) k_ilu_mid(LineArgs<S> a) {
   using R = typename Prec<S>::R;
   using Lk = typename Prec<S>::L;
   extern __shared__ char smem_raw[];
   cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
+  // b = T^-1 u_lo is needed again only at the end: it waits in LDS ([CH][6][threads],
+  // consecutive threads adjacent) instead of registers while y and the second scans run
+  cx<R>* park = lds + a.lds_table;
+  const int nthr = blockDim.x;
   ScanCtx<R> sc = make_ctx<S>(a, CH);
   const int s = sc.active ? sc.s : 0;
   cx<R> b[CH][6], f[CH][6], uup[CH][6];
@@ -402,6 +409,10 @@ __global__ void __launch_bounds__(1024) k_ilu_mid(LineArgs<S> a) {
   }
   scan_core<R, CH, 6, true>(b, lds, sc);
   scan_core<R, CH, 6, false>(f, lds, sc);
+#pragma unroll
+  for (int k = 0; k < CH; ++k)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) park[(k * 6 + c) * nthr + threadIdx.x] = b[k][c];
   // y = A w; write chi_up; second-phase inputs y_lo (backward) and y_up - u_up (forward)
 #pragma unroll
   for (int k = 0; k < CH; ++k) {
@@ -410,7 +421,7 @@ __global__ void __launch_bounds__(1024) k_ilu_mid(LineArgs<S> a) {
       cx<R> w[12], y[12], pl[6], ps[6];
       load_half<S, R>(a.in, 1, i, pl);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) { w[c] = f[k][c]; w[6 + c] = b[k][c] + pl[c]; }
+      for (int c = 0; c < 6; ++c) { w[c] = f[k][c]; w[6 + c] = park[(k * 6 + c) * nthr + threadIdx.x] + pl[c]; }
       clover_apply<R, Lk>(a.clov, a.g.V2, i, w, y);
       load_half<S, R>(a.in, 0, i, ps);
 #pragma unroll
@@ -437,7 +448,7 @@ __global__ void __launch_bounds__(1024) k_ilu_mid(LineArgs<S> a) {
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       pl[c] += uup[k][c];
-      n[c] = uup[k][c] - b[k][c];
+      n[c] = uup[k][c] - park[(k * 6 + c) * nthr + threadIdx.x];
     }
     store_half<S, R>(a.out, 1, i, pl);
     store_half<S, R>(a.base, 0, i, f[k]);
@@ -475,7 +486,8 @@ LineArgs<S> base_args(tp_op op, int par) {
     if constexpr (sizeof(Lk) == 16) a.clov = (const Lk*)op->c->a3_d + (int64_t)par * 36 * L.V2;
     else a.clov = (const Lk*)op->c->a3_f + (int64_t)par * 36 * L.V2;
   }
-  a.G = op->gclos;
+  if constexpr (sizeof(Lk) == 16) a.G = (const Lk*)op->gclos;
+  else a.G = (const Lk*)op->gclos_f;
   if constexpr (sizeof(Lk) == 16) a.mupow = (const typename Prec<S>::R*)op->mupow_d;
   else a.mupow = (const typename Prec<S>::R*)op->mupow_f;
   a.inv_mu = 1.0 / op->mu;
@@ -496,14 +508,18 @@ SpinorF<S> pv(const Field* f, int p) {
 template <typename S>
 constexpr int max_threads() { return sizeof(typename Prec<S>::R) == 8 ? 512 : 1024; }
 
+// LDS of a line kernel: the chunk-combine table (shuffle path: [tile][16 segments][4 lines][6];
+// LDS path: [chunk][line][6]) followed by `park` complex values per thread.
 template <typename S, typename K>
-void go(tp_op op, K kern, LineArgs<S>& a, Shape sh) {
+void go(tp_op op, K kern, LineArgs<S>& a, Shape sh, int park = 0) {
   tp_ctx ctx = op->g->ctx;
   const Lattice& L = ctx->lat;
   a.LPB = sh.LPB;
   a.NCH = sh.NCH;
   a.f = pow(op->mu, -double(sh.CH));
-  size_t lds = size_t(sh.LPB) * sh.NCH * 6 * sizeof(cx<typename Prec<S>::R>);
+  const bool fast = sh.NCH % 16 == 0;
+  a.lds_table = fast ? sh.LPB * 16 * 6 : sh.LPB * sh.NCH * 6;
+  size_t lds = (size_t(a.lds_table) + size_t(park) * sh.LPB * sh.NCH) * sizeof(cx<typename Prec<S>::R>);
   dim3 grid((unsigned)((L.Vs2 + sh.LPB - 1) / sh.LPB));
   hipLaunchKernelGGL(kern, grid, dim3(sh.LPB * sh.NCH), lds, ctx->stream, a);
   LAUNCH_CHECK();
@@ -558,8 +574,17 @@ void mid_t(tp_op op, const Field& psi, const Field& u, Field& chi, Field& n) {
   a.aux = pv<S>(&u, 0);
   a.out = pv<S>(&chi, 0);
   a.base = pv<S>(&n, 0);
-  Shape sh = pick_shape(L.L[3], 16, max_threads<S>(), {1, 2, 4});
-  TP_CH_DISPATCH(sh.CH, go<S>(op, k_ilu_mid<S, CH>, a, sh))
+  const int Lt = L.L[3];
+  // one slice per thread where the line fits a workgroup (measured fastest), else more
+  Shape sh{0, 0, 0};
+  for (int ch : {1, 2, 4}) {
+    const int mt = std::min(max_threads<S>(), ch == 1 ? mid_threads<1>() : mid_threads<2>());
+    if (Lt % ch || (Lt / ch) * kTile > mt) continue;
+    sh = pick_shape(Lt, 16, mt, {ch});
+    break;
+  }
+  if (sh.CH == 0) TP_THROW(TP_EDIMS, "time extent not supported by the line kernels");
+  TP_CH_DISPATCH(sh.CH, go<S>(op, k_ilu_mid<S, CH>, a, sh, 6 * CH))
 }
 
 }  // namespace

@@ -279,8 +279,8 @@ TP_DEV double norm1(const cx<double>* m) {
 
 // Closure of the temporal inverse per line: K = (I - mu^-Lt P)^-1 and G = K P / mu,
 // so that delta = G sigma(0) for T^-1 and delta' = G^dagger rho(Lt-1) for T^dagger^-1.
-__global__ void k_closure(const double2* __restrict__ poly, double2* gclos, double* cond,
-                          Geom g, double mu, double mu_mlt) {
+__global__ void k_closure(const double2* __restrict__ poly, double2* gclos, float2* gclos_f,
+                          double* cond, Geom g, double mu, double mu_mlt) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   int p = blockIdx.y;
   if (s >= g.Vs2) return;
@@ -303,8 +303,12 @@ __global__ void k_closure(const double2* __restrict__ poly, double2* gclos, doub
   if (!isfinite(c)) c = INFINITY;
   cond[(int64_t)p * g.Vs2 + s] = c;
   double2* go = gclos + (int64_t)p * 9 * g.Vs2;
+  float2* gf = gclos_f + (int64_t)p * 9 * g.Vs2;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) go[(int64_t)k * g.Vs2 + s] = make_double2(G[k].re / mu, G[k].im / mu);
+  for (int k = 0; k < 9; ++k) {
+    go[(int64_t)k * g.Vs2 + s] = make_double2(G[k].re / mu, G[k].im / mu);
+    gf[(int64_t)k * g.Vs2 + s] = make_float2(float(G[k].re / mu), float(G[k].im / mu));
+  }
 }
 
 // ---- clover ------------------------------------------------------------------------------
@@ -616,7 +620,7 @@ void launch_closure(tp_ctx ctx, tp_op op, double* cond) {
   const Lattice& L = ctx->lat;
   double mu_mlt = pow(op->mu, -double(L.L[3]));
   hipLaunchKernelGGL(k_closure, dim3((L.Vs2 + 63) / 64, 2), dim3(64), 0, ctx->stream,
-                     op->g->poly, op->gclos, cond, L.g, op->mu, mu_mlt);
+                     op->g->poly, op->gclos, op->gclos_f, cond, L.g, op->mu, mu_mlt);
   LAUNCH_CHECK();
 }
 

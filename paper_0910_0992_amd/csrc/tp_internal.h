@@ -132,6 +132,7 @@ struct tp_op_s {
   tp_clover c = nullptr;
   double m0 = 0, gf = 1, mu = 1;
   double2* gclos = nullptr;  // per line G = (I - mu^-Lt P)^-1 P / mu  [2 par][9][Vs2]
+  float2* gclos_f = nullptr;  // the same, rounded to FP32 (for the FP32 and FP16 scans)
   double2* a4_mu = nullptr;     // p4 (A+mu)/2 chiral blocks [2][36][V2]
   double2* a4_inv = nullptr;    // p4 (A+mu)^-1 / 2 chiral blocks [2][36][V2]
   float2* a4_mu_f = nullptr;

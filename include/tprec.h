@@ -157,18 +157,19 @@ typedef struct {
   int32_t solver;          /* TP_CGNR or TP_BICGSTAB                                */
   int32_t prec;            /* inner precision: TP_F64, TP_F32, TP_F16N              */
   int32_t max_iter;        /* cap on inner Krylov iterations summed over restarts  */
-  int32_t max_restarts;    /* cap on outer (defect-correction) cycles               */
+  int32_t max_restarts;    /* cap on FP64 corrections (updates or cycles)           */
   int32_t use_x0;          /* 1: x holds the initial guess on entry                 */
   int32_t estimate_kappa;  /* 1 (CGNR only): Lanczos estimate of kappa(Mt^dag Mt)  */
   int32_t reserved;
   double tol;              /* target true relative residual |eta - M x| / |eta|     */
-  double inner_tol;        /* relative reduction per inner solve; 0 = default
-                              (1e-12 F64, 1e-6 F32, 2e-3 F16N)                      */
+  double inner_tol;        /* BiCGStab in F32/F16N: reliable-update threshold delta
+                              (0 = default 1e-3 F32, 0.1 F16N); CGNR: relative
+                              reduction per inner solve (0 = 1e-6 F32, 2e-3 F16N)   */
 } tp_solve_params;
 
 typedef struct {
   int32_t iters;           /* inner Krylov iterations, all cycles                   */
-  int32_t outer_iters;     /* defect-correction cycles                              */
+  int32_t outer_iters;     /* FP64 corrections: reliable updates or cycles          */
   int32_t applies;         /* preconditioned-operator applies                       */
   int32_t restarts;        /* BiCGStab breakdown restarts                           */
   double true_rel_resid;   /* FP64 |eta - M x| / |eta| at exit                      */
@@ -179,9 +180,15 @@ typedef struct {
 } tp_solve_info;
 
 /* Solves M x = eta (canonical device spinors) to the FP64 true relative
- * residual `tol`: eta~ = S_L r, Krylov on Mt y = eta~ in `prec`, x += S_R y,
- * r = eta - M x in FP64, repeated until |r| <= tol |eta| (defect correction).
- * Returns TP_ENOCONV with x = best iterate if the caps are reached. */
+ * residual `tol` with the preconditioned operator Mt = S_L M S_R of `scheme`
+ * (eta~ = S_L r, Krylov on Mt y = eta~ in `prec`, x += S_R y, r = eta - M x in
+ * FP64).  F64: one Krylov solve.  F32/F16N BiCGStab: reliable updates (Sleijpen
+ * and van der Vorst 1996): when the recursive residual has dropped by delta below
+ * its maximum since the last update, y is folded into x in FP64 and the recursion
+ * continues from the preconditioned FP64 true residual, keeping its search
+ * direction.  CGNR, and BiCGStab after a stall, use defect correction: each cycle
+ * restarts the Krylov solve on the new residual.  Returns TP_ENOCONV with x = best
+ * iterate if the caps are reached. */
 tp_status tp_solve(tp_op op, const tp_solve_params* params, void* x, const void* eta,
                    tp_solve_info* info);
 

@@ -498,6 +498,152 @@ double true_residual(tp_op op, bool l4, const Field& x, const Field& eta, Field&
   return red[0];
 }
 
+// Mixed-precision BiCGStab with reliable updates (Sleijpen and van der Vorst 1996): the
+// inner recurrences run in the low precision on the preconditioned operator, and whenever
+// the recursive residual has dropped by `delta` below its largest value since the last
+// update (or reached the target), the accumulated correction is folded into the FP64
+// solution and the recursive residual is replaced by the preconditioned FP64 true residual.
+// The search direction and the shadow residual carry on, so the Krylov space is kept
+// across updates.  Returns false (x64 holds the best iterate, r64 its residual) when the
+// recurrence stalls or diverges, for the caller's fallback.
+bool bicgstab_reliable(tp_op op, const tp_solve_params& P, const KrylovOp& A, bool l4, bool sub,
+                       double delta, Field& x64, const Field& eta64, Field& r64, double eta2, double& r2,
+                       double tol, int max_iter, tp_solve_info& info) {
+  tp_ctx ctx = op->g->ctx;
+  Field& xbest = ws_get(op, TP_F64, W_TMP64);
+  const int pr = A.prec, p0 = A.par0, np = A.npar;
+  Field& r = ws_get(op, pr, W_R);
+  Field& rh = ws_get(op, pr, W_RHAT);
+  Field& p = ws_get(op, pr, W_P);
+  Field& v = ws_get(op, pr, W_V);
+  Field& s = ws_get(op, pr, W_S);
+  Field& t = ws_get(op, pr, W_T);
+  Field& y = ws_get(op, pr, W_Y);
+  Field& rin = ws_get(op, pr, W_B);
+  Field& et = ws_get(op, pr, W_D);
+  Field& d = ws_get(op, pr, W_X);
+  double red[8];
+  // preconditioned residual of the current x64 into `et` (and r), y = 0; returns |r|^2
+  auto restart_residual = [&]() {
+    blas(ctx, B_CONVERT, 0, 2, {&r64, &rin});
+    op_prepare(op, P.scheme, pr, rin, et);
+    blas(ctx, B_COPY, p0, np, {&et, &r});
+    blas(ctx, B_ZERO, p0, np, {nullptr, &y});
+    blas(ctx, B_NORM2, p0, np, {&r}, BlasArgs{}, red);
+    return red[0];
+  };
+  // x64 += S_R y (with the even block of a subset scheme from the segment's source)
+  auto fold = [&]() {
+    if (sub) {
+      if (P.scheme == TP_SCHUR4D) launch_schur4d(op, pr, 4, 0, nullptr, y, &et, 0.0, 0.0, 3);
+      else blas(ctx, B_COPY, 0, 1, {&et, &y});
+    }
+    op_reconstruct(op, P.scheme, pr, y, d);
+    blas(ctx, B_MIXED_ACC, 0, 2, {&d, &x64});
+    r2 = true_residual(op, l4, x64, eta64, r64);
+    info.outer_iters++;
+  };
+  blas(ctx, B_COPY, 0, 2, {&x64, &xbest});
+  // on failure: back to the best FP64 iterate seen
+  auto give_up = [&]() {
+    blas(ctx, B_COPY, 0, 2, {&xbest, &x64});
+    r2 = true_residual(op, l4, x64, eta64, r64);
+    return false;
+  };
+  double rr2 = restart_residual();
+  // the preconditioned residual that corresponds to the true target, scaled per segment
+  double seg_r2 = r2, seg_rr2 = rr2;
+  blas(ctx, B_COPY, p0, np, {&r, &rh});
+  blas(ctx, B_COPY, p0, np, {&r, &p});
+  blas(ctx, B_DOT, p0, np, {&rh, &r}, BlasArgs{}, red);
+  double rho_r = red[0], rho_i = red[1];
+  double rmax2 = rr2;
+  double best2 = r2;
+  int since_best = 0;
+  // stall / divergence guard on the recursive residual within a segment
+  double seg_best = rr2;
+  int seg_start = info.iters, seg_best_it = info.iters;
+  while (true) {
+    const double tgt2 = 0.25 * tol * tol * eta2 / seg_r2 * seg_rr2;
+    if (info.iters >= max_iter) return give_up();
+    A.apply(p, v, false);
+    info.applies++;
+    blas(ctx, B_DOT, p0, np, {&rh, &v}, BlasArgs{}, red);
+    double den = red[0] * red[0] + red[1] * red[1];
+    if (den == 0.0 || !isfinite(den)) return give_up();
+    double al_r = (rho_r * red[0] + rho_i * red[1]) / den;
+    double al_i = (rho_i * red[0] - rho_r * red[1]) / den;
+    blas(ctx, B_AXPYZ_NORM, p0, np, {&v, &r, &s}, cplx(-al_r, -al_i), red);
+    double s2 = red[0];
+    info.iters++;
+    bool upd = false;
+    if (s2 <= tgt2) {
+      blas(ctx, B_AXPY, p0, np, {&p, &y}, cplx(al_r, al_i));
+      blas(ctx, B_COPY, p0, np, {&s, &r});
+      rr2 = s2;
+      upd = true;
+    } else {
+      A.apply(s, t, false);
+      info.applies++;
+      blas(ctx, B_DOT4_TS, p0, np, {&t, &s, &rh}, BlasArgs{}, red);
+      double om_r = red[0] / red[2], om_i = red[1] / red[2];
+      double rn_r = red[3] - (om_r * red[5] - om_i * red[6]);
+      double rn_i = red[4] - (om_r * red[6] + om_i * red[5]);
+      double rr = rho_r * rho_r + rho_i * rho_i;
+      double oo = om_r * om_r + om_i * om_i;
+      if (red[2] == 0.0 || !isfinite(oo) || oo == 0.0 || rr == 0.0) return give_up();
+      double q_r = (rn_r * rho_r + rn_i * rho_i) / rr, q_i = (rn_i * rho_r - rn_r * rho_i) / rr;
+      double w_r = (al_r * om_r + al_i * om_i) / oo, w_i = (al_i * om_r - al_r * om_i) / oo;
+      double be_r = q_r * w_r - q_i * w_i, be_i = q_r * w_i + q_i * w_r;
+      blas(ctx, B_BICG_FUSED, p0, np, {&y, &p, &s, &t, &v, &r},
+           cplx(al_r, al_i, om_r, om_i, be_r, be_i), red);
+      rr2 = red[0];
+      if (!isfinite(rr2)) return give_up();
+      if (rr2 < seg_best) {
+        seg_best = rr2;
+        seg_best_it = info.iters;
+      }
+      if (rr2 > 1e8 * seg_best || info.iters - seg_best_it > std::max(500, 2 * (seg_best_it - seg_start)))
+        return give_up();
+      rho_r = rn_r;
+      rho_i = rn_i;
+      rmax2 = std::max(rmax2, rr2);
+      upd = rr2 <= tgt2 || rr2 <= delta * delta * rmax2;
+    }
+    if (!upd) continue;
+    fold();
+    if (getenv("TPREC_VERBOSE"))
+      fprintf(stderr, "[tprec] reliable update %d at iteration %d: true %.3e\n", info.outer_iters,
+              info.iters, sqrt(r2 / eta2));
+    if (sqrt(r2 / eta2) <= tol) return true;
+    if (r2 < best2) {
+      best2 = r2;
+      since_best = 0;
+      blas(ctx, B_COPY, 0, 2, {&x64, &xbest});
+    } else if (++since_best >= 3 || r2 > 1e4 * best2) {
+      return give_up();  // the low-precision recurrence no longer reduces the true residual
+    }
+    if (info.outer_iters >= (P.max_restarts > 0 ? P.max_restarts : 200)) return give_up();
+    rr2 = restart_residual();
+    seg_r2 = r2;
+    seg_rr2 = rr2;
+    rmax2 = rr2;
+    seg_best = rr2;
+    seg_start = seg_best_it = info.iters;
+    blas(ctx, B_DOT, p0, np, {&rh, &r}, BlasArgs{}, red);
+    rho_r = red[0];
+    rho_i = red[1];
+    if (rho_r * rho_r + rho_i * rho_i < 1e-24 * rr2 * rr2) {
+      // the shadow residual has become orthogonal to the new residual: restart it
+      blas(ctx, B_COPY, p0, np, {&r, &rh});
+      blas(ctx, B_COPY, p0, np, {&r, &p});
+      rho_r = rr2;
+      rho_i = 0;
+      info.restarts++;
+    }
+  }
+}
+
 }  // namespace
 
 tp_status op_solve(tp_op op, const tp_solve_params& P, Field& x64, const Field& eta64,
@@ -538,8 +684,15 @@ tp_status op_solve(tp_op op, const tp_solve_params& P, Field& x64, const Field& 
   tp_status st = TP_OK;
   int solver = P.solver;
   int failures = 0;  // cycles rolled back
+  if (pr != TP_F64 && solver == TP_BICGSTAB && sqrt(r2 / eta2) > tol) {
+    // reliable updates; on a stall the defect-correction loop below continues with CGNR
+    double delta = P.inner_tol > 0 ? P.inner_tol : (pr == TP_F32 ? 1e-3 : 0.1);
+    if (!bicgstab_reliable(op, P, A, l4, sub, delta, x64, eta64, r64, eta2, r2, tol, max_iter, info))
+      solver = TP_CGNR;
+  }
+  int cycles = 0;
   while (sqrt(r2 / eta2) > tol) {
-    if (info.outer_iters >= max_restarts || info.iters >= max_iter) { st = TP_ENOCONV; break; }
+    if (cycles++ >= max_restarts || info.iters >= max_iter) { st = TP_ENOCONV; break; }
     // inner source in the inner precision
     const Field* rsrc = &r64;
     if (pr != TP_F64) {

@@ -75,7 +75,8 @@ enum {
   TP_F64 = 0,    /* FP64 storage and arithmetic                                  */
   TP_F32 = 1,    /* FP32 storage and arithmetic                                  */
   TP_F16N = 2    /* FP16 spinors with one FP32 scale per half-spinor and site,
-                    FP32 links and clover, FP32 arithmetic                        */
+                    FP16 links and clover, FP32 arithmetic (3D-parity schemes;
+                    SCHUR4D takes F64 and F32)                                    */
 };
 
 typedef struct tp_ctx_s* tp_ctx;
@@ -163,7 +164,7 @@ typedef struct {
   int32_t reserved;
   double tol;              /* target true relative residual |eta - M x| / |eta|     */
   double inner_tol;        /* BiCGStab in F32/F16N: reliable-update threshold delta
-                              (0 = default 1e-3 F32, 0.1 F16N); CGNR: relative
+                              (0 = default 1e-3 F32, 0.02 F16N); CGNR: relative
                               reduction per inner solve (0 = 1e-6 F32, 2e-3 F16N)   */
 } tp_solve_params;
 

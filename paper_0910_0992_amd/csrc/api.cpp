@@ -244,7 +244,8 @@ tp_status tp_ctx_create(const int32_t dims[4], int32_t bc_t, int32_t device, tp_
       if (dims[k] < 2 || dims[k] % 2) TP_THROW(TP_EDIMS, "spatial extents must be even and >= 2");
     if (dims[3] < 2) TP_THROW(TP_EDIMS, "time extent must be >= 2");
     if (bc_t != 1 && bc_t != -1) TP_THROW(TP_EINVAL, "bc_t must be +1 or -1");
-    if ((int64_t)dims[0] * dims[1] * dims[2] * (int64_t)dims[3] > (int64_t)1 << 31)
+    // device code addresses a field plane with 32-bit byte offsets: V/2 * 16 B < 2^32
+    if ((int64_t)dims[0] * dims[1] * dims[2] * (int64_t)dims[3] > (int64_t)1 << 29)
       TP_THROW(TP_EDIMS, "volume too large");
     int ndev = 0;
     HIP_CHECK(hipGetDeviceCount(&ndev));
@@ -312,6 +313,7 @@ tp_status tp_gauge_create(tp_ctx ctx, const void* links, int32_t where, tp_gauge
                                ctx->stream));
       g->u3_d = static_cast<double2*>(dev_alloc(lb));
       g->u3_f = static_cast<float2*>(dev_alloc(lb / 2));
+      g->u3_h = static_cast<__half2*>(dev_alloc(lb / 4));
       g->u4_d = static_cast<double2*>(dev_alloc(lb));
       g->u4_f = static_cast<float2*>(dev_alloc(lb / 2));
       g->w_d = static_cast<double2*>(dev_alloc(size_t(2) * 9 * L.V2 * sizeof(double2)));
@@ -323,6 +325,7 @@ tp_status tp_gauge_create(tp_ctx ctx, const void* links, int32_t where, tp_gauge
         HIP_CHECK(hipMemsetAsync(flags, 0, 2 * sizeof(int), ctx->stream));
         launch_wline(ctx, g);
         launch_axial_links(ctx, g, flags);
+        launch_to_half(ctx, g->u3_f, g->u3_h, int64_t(lb / sizeof(double2)));
         launch_pack_links(ctx, g);
         HIP_CHECK(hipMemcpyAsync(hf, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
         HIP_CHECK(hipStreamSynchronize(ctx->stream));
@@ -349,6 +352,7 @@ tp_status tp_gauge_destroy(tp_gauge g) {
     dev_free(g->canon);
     dev_free(g->u3_d);
     dev_free(g->u3_f);
+    dev_free(g->u3_h);
     dev_free(g->u4_d);
     dev_free(g->u4_f);
     dev_free(g->w_d);
@@ -406,11 +410,13 @@ tp_status tp_clover_create(tp_gauge g, double c_s, double c_t, tp_clover* out) {
       size_t cb = size_t(2) * 36 * L.V2;
       c->a3_d = static_cast<double2*>(dev_alloc(cb * sizeof(double2)));
       c->a3_f = static_cast<float2*>(dev_alloc(cb * sizeof(float2)));
+      c->a3_h = static_cast<__half2*>(dev_alloc(cb * sizeof(__half2)));
       c->a4_d = static_cast<double2*>(dev_alloc(cb * sizeof(double2)));
       c->a4_f = static_cast<float2*>(dev_alloc(cb * sizeof(float2)));
       double sig[6][2][2][2][2];
       clover_sigma_table(c_s, c_t, sig);
       launch_clover_build(ctx, c, sig);
+      launch_to_half(ctx, c->a3_f, c->a3_h, int64_t(cb));
       HIP_CHECK(hipStreamSynchronize(ctx->stream));
     } catch (...) {
       tp_clover_destroy(c);
@@ -427,6 +433,7 @@ tp_status tp_clover_destroy(tp_clover c) {
     (void)hipStreamSynchronize(c->g->ctx->stream);
     dev_free(c->a3_d);
     dev_free(c->a3_f);
+    dev_free(c->a3_h);
     dev_free(c->a4_d);
     dev_free(c->a4_f);
     delete c;
@@ -464,6 +471,8 @@ tp_status tp_op_create(tp_gauge g, tp_clover c, double m0, double gamma_f, tp_op
       op->a3_inv = static_cast<double2*>(dev_alloc(cb * sizeof(double2)));
       op->a3_mu_f = static_cast<float2*>(dev_alloc(cb * sizeof(float2)));
       op->a3_inv_f = static_cast<float2*>(dev_alloc(cb * sizeof(float2)));
+      op->a3_mu_h = static_cast<__half2*>(dev_alloc(cb * sizeof(__half2)));
+      op->a3_inv_h = static_cast<__half2*>(dev_alloc(cb * sizeof(__half2)));
       std::vector<double> pw(L.L[3] + 1);
       std::vector<float> pwf(L.L[3] + 1);
       for (int k = 0; k <= L.L[3]; ++k) {
@@ -479,6 +488,8 @@ tp_status tp_op_create(tp_gauge g, tp_clover c, double m0, double gamma_f, tp_op
       HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
       launch_closure(ctx, op, cond);
       launch_clover_derived(ctx, op, bad);
+      launch_to_half(ctx, op->a3_mu_f, op->a3_mu_h, int64_t(cb));
+      launch_to_half(ctx, op->a3_inv_f, op->a3_inv_h, int64_t(cb));
       std::vector<double> hc(2 * L.Vs2);
       int hb = 0;
       HIP_CHECK(hipMemcpyAsync(hc.data(), cond, sizeof(double) * hc.size(), hipMemcpyDeviceToHost,
@@ -518,6 +529,8 @@ tp_status tp_op_destroy(tp_op op) {
     dev_free(op->a3_inv);
     dev_free(op->a3_mu_f);
     dev_free(op->a3_inv_f);
+    dev_free(op->a3_mu_h);
+    dev_free(op->a3_inv_h);
     dev_free(op->mupow_d);
     dev_free(op->mupow_f);
     delete op;

@@ -17,8 +17,8 @@ TP_DECL(f16)
   }
 
 double spinor_bytes(int prec) { return prec == TP_F64 ? 192 : (prec == TP_F32 ? 96 : 56); }
-double link_bytes(int prec) { return prec == TP_F64 ? 144 : 72; }
-double clov_bytes(int prec) { return prec == TP_F64 ? 576 : 288; }
+double link_bytes(int prec) { return prec == TP_F64 ? 144 : (prec == TP_F32 ? 72 : 36); }
+double clov_bytes(int prec) { return prec == TP_F64 ? 576 : (prec == TP_F32 ? 288 : 144); }
 
 void launch_line(tp_op op, int prec, int mode, int par, const LineIO& io, Field& dst) {
   const Lattice& L = op->g->ctx->lat;

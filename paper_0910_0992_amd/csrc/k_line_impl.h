@@ -242,7 +242,7 @@ template <typename S>
 struct LineArgs {
   SpinorF<S> in, out, aux, self, base;
   const typename Prec<S>::L* clov;  // A/2 blocks of this parity
-  const typename Prec<S>::L* G;  // closure, FP64 or FP32
+  const typename Cplx2<typename Prec<S>::R>::T* G;  // closure, FP64 or FP32
   const typename Prec<S>::R* mupow;
   double inv_mu, f, c_out, c_base;
   Geom g;
@@ -484,12 +484,16 @@ LineArgs<S> base_args(tp_op op, int par) {
   a.clov = nullptr;
   if (op->c) {
     if constexpr (sizeof(Lk) == 16) a.clov = (const Lk*)op->c->a3_d + (int64_t)par * 36 * L.V2;
-    else a.clov = (const Lk*)op->c->a3_f + (int64_t)par * 36 * L.V2;
+    else if constexpr (sizeof(Lk) == 8) a.clov = (const Lk*)op->c->a3_f + (int64_t)par * 36 * L.V2;
+    else a.clov = (const Lk*)op->c->a3_h + (int64_t)par * 36 * L.V2;
   }
-  if constexpr (sizeof(Lk) == 16) a.G = (const Lk*)op->gclos;
-  else a.G = (const Lk*)op->gclos_f;
-  if constexpr (sizeof(Lk) == 16) a.mupow = (const typename Prec<S>::R*)op->mupow_d;
-  else a.mupow = (const typename Prec<S>::R*)op->mupow_f;
+  if constexpr (sizeof(Lk) == 16) {
+    a.G = op->gclos;
+    a.mupow = (const typename Prec<S>::R*)op->mupow_d;
+  } else {
+    a.G = op->gclos_f;
+    a.mupow = (const typename Prec<S>::R*)op->mupow_f;
+  }
   a.inv_mu = 1.0 / op->mu;
   a.g = L.g;
   a.par = par;

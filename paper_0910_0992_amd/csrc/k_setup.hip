@@ -246,6 +246,11 @@ __global__ void k_axial_links(const double2* __restrict__ canon, const double2* 
   }
 }
 
+__global__ void k_to_half(const float2* __restrict__ src, __half2* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = __float22half2_rn(src[i]);
+}
+
 TP_DEV bool inv3(const cx<double>* m, cx<double>* r) {
   // adjugate / determinant
   cx<double> c00 = cmul(m[4], m[8]) - cmul(m[5], m[7]);
@@ -606,6 +611,13 @@ void launch_wline(tp_ctx ctx, tp_gauge g) {
   const Lattice& L = ctx->lat;
   hipLaunchKernelGGL(k_wline, dim3((L.Vs2 + 63) / 64, 2), dim3(64), 0, ctx->stream, g->canon,
                      g->w_d, g->poly, L.g, L.V, double(ctx->bc));
+  LAUNCH_CHECK();
+}
+
+void launch_to_half(tp_ctx ctx, const float2* src, __half2* dst, int64_t n) {
+  int64_t nb = (n + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(k_to_half, dim3((unsigned)nb), dim3(256), 0, ctx->stream, src, dst, n);
   LAUNCH_CHECK();
 }
 

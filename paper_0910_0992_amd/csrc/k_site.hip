@@ -20,8 +20,7 @@ struct SiteArgsP3 {
   const typename Prec<S>::L* clov[2];
   double c_mu, c_A, c_t, c_s, c_in;
   Geom g;
-  int par0;
-  int64_t n;  // number of output sites (npar * V2)
+  int par;  // output parity of this launch
   double* partial;
 };
 
@@ -32,12 +31,10 @@ __global__ void __launch_bounds__(kBlock) k_site_p3(SiteArgsP3<S> a) {
   using Lt = typename Prec<S>::L;
   __shared__ double red[kBlock / 64];
   double acc = 0.0;
-  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < a.n;
-       n += (int64_t)gridDim.x * blockDim.x) {
-    int p = a.par0 + int(n / a.g.V2);
-    const int64_t i = n % a.g.V2;
+  const int p = a.par;  // one parity per launch: every field plane address is uniform
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < uint32_t(a.g.V2); i += gridDim.x * blockDim.x) {
     int t, s;
-    p3_ts(a.g, i, t, s);
+    p3_ts32(a.g, i, t, s);
     cx<R> out[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) out[c] = czero<R>();
@@ -255,7 +252,8 @@ template <> struct LinkSrc<float2> {
   static const float2* get(tp_gauge g, bool l4) { return l4 ? g->u4_f : g->u3_f; }
 };
 template <> struct LinkSrc<__half2> {
-  static const float2* get(tp_gauge g, bool l4) { return l4 ? g->u4_f : g->u3_f; }
+  // F16N runs only in the p3 layout (the 4D scheme is F64/F32)
+  static const __half2* get(tp_gauge g, bool l4) { return l4 ? nullptr : g->u3_h; }
 };
 
 template <typename S>
@@ -282,26 +280,34 @@ template <> const float2* clover_base<float2>(tp_op op, int kind, bool l4) {
   if (kind == 3) return l4 ? op->a4_inv_f : op->a3_inv_f;
   return nullptr;
 }
-template <> const float2* clover_base<__half2>(tp_op op, int kind, bool l4) {
-  return clover_base<float2>(op, kind, l4);
+template <> const __half2* clover_base<__half2>(tp_op op, int kind, bool l4) {
+  if (l4) return nullptr;
+  if (kind == 1) return op->c ? op->c->a3_h : nullptr;
+  if (kind == 2) return op->a3_mu_h;
+  if (kind == 3) return op->a3_inv_h;
+  return nullptr;
 }
 
 template <typename S, bool DT, int DS, bool CLOV, bool IN2, bool NORM>
-void site_go(tp_op op, SiteArgsP3<S>& a, int64_t nblocks) {
+void site_go(tp_op op, SiteArgsP3<S> a, int64_t nblocks, int par0, int npar) {
   tp_ctx ctx = op->g->ctx;
-  hipLaunchKernelGGL((k_site_p3<S, DT, DS, CLOV, IN2, NORM>), dim3((unsigned)nblocks), dim3(kBlock), 0,
-                     ctx->stream, a);
-  LAUNCH_CHECK();
+  for (int q = 0; q < npar; ++q) {
+    a.par = par0 + q;
+    a.partial = ctx->red_partial + (int64_t)q * nblocks * 8;
+    hipLaunchKernelGGL((k_site_p3<S, DT, DS, CLOV, IN2, NORM>), dim3((unsigned)nblocks), dim3(kBlock), 0,
+                       ctx->stream, a);
+    LAUNCH_CHECK();
+  }
 }
 
 template <typename S, bool DT, int DS, bool CLOV>
-void site_in2(tp_op op, SiteArgsP3<S>& a, int64_t nb, bool in2, bool norm) {
+void site_in2(tp_op op, SiteArgsP3<S>& a, int64_t nb, bool in2, bool norm, int par0, int npar) {
   if (in2) {
-    if (norm) site_go<S, DT, DS, CLOV, true, true>(op, a, nb);
-    else site_go<S, DT, DS, CLOV, true, false>(op, a, nb);
+    if (norm) site_go<S, DT, DS, CLOV, true, true>(op, a, nb, par0, npar);
+    else site_go<S, DT, DS, CLOV, true, false>(op, a, nb, par0, npar);
   } else {
-    if (norm) site_go<S, DT, DS, CLOV, false, true>(op, a, nb);
-    else site_go<S, DT, DS, CLOV, false, false>(op, a, nb);
+    if (norm) site_go<S, DT, DS, CLOV, false, true>(op, a, nb, par0, npar);
+    else site_go<S, DT, DS, CLOV, false, false>(op, a, nb, par0, npar);
   }
 }
 
@@ -336,11 +342,9 @@ int site_t(tp_op op, const SiteIO& io, Field& dst, SiteCoef cf, int ck, int par0
   a.c_s = cf.c_s;
   a.c_in = cf.c_in;
   a.g = L.g;
-  a.par0 = par0;
-  a.n = (int64_t)npar * L.V2;
-  a.partial = ctx->red_partial;
-  int64_t nb = (a.n + kBlock - 1) / kBlock;
-  if (norm) nb = nb < kRedBlocks ? nb : kRedBlocks;
+  // one launch per output parity; with a norm, each launch's partials follow the previous
+  int64_t nb = (L.V2 + kBlock - 1) / kBlock;
+  if (norm) nb = std::min<int64_t>(nb, kRedBlocks / 2);
   bool dt = cf.c_t != 0.0, ds = cf.c_s != 0.0;
   bool i2 = in2 != nullptr;
   // reduced-precision spatial hops read SU(3) links as two rows
@@ -348,28 +352,28 @@ int site_t(tp_op op, const SiteIO& io, Field& dst, SiteCoef cf, int ck, int par0
   const bool two = kReduced && op->g->su3_spatial;
   if (dt && ds) {
     if (two) {
-      if (clov) site_in2<S, true, kReduced ? 2 : 3, true>(op, a, nb, i2, norm);
-      else site_in2<S, true, kReduced ? 2 : 3, false>(op, a, nb, i2, norm);
+      if (clov) site_in2<S, true, kReduced ? 2 : 3, true>(op, a, nb, i2, norm, par0, npar);
+      else site_in2<S, true, kReduced ? 2 : 3, false>(op, a, nb, i2, norm, par0, npar);
     } else {
-      if (clov) site_in2<S, true, 3, true>(op, a, nb, i2, norm);
-      else site_in2<S, true, 3, false>(op, a, nb, i2, norm);
+      if (clov) site_in2<S, true, 3, true>(op, a, nb, i2, norm, par0, npar);
+      else site_in2<S, true, 3, false>(op, a, nb, i2, norm, par0, npar);
     }
   } else if (ds) {
     if (two) {
-      if (clov) site_in2<S, false, kReduced ? 2 : 3, true>(op, a, nb, i2, norm);
-      else site_in2<S, false, kReduced ? 2 : 3, false>(op, a, nb, i2, norm);
+      if (clov) site_in2<S, false, kReduced ? 2 : 3, true>(op, a, nb, i2, norm, par0, npar);
+      else site_in2<S, false, kReduced ? 2 : 3, false>(op, a, nb, i2, norm, par0, npar);
     } else {
-      if (clov) site_in2<S, false, 3, true>(op, a, nb, i2, norm);
-      else site_in2<S, false, 3, false>(op, a, nb, i2, norm);
+      if (clov) site_in2<S, false, 3, true>(op, a, nb, i2, norm, par0, npar);
+      else site_in2<S, false, 3, false>(op, a, nb, i2, norm, par0, npar);
     }
   } else if (dt) {
-    if (clov) site_in2<S, true, 0, true>(op, a, nb, i2, norm);
-    else site_in2<S, true, 0, false>(op, a, nb, i2, norm);
+    if (clov) site_in2<S, true, 0, true>(op, a, nb, i2, norm, par0, npar);
+    else site_in2<S, true, 0, false>(op, a, nb, i2, norm, par0, npar);
   } else {
-    if (clov) site_in2<S, false, 0, true>(op, a, nb, i2, norm);
-    else site_in2<S, false, 0, false>(op, a, nb, i2, norm);
+    if (clov) site_in2<S, false, 0, true>(op, a, nb, i2, norm, par0, npar);
+    else site_in2<S, false, 0, false>(op, a, nb, i2, norm, par0, npar);
   }
-  return norm ? int(nb) : 0;
+  return norm ? int(nb * npar) : 0;
 }
 
 template <typename S, bool HOP, bool IN2, int CL>

@@ -686,7 +686,7 @@ tp_status op_solve(tp_op op, const tp_solve_params& P, Field& x64, const Field& 
   int failures = 0;  // cycles rolled back
   if (pr != TP_F64 && solver == TP_BICGSTAB && sqrt(r2 / eta2) > tol) {
     // reliable updates; on a stall the defect-correction loop below continues with CGNR
-    double delta = P.inner_tol > 0 ? P.inner_tol : (pr == TP_F32 ? 1e-3 : 0.1);
+    double delta = P.inner_tol > 0 ? P.inner_tol : (pr == TP_F32 ? 1e-3 : 0.02);
     if (!bicgstab_reliable(op, P, A, l4, sub, delta, x64, eta64, r64, eta2, r2, tol, max_iter, info))
       solver = TP_CGNR;
   }

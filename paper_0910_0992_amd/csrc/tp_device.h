@@ -72,7 +72,8 @@ template <typename R> TP_DEV void mvd(const su3<R>& u, const cx<R>* v, cx<R>* ou
 template <typename S> struct Prec;
 template <> struct Prec<double2> { using R = double; using L = double2; static constexpr bool half = false; };
 template <> struct Prec<float2> { using R = float; using L = float2; static constexpr bool half = false; };
-template <> struct Prec<__half2> { using R = float; using L = float2; static constexpr bool half = true; };
+// F16N: FP16 spinors with per-site scales; p3 links and clover stored in FP16 as well
+template <> struct Prec<__half2> { using R = float; using L = __half2; static constexpr bool half = true; };
 
 template <typename R, typename S> TP_DEV cx<R> ld(const S* p) {
   S v = *p;
@@ -98,6 +99,48 @@ struct SpinorF {
   int64_t stride;
 };
 
+// Element i of a plane, addressed as plane + a 32-bit byte offset: with the plane pointer
+// uniform across the wavefront this is the scalar-base + vector-offset load form, with no
+// per-load 64-bit address arithmetic.  Every field here is below 2^32 bytes per plane
+// (the context limits the volume to 2^29 sites).
+template <typename T> TP_DEV const T* at(const T* plane, uint32_t i) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(plane) + uint32_t(i * uint32_t(sizeof(T))));
+}
+template <typename T> TP_DEV T* at(T* plane, uint32_t i) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + uint32_t(i * uint32_t(sizeof(T))));
+}
+
+template <typename S, typename R = typename Prec<S>::R>
+TP_DEV void load_half(const SpinorF<S>& f, int h, uint32_t i, cx<R>* v) {
+  const S* b = f.p[h];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) v[c] = ld<R, S>(at(b + (int64_t)c * f.stride, i));
+  if constexpr (Prec<S>::half) {
+    R s = *at(f.nrm[h], i);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = s * v[c];
+  }
+}
+
+template <typename S, typename R = typename Prec<S>::R>
+TP_DEV void store_half(const SpinorF<S>& f, int h, uint32_t i, const cx<R>* v) {
+  S* b = f.p[h];
+  if constexpr (Prec<S>::half) {
+    R m = R(0);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+    R inv = m > R(0) ? R(1) / m : R(0);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) st(at(b + (int64_t)c * f.stride, i), inv * v[c]);
+    *at(f.nrm[h], i) = m;
+  } else {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) st(at(b + (int64_t)c * f.stride, i), v[c]);
+  }
+}
+
+// The same with a 64-bit site index and 64-bit addresses (the line kernels, whose
+// register budget is better spent elsewhere than on uniform plane bases).
 template <typename S, typename R = typename Prec<S>::R>
 TP_DEV void load_half(const SpinorF<S>& f, int h, int64_t i, cx<R>* v) {
   const S* b = f.p[h];
@@ -109,7 +152,6 @@ TP_DEV void load_half(const SpinorF<S>& f, int h, int64_t i, cx<R>* v) {
     for (int c = 0; c < 6; ++c) v[c] = s * v[c];
   }
 }
-
 template <typename S, typename R = typename Prec<S>::R>
 TP_DEV void store_half(const SpinorF<S>& f, int h, int64_t i, const cx<R>* v) {
   S* b = f.p[h];
@@ -128,12 +170,12 @@ TP_DEV void store_half(const SpinorF<S>& f, int h, int64_t i, const cx<R>* v) {
 }
 
 template <typename S, typename R = typename Prec<S>::R>
-TP_DEV void load_spinor(const SpinorF<S>& f, int64_t i, cx<R>* v) {
+TP_DEV void load_spinor(const SpinorF<S>& f, uint32_t i, cx<R>* v) {
   load_half<S, R>(f, 0, i, v);
   load_half<S, R>(f, 1, i, v + 6);
 }
 template <typename S, typename R = typename Prec<S>::R>
-TP_DEV void store_spinor(const SpinorF<S>& f, int64_t i, const cx<R>* v) {
+TP_DEV void store_spinor(const SpinorF<S>& f, uint32_t i, const cx<R>* v) {
   store_half<S, R>(f, 0, i, v);
   store_half<S, R>(f, 1, i, v + 6);
 }
@@ -148,11 +190,11 @@ struct LinkF {
 // rebuilds the third: the rows are orthonormal with unit determinant, so the third row is
 // the complex conjugate of the cross product of the first two.
 template <typename R, typename L, int ROWS = 3>
-TP_DEV su3<R> load_su3(const LinkF<L>& f, int64_t i) {
+TP_DEV su3<R> load_su3(const LinkF<L>& f, uint32_t i) {
   su3<R> u;
   if constexpr (ROWS == 2) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) u.e[k] = ld<R, L>(f.p + (int64_t)k * f.stride + i);
+    for (int k = 0; k < 6; ++k) u.e[k] = ld<R, L>(at(f.p + (int64_t)k * f.stride, i));
     const cx<R>* a = u.e;
     const cx<R>* b = u.e + 3;
     u.e[6] = conj(cmul(a[1], b[2]) - cmul(a[2], b[1]));
@@ -160,7 +202,7 @@ TP_DEV su3<R> load_su3(const LinkF<L>& f, int64_t i) {
     u.e[8] = conj(cmul(a[0], b[1]) - cmul(a[1], b[0]));
   } else {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) u.e[k] = ld<R, L>(f.p + (int64_t)k * f.stride + i);
+    for (int k = 0; k < 9; ++k) u.e[k] = ld<R, L>(at(f.p + (int64_t)k * f.stride, i));
   }
   return u;
 }
@@ -228,6 +270,42 @@ template <int K, typename R> TP_DEV void recon_plus(cx<R>* out, const cx<R>* g, 
 // Per block: 18 complex slots: slots 0..2 hold the six real diagonal entries in
 // pairs, slots 3..17 the strictly lower triangle in row-major order.  Planes [36][stride].
 template <typename R, typename L>
+TP_DEV void herm6_apply(const L* base, int64_t stride, uint32_t i, const cx<R>* v, cx<R>* out) {
+  R d[6];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    cx<R> t = ld<R, L>(at(base + (int64_t)k * stride, i));
+    d[2 * k] = t.re;
+    d[2 * k + 1] = t.im;
+  }
+#pragma unroll
+  for (int r = 0; r < 6; ++r) out[r] = d[r] * v[r];
+  int slot = 3;
+#pragma unroll
+  for (int r = 1; r < 6; ++r) {
+#pragma unroll
+    for (int c = 0; c < r; ++c) {
+      cx<R> l = ld<R, L>(at(base + (int64_t)slot * stride, i));
+      out[r] += cmul(l, v[c]);
+      out[c] += cmulc(l, v[r]);
+      ++slot;
+    }
+  }
+}
+
+template <typename R, typename L>
+TP_DEV void clover_apply(const L* cl, int64_t stride, uint32_t i, const cx<R>* psi, cx<R>* out) {
+  cx<R> up[6], um[6], bp[6], bm[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) { up[c] = psi[c] - psi[6 + c]; um[c] = psi[c] + psi[6 + c]; }
+  herm6_apply<R, L>(cl, stride, i, up, bp);
+  herm6_apply<R, L>(cl + 18 * stride, stride, i, um, bm);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) { out[c] = bp[c] + bm[c]; out[6 + c] = bm[c] - bp[c]; }
+}
+
+// 64-bit-index forms (line kernels)
+template <typename R, typename L>
 TP_DEV void herm6_apply(const L* base, int64_t stride, int64_t i, const cx<R>* v, cx<R>* out) {
   R d[6];
 #pragma unroll
@@ -289,6 +367,16 @@ TP_DEV int p3_index(const Geom& g, int x, int y, int z) { return (x + g.Lx * (y 
 constexpr int kTile = 4;
 TP_HD int64_t p3_idx(const Geom& g, int t, int s) {
   return ((int64_t)(s >> 2) * g.Lt + t) * kTile + (s & 3);
+}
+TP_DEV uint32_t p3_idx32(const Geom& g, int t, int s) {
+  return (uint32_t(s >> 2) * uint32_t(g.Lt) + uint32_t(t)) * kTile + uint32_t(s & 3);
+}
+TP_DEV void p3_ts32(const Geom& g, uint32_t i, int& t, int& s) {
+  const uint32_t per = uint32_t(kTile) * uint32_t(g.Lt);
+  const uint32_t tile = i / per;
+  const uint32_t r = i - tile * per;
+  t = int(r >> 2);
+  s = int(tile * kTile + (r & 3));
 }
 TP_HD void p3_ts(const Geom& g, int64_t i, int& t, int& s) {
   int64_t tile = i / ((int64_t)kTile * g.Lt);

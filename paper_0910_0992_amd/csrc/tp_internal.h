@@ -107,6 +107,7 @@ struct tp_gauge_s {
   // time links are the identity, U_t(Lt-1) = P (Polyakov loop with the phase b)
   double2* u3_d = nullptr;
   float2* u3_f = nullptr;
+  __half2* u3_h = nullptr;   // FP16 copy of u3 for the F16N operators
   double2* u4_d = nullptr;   // p4 layout [4 dir][2 par][9][V2], time phase folded
   float2* u4_f = nullptr;
   double2* w_d = nullptr;    // p3 layout W(t) = U(t)...U(Lt-1) [2 par][9][V2], FP64
@@ -121,6 +122,7 @@ struct tp_clover_s {
   double cs = 0, ct = 0;
   double2* a3_d = nullptr;  // p3 layout chiral blocks of A/2 [2 par][36][V2]
   float2* a3_f = nullptr;
+  __half2* a3_h = nullptr;  // FP16 copy for the F16N operators
   double2* a4_d = nullptr;  // p4 layout chiral blocks of A/2 [2 par][36][V2]
   float2* a4_f = nullptr;
 };
@@ -141,6 +143,8 @@ struct tp_op_s {
   double2* a3_inv = nullptr;
   float2* a3_mu_f = nullptr;
   float2* a3_inv_f = nullptr;
+  __half2* a3_mu_h = nullptr;
+  __half2* a3_inv_h = nullptr;
   double* mupow_d = nullptr;    // mu^-k, k = 0..Lt
   float* mupow_f = nullptr;
   Workspace* ws = nullptr;
@@ -177,6 +181,8 @@ void launch_wline(tp_ctx ctx, tp_gauge g);        // W(t), P from the canonical 
 // axial-frame spatial link deviates from SU(3) by more than 1e-9, [1] when a time link
 // deviates from unitarity by more than 1e-10
 void launch_axial_links(tp_ctx ctx, tp_gauge g, int* flags);
+// dst = src rounded to FP16 (n complex values)
+void launch_to_half(tp_ctx ctx, const float2* src, __half2* dst, int64_t n);
 void launch_closure(tp_ctx ctx, tp_op op, double* cond_out /*device [2*Vs2]*/);
 void launch_clover_build(tp_ctx ctx, tp_clover c, const double sig[6][2][2][2][2]);
 void launch_clover_derived(tp_ctx ctx, tp_op op, int* bad /*device counter*/);

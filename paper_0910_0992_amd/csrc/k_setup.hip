@@ -124,14 +124,14 @@ __global__ void k_pack_links4(const double2* __restrict__ canon, double2* u4d, f
   const double2* src = canon + ((int64_t)mu * V + n) * 9;
   int64_t V2 = V / 2;
   double2* d4 = u4d + ((int64_t)(mu * 2 + p4) * 9) * V2 + i4;
-  float2* f4 = u4f + ((int64_t)(mu * 2 + p4) * 9) * V2 + i4;
+  float2* f4 = u4f + ((int64_t)(mu * 2 + p4) * 9) * V2;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
     double2 e = src[k];
     e.x *= ph;
     e.y *= ph;
     d4[(int64_t)k * V2] = e;
-    f4[(int64_t)k * V2] = make_float2(float(e.x), float(e.y));
+    f4[comp_off<float2>(k, 9, V2, i4)] = make_float2(float(e.x), float(e.y));
   }
 }
 
@@ -237,11 +237,11 @@ __global__ void k_axial_links(const double2* __restrict__ canon, const double2* 
     }
   }
   double2* d3 = u3d + ((int64_t)(mu * 2 + pa) * 9) * V2 + ia;
-  float2* f3 = u3f + ((int64_t)(mu * 2 + pa) * 9) * V2 + ia;
+  float2* f3 = u3f + ((int64_t)(mu * 2 + pa) * 9) * V2;
   double2* ca = canon_ax + ((int64_t)mu * V + n) * 9;
   for (int k = 0; k < 9; ++k) {
     d3[(int64_t)k * V2] = make_double2(T2[k].re, T2[k].im);
-    f3[(int64_t)k * V2] = make_float2(float(T2[k].re), float(T2[k].im));
+    f3[comp_off<float2>(k, 9, V2, ia)] = make_float2(float(T2[k].re), float(T2[k].im));
     ca[k] = make_double2(T2[k].re, T2[k].im);
   }
 }
@@ -385,17 +385,17 @@ TP_DEV void store_herm6(const cx<double>* m /*36 row-major*/, double2* d3, float
   for (int k = 0; k < 3; ++k, ++slot) {
     double2 v = make_double2(m[(2 * k) * 7].re, m[(2 * k + 1) * 7].re);
     if (d3) d3[(int64_t)slot * st + i3] = v;
-    if (f3) f3[(int64_t)slot * st + i3] = make_float2(float(v.x), float(v.y));
+    if (f3) f3[comp_off<float2>(slot, 18, st, i3)] = make_float2(float(v.x), float(v.y));
     if (d4) d4[(int64_t)slot * st + i4] = v;
-    if (f4) f4[(int64_t)slot * st + i4] = make_float2(float(v.x), float(v.y));
+    if (f4) f4[comp_off<float2>(slot, 18, st, i4)] = make_float2(float(v.x), float(v.y));
   }
   for (int r = 1; r < 6; ++r)
     for (int c = 0; c < r; ++c, ++slot) {
       double2 v = make_double2(m[6 * r + c].re, m[6 * r + c].im);
       if (d3) d3[(int64_t)slot * st + i3] = v;
-      if (f3) f3[(int64_t)slot * st + i3] = make_float2(float(v.x), float(v.y));
+      if (f3) f3[comp_off<float2>(slot, 18, st, i3)] = make_float2(float(v.x), float(v.y));
       if (d4) d4[(int64_t)slot * st + i4] = v;
-      if (f4) f4[(int64_t)slot * st + i4] = make_float2(float(v.x), float(v.y));
+      if (f4) f4[comp_off<float2>(slot, 18, st, i4)] = make_float2(float(v.x), float(v.y));
     }
 }
 

@@ -87,9 +87,45 @@ template <typename R> TP_DEV void st(double2* p, cx<R> v) { *p = make_double2(do
 template <typename R> TP_DEV void st(float2* p, cx<R> v) { *p = make_float2(float(v.re), float(v.im)); }
 template <typename R> TP_DEV void st(__half2* p, cx<R> v) { *p = __floats2half2_rn(float(v.re), float(v.im)); }
 
+// ---- field storage --------------------------------------------------------------------------
+// A field of n complex components per site is stored as planes of `stride` sites.  FP32 and
+// FP16 fields pair the planes (2k, 2k+1): the two values of one site are adjacent, so a
+// single 16-byte (FP32) or 8-byte (FP16) load fetches both, halving the load instructions of
+// the bandwidth-bound kernels.  A last odd plane (links: 9 components) stays single.  FP64
+// fields keep one plane per component (a pair would exceed one 16-byte load).
+template <typename T> TP_HD constexpr bool paired() { return sizeof(T) <= 8; }
+template <typename T> TP_HD int64_t comp_off(int c, int n, int64_t stride, int64_t i) {
+  if (paired<T>() && c < (n & ~1)) return (int64_t)(c & ~1) * stride + 2 * i + (c & 1);
+  return (int64_t)c * stride + i;
+}
+// Two adjacent components of a paired field: p points at the even one.
+template <typename R, typename T> TP_DEV void ld2(const T* p, cx<R>& a, cx<R>& b);
+template <> TP_DEV void ld2<float, float2>(const float2* p, cx<float>& a, cx<float>& b) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  a = {v.x, v.y};
+  b = {v.z, v.w};
+}
+struct alignas(8) Half2x2 { __half2 a, b; };
+template <> TP_DEV void ld2<float, __half2>(const __half2* p, cx<float>& a, cx<float>& b) {
+  const Half2x2 v = *reinterpret_cast<const Half2x2*>(p);
+  const float2 fa = __half22float2(v.a), fb = __half22float2(v.b);
+  a = {fa.x, fa.y};
+  b = {fb.x, fb.y};
+}
+template <typename R> TP_DEV void st2(float2* p, cx<R> a, cx<R> b) {
+  *reinterpret_cast<float4*>(p) = make_float4(float(a.re), float(a.im), float(b.re), float(b.im));
+}
+template <typename R> TP_DEV void st2(__half2* p, cx<R> a, cx<R> b) {
+  Half2x2 v;
+  v.a = __floats2half2_rn(float(a.re), float(a.im));
+  v.b = __floats2half2_rn(float(b.re), float(b.im));
+  *reinterpret_cast<Half2x2*>(p) = v;
+}
+
 // A spinor field of one parity, seen as two half-spinor fields: h = 0 holds spins
 // 0-1 (the P+ = (1+gamma_t)/2 subspace in the Dirac-Pauli basis), h = 1 spins 2-3.
-// Each half is 6 planes [6][stride] (component = spin_in_half*3 + colour); for FP16,
+// Each half is 6 components [6][stride] (component = spin_in_half*3 + colour, paired as
+// above for FP32 / FP16); for FP16,
 // nrm[h] holds one FP32 scale per site.  The two halves may live in different
 // buffers, so a field can be assembled from the halves of two others.
 template <typename S>
@@ -113,8 +149,13 @@ template <typename T> TP_DEV T* at(T* plane, uint32_t i) {
 template <typename S, typename R = typename Prec<S>::R>
 TP_DEV void load_half(const SpinorF<S>& f, int h, uint32_t i, cx<R>* v) {
   const S* b = f.p[h];
+  if constexpr (paired<S>()) {
 #pragma unroll
-  for (int c = 0; c < 6; ++c) v[c] = ld<R, S>(at(b + (int64_t)c * f.stride, i));
+    for (int q = 0; q < 3; ++q) ld2<R, S>(at(b + (int64_t)(2 * q) * f.stride, 2 * i), v[2 * q], v[2 * q + 1]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = ld<R, S>(at(b + (int64_t)c * f.stride, i));
+  }
   if constexpr (Prec<S>::half) {
     R s = *at(f.nrm[h], i);
 #pragma unroll
@@ -131,8 +172,11 @@ TP_DEV void store_half(const SpinorF<S>& f, int h, uint32_t i, const cx<R>* v) {
     for (int c = 0; c < 6; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
     R inv = m > R(0) ? R(1) / m : R(0);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) st(at(b + (int64_t)c * f.stride, i), inv * v[c]);
+    for (int q = 0; q < 3; ++q) st2(at(b + (int64_t)(2 * q) * f.stride, 2 * i), inv * v[2 * q], inv * v[2 * q + 1]);
     *at(f.nrm[h], i) = m;
+  } else if constexpr (paired<S>()) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) st2(at(b + (int64_t)(2 * q) * f.stride, 2 * i), v[2 * q], v[2 * q + 1]);
   } else {
 #pragma unroll
     for (int c = 0; c < 6; ++c) st(at(b + (int64_t)c * f.stride, i), v[c]);
@@ -144,8 +188,13 @@ TP_DEV void store_half(const SpinorF<S>& f, int h, uint32_t i, const cx<R>* v) {
 template <typename S, typename R = typename Prec<S>::R>
 TP_DEV void load_half(const SpinorF<S>& f, int h, int64_t i, cx<R>* v) {
   const S* b = f.p[h];
+  if constexpr (paired<S>()) {
 #pragma unroll
-  for (int c = 0; c < 6; ++c) v[c] = ld<R, S>(b + (int64_t)c * f.stride + i);
+    for (int q = 0; q < 3; ++q) ld2<R, S>(b + (int64_t)(2 * q) * f.stride + 2 * i, v[2 * q], v[2 * q + 1]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = ld<R, S>(b + (int64_t)c * f.stride + i);
+  }
   if constexpr (Prec<S>::half) {
     R s = f.nrm[h][i];
 #pragma unroll
@@ -161,8 +210,11 @@ TP_DEV void store_half(const SpinorF<S>& f, int h, int64_t i, const cx<R>* v) {
     for (int c = 0; c < 6; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
     R inv = m > R(0) ? R(1) / m : R(0);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) st(b + (int64_t)c * f.stride + i, inv * v[c]);
+    for (int q = 0; q < 3; ++q) st2(b + (int64_t)(2 * q) * f.stride + 2 * i, inv * v[2 * q], inv * v[2 * q + 1]);
     f.nrm[h][i] = m;
+  } else if constexpr (paired<S>()) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) st2(b + (int64_t)(2 * q) * f.stride + 2 * i, v[2 * q], v[2 * q + 1]);
   } else {
 #pragma unroll
     for (int c = 0; c < 6; ++c) st(b + (int64_t)c * f.stride + i, v[c]);
@@ -192,17 +244,21 @@ struct LinkF {
 template <typename R, typename L, int ROWS = 3>
 TP_DEV su3<R> load_su3(const LinkF<L>& f, uint32_t i) {
   su3<R> u;
-  if constexpr (ROWS == 2) {
+  if constexpr (paired<L>()) {
+    constexpr int npair = ROWS == 2 ? 3 : 4;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) u.e[k] = ld<R, L>(at(f.p + (int64_t)k * f.stride, i));
+    for (int q = 0; q < npair; ++q) ld2<R, L>(at(f.p + (int64_t)(2 * q) * f.stride, 2 * i), u.e[2 * q], u.e[2 * q + 1]);
+    if constexpr (ROWS == 3) u.e[8] = ld<R, L>(at(f.p + (int64_t)8 * f.stride, i));
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3 * ROWS; ++k) u.e[k] = ld<R, L>(at(f.p + (int64_t)k * f.stride, i));
+  }
+  if constexpr (ROWS == 2) {
     const cx<R>* a = u.e;
     const cx<R>* b = u.e + 3;
     u.e[6] = conj(cmul(a[1], b[2]) - cmul(a[2], b[1]));
     u.e[7] = conj(cmul(a[2], b[0]) - cmul(a[0], b[2]));
     u.e[8] = conj(cmul(a[0], b[1]) - cmul(a[1], b[0]));
-  } else {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) u.e[k] = ld<R, L>(at(f.p + (int64_t)k * f.stride, i));
   }
   return u;
 }
@@ -267,75 +323,68 @@ template <int K, typename R> TP_DEV void recon_plus(cx<R>* out, const cx<R>* g, 
 // acting on u+ = psi_up - psi_lo and u- = psi_up + psi_lo (index spin_in_pair*3 + colour),
 // pre-multiplied by 1/2 so that
 //   (A psi)_up = B+ u+ + B- u-,   (A psi)_lo = B- u- - B+ u+.
-// Per block: 18 complex slots: slots 0..2 hold the six real diagonal entries in
-// pairs, slots 3..17 the strictly lower triangle in row-major order.  Planes [36][stride].
-template <typename R, typename L>
-TP_DEV void herm6_apply(const L* base, int64_t stride, uint32_t i, const cx<R>* v, cx<R>* out) {
-  R d[6];
+// Per block: 18 complex slots (36 components per site, paired for FP32 / FP16).
+// out = B v for one hermitian 6x6 block from its 18 slots: slots 0..2 hold the six real
+// diagonal entries in pairs, slots 3..17 the strictly lower triangle in row-major order.
+template <typename R>
+TP_DEV void herm6_from_slots(const cx<R>* sl, const cx<R>* v, cx<R>* out) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    cx<R> t = ld<R, L>(at(base + (int64_t)k * stride, i));
-    d[2 * k] = t.re;
-    d[2 * k + 1] = t.im;
+    out[2 * k] = sl[k].re * v[2 * k];
+    out[2 * k + 1] = sl[k].im * v[2 * k + 1];
   }
-#pragma unroll
-  for (int r = 0; r < 6; ++r) out[r] = d[r] * v[r];
   int slot = 3;
 #pragma unroll
   for (int r = 1; r < 6; ++r) {
 #pragma unroll
     for (int c = 0; c < r; ++c) {
-      cx<R> l = ld<R, L>(at(base + (int64_t)slot * stride, i));
-      out[r] += cmul(l, v[c]);
-      out[c] += cmulc(l, v[r]);
+      out[r] += cmul(sl[slot], v[c]);
+      out[c] += cmulc(sl[slot], v[r]);
       ++slot;
     }
   }
 }
 
+// The 18 slots of the block whose planes start at `base` (an even component index).
 template <typename R, typename L>
-TP_DEV void clover_apply(const L* cl, int64_t stride, uint32_t i, const cx<R>* psi, cx<R>* out) {
-  cx<R> up[6], um[6], bp[6], bm[6];
+TP_DEV void herm6_slots(const L* base, int64_t stride, uint32_t i, cx<R>* sl) {
+  if constexpr (paired<L>()) {
 #pragma unroll
-  for (int c = 0; c < 6; ++c) { up[c] = psi[c] - psi[6 + c]; um[c] = psi[c] + psi[6 + c]; }
-  herm6_apply<R, L>(cl, stride, i, up, bp);
-  herm6_apply<R, L>(cl + 18 * stride, stride, i, um, bm);
+    for (int q = 0; q < 9; ++q) ld2<R, L>(at(base + (int64_t)(2 * q) * stride, 2 * i), sl[2 * q], sl[2 * q + 1]);
+  } else {
 #pragma unroll
-  for (int c = 0; c < 6; ++c) { out[c] = bp[c] + bm[c]; out[6 + c] = bm[c] - bp[c]; }
-}
-
-// 64-bit-index forms (line kernels)
-template <typename R, typename L>
-TP_DEV void herm6_apply(const L* base, int64_t stride, int64_t i, const cx<R>* v, cx<R>* out) {
-  R d[6];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    cx<R> t = ld<R, L>(base + (int64_t)k * stride + i);
-    d[2 * k] = t.re;
-    d[2 * k + 1] = t.im;
+    for (int k = 0; k < 18; ++k) sl[k] = ld<R, L>(at(base + (int64_t)k * stride, i));
   }
+}
+template <typename R, typename L>
+TP_DEV void herm6_slots(const L* base, int64_t stride, int64_t i, cx<R>* sl) {
+  if constexpr (paired<L>()) {
 #pragma unroll
-  for (int r = 0; r < 6; ++r) out[r] = d[r] * v[r];
-  int slot = 3;
+    for (int q = 0; q < 9; ++q) ld2<R, L>(base + (int64_t)(2 * q) * stride + 2 * i, sl[2 * q], sl[2 * q + 1]);
+  } else {
 #pragma unroll
-  for (int r = 1; r < 6; ++r) {
-#pragma unroll
-    for (int c = 0; c < r; ++c) {
-      cx<R> l = ld<R, L>(base + (int64_t)slot * stride + i);
-      out[r] += cmul(l, v[c]);
-      out[c] += cmulc(l, v[r]);
-      ++slot;
-    }
+    for (int k = 0; k < 18; ++k) sl[k] = ld<R, L>(base + (int64_t)k * stride + i);
   }
 }
 
-template <typename R, typename L>
-TP_DEV void clover_apply(const L* cl, int64_t stride, int64_t i, const cx<R>* psi, cx<R>* out) {
+// A psi for the clover term stored as two chiral blocks acting on psi_up -+ psi_lo
+// (planes [36][stride], block c at component 18c), with I = uint32_t (uniform plane
+// addressing) or int64_t.
+template <typename R, typename L, typename I>
+TP_DEV void clover_apply(const L* cl, int64_t stride, I i, const cx<R>* psi, cx<R>* out) {
   cx<R> up[6], um[6], bp[6], bm[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) { up[c] = psi[c] - psi[6 + c]; um[c] = psi[c] + psi[6 + c]; }
-  herm6_apply<R, L>(cl, stride, i, up, bp);
-  herm6_apply<R, L>(cl + 18 * stride, stride, i, um, bm);
+  {
+    cx<R> sl[18];
+    herm6_slots<R, L>(cl, stride, i, sl);
+    herm6_from_slots<R>(sl, up, bp);
+  }
+  {
+    cx<R> sl[18];
+    herm6_slots<R, L>(cl + 18 * stride, stride, i, sl);
+    herm6_from_slots<R>(sl, um, bm);
+  }
 #pragma unroll
   for (int c = 0; c < 6; ++c) { out[c] = bp[c] + bm[c]; out[6 + c] = bm[c] - bp[c]; }
 }

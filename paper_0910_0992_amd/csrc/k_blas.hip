@@ -1,7 +1,9 @@
 // Level-1 kernels for the Krylov solvers: fused updates with FP64 reductions.
 // Work unit = one half spinor (6 complex) of one site, so FP16 fields with a
-// scale per half spinor are updated consistently.  Reductions are deterministic:
-// a fixed grid writes per-block partials, one block sums them in a fixed order.
+// scale per half spinor are updated consistently.  The parity and the half are loop
+// indices uniform across the grid, so every plane address is a uniform base plus a
+// 32-bit site offset.  Reductions are deterministic: a fixed grid writes per-block
+// partials, one block sums them in a fixed order.
 #include "tp_internal.h"
 
 namespace {
@@ -16,8 +18,8 @@ template <typename S>
 struct BlasK {
   SpinorF<S> f[6][2];
   double a[2], b[2], c[2];
-  int par0;
-  int64_t V2, n;
+  int par0, npar;
+  uint32_t V2;
   double* partial;
 };
 
@@ -53,11 +55,11 @@ __global__ void __launch_bounds__(kBlock) k_blas(BlasK<S> k) {
   using R = typename Prec<S>::R;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const cx<R> A = cc<R>(k.a), B = cc<R>(k.b), C = cc<R>(k.c);
-  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < k.n;
-       u += (int64_t)gridDim.x * blockDim.x) {
-    int p = k.par0 + int(u / (2 * k.V2));
-    int h = int((u / k.V2) & 1);
-    int64_t i = u % k.V2;
+  for (int q = 0; q < k.npar; ++q)
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k.V2; i += gridDim.x * blockDim.x) {
+    const int p = k.par0 + q;
     cx<R> x[6], y[6], z[6], w[6], v[6];
     if constexpr (OP == B_ZERO) {
       for (int c = 0; c < 6; ++c) y[c] = czero<R>();
@@ -144,14 +146,14 @@ __global__ void __launch_bounds__(kBlock) k_blas(BlasK<S> k) {
 // y (precision SY) = x (precision SX), or y += x when ACC.
 template <typename SX, typename SY, bool ACC>
 __global__ void __launch_bounds__(kBlock) k_convert(SpinorF<SX> x0, SpinorF<SX> x1, SpinorF<SY> y0,
-                                                    SpinorF<SY> y1, int par0, int64_t V2, int64_t n) {
+                                                    SpinorF<SY> y1, int par0, int npar, int64_t V2) {
   using RX = typename Prec<SX>::R;
   using RY = typename Prec<SY>::R;
-  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
-       u += (int64_t)gridDim.x * blockDim.x) {
-    int p = par0 + int(u / (2 * V2));
-    int h = int((u / V2) & 1);
-    int64_t i = u % V2;
+  for (int q = 0; q < npar; ++q)
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < uint32_t(V2); i += gridDim.x * blockDim.x) {
+    const int p = par0 + q;
     cx<RX> a[6];
     load_half<SX, RX>(p ? x1 : x0, h, i, a);
     cx<RY> b[6];
@@ -196,10 +198,10 @@ int blas_go(tp_ctx ctx, int par0, int npar, const Field* const* fs, BlasArgs k) 
     for (int p = 0; p < 2; ++p) a.f[q][p] = fv<S>(fs[q], p);
   for (int r = 0; r < 2; ++r) { a.a[r] = k.a[r]; a.b[r] = k.b[r]; a.c[r] = k.c[r]; }
   a.par0 = par0;
-  a.V2 = ctx->lat.V2;
-  a.n = (int64_t)npar * 2 * a.V2;
+  a.npar = npar;
+  a.V2 = uint32_t(ctx->lat.V2);
   a.partial = ctx->red_partial;
-  int64_t nb = (a.n + kBlock - 1) / kBlock;
+  int64_t nb = ((int64_t)npar * 2 * a.V2 + kBlock - 1) / kBlock;
   if (nb > kBlasBlocks) nb = kBlasBlocks;
   hipLaunchKernelGGL((k_blas<S, OP>), dim3((unsigned)nb), dim3(kBlock), 0, ctx->stream, a);
   LAUNCH_CHECK();
@@ -218,12 +220,11 @@ int blas_prec(tp_ctx ctx, int prec, int par0, int npar, const Field* const* fs, 
 template <typename SX, typename SY, bool ACC>
 void conv_go(tp_ctx ctx, int par0, int npar, const Field& x, const Field& y) {
   int64_t V2 = ctx->lat.V2;
-  int64_t n = (int64_t)npar * 2 * V2;
-  int64_t nb = (n + kBlock - 1) / kBlock;
-  if (nb > 65536) nb = 65536;
+  int64_t nb = (V2 + kBlock - 1) / kBlock;
+  if (nb > 2048) nb = 2048;
   hipLaunchKernelGGL((k_convert<SX, SY, ACC>), dim3((unsigned)nb), dim3(kBlock), 0, ctx->stream,
                      x.template par<SX>(0), x.template par<SX>(1), y.template par<SY>(0),
-                     y.template par<SY>(1), par0, V2, n);
+                     y.template par<SY>(1), par0, npar, V2);
   LAUNCH_CHECK();
 }
 

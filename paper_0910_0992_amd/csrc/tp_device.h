@@ -134,6 +134,16 @@ struct SpinorF {
   float* nrm[2];
   int64_t stride;
 };
+// Field r of a batch of fields allocated back to back (24 planes of `stride` sites and 4
+// scale planes apart): the right-hand sides of a batched solve share one launch.
+template <typename S> TP_DEV SpinorF<S> rhs_view(SpinorF<S> f, uint32_t r) {
+  const int64_t e = (int64_t)r * 24 * f.stride, n = (int64_t)r * 4 * f.stride;
+  if (f.p[0]) f.p[0] += e;
+  if (f.p[1]) f.p[1] += e;
+  if (f.nrm[0]) f.nrm[0] += n;
+  if (f.nrm[1]) f.nrm[1] += n;
+  return f;
+}
 
 // Element i of a plane, addressed as plane + a 32-bit byte offset: with the plane pointer
 // uniform across the wavefront this is the scalar-base + vector-offset load form, with no
@@ -170,6 +180,10 @@ TP_DEV void store_half(const SpinorF<S>& f, int h, uint32_t i, const cx<R>* v) {
     R m = R(0);
 #pragma unroll
     for (int c = 0; c < 6; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+    // below the smallest normal FP32 value 1/m would overflow (a point source decaying as
+    // mu^-t along a long line gets there): such a half spinor is stored as zero.  A NaN
+    // fails the comparison and propagates.
+    if (m < R(1.17549435e-38f)) m = R(0);
     R inv = m > R(0) ? R(1) / m : R(0);
 #pragma unroll
     for (int q = 0; q < 3; ++q) st2(at(b + (int64_t)(2 * q) * f.stride, 2 * i), inv * v[2 * q], inv * v[2 * q + 1]);
@@ -208,6 +222,10 @@ TP_DEV void store_half(const SpinorF<S>& f, int h, int64_t i, const cx<R>* v) {
     R m = R(0);
 #pragma unroll
     for (int c = 0; c < 6; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+    // below the smallest normal FP32 value 1/m would overflow (a point source decaying as
+    // mu^-t along a long line gets there): such a half spinor is stored as zero.  A NaN
+    // fails the comparison and propagates.
+    if (m < R(1.17549435e-38f)) m = R(0);
     R inv = m > R(0) ? R(1) / m : R(0);
 #pragma unroll
     for (int q = 0; q < 3; ++q) st2(b + (int64_t)(2 * q) * f.stride + 2 * i, inv * v[2 * q], inv * v[2 * q + 1]);

@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--schemes", action="store_true",
                     help="only compare the four schemes in FP64 on the workload: BiCGStab iterations "
                          "and time, CGNR iterations and the Lanczos condition number")
+    ap.add_argument("--point-sources", action="store_true",
+                    help="only time the 12 spin-colour point sources at the origin: one after "
+                         "another, as one batch, and with FP64 even-odd")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -159,8 +162,59 @@ def compare_schemes(args):
                       "m0": cfg["m0"], "results": out}))
 
 
+def point_sources(args):
+    """The 12 unit spin-colour sources at the origin of the workload, each to 1e-10: mixed
+    temporal+3D-ILU one after another, the same as one batch (tp_solve_multi), and FP64 4D
+    even-odd one after another.  One JSON line."""
+    import torch
+
+    import synth
+    from paper_0910_0992_amd import Operator
+
+    cfg = synth.WORKLOADS[args.workload]
+    dims, xi = cfg["dims"], cfg["xi"]
+    U = synth.make_links(dims, cfg["eps_s"], cfg["eps_t"], cfg["seed"])
+    op = Operator(torch.from_numpy(U).cuda(), cfg["m0"], xi, cfg["csw_s"] / xi, cfg["csw_t"], -1)
+    del U
+    etas = [torch.from_numpy(synth.make_point_source(dims, k // 3, k % 3)).cuda() for k in range(12)]
+
+    def timed(f):
+        f()  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = f()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+
+    res = {"mode": "point_sources", "workload": args.workload, "dims": dims, "prec": args.prec}
+    t_seq, infos = timed(lambda: [op.solve(e, scheme="TEMPORAL_SCHUR", prec=args.prec, tol=1e-10)[1]
+                                  for e in etas])
+    res["sequential_s"] = t_seq
+    res["sequential_iters"] = [i["iters"] for i in infos]
+    print(f"[bench] 12 sources one at a time: {t_seq:.3f} s", file=sys.stderr, flush=True)
+    t_b, (xs, binfo) = timed(lambda: op.solve_multi(etas, scheme="TEMPORAL_SCHUR", prec=args.prec,
+                                                    tol=1e-10))
+    res["batched_s"] = t_b
+    res["batched_iters"] = [i["iters"] for i in binfo]
+    res["batched_max_true_rel_resid"] = max(i["true_rel_resid"] for i in binfo)
+    print(f"[bench] 12 sources as one batch: {t_b:.3f} s", file=sys.stderr, flush=True)
+    del xs
+    if not args.no_baseline:
+        t_64, i64 = timed(lambda: [op.solve(e, scheme="SCHUR4D", prec="F64", tol=1e-10)[1] for e in etas])
+        res["fp64_even_odd_sequential_s"] = t_64
+        res["fp64_even_odd_iters"] = [i["iters"] for i in i64]
+        res["speedup_batched_vs_fp64_even_odd"] = t_64 / t_b
+        print(f"[bench] 12 sources FP64 even-odd: {t_64:.3f} s", file=sys.stderr, flush=True)
+    res["speedup_batched_vs_sequential"] = t_seq / t_b
+    op.close()
+    print(json.dumps(res))
+
+
 def main():
     args = parse()
+    if args.point_sources:
+        point_sources(args)
+        return
     if args.schemes:
         compare_schemes(args)
         return

@@ -193,6 +193,18 @@ typedef struct {
 tp_status tp_solve(tp_op op, const tp_solve_params* params, void* x, const void* eta,
                    tp_solve_info* info);
 
+/* Solves M x[k] = eta[k] for k < nrhs (1..16) with the same parameters.  For
+ * mixed-precision BiCGStab on the full-lattice schemes (UNPREC, TEMPORAL, and
+ * TEMPORAL_SCHUR with clover) the right-hand sides iterate in lockstep: every
+ * operator application is one launch per kernel for all of them, so links and
+ * clover are read once per site for the batch, and each inner product is one
+ * synchronisation; scalars, reliable updates and stopping are per right-hand
+ * side.  Other settings solve the right-hand sides one after another.  x[k],
+ * eta[k]: canonical device spinors (x[k] distinct, none equal to any eta);
+ * info: array of nrhs.  Returns the worst status over the right-hand sides. */
+tp_status tp_solve_multi(tp_op op, const tp_solve_params* params, int32_t nrhs, void* const* x,
+                         const void* const* eta, tp_solve_info* info);
+
 /* ---- gradient ----------------------------------------------------------------------
  * For L(x, lambda) with lambda = M^-dagger dL/dx*: per link U_mu(s),
  *   Y = sum_a [P-^mu x(s+mu)]_a lambda(s)_a^dag,  Z = sum_a [P+^mu x(s)]_a lambda(s+mu)_a^dag,

@@ -67,6 +67,7 @@ SIGNATURES = [
     ("tp_prepare_source", [_P, _I, _I, _P, _P], _I),
     ("tp_reconstruct", [_P, _I, _I, _P, _P], _I),
     ("tp_solve", [_P, C.POINTER(SolveParams), _P, _P, C.POINTER(SolveInfo)], _I),
+    ("tp_solve_multi", [_P, C.POINTER(SolveParams), _I, C.POINTER(_P), C.POINTER(_P), C.POINTER(SolveInfo)], _I),
     ("tp_force", [_P, _P, _P, _P, _I], _I),
     ("tp_status_string", [_I], C.c_char_p),
     ("tp_last_error", [], C.c_char_p),

@@ -175,6 +175,29 @@ class Operator:
             L.check(st)
         return x, d
 
+    def solve_multi(self, etas, scheme="TEMPORAL_SCHUR", solver="BICGSTAB", prec="F64", tol=1e-10,
+                    inner_tol=0.0, max_iter=0, max_restarts=0, x0=None, raise_on_noconv=True):
+        """x[k] with |eta[k] - M x[k]| <= tol |eta[k]| for a batch of up to 16 sources solved
+        together (tp_solve_multi); etas: [n, Lt, Lz, Ly, Lx, 4, 3].  Returns (x, [info])."""
+        n = len(etas)
+        srcs = [self._in(e) for e in etas]
+        xs = [self._in(x0[k]).clone() if x0 is not None else self._out() for k in range(n)]
+        P = L.SolveParams(scheme=_scheme(scheme), solver=L.SOLVERS[solver.upper()], prec=_prec(prec),
+                          max_iter=int(max_iter), max_restarts=int(max_restarts),
+                          use_x0=int(x0 is not None), estimate_kappa=0,
+                          reserved=0, tol=float(tol), inner_tol=float(inner_tol))
+        infos = (L.SolveInfo * n)()
+        xp = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
+        ep = (C.c_void_p * n)(*[e.data_ptr() for e in srcs])
+        self._bind_stream()
+        st = self._lib.tp_solve_multi(self._op, C.byref(P), n, xp, ep, infos)
+        out = [infos[k].as_dict() for k in range(n)]
+        for d in out:
+            d["status"] = st
+        if st != L.TP_OK and (raise_on_noconv or st != L.TP_ENOCONV):
+            L.check(st)
+        return torch.stack(xs), out
+
     def force(self, x, lam, projected=True):
         """Link gradient from x and lambda (see tp_force): [4, Lt, Lz, Ly, Lx, 3, 3]."""
         xs, ls = self._in(x), self._in(lam)

@@ -12,6 +12,8 @@
 
 tp_status op_solve(tp_op op, const tp_solve_params& P, Field& x64, const Field& eta64,
                    tp_solve_info& info);
+tp_status op_solve_multi(tp_op op, const tp_solve_params& P, int nr, Field& x64, const Field& eta64,
+                         tp_solve_info* info);
 
 const char* const kKernelNames[KID_COUNT] = {
     "pack_unpack", "site_p3",  "schur4d_eo_clover_inv", "schur4d_oe_clover", "line_scan",
@@ -134,15 +136,18 @@ void dev_free(void* p) {
   if (p) (void)hipFree(p);
 }
 
-Field field_alloc(const Lattice& lat, int prec) {
+Field field_alloc(const Lattice& lat, int prec, int nr) {
   Field f;
   f.prec = prec;
   f.V2 = lat.V2;
-  f.data = dev_alloc(size_t(2) * 12 * lat.V2 * f.elem_bytes());
-  HIP_CHECK(hipMemset(f.data, 0, size_t(2) * 12 * lat.V2 * f.elem_bytes()));
+  f.nr = nr;
+  const size_t db = size_t(nr) * 2 * 12 * lat.V2 * f.elem_bytes();
+  f.data = dev_alloc(db);
+  HIP_CHECK(hipMemset(f.data, 0, db));
   if (prec == TP_F16N) {
-    f.nrm = static_cast<float*>(dev_alloc(size_t(2) * 2 * lat.V2 * sizeof(float)));
-    HIP_CHECK(hipMemset(f.nrm, 0, size_t(2) * 2 * lat.V2 * sizeof(float)));
+    const size_t nb = size_t(nr) * 2 * 2 * lat.V2 * sizeof(float);
+    f.nrm = static_cast<float*>(dev_alloc(nb));
+    HIP_CHECK(hipMemset(f.nrm, 0, nb));
   }
   f.owned = true;
   return f;
@@ -257,8 +262,8 @@ tp_status tp_ctx_create(const int32_t dims[4], int32_t bc_t, int32_t device, tp_
     try {
       HIP_CHECK(hipSetDevice(device));
       c->red_partial = static_cast<double*>(dev_alloc(sizeof(double) * 8 * kRedBlocks));
-      c->red_result = static_cast<double*>(dev_alloc(sizeof(double) * 8));
-      HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&c->red_host), sizeof(double) * 8,
+      c->red_result = static_cast<double*>(dev_alloc(sizeof(double) * 8 * kMaxRhs));
+      HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&c->red_host), sizeof(double) * 8 * kMaxRhs,
                               hipHostMallocDefault));
     } catch (...) {
       dev_free(c->red_partial);
@@ -640,6 +645,55 @@ tp_status tp_solve(tp_op op, const tp_solve_params* params, void* x, const void*
     if (P.use_x0) launch_pack(ctx, static_cast<const double2*>(x), x64, l4, false, w);
     st = op_solve(op, P, x64, eta64, *info);
     launch_unpack(ctx, x64, static_cast<double2*>(x), l4, false, w);
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    prof_flush(ctx);
+    if (st != TP_OK)
+      g_last_error = st == TP_ENOCONV ? "iteration cap reached before the target residual"
+                                      : "Krylov breakdown";
+  });
+  if (g != TP_OK) return g;
+  return st;
+}
+
+tp_status tp_solve_multi(tp_op op, const tp_solve_params* params, int32_t nrhs, void* const* x,
+                         const void* const* eta, tp_solve_info* info) {
+  tp_status st = TP_OK;
+  tp_status g = guard([&] {
+    need(op, "op");
+    need(params, "params");
+    need(x, "x");
+    need(eta, "eta");
+    need(info, "info");
+    if (nrhs < 1 || nrhs > kMaxRhs) TP_THROW(TP_EINVAL, "nrhs must be 1..16");
+    for (int q = 0; q < nrhs; ++q) {
+      need(x[q], "x[k]");
+      need(eta[q], "eta[k]");
+      for (int k = 0; k < nrhs; ++k)
+        if (x[q] == eta[k] || (k != q && x[q] == x[k])) TP_THROW(TP_EINVAL, "x[k] must be distinct buffers");
+    }
+    const tp_solve_params& P = *params;
+    check_scheme(P.scheme);
+    check_prec(P.prec);
+    if (P.solver != TP_CGNR && P.solver != TP_BICGSTAB) TP_THROW(TP_EINVAL, "bad solver");
+    if (P.scheme == TP_SCHUR4D && P.prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
+    if (!(P.tol >= 0) || !(P.inner_tol >= 0)) TP_THROW(TP_EINVAL, "tolerances");
+    tp_ctx ctx = op->g->ctx;
+    set_device(ctx);
+    bool l4 = scheme_layout4(P.scheme);
+    if (l4 && ctx->lat.L[3] % 2) TP_THROW(TP_EDIMS, "SCHUR4D needs an even time extent");
+    Field& eta64 = ws_get_n(op, TP_F64, 62, nrhs);
+    Field& x64 = ws_get_n(op, TP_F64, 63, nrhs);
+    const double2* w = l4 ? nullptr : op->g->w_d;  // p3 schemes solve in the axial frame
+    for (int q = 0; q < nrhs; ++q) {
+      Field e = eta64.view(q), xq = x64.view(q);
+      launch_pack(ctx, static_cast<const double2*>(eta[q]), e, l4, false, w);
+      if (P.use_x0) launch_pack(ctx, static_cast<const double2*>(x[q]), xq, l4, false, w);
+    }
+    st = op_solve_multi(op, P, nrhs, x64, eta64, info);
+    for (int q = 0; q < nrhs; ++q) {
+      Field xq = x64.view(q);
+      launch_unpack(ctx, xq, static_cast<double2*>(x[q]), l4, false, w);
+    }
     HIP_CHECK(hipStreamSynchronize(ctx->stream));
     prof_flush(ctx);
     if (st != TP_OK)

@@ -20,10 +20,12 @@ struct BlasK {
   double a[2], b[2], c[2];
   int par0, npar;
   uint32_t V2;
-  double* partial;
+  int nr;                      // right-hand sides: block b works on field b % nr of each batch
+  double coef[kMaxRhs][8];     // nr > 1: per right-hand side a, b, c (complex) and a skip flag
+  double* partial;             // [nr][blocks per right-hand side][8]
 };
 
-TP_DEV void block_reduce(double (&acc)[8], int nred, double* partial) {
+TP_DEV void block_reduce(double (&acc)[8], int nred, double* partial, uint32_t blk) {
   __shared__ double sh[kBlock / 64][8];
   for (int k = 0; k < nred; ++k) {
     double v = acc[k];
@@ -34,7 +36,7 @@ TP_DEV void block_reduce(double (&acc)[8], int nred, double* partial) {
   if (threadIdx.x < (unsigned)nred) {
     double s = 0;
     for (int w = 0; w < kBlock / 64; ++w) s += sh[w][threadIdx.x];
-    partial[(int64_t)blockIdx.x * 8 + threadIdx.x] = s;
+    partial[(int64_t)blk * 8 + threadIdx.x] = s;
   }
 }
 
@@ -54,71 +56,76 @@ template <typename S, int OP>
 __global__ void __launch_bounds__(kBlock) k_blas(BlasK<S> k) {
   using R = typename Prec<S>::R;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const cx<R> A = cc<R>(k.a), B = cc<R>(k.b), C = cc<R>(k.c);
-  for (int q = 0; q < k.npar; ++q)
+  const uint32_t nr = uint32_t(k.nr), rhs = blockIdx.x % nr, blk = blockIdx.x / nr, nblk = gridDim.x / nr;
+  const double* cf = nr > 1 ? k.coef[rhs] : nullptr;
+  const cx<R> A = cc<R>(cf ? cf : k.a), B = cc<R>(cf ? cf + 2 : k.b), C = cc<R>(cf ? cf + 4 : k.c);
+  const int npar = (cf && cf[6] != 0.0) ? 0 : k.npar;  // a skipped right-hand side is left untouched
+  for (int q = 0; q < npar; ++q)
 #pragma unroll
   for (int h = 0; h < 2; ++h)
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < k.V2; i += gridDim.x * blockDim.x) {
+  for (uint32_t i = blk * blockDim.x + threadIdx.x; i < k.V2; i += nblk * blockDim.x) {
     const int p = k.par0 + q;
+    const SpinorF<S> f0 = rhs_view(k.f[0][p], rhs), f1 = rhs_view(k.f[1][p], rhs), f2 = rhs_view(k.f[2][p], rhs);
+    const SpinorF<S> f3 = rhs_view(k.f[3][p], rhs), f4 = rhs_view(k.f[4][p], rhs), f5 = rhs_view(k.f[5][p], rhs);
     cx<R> x[6], y[6], z[6], w[6], v[6];
     if constexpr (OP == B_ZERO) {
       for (int c = 0; c < 6; ++c) y[c] = czero<R>();
-      store_half<S, R>(k.f[1][p], h, i, y);
+      store_half<S, R>(f1, h, i, y);
     } else if constexpr (OP == B_COPY) {
-      load_half<S, R>(k.f[0][p], h, i, x);
-      store_half<S, R>(k.f[1][p], h, i, x);
+      load_half<S, R>(f0, h, i, x);
+      store_half<S, R>(f1, h, i, x);
     } else if constexpr (OP == B_AXPY) {
-      load_half<S, R>(k.f[0][p], h, i, x);
-      load_half<S, R>(k.f[1][p], h, i, y);
+      load_half<S, R>(f0, h, i, x);
+      load_half<S, R>(f1, h, i, y);
       for (int c = 0; c < 6; ++c) y[c] += cmul(A, x[c]);
-      store_half<S, R>(k.f[1][p], h, i, y);
+      store_half<S, R>(f1, h, i, y);
     } else if constexpr (OP == B_XPAY) {
-      load_half<S, R>(k.f[0][p], h, i, x);
-      load_half<S, R>(k.f[1][p], h, i, y);
+      load_half<S, R>(f0, h, i, x);
+      load_half<S, R>(f1, h, i, y);
       for (int c = 0; c < 6; ++c) y[c] = x[c] + cmul(A, y[c]);
-      store_half<S, R>(k.f[1][p], h, i, y);
+      store_half<S, R>(f1, h, i, y);
     } else if constexpr (OP == B_NORM2) {
-      load_half<S, R>(k.f[0][p], h, i, x);
+      load_half<S, R>(f0, h, i, x);
       for (int c = 0; c < 6; ++c) acc[0] += double(norm2(x[c]));
     } else if constexpr (OP == B_DOT || OP == B_DOT_NORM) {
-      load_half<S, R>(k.f[0][p], h, i, x);
-      load_half<S, R>(k.f[1][p], h, i, y);
+      load_half<S, R>(f0, h, i, x);
+      load_half<S, R>(f1, h, i, y);
       for (int c = 0; c < 6; ++c) {
         acc[0] += double(x[c].re) * double(y[c].re) + double(x[c].im) * double(y[c].im);
         acc[1] += double(x[c].re) * double(y[c].im) - double(x[c].im) * double(y[c].re);
         if constexpr (OP == B_DOT_NORM) acc[2] += double(norm2(y[c]));
       }
     } else if constexpr (OP == B_CAXPY_NORM) {
-      load_half<S, R>(k.f[0][p], h, i, x);
-      load_half<S, R>(k.f[1][p], h, i, y);
+      load_half<S, R>(f0, h, i, x);
+      load_half<S, R>(f1, h, i, y);
       for (int c = 0; c < 6; ++c) {
         y[c] += cmul(A, x[c]);
         acc[0] += double(norm2(y[c]));
       }
-      store_half<S, R>(k.f[1][p], h, i, y);
+      store_half<S, R>(f1, h, i, y);
     } else if constexpr (OP == B_AXPYZ_NORM) {
-      load_half<S, R>(k.f[0][p], h, i, x);
-      load_half<S, R>(k.f[1][p], h, i, y);
+      load_half<S, R>(f0, h, i, x);
+      load_half<S, R>(f1, h, i, y);
       for (int c = 0; c < 6; ++c) {
         y[c] += cmul(A, x[c]);
         acc[0] += double(norm2(y[c]));
       }
-      store_half<S, R>(k.f[2][p], h, i, y);
+      store_half<S, R>(f2, h, i, y);
     } else if constexpr (OP == B_DOT4_TS) {
-      load_half<S, R>(k.f[0][p], h, i, x);  // t
-      load_half<S, R>(k.f[1][p], h, i, y);  // s
-      load_half<S, R>(k.f[2][p], h, i, z);  // rhat
+      load_half<S, R>(f0, h, i, x);  // t
+      load_half<S, R>(f1, h, i, y);  // s
+      load_half<S, R>(f2, h, i, z);  // rhat
       dot_acc(x, y, acc);
       for (int c = 0; c < 6; ++c) acc[2] += double(norm2(x[c]));
       dot_acc(z, y, acc + 3);
       dot_acc(z, x, acc + 5);
     } else if constexpr (OP == B_BICG_FUSED) {
       // f0 = x, f1 = p, f2 = s, f3 = t, f4 = v, f5 = r (out); A = alpha, B = omega, C = beta
-      load_half<S, R>(k.f[0][p], h, i, x);
-      load_half<S, R>(k.f[1][p], h, i, y);
-      load_half<S, R>(k.f[2][p], h, i, z);
-      load_half<S, R>(k.f[3][p], h, i, w);
-      load_half<S, R>(k.f[4][p], h, i, v);
+      load_half<S, R>(f0, h, i, x);
+      load_half<S, R>(f1, h, i, y);
+      load_half<S, R>(f2, h, i, z);
+      load_half<S, R>(f3, h, i, w);
+      load_half<S, R>(f4, h, i, v);
       const cx<R> BC = cmul(B, C);
       for (int c = 0; c < 6; ++c) {
         x[c] += cmul(A, y[c]) + cmul(B, z[c]);
@@ -126,13 +133,13 @@ __global__ void __launch_bounds__(kBlock) k_blas(BlasK<S> k) {
         y[c] = z[c] + cmul(C, y[c]) - cmul(BC, v[c]);  // p = r + beta (p - omega v)
         acc[0] += double(norm2(z[c]));
       }
-      store_half<S, R>(k.f[0][p], h, i, x);
-      store_half<S, R>(k.f[5][p], h, i, z);
-      store_half<S, R>(k.f[1][p], h, i, y);
+      store_half<S, R>(f0, h, i, x);
+      store_half<S, R>(f5, h, i, z);
+      store_half<S, R>(f1, h, i, y);
     } else if constexpr (OP == B_G5) {
-      load_half<S, R>(k.f[0][p], h, i, x);
+      load_half<S, R>(f0, h, i, x);
       for (int c = 0; c < 6; ++c) x[c] = -x[c];
-      store_half<S, R>(k.f[1][p], 1 - h, i, x);
+      store_half<S, R>(f1, 1 - h, i, x);
     }
   }
   constexpr int nred =
@@ -140,7 +147,7 @@ __global__ void __launch_bounds__(kBlock) k_blas(BlasK<S> k) {
       : (OP == B_DOT) ? 2
       : (OP == B_DOT_NORM) ? 3
       : (OP == B_DOT4_TS) ? 7 : 0;
-  if constexpr (nred > 0) block_reduce(acc, nred, k.partial);
+  if constexpr (nred > 0) block_reduce(acc, nred, k.partial + (int64_t)rhs * nblk * 8, blk);
 }
 
 // y (precision SY) = x (precision SX), or y += x when ACC.
@@ -166,8 +173,11 @@ __global__ void __launch_bounds__(kBlock) k_convert(SpinorF<SX> x0, SpinorF<SX> 
   }
 }
 
+// Block r sums the `nblocks` partials of right-hand side r into result[r][0..nred).
 __global__ void k_finish(const double* partial, int nblocks, int nred, double* result) {
   __shared__ double sh[kBlock];
+  partial += (int64_t)blockIdx.x * nblocks * 8;
+  result += (int64_t)blockIdx.x * 8;
   for (int k = 0; k < nred; ++k) {
     double s = 0;
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partial[(int64_t)b * 8 + k];
@@ -191,29 +201,51 @@ SpinorF<S> fv(const Field* f, int p) {
   return f->template par<S>(p);
 }
 
+// Coefficients of one call: the same for every right-hand side (per == null) or one set per
+// right-hand side, with optional skip flags.
+struct BlasCall {
+  BlasArgs k;
+  int nr;
+  const BlasArgs* per;
+  const bool* skip;
+};
+
 template <typename S, int OP>
-int blas_go(tp_ctx ctx, int par0, int npar, const Field* const* fs, BlasArgs k) {
+int blas_go(tp_ctx ctx, int par0, int npar, const Field* const* fs, const BlasCall& c) {
   BlasK<S> a;
   for (int q = 0; q < 6; ++q)
     for (int p = 0; p < 2; ++p) a.f[q][p] = fv<S>(fs[q], p);
-  for (int r = 0; r < 2; ++r) { a.a[r] = k.a[r]; a.b[r] = k.b[r]; a.c[r] = k.c[r]; }
+  for (int r = 0; r < 2; ++r) { a.a[r] = c.k.a[r]; a.b[r] = c.k.b[r]; a.c[r] = c.k.c[r]; }
+  a.nr = c.nr;
+  for (int q = 0; q < kMaxRhs; ++q)
+    for (int r = 0; r < 8; ++r) a.coef[q][r] = 0.0;
+  if (c.nr > 1) {
+    for (int q = 0; q < c.nr; ++q) {
+      const BlasArgs& k = c.per ? c.per[q] : c.k;
+      a.coef[q][0] = k.a[0]; a.coef[q][1] = k.a[1];
+      a.coef[q][2] = k.b[0]; a.coef[q][3] = k.b[1];
+      a.coef[q][4] = k.c[0]; a.coef[q][5] = k.c[1];
+      a.coef[q][6] = (c.skip && c.skip[q]) ? 1.0 : 0.0;
+    }
+  }
   a.par0 = par0;
   a.npar = npar;
   a.V2 = uint32_t(ctx->lat.V2);
   a.partial = ctx->red_partial;
+  // blocks per right-hand side: the whole grid stays near kBlasBlocks
   int64_t nb = ((int64_t)npar * 2 * a.V2 + kBlock - 1) / kBlock;
-  if (nb > kBlasBlocks) nb = kBlasBlocks;
-  hipLaunchKernelGGL((k_blas<S, OP>), dim3((unsigned)nb), dim3(kBlock), 0, ctx->stream, a);
+  nb = std::min<int64_t>(nb, std::max(1, kBlasBlocks / c.nr));
+  hipLaunchKernelGGL((k_blas<S, OP>), dim3((unsigned)(nb * c.nr)), dim3(kBlock), 0, ctx->stream, a);
   LAUNCH_CHECK();
   return int(nb);
 }
 
 template <int OP>
-int blas_prec(tp_ctx ctx, int prec, int par0, int npar, const Field* const* fs, BlasArgs k) {
+int blas_prec(tp_ctx ctx, int prec, int par0, int npar, const Field* const* fs, const BlasCall& c) {
   switch (prec) {
-    case TP_F64: return blas_go<double2, OP>(ctx, par0, npar, fs, k);
-    case TP_F32: return blas_go<float2, OP>(ctx, par0, npar, fs, k);
-    default: return blas_go<__half2, OP>(ctx, par0, npar, fs, k);
+    case TP_F64: return blas_go<double2, OP>(ctx, par0, npar, fs, c);
+    case TP_F32: return blas_go<float2, OP>(ctx, par0, npar, fs, c);
+    default: return blas_go<__half2, OP>(ctx, par0, npar, fs, c);
   }
 }
 
@@ -250,17 +282,32 @@ void conv(tp_ctx ctx, int par0, int npar, const Field& x, const Field& y) {
 
 void blas(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<const Field*> fl,
           BlasArgs k, double* red_out) {
+  blas_multi(ctx, op, par0, npar, fl, nullptr, nullptr, red_out, k);
+}
+
+void blas_multi(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<const Field*> fl,
+                const BlasArgs* per, const bool* skip, double* red_out, BlasArgs k) {
   const Field* fs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int nr = 0;
   {
     int q = 0;
-    for (const Field* f : fl) fs[q++] = f;
+    for (const Field* f : fl) {
+      fs[q++] = f;
+      if (f) {
+        if (nr && f->nr != nr) TP_THROW(TP_EINVAL, "blas: fields of different batch sizes");
+        nr = f->nr;
+      }
+    }
   }
+  if (nr < 1 || nr > kMaxRhs) TP_THROW(TP_EINVAL, "blas: batch size");
+  const BlasCall call{k, nr, per, skip};
   const Field* x = fs[0];
   const Field* y = fs[1];
   int prec = x ? x->prec : y->prec;
   double S = double(x ? x->elem_bytes() : y->elem_bytes()) * 12;
-  double n = double(npar) * ctx->lat.V2;
+  double n = double(npar) * ctx->lat.V2 * nr;
   if (op == B_CONVERT || op == B_MIXED_ACC) {
+    if (nr != 1) TP_THROW(TP_EINVAL, "blas: conversions take single fields");
     ProfScope ps(ctx, KID_BLAS, n * (S + double(y->elem_bytes()) * 12 * (op == B_MIXED_ACC ? 2 : 1)));
     if (op == B_CONVERT) conv<false>(ctx, par0, npar, *x, *y);
     else conv<true>(ctx, par0, npar, *x, *y);
@@ -279,33 +326,33 @@ void blas(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<const
     }
     ProfScope ps(ctx, KID_BLAS, n * S * passes);
     switch (op) {
-      case B_ZERO: nb = blas_prec<B_ZERO>(ctx, prec, par0, npar, fs, k); break;
-      case B_COPY: nb = blas_prec<B_COPY>(ctx, prec, par0, npar, fs, k); break;
-      case B_AXPY: nb = blas_prec<B_AXPY>(ctx, prec, par0, npar, fs, k); break;
-      case B_XPAY: nb = blas_prec<B_XPAY>(ctx, prec, par0, npar, fs, k); break;
-      case B_NORM2: nb = blas_prec<B_NORM2>(ctx, prec, par0, npar, fs, k); nred = 1; break;
-      case B_DOT: nb = blas_prec<B_DOT>(ctx, prec, par0, npar, fs, k); nred = 2; break;
-      case B_DOT_NORM: nb = blas_prec<B_DOT_NORM>(ctx, prec, par0, npar, fs, k); nred = 3; break;
-      case B_CAXPY_NORM: nb = blas_prec<B_CAXPY_NORM>(ctx, prec, par0, npar, fs, k); nred = 1; break;
-      case B_AXPYZ_NORM: nb = blas_prec<B_AXPYZ_NORM>(ctx, prec, par0, npar, fs, k); nred = 1; break;
-      case B_DOT4_TS: nb = blas_prec<B_DOT4_TS>(ctx, prec, par0, npar, fs, k); nred = 7; break;
-      case B_BICG_FUSED: nb = blas_prec<B_BICG_FUSED>(ctx, prec, par0, npar, fs, k); nred = 1; break;
-      case B_G5: nb = blas_prec<B_G5>(ctx, prec, par0, npar, fs, k); break;
+      case B_ZERO: nb = blas_prec<B_ZERO>(ctx, prec, par0, npar, fs, call); break;
+      case B_COPY: nb = blas_prec<B_COPY>(ctx, prec, par0, npar, fs, call); break;
+      case B_AXPY: nb = blas_prec<B_AXPY>(ctx, prec, par0, npar, fs, call); break;
+      case B_XPAY: nb = blas_prec<B_XPAY>(ctx, prec, par0, npar, fs, call); break;
+      case B_NORM2: nb = blas_prec<B_NORM2>(ctx, prec, par0, npar, fs, call); nred = 1; break;
+      case B_DOT: nb = blas_prec<B_DOT>(ctx, prec, par0, npar, fs, call); nred = 2; break;
+      case B_DOT_NORM: nb = blas_prec<B_DOT_NORM>(ctx, prec, par0, npar, fs, call); nred = 3; break;
+      case B_CAXPY_NORM: nb = blas_prec<B_CAXPY_NORM>(ctx, prec, par0, npar, fs, call); nred = 1; break;
+      case B_AXPYZ_NORM: nb = blas_prec<B_AXPYZ_NORM>(ctx, prec, par0, npar, fs, call); nred = 1; break;
+      case B_DOT4_TS: nb = blas_prec<B_DOT4_TS>(ctx, prec, par0, npar, fs, call); nred = 7; break;
+      case B_BICG_FUSED: nb = blas_prec<B_BICG_FUSED>(ctx, prec, par0, npar, fs, call); nred = 1; break;
+      case B_G5: nb = blas_prec<B_G5>(ctx, prec, par0, npar, fs, call); break;
       default: TP_THROW(TP_EINVAL, "blas op");
     }
   }
   if (nred > 0) {
     {
-      ProfScope ps(ctx, KID_REDUCE, double(nb) * 8 * 8);
-      hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, ctx->stream, ctx->red_partial, nb, nred,
+      ProfScope ps(ctx, KID_REDUCE, double(nb) * nr * 8 * 8);
+      hipLaunchKernelGGL(k_finish, dim3(nr), dim3(kBlock), 0, ctx->stream, ctx->red_partial, nb, nred,
                          ctx->red_result);
       LAUNCH_CHECK();
     }
-    HIP_CHECK(hipMemcpyAsync(ctx->red_host, ctx->red_result, sizeof(double) * nred,
+    HIP_CHECK(hipMemcpyAsync(ctx->red_host, ctx->red_result, sizeof(double) * 8 * nr,
                              hipMemcpyDeviceToHost, ctx->stream));
     HIP_CHECK(hipStreamSynchronize(ctx->stream));
     prof_flush(ctx);
-    for (int q = 0; q < nred; ++q) red_out[q] = ctx->red_host[q];
+    for (int q = 0; q < 8 * (nr - 1) + nred; ++q) red_out[q] = ctx->red_host[q];
   }
 }
 

@@ -26,7 +26,7 @@ void launch_line(tp_op op, int prec, int mode, int par, const LineIO& io, Field&
   int nscan = (mode == LM_CRCL || mode == LM_TINV || mode == LM_TDINV) ? 2 : 1;
   int nio = io.pass ? 2 : nscan;  // halves read and written
   double per = nio * 2 * hs + (io.base ? nio * hs : 0);
-  ProfScope ps(op->g->ctx, KID_LINE_CR, double(L.V2) * per);
+  ProfScope ps(op->g->ctx, KID_LINE_CR, double(L.V2) * per * dst.nr);
   TP_DISPATCH(prec, line_, op, mode, par, io, dst)
 }
 
@@ -34,6 +34,6 @@ void launch_ilu_mid(tp_op op, int prec, const Field& psi, const Field& u, Field&
   // reads psi_e, u, A_e; writes chi_e, n_e
   const Lattice& L = op->g->ctx->lat;
   double S = spinor_bytes(prec), C = clov_bytes(prec);
-  ProfScope ps(op->g->ctx, KID_ILU_MID, double(L.V2) * (4 * S + C));
+  ProfScope ps(op->g->ctx, KID_ILU_MID, double(L.V2) * (4 * S * chi.nr + C));
   TP_DISPATCH(prec, ilu_mid_, op, psi, u, chi, n)
 }

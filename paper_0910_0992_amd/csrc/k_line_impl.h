@@ -248,10 +248,24 @@ struct LineArgs {
   Geom g;
   int par, LPB, NCH;
   int lds_table;  // complex elements of LDS used by the chunk combine (the rest follows it)
+  int nr;         // right-hand sides: block b works on field b % nr of each batch
 };
 
+// Selects this block's right-hand side in every spinor argument; returns the block index
+// within that right-hand side.
 template <typename S>
-TP_DEV ScanCtx<typename Prec<S>::R> make_ctx(const LineArgs<S>& a, int CH) {
+TP_DEV uint32_t batch_select(LineArgs<S>& a) {
+  const uint32_t nr = uint32_t(a.nr), rhs = blockIdx.x % nr;
+  a.in = rhs_view(a.in, rhs);
+  a.out = rhs_view(a.out, rhs);
+  a.aux = rhs_view(a.aux, rhs);
+  a.self = rhs_view(a.self, rhs);
+  a.base = rhs_view(a.base, rhs);
+  return blockIdx.x / nr;
+}
+
+template <typename S>
+TP_DEV ScanCtx<typename Prec<S>::R> make_ctx(const LineArgs<S>& a, int CH, uint32_t blk) {
   using R = typename Prec<S>::R;
   ScanCtx<R> sc;
   const int tid = threadIdx.x;
@@ -265,7 +279,7 @@ TP_DEV ScanCtx<typename Prec<S>::R> make_ctx(const LineArgs<S>& a, int CH) {
   sc.NCH = a.NCH;
   sc.t0 = sc.j * CH;
   sc.Lt = a.g.Lt;
-  sc.s = blockIdx.x * a.LPB + sc.l;
+  sc.s = int(blk) * a.LPB + sc.l;
   sc.active = sc.s < a.g.Vs2;
   sc.inv_mu = R(a.inv_mu);
   sc.f = R(a.f);
@@ -307,7 +321,8 @@ __global__ void __launch_bounds__(1024) k_line(LineArgs<S> a) {
   using M = ModeT<MODE>;
   extern __shared__ char smem_raw[];
   cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
-  ScanCtx<R> sc = make_ctx<S>(a, CH);
+  const uint32_t blk = batch_select(a);
+  ScanCtx<R> sc = make_ctx<S>(a, CH, blk);
   const int s = sc.active ? sc.s : 0;
   cx<R> vb[CH][Arr<M::nb>::n], vf[CH][Arr<M::nf>::n];
   const R cout = R(a.c_out), cbase = R(a.c_base);
@@ -389,7 +404,8 @@ __global__ void __launch_bounds__(mid_threads<CH>()) k_ilu_mid(LineArgs<S> a) {
   // consecutive threads adjacent) instead of registers while y and the second scans run
   cx<R>* park = lds + a.lds_table;
   const int nthr = blockDim.x;
-  ScanCtx<R> sc = make_ctx<S>(a, CH);
+  const uint32_t blk = batch_select(a);
+  ScanCtx<R> sc = make_ctx<S>(a, CH, blk);
   const int s = sc.active ? sc.s : 0;
   cx<R> b[CH][6], f[CH][6], uup[CH][6];
 #pragma unroll
@@ -524,7 +540,7 @@ void go(tp_op op, K kern, LineArgs<S>& a, Shape sh, int park = 0) {
   const bool fast = sh.NCH % 16 == 0;
   a.lds_table = fast ? sh.LPB * 16 * 6 : sh.LPB * sh.NCH * 6;
   size_t lds = (size_t(a.lds_table) + size_t(park) * sh.LPB * sh.NCH) * sizeof(cx<typename Prec<S>::R>);
-  dim3 grid((unsigned)((L.Vs2 + sh.LPB - 1) / sh.LPB));
+  dim3 grid((unsigned)((L.Vs2 + sh.LPB - 1) / sh.LPB * a.nr));
   hipLaunchKernelGGL(kern, grid, dim3(sh.LPB * sh.NCH), lds, ctx->stream, a);
   LAUNCH_CHECK();
 }
@@ -547,6 +563,7 @@ void line_t(tp_op op, int par, const LineIO& io, Field& dst) {
   a.in.nrm[1] = lo.nrm[1];
   a.out = pv<S>(&dst, par);
   a.base = pv<S>(io.base, par);
+  a.nr = dst.nr;
   a.c_out = io.c_out;
   a.c_base = io.c_base;
   Shape sh = pick_shape(op->g->ctx->lat.L[3], 16, max_threads<S>(), {1, 2, 4});
@@ -578,6 +595,7 @@ void mid_t(tp_op op, const Field& psi, const Field& u, Field& chi, Field& n) {
   a.aux = pv<S>(&u, 0);
   a.out = pv<S>(&chi, 0);
   a.base = pv<S>(&n, 0);
+  a.nr = chi.nr;
   const int Lt = L.L[3];
   // one slice per thread where the line fits a workgroup (measured fastest), else more
   Shape sh{0, 0, 0};

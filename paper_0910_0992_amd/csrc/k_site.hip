@@ -21,6 +21,7 @@ struct SiteArgsP3 {
   double c_mu, c_A, c_t, c_s, c_in;
   Geom g;
   int par;  // output parity of this launch
+  int nr;   // right-hand sides: block b works on field b % nr of each batch
   double* partial;
 };
 
@@ -32,7 +33,10 @@ __global__ void __launch_bounds__(kBlock) k_site_p3(SiteArgsP3<S> a) {
   __shared__ double red[kBlock / 64];
   double acc = 0.0;
   const int p = a.par;  // one parity per launch: every field plane address is uniform
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < uint32_t(a.g.V2); i += gridDim.x * blockDim.x) {
+  const uint32_t nr = uint32_t(a.nr), rhs = blockIdx.x % nr, blk = blockIdx.x / nr, nblk = gridDim.x / nr;
+  const SpinorF<S> self = rhs_view(a.self[p], rhs), nbf = rhs_view(a.nb[p], rhs);
+  const SpinorF<S> in2 = rhs_view(a.in2[p], rhs), dst = rhs_view(a.dst[p], rhs);
+  for (uint32_t i = blk * blockDim.x + threadIdx.x; i < uint32_t(a.g.V2); i += nblk * blockDim.x) {
     int t, s;
     p3_ts32(a.g, i, t, s);
     cx<R> out[12];
@@ -40,7 +44,7 @@ __global__ void __launch_bounds__(kBlock) k_site_p3(SiteArgsP3<S> a) {
     for (int c = 0; c < 12; ++c) out[c] = czero<R>();
     if (a.c_mu != 0.0 || CLOV) {
       cx<R> psi[12];
-      load_spinor<S, R>(a.self[p], i, psi);
+      load_spinor<S, R>(self, i, psi);
       R cm = R(a.c_mu);
 #pragma unroll
       for (int c = 0; c < 12; ++c) out[c] = cm * psi[c];
@@ -53,14 +57,14 @@ __global__ void __launch_bounds__(kBlock) k_site_p3(SiteArgsP3<S> a) {
       }
     }
     if constexpr (DT) {
-      hop_time_p3<S, R, Lt>(a.self[p], a.u[p][3], a.g, t, s, R(a.c_t), out);
+      hop_time_p3<S, R, Lt>(self, a.u[p][3], a.g, t, s, R(a.c_t), out);
     }
     if constexpr (DS != 0) {
-      hop_space_p3<S, R, Lt, DS>(a.nb[p], a.u[p], a.u[1 - p], a.g, p, t, s, R(0.5 * a.c_s), out);
+      hop_space_p3<S, R, Lt, DS>(nbf, a.u[p], a.u[1 - p], a.g, p, t, s, R(0.5 * a.c_s), out);
     }
     if constexpr (IN2) {
       cx<R> e[12];
-      load_spinor<S, R>(a.in2[p], i, e);
+      load_spinor<S, R>(in2, i, e);
       R ci = R(a.c_in);
 #pragma unroll
       for (int c = 0; c < 12; ++c) out[c] += ci * e[c];
@@ -69,7 +73,7 @@ __global__ void __launch_bounds__(kBlock) k_site_p3(SiteArgsP3<S> a) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) acc += double(norm2(out[c]));
     }
-    store_spinor<S, R>(a.dst[p], i, out);
+    store_spinor<S, R>(dst, i, out);
   }
   if constexpr (NORM) {
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
@@ -294,8 +298,8 @@ void site_go(tp_op op, SiteArgsP3<S> a, int64_t nblocks, int par0, int npar) {
   for (int q = 0; q < npar; ++q) {
     a.par = par0 + q;
     a.partial = ctx->red_partial + (int64_t)q * nblocks * 8;
-    hipLaunchKernelGGL((k_site_p3<S, DT, DS, CLOV, IN2, NORM>), dim3((unsigned)nblocks), dim3(kBlock), 0,
-                       ctx->stream, a);
+    hipLaunchKernelGGL((k_site_p3<S, DT, DS, CLOV, IN2, NORM>), dim3((unsigned)(nblocks * a.nr)), dim3(kBlock),
+                       0, ctx->stream, a);
     LAUNCH_CHECK();
   }
 }
@@ -343,6 +347,8 @@ int site_t(tp_op op, const SiteIO& io, Field& dst, SiteCoef cf, int ck, int par0
   a.c_in = cf.c_in;
   a.g = L.g;
   // one launch per output parity; with a norm, each launch's partials follow the previous
+  a.nr = dst.nr;
+  if (norm && a.nr != 1) TP_THROW(TP_EINVAL, "a fused norm needs a single right-hand side");
   int64_t nb = (L.V2 + kBlock - 1) / kBlock;
   if (norm) nb = std::min<int64_t>(nb, kRedBlocks / 2);
   bool dt = cf.c_t != 0.0, ds = cf.c_s != 0.0;
@@ -419,9 +425,10 @@ int launch_site(tp_op op, int prec, const SiteIO& io, Field& dst, SiteCoef cf, i
   // spatial links read as two rows (12 reals) when they are SU(3) and the precision is reduced
   double Ls = (prec != TP_F64 && op->g->su3_spatial) ? Lb * 2 / 3 : Lb;
   bool self = cf.c_mu != 0 || (ck && cf.c_A != 0);
-  double bytes = double(npar) * L.V2 *
-                 (S + (self ? S : 0) + (cf.c_s != 0 ? S + 6 * Ls : 0) + (cf.c_t != 0 ? S + 2 * Lb : 0) +
-                  (ck && cf.c_A != 0 ? C : 0) + (io.in2 ? S : 0));
+  // spinor bytes per right-hand side; links and clover once for a whole batch
+  double sp = S + (self ? S : 0) + (cf.c_s != 0 ? S : 0) + (cf.c_t != 0 ? S : 0) + (io.in2 ? S : 0);
+  double lk = (cf.c_s != 0 ? 6 * Ls : 0) + (cf.c_t != 0 ? 2 * Lb : 0) + (ck && cf.c_A != 0 ? C : 0);
+  double bytes = double(npar) * L.V2 * (dst.nr * sp + lk);
   // the time-line pipeline's stencils are accounted separately from M / residual applies
   ProfScope ps(ctx, cf.c_t != 0 || io.in2 ? KID_SITE_P3 : KID_HOP, bytes);
   switch (prec) {

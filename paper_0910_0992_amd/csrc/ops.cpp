@@ -23,21 +23,26 @@
 #include <algorithm>
 #include <chrono>
 #include <map>
+#include <memory>
+#include <tuple>
+#include <vector>
 
 #include "tp_internal.h"
 
 struct Workspace {
-  std::map<std::pair<int, int>, Field> f;
+  std::map<std::tuple<int, int, int>, Field> f;
 };
 
-Field& ws_get(tp_op op, int prec, int slot) {
+Field& ws_get_n(tp_op op, int prec, int slot, int nr) {
   if (!op->ws) op->ws = new Workspace();
-  auto key = std::make_pair(prec, slot);
+  auto key = std::make_tuple(prec, slot, nr);
   auto it = op->ws->f.find(key);
   if (it != op->ws->f.end()) return it->second;
-  Field nf = field_alloc(op->g->ctx->lat, prec);
+  Field nf = field_alloc(op->g->ctx->lat, prec, nr);
   return op->ws->f.emplace(key, nf).first->second;
 }
+
+Field& ws_get(tp_op op, int prec, int slot) { return ws_get_n(op, prec, slot, op->batch_nr); }
 
 void ws_free(tp_op op) {
   if (!op->ws) return;
@@ -171,8 +176,16 @@ struct KrylovOp {
   tp_op op;
   int scheme, prec;
   int par0, npar;
+  int nr = 1;  // right-hand sides per field (batched applies)
   void apply(const Field& src, Field& dst, bool dagger) const {
     tp_ctx ctx = op->g->ctx;
+    // the composite operators' temporaries are batches of nr fields while this runs
+    struct BatchScope {
+      tp_op op;
+      int saved;
+      BatchScope(tp_op o, int n) : op(o), saved(o->batch_nr) { o->batch_nr = n; }
+      ~BatchScope() { op->batch_nr = saved; }
+    } scope(op, nr);
     const Field* in = &src;
     Field* out = &dst;
     Field* ga = nullptr;
@@ -748,4 +761,258 @@ tp_status op_solve(tp_op op, const tp_solve_params& P, Field& x64, const Field& 
   prof_flush(ctx);
   info.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return st;
+}
+
+// ---------------------------------------------------------------- batched right-hand sides
+// nr right-hand sides solved together: the Krylov recurrences of every right-hand side run in
+// lockstep, so each operator application is one batched launch per kernel (links and clover
+// read once per site for all of them) and each reduction one synchronisation.  Scalars,
+// reliable updates and stopping are per right-hand side; a right-hand side that has
+// converged (or stalled) is skipped by the vector updates.  Mixed-precision BiCGStab on the
+// full-lattice schemes only; everything else runs the right-hand sides one after another.
+tp_status op_solve_multi(tp_op op, const tp_solve_params& P, int nr, Field& x64, const Field& eta64,
+                         tp_solve_info* info) {
+  tp_ctx ctx = op->g->ctx;
+  auto t0 = std::chrono::steady_clock::now();
+  const bool l4 = scheme_layout4(P.scheme);
+  const bool sub = (P.scheme == TP_SCHUR4D) || (P.scheme == TP_TEMPORAL_SCHUR && !op->c);
+  const int pr = P.prec;
+  tp_status worst = TP_OK;
+  auto merge = [&](tp_status st) {
+    if (st != TP_OK && (worst == TP_OK || st == TP_EBREAKDOWN)) worst = st;
+  };
+  if (nr == 1 || pr == TP_F64 || P.solver != TP_BICGSTAB || sub) {
+    for (int q = 0; q < nr; ++q) {
+      Field xq = x64.view(q);
+      merge(op_solve(op, P, xq, eta64.view(q), info[q]));
+    }
+    return worst;
+  }
+  const double tol = P.tol > 0 ? P.tol : 1e-10;
+  const double delta = P.inner_tol > 0 ? P.inner_tol : (pr == TP_F32 ? 1e-3 : 0.02);
+  const int max_iter = P.max_iter > 0 ? P.max_iter : 100000;
+  const int max_upd = P.max_restarts > 0 ? P.max_restarts : 200;
+  KrylovOp A{op, P.scheme, pr, 0, 2, nr};
+  Field& r = ws_get_n(op, pr, W_R, nr);
+  Field& rh = ws_get_n(op, pr, W_RHAT, nr);
+  Field& p = ws_get_n(op, pr, W_P, nr);
+  Field& v = ws_get_n(op, pr, W_V, nr);
+  Field& s = ws_get_n(op, pr, W_S, nr);
+  Field& t = ws_get_n(op, pr, W_T, nr);
+  Field& y = ws_get_n(op, pr, W_Y, nr);
+  Field& xbest = ws_get_n(op, TP_F64, W_TMP64, nr);
+  Field& r64 = ws_get_n(op, TP_F64, W_R64, 1);
+  Field& rin = ws_get_n(op, pr, W_B, 1);
+  Field& et = ws_get_n(op, pr, W_D, 1);
+  Field& d = ws_get_n(op, pr, W_X, 1);
+  struct St {
+    double eta2 = 0, r2 = 0, rr2 = 0, rho_r = 0, rho_i = 0, rmax2 = 0, seg_r2 = 0, seg_rr2 = 0;
+    double best2 = 0, seg_best = 0, al_r = 0, al_i = 0;
+    int since_best = 0, seg_start = 0, seg_best_it = 0;
+    bool done = false, failed = false, upd = false;
+  };
+  std::vector<St> S(nr);
+  std::vector<double> red(8 * nr);
+  std::vector<BlasArgs> args(nr);
+  std::unique_ptr<bool[]> skip(new bool[nr]);
+  for (int q = 0; q < nr; ++q) info[q] = tp_solve_info{};
+  blas_multi(ctx, B_NORM2, 0, 2, {&eta64}, nullptr, nullptr, red.data());
+  for (int q = 0; q < nr; ++q) {
+    S[q].eta2 = red[8 * q];
+    if (!isfinite(S[q].eta2)) TP_THROW(TP_EINVAL, "source contains NaN or Inf");
+  }
+  if (!P.use_x0) blas(ctx, B_ZERO, 0, 2, {nullptr, &x64});
+  blas(ctx, B_COPY, 0, 2, {&x64, &xbest});
+  // preconditioned FP64 residual of right-hand side q into r[q]; y[q] = 0
+  auto restart_residual = [&](int q) {
+    Field rq = r.view(q), yq = y.view(q);
+    double rr[8];
+    blas(ctx, B_CONVERT, 0, 2, {&r64, &rin});
+    op_prepare(op, P.scheme, pr, rin, et);
+    blas(ctx, B_COPY, 0, 2, {&et, &rq});
+    blas(ctx, B_ZERO, 0, 2, {nullptr, &yq});
+    blas(ctx, B_NORM2, 0, 2, {&rq}, BlasArgs{}, rr);
+    St& z = S[q];
+    z.rr2 = z.seg_rr2 = z.rmax2 = z.seg_best = rr[0];
+    z.seg_r2 = z.r2;
+    z.seg_start = z.seg_best_it = info[q].iters;
+  };
+  auto give_up = [&](int q) {
+    Field xq = x64.view(q), bq = xbest.view(q);
+    blas(ctx, B_COPY, 0, 2, {&bq, &xq});
+    S[q].failed = true;
+  };
+  for (int q = 0; q < nr; ++q) {
+    St& z = S[q];
+    if (z.eta2 == 0.0) {
+      Field xq = x64.view(q);
+      blas(ctx, B_ZERO, 0, 2, {nullptr, &xq});
+      z.done = true;
+      continue;
+    }
+    Field xq = x64.view(q);
+    z.r2 = z.best2 = true_residual(op, l4, xq, eta64.view(q), r64);
+    if (sqrt(z.r2 / z.eta2) <= tol) {
+      z.done = true;
+      continue;
+    }
+    restart_residual(q);
+  }
+  blas(ctx, B_COPY, 0, 2, {&r, &rh});
+  blas(ctx, B_COPY, 0, 2, {&r, &p});
+  blas_multi(ctx, B_DOT, 0, 2, {&rh, &r}, nullptr, nullptr, red.data());
+  for (int q = 0; q < nr; ++q) {
+    S[q].rho_r = red[8 * q];
+    S[q].rho_i = red[8 * q + 1];
+  }
+  int iter = 0;
+  while (true) {
+    bool any = false;
+    for (int q = 0; q < nr; ++q) {
+      skip[q] = S[q].done || S[q].failed;
+      any = any || !skip[q];
+    }
+    if (!any || iter >= max_iter) break;
+    ++iter;
+    A.apply(p, v, false);
+    blas_multi(ctx, B_DOT, 0, 2, {&rh, &v}, nullptr, skip.get(), red.data());
+    for (int q = 0; q < nr; ++q) {
+      St& z = S[q];
+      if (skip[q]) continue;
+      const double dr = red[8 * q], di = red[8 * q + 1];
+      const double den = dr * dr + di * di;
+      if (den == 0.0 || !isfinite(den)) {
+        give_up(q);
+        skip[q] = true;
+        continue;
+      }
+      z.al_r = (z.rho_r * dr + z.rho_i * di) / den;
+      z.al_i = (z.rho_i * dr - z.rho_r * di) / den;
+      args[q] = cplx(-z.al_r, -z.al_i);
+    }
+    blas_multi(ctx, B_AXPYZ_NORM, 0, 2, {&v, &r, &s}, args.data(), skip.get(), red.data());
+    for (int q = 0; q < nr; ++q) {
+      St& z = S[q];
+      z.upd = false;
+      if (skip[q]) continue;
+      info[q].iters++;
+      info[q].applies += 2;
+      const double tgt2 = 0.25 * tol * tol * z.eta2 / z.seg_r2 * z.seg_rr2;
+      if (red[8 * q] <= tgt2) {
+        // converged at the half step: y += alpha p, r = s, and no second half
+        Field yq = y.view(q), pq = p.view(q), sq = s.view(q), rq = r.view(q);
+        blas(ctx, B_AXPY, 0, 2, {&pq, &yq}, cplx(z.al_r, z.al_i));
+        blas(ctx, B_COPY, 0, 2, {&sq, &rq});
+        z.rr2 = red[8 * q];
+        z.upd = true;
+        skip[q] = true;
+      }
+    }
+    bool second = false;
+    for (int q = 0; q < nr; ++q) second = second || !skip[q];
+    if (second) {
+      A.apply(s, t, false);
+      blas_multi(ctx, B_DOT4_TS, 0, 2, {&t, &s, &rh}, nullptr, skip.get(), red.data());
+      for (int q = 0; q < nr; ++q) {
+        St& z = S[q];
+        if (skip[q]) continue;
+        const double* w = &red[8 * q];
+        const double om_r = w[0] / w[2], om_i = w[1] / w[2];
+        const double rn_r = w[3] - (om_r * w[5] - om_i * w[6]);
+        const double rn_i = w[4] - (om_r * w[6] + om_i * w[5]);
+        const double rr = z.rho_r * z.rho_r + z.rho_i * z.rho_i;
+        const double oo = om_r * om_r + om_i * om_i;
+        if (w[2] == 0.0 || !isfinite(oo) || oo == 0.0 || rr == 0.0) {
+          give_up(q);
+          skip[q] = true;
+          continue;
+        }
+        const double q_r = (rn_r * z.rho_r + rn_i * z.rho_i) / rr, q_i = (rn_i * z.rho_r - rn_r * z.rho_i) / rr;
+        const double w_r = (z.al_r * om_r + z.al_i * om_i) / oo, w_i = (z.al_i * om_r - z.al_r * om_i) / oo;
+        args[q] = cplx(z.al_r, z.al_i, om_r, om_i, q_r * w_r - q_i * w_i, q_r * w_i + q_i * w_r);
+        z.rho_r = rn_r;
+        z.rho_i = rn_i;
+      }
+      blas_multi(ctx, B_BICG_FUSED, 0, 2, {&y, &p, &s, &t, &v, &r}, args.data(), skip.get(), red.data());
+      for (int q = 0; q < nr; ++q) {
+        St& z = S[q];
+        if (skip[q]) continue;
+        z.rr2 = red[8 * q];
+        if (!isfinite(z.rr2)) {
+          give_up(q);
+          continue;
+        }
+        if (z.rr2 < z.seg_best) {
+          z.seg_best = z.rr2;
+          z.seg_best_it = info[q].iters;
+        }
+        if (z.rr2 > 1e8 * z.seg_best ||
+            info[q].iters - z.seg_best_it > std::max(500, 2 * (z.seg_best_it - z.seg_start))) {
+          give_up(q);
+          continue;
+        }
+        z.rmax2 = std::max(z.rmax2, z.rr2);
+        const double tgt2 = 0.25 * tol * tol * z.eta2 / z.seg_r2 * z.seg_rr2;
+        z.upd = z.rr2 <= tgt2 || z.rr2 <= delta * delta * z.rmax2;
+      }
+    }
+    // reliable updates, one right-hand side at a time
+    for (int q = 0; q < nr; ++q) {
+      St& z = S[q];
+      if (!z.upd || z.failed) continue;
+      Field yq = y.view(q), xq = x64.view(q), rq = r.view(q), rhq = rh.view(q), pq = p.view(q);
+      op_reconstruct(op, P.scheme, pr, yq, d);
+      blas(ctx, B_MIXED_ACC, 0, 2, {&d, &xq});
+      z.r2 = true_residual(op, l4, xq, eta64.view(q), r64);
+      info[q].outer_iters++;
+      if (sqrt(z.r2 / z.eta2) <= tol) {
+        z.done = true;
+        continue;
+      }
+      if (z.r2 < z.best2) {
+        z.best2 = z.r2;
+        z.since_best = 0;
+        Field bq = xbest.view(q);
+        blas(ctx, B_COPY, 0, 2, {&xq, &bq});
+      } else if (++z.since_best >= 3 || z.r2 > 1e4 * z.best2 || info[q].outer_iters >= max_upd) {
+        give_up(q);
+        continue;
+      }
+      restart_residual(q);
+      double rr[8];
+      blas(ctx, B_DOT, 0, 2, {&rhq, &rq}, BlasArgs{}, rr);
+      z.rho_r = rr[0];
+      z.rho_i = rr[1];
+      if (z.rho_r * z.rho_r + z.rho_i * z.rho_i < 1e-24 * z.rr2 * z.rr2) {
+        blas(ctx, B_COPY, 0, 2, {&rq, &rhq});
+        blas(ctx, B_COPY, 0, 2, {&rq, &pq});
+        z.rho_r = z.rr2;
+        z.rho_i = 0;
+        info[q].restarts++;
+      }
+    }
+  }
+  // right-hand sides that stalled continue alone from their best iterate
+  for (int q = 0; q < nr; ++q) {
+    St& z = S[q];
+    Field xq = x64.view(q);
+    if (z.done) {
+      info[q].true_rel_resid = z.eta2 > 0 ? sqrt(z.r2 / z.eta2) : 0.0;
+      continue;
+    }
+    tp_solve_params P2 = P;
+    P2.use_x0 = 1;
+    tp_solve_info extra{};
+    merge(op_solve(op, P2, xq, eta64.view(q), extra));
+    info[q].iters += extra.iters;
+    info[q].applies += extra.applies;
+    info[q].outer_iters += extra.outer_iters;
+    info[q].restarts += extra.restarts;
+    info[q].true_rel_resid = extra.true_rel_resid;
+  }
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  prof_flush(ctx);
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  for (int q = 0; q < nr; ++q) info[q].ms = ms;
+  return worst;
 }

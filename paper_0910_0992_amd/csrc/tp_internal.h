@@ -47,11 +47,14 @@ extern const char* const kKernelNames[KID_COUNT];
 // A spinor field in an internal layout (p3 or p4), both parities:
 // data [2 parity][12 component][V2] of the storage type of `prec`,
 // nrm [2 parity][2 half][V2] FP32 scales for TP_F16N (else null).
+// A batch of nr such fields is one allocation of nr consecutive fields (kernels offset by
+// the right-hand-side index, see rhs_view); view(r) is field r alone.
 struct Field {
   int prec = TP_F64;
   void* data = nullptr;
   float* nrm = nullptr;
   int64_t V2 = 0;
+  int nr = 1;
   bool owned = false;
 
   size_t elem_bytes() const { return prec == TP_F64 ? 16 : (prec == TP_F32 ? 8 : 4); }
@@ -64,6 +67,14 @@ struct Field {
     f.nrm[0] = nrm ? nrm + (int64_t)(2 * p) * V2 : nullptr;
     f.nrm[1] = nrm ? nrm + (int64_t)(2 * p + 1) * V2 : nullptr;
     f.stride = V2;
+    return f;
+  }
+  Field view(int r) const {
+    Field f = *this;
+    f.data = static_cast<char*>(data) + (size_t)r * 24 * V2 * elem_bytes();
+    f.nrm = nrm ? nrm + (int64_t)r * 4 * V2 : nullptr;
+    f.nr = 1;
+    f.owned = false;
     return f;
   }
 };
@@ -148,12 +159,13 @@ struct tp_op_s {
   double* mupow_d = nullptr;    // mu^-k, k = 0..Lt
   float* mupow_f = nullptr;
   Workspace* ws = nullptr;
+  int batch_nr = 1;  // right-hand sides of the batched apply in progress (workspace size)
 };
 
 // ---------------------------------------------------------------- memory helpers
 void* dev_alloc(size_t bytes);
 void dev_free(void* p);
-Field field_alloc(const Lattice& lat, int prec);
+Field field_alloc(const Lattice& lat, int prec, int nr = 1);
 void field_free(Field& f);
 
 // ---------------------------------------------------------------- profiling helpers
@@ -244,6 +256,7 @@ double clov_bytes(int prec);
 
 // ---------------------------------------------------------------- BLAS
 constexpr int kRedBlocks = 4096;
+constexpr int kMaxRhs = 16;  // right-hand sides of one batched solve
 // Generic unit-wise BLAS on fields over parities [par0, par0+npar).
 enum BlasOp {
   B_ZERO,         // y = 0
@@ -270,6 +283,11 @@ struct BlasArgs {
 // synchronously in red_out when the op reduces.
 void blas(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<const Field*> fs,
           BlasArgs k = BlasArgs{}, double* red_out = nullptr);
+// The same on batches of nr fields: per[r] (or k for all when null) are the coefficients of
+// right-hand side r, skip[r] leaves it untouched (and its reductions zero); red_out holds
+// [nr][8] values.
+void blas_multi(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<const Field*> fs,
+                const BlasArgs* per, const bool* skip, double* red_out, BlasArgs k = BlasArgs{});
 // Sum of the first nblocks per-block partials written by a site kernel with want_norm.
 double finish_norm(tp_ctx ctx, int nblocks);
 
@@ -283,5 +301,8 @@ void op_prepare(tp_op op, int scheme, int prec, const Field& eta, Field& et);
 void op_reconstruct(tp_op op, int scheme, int prec, const Field& y, Field& x);
 bool scheme_layout4(int scheme);
 // Workspace vectors (allocated lazily, owned by the op).
+// Workspace field `slot` in `prec`, a batch of op->batch_nr fields (1 outside batched
+// operator applications).
 Field& ws_get(tp_op op, int prec, int slot);
+Field& ws_get_n(tp_op op, int prec, int slot, int nr);
 void ws_free(tp_op op);

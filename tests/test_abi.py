@@ -28,7 +28,7 @@ def test_header_declares_the_expected_entry_points():
     names = _declared()
     for must in ["tp_ctx_create", "tp_gauge_create", "tp_clover_create", "tp_op_create", "tp_apply_M",
                  "tp_apply_Tinv", "tp_apply_prec", "tp_prepare_source", "tp_reconstruct", "tp_solve",
-                 "tp_force"]:
+                 "tp_solve_multi", "tp_force"]:
         assert must in names
 
 
@@ -65,6 +65,7 @@ def test_bad_boundary_phase_rejected(lib):
 def test_null_handles_rejected(lib):
     assert lib.tp_apply_M(None, 0, None, None, 0) == -1
     assert lib.tp_solve(None, None, None, None, None) == -1
+    assert lib.tp_solve_multi(None, None, 2, None, None, None) == -1
     assert lib.tp_force(None, None, None, None, 1) == -1
     # destroy of a null handle is a no-op
     assert lib.tp_op_destroy(None) == 0

@@ -8,7 +8,8 @@ benchmark uses, against the oracle evaluated at sampled sites and time lines
 * the benchmark solve (temporal+3D-ILU, mixed FP32): the oracle's residual at sampled
   sites is bounded by the library's FP64 true residual, which must be <= 1e-10;
 * 24^3x128: the 12 spin-colour point sources at the origin, FP32 and FP16+norm inner
-  solves, each to 1e-10, against the FP64 even-odd solution;
+  solves, each to 1e-10, one at a time and as one batch, against the FP64 even-odd
+  solution;
 * 12^3x64: the gradient of |M^-1 eta|^2 against central finite differences
   (h = 1e-6, 32 random su(3) directions) with FP64 solves to 1e-13.
 """
@@ -125,11 +126,13 @@ def test_point_sources_24x128():
     g = Operator(torch.from_numpy(U).cuda(), cfg["m0"], xi, cfg["csw_s"] / xi, cfg["csw_t"], -1)
     try:
         sites = [(0, 0, 0, 0), (1, 0, 0, 0), (0, 0, 0, 1), (23, 23, 23, 127)]
+        ref = []
         for k in range(12):
             eta = synth.make_point_source(dims, k // 3, k % 3)
             te = torch.from_numpy(eta).cuda()
             x64, i64 = g.solve(te, scheme="SCHUR4D", prec="F64", tol=1e-10)
             assert i64["true_rel_resid"] <= 1e-10, i64
+            ref.append(x64)
             for prec in ("F32", "F16N"):
                 x, info = g.solve(te, scheme="TEMPORAL_SCHUR", prec=prec, tol=1e-10)
                 assert info["true_rel_resid"] <= 1e-10, (k, prec, info)
@@ -141,6 +144,17 @@ def test_point_sources_24x128():
                 assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(eta)
             print(f"[fullsize] point source {k}: FP64 {i64['iters']} its, mixed {info['iters']} its",
                   flush=True)
+        # the 12 sources as one batch (lockstep, one launch per kernel for all of them)
+        etas = [torch.from_numpy(synth.make_point_source(dims, k // 3, k % 3)).cuda() for k in range(12)]
+        for prec in ("F16N", "F32"):
+            xs, infos = g.solve_multi(etas, scheme="TEMPORAL_SCHUR", prec=prec, tol=1e-10)
+            for k in range(12):
+                assert infos[k]["true_rel_resid"] <= 1e-10, (k, prec, infos[k])
+                rel = (torch.linalg.vector_norm(xs[k] - ref[k]) / torch.linalg.vector_norm(ref[k])).item()
+                assert rel < 1e-7, (k, prec, rel)
+            print(f"[fullsize] 12 point sources batched {prec}: {infos[0]['ms']:.0f} ms, "
+                  f"iterations {[i['iters'] for i in infos]}", flush=True)
+            del xs
     finally:
         g.close()
 

@@ -113,6 +113,23 @@ def test_temporal_inverses(case, prec):
     _close(_np(g.apply_CR(te, prec)), o.tmp.CR(e), tol, '_np(g.apply_CR(te, prec)), o.tmp.CR(e)')
 
 
+@pytest.mark.parametrize("prec", ["F32", "F16N"])
+def test_point_source_reduced_precision(case, prec):
+    """A point source: along a long line T^-1 decays as mu^-t far below the FP32 normal
+    range (mu^-256 ~ 5e-42 on the 256-slice lattice); the FP16 form must stay finite and
+    accurate there."""
+    o, g = case["oop"], case["gop"]
+    e = synth.make_point_source(case["dims"], 1, 2, (1, 0, 1, 2))
+    te = torch.from_numpy(e).cuda()
+    for got, want, what in [(g.apply_Tinv(te, prec), o.tmp.Tinv(e), "T^-1"),
+                            (g.apply_Tinv(te, prec, dagger=True), o.tmp.Tdaginv(e), "T^dag^-1"),
+                            (g.prepare_source(te, "TEMPORAL_SCHUR", prec), o.prepare_source("TEMPORAL_SCHUR", e),
+                             "prepare")]:
+        got = _np(got)
+        assert np.all(np.isfinite(got)), what
+        _close(got, want, TOL[prec][1], what)
+
+
 @pytest.mark.parametrize("prec", ["F64", "F32", "F16N"])
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_apply_prec(case, scheme, prec):
@@ -150,6 +167,31 @@ def test_solve_mixed(case, prec, scheme):
     true = np.linalg.norm(case["eta"] - o.M(xn)) / np.linalg.norm(case["eta"])
     assert true <= 1.05e-10, (info, true)
     assert info["outer_iters"] >= 2  # the inner precision alone cannot reach 1e-10
+
+
+@pytest.mark.parametrize("prec", ["F32", "F16N"])
+@pytest.mark.parametrize("scheme", ["TEMPORAL_SCHUR", "TEMPORAL", "UNPREC", "SCHUR4D"])
+def test_solve_multi(case, prec, scheme):
+    """Batched right-hand sides (lockstep BiCGStab, or one after another where the scheme
+    has no batched path): each solution meets the oracle's true residual, a zero source
+    gives zero, and the batch agrees with the single-source solve."""
+    if scheme == "SCHUR4D" and prec == "F16N":
+        pytest.skip("SCHUR4D takes F64 and F32")
+    o, g = case["oop"], case["gop"]
+    etas = [case["eta"], synth.make_source(case["dims"], 2004), np.zeros_like(case["eta"]),
+            synth.make_point_source(case["dims"], 1, 2, (1, 0, 1, 2))]
+    xs, infos = g.solve_multi([torch.from_numpy(e).cuda() for e in etas], scheme=scheme, prec=prec,
+                              tol=1e-10)
+    xs = _np(xs)
+    for k, e in enumerate(etas):
+        if not np.any(e):
+            assert not np.any(xs[k]) and infos[k]["true_rel_resid"] == 0.0
+            continue
+        true = np.linalg.norm(e - o.M(xs[k])) / np.linalg.norm(e)
+        assert true <= 1.05e-10, (k, infos[k], true)
+        assert infos[k]["true_rel_resid"] <= 1e-10, (k, infos[k])
+    x1, _ = g.solve(torch.from_numpy(etas[1]).cuda(), scheme=scheme, prec=prec, tol=1e-10)
+    _close(xs[1], _np(x1), 1e-7, "batched vs single solve")
 
 
 def test_solve_schur4d_f32_mixed(case):

@@ -48,6 +48,7 @@ class Operator:
         self.m0 = m0
         self.gamma_f = gamma_f
         self.b = b
+        self.c_s, self.c_t = c_s, c_t
         self.mu = W.mass_term(m0, gamma_f)
         self.dims = (U.shape[4], U.shape[3], U.shape[2], U.shape[1])
         self.clover = (c_s != 0.0) or (c_t != 0.0)

@@ -206,15 +206,22 @@ tp_status tp_solve_multi(tp_op op, const tp_solve_params* params, int32_t nrhs, 
                          const void* const* eta, tp_solve_info* info);
 
 /* ---- gradient ----------------------------------------------------------------------
- * For L(x, lambda) with lambda = M^-dagger dL/dx*: per link U_mu(s),
+ * Link gradient of a real L(x) with x = M^-1 eta and lambda = M^-dagger dL/dx* (for
+ * L = |x|^2: M^dagger lambda = 2x), dL = -Re <lambda, dM x>.  The hopping terms give, per
+ * link U_mu(s),
  *   Y = sum_a [P-^mu x(s+mu)]_a lambda(s)_a^dag,  Z = sum_a [P+^mu x(s)]_a lambda(s+mu)_a^dag,
- *   raw:        grad_U = k_mu b_mu(s) (Y + Z^dag)^dag   (d L = Re <grad_U, dU>),
- *   projected:  G = k_mu b_mu(s) TH[i U (Y + Z^dag)]    (dL/dh = tr(omega G) for
- *               U -> exp(i h omega) U),  TH = traceless hermitian part,
- * with k_t = 1, k_i = 1/gamma_f, b_mu(s) = bc_t on time links of the last slice.
- * The clover term is held fixed.  grad_links: device complex128 [4][Lt][Lz][Ly][Lx][3][3]. */
-tp_status tp_force(tp_op op, const void* x, const void* lambda, void* grad_links,
-                   int32_t projected);
+ *   grad_U = k_mu b_mu(s) (Y + Z^dag)^dag,
+ * with k_t = 1, k_i = 1/gamma_f, b_mu(s) = bc_t on time links of the last slice.  With a
+ * clover term the SW part is added (unless TP_FORCE_HOPPING_ONLY): A depends on the links
+ * through the four-leaf field strength (Sec. II), and each plaquette containing the link
+ * contributes the product of its other three links with, at every corner x,
+ * (c/2)(Zc - Zc^dag), Zc = W/8 - tr(W)/24, W = sum sigma_{mu nu}[s][s'] x_s'(x) lambda_s(x)^dag.
+ * Raw form: d L = Re <grad_U, dU>.  TP_FORCE_PROJECTED: G = TH[i U grad_U^dag] with
+ * dL/dh = tr(omega G) for U -> exp(i h omega) U, TH = traceless hermitian part.
+ * x, lambda: canonical device spinors; grad_links: device complex128
+ * [4][Lt][Lz][Ly][Lx][3][3], overwritten. */
+enum { TP_FORCE_PROJECTED = 1, TP_FORCE_HOPPING_ONLY = 2 };
+tp_status tp_force(tp_op op, const void* x, const void* lambda, void* grad_links, int32_t flags);
 
 /* ---- diagnostics -------------------------------------------------------------------- */
 const char* tp_status_string(tp_status s);

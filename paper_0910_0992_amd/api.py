@@ -198,13 +198,15 @@ class Operator:
             L.check(st)
         return torch.stack(xs), out
 
-    def force(self, x, lam, projected=True):
-        """Link gradient from x and lambda (see tp_force): [4, Lt, Lz, Ly, Lx, 3, 3]."""
+    def force(self, x, lam, projected=True, hopping_only=False):
+        """Link gradient from x and lambda (see tp_force): [4, Lt, Lz, Ly, Lx, 3, 3]; with a
+        clover term it includes the SW term's dependence on the links unless hopping_only."""
         xs, ls = self._in(x), self._in(lam)
         lx, ly, lz, lt = self.dims
         g = torch.empty((4, lt, lz, ly, lx, 3, 3), dtype=torch.complex128, device=self.device)
         self._call(self._lib.tp_force, self._op, C.c_void_p(xs.data_ptr()),
-                   C.c_void_p(ls.data_ptr()), C.c_void_p(g.data_ptr()), int(bool(projected)))
+                   C.c_void_p(ls.data_ptr()), C.c_void_p(g.data_ptr()),
+                   int(bool(projected)) | (2 if hopping_only else 0))
         return g
 
     def plaquette(self):
@@ -248,8 +250,8 @@ class SolveFn(torch.autograd.Function):
     """x = M(U)^-1 eta with a hand-written backward.
 
     Backward: lambda solves M^dagger lambda = g (as M (g5 lambda) = g5 g, with the
-    same preconditioned solver), grad_eta = lambda, and grad_U is the hopping
-    term's link gradient (tp_force, raw form) with the SW term held fixed.
+    same preconditioned solver), grad_eta = lambda, and grad_U is the link gradient
+    (tp_force, raw form), including the SW term's dependence on the links.
     Conventions follow torch: dL = Re <grad, dz>.
     """
 

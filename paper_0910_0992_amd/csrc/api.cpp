@@ -97,6 +97,23 @@ void clover_sigma_table(double cs, double ct, double sig[6][2][2][2][2]) {
   }
 }
 
+// sigma_{mu nu} = [gamma_mu, gamma_nu]/2 for the planes 03 13 23 01 02 12
+void sigma_planes(double out[6][4][4][2]) {
+  zc g[4][4][4];
+  gammas(g);
+  const int planes[6][2] = {{0, 3}, {1, 3}, {2, 3}, {0, 1}, {0, 2}, {1, 2}};
+  for (int p = 0; p < 6; ++p)
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        zc v = 0;
+        for (int c = 0; c < 4; ++c)
+          v += g[planes[p][0]][a][c] * g[planes[p][1]][c][b] - g[planes[p][1]][a][c] * g[planes[p][0]][c][b];
+        v *= 0.5;
+        out[p][a][b][0] = v.real();
+        out[p][a][b][1] = v.imag();
+      }
+}
+
 Lattice make_lattice(const int32_t d[4]) {
   Lattice L;
   for (int k = 0; k < 4; ++k) L.L[k] = d[k];
@@ -704,7 +721,7 @@ tp_status tp_solve_multi(tp_op op, const tp_solve_params* params, int32_t nrhs, 
   return st;
 }
 
-tp_status tp_force(tp_op op, const void* x, const void* lambda, void* grad, int32_t projected) {
+tp_status tp_force(tp_op op, const void* x, const void* lambda, void* grad, int32_t flags) {
   return guard([&] {
     need(op, "op");
     need(x, "x");
@@ -716,7 +733,14 @@ tp_status tp_force(tp_op op, const void* x, const void* lambda, void* grad, int3
     Field& b = tmp_field(op, TP_F64, 1);
     launch_pack(ctx, static_cast<const double2*>(x), a, false, false, nullptr);
     launch_pack(ctx, static_cast<const double2*>(lambda), b, false, false, nullptr);
-    launch_force(op, a, b, static_cast<double2*>(grad), projected != 0);
+    if (flags & ~(TP_FORCE_PROJECTED | TP_FORCE_HOPPING_ONLY)) TP_THROW(TP_EINVAL, "bad force flags");
+    const bool projected = (flags & TP_FORCE_PROJECTED) != 0;
+    launch_force(op, a, b, static_cast<double2*>(grad), projected);
+    if (op->c && !(flags & TP_FORCE_HOPPING_ONLY)) {
+      double sig[6][4][4][2];
+      sigma_planes(sig);
+      launch_clover_force(op, a, b, static_cast<double2*>(grad), projected, sig);
+    }
   });
 }
 

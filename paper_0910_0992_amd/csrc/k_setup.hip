@@ -580,6 +580,173 @@ void unpack_t(tp_ctx ctx, const Field& src, double2* canon, bool l4, bool g5, co
   LAUNCH_CHECK();
 }
 
+
+// ---- SW-term link force -----------------------------------------------------------------
+// With x and lambda (dL = -Re <lambda, dM x>), the SW term contributes
+//   s(U) = Re sum_x sum_p tr(Q_p(x) Yh_p(x)),  Yh_p = (c_p/2)(Z - Z^dag),
+//   Z = W/8 - tr(W)/24,  W_p(x) = sum_{s s'} sigma_p[s][s'] x_s'(x) lambda_s(x)^dag,
+// Q_p the four-leaf sum of plane p.  Each leaf is a plaquette read from one of its corners,
+// so a link's derivative collects, from each plaquette that contains it, the product of the
+// other three factors with Yh of every corner inserted at that corner.
+struct SigmaTab {
+  double2 s[6][4][4];  // sigma_{mu nu} = [gamma_mu, gamma_nu]/2, planes (03 13 23 01 02 12)
+};
+
+TP_DEV int plane_index(int a, int b) {  // a < b
+  return b == 3 ? a : (a == 0 ? (b == 1 ? 3 : 4) : 5);
+}
+
+__global__ void __launch_bounds__(128) k_clover_Y(SpinorF<double2> x0, SpinorF<double2> x1,
+                                                   SpinorF<double2> l0, SpinorF<double2> l1,
+                                                   double2* Y, Geom g, int64_t V, SigmaTab sig,
+                                                   double c_s, double c_t) {
+  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= V) return;
+  int x, y, z, t;
+  canon_coords(n, g, x, y, z, t);
+  const int p = (x + y + z) & 1;
+  const int64_t i = p3_idx(g, t, (x + g.Lx * (y + g.Ly * z)) >> 1);
+  cx<double> xs[12], ls[12];
+  load_spinor<double2, double>(p ? x1 : x0, i, xs);
+  load_spinor<double2, double>(p ? l1 : l0, i, ls);
+  for (int pl = 0; pl < 6; ++pl) {
+    cx<double> W[9];
+    for (int k = 0; k < 9; ++k) W[k] = czero<double>();
+    for (int s = 0; s < 4; ++s)
+      for (int sp = 0; sp < 4; ++sp) {
+        const cx<double> sg = cx<double>{sig.s[pl][s][sp].x, sig.s[pl][s][sp].y};
+        if (sg.re == 0.0 && sg.im == 0.0) continue;
+        for (int b = 0; b < 3; ++b)
+          for (int a = 0; a < 3; ++a) W[3 * b + a] += cmul(sg, cmul(xs[3 * sp + b], conj(ls[3 * s + a])));
+      }
+    const cx<double> tr = W[0] + W[4] + W[8];
+    const double c = 0.5 * (pl < 3 ? c_t : c_s);
+    double2* out = Y + ((int64_t)pl * V + n) * 9;
+    for (int r = 0; r < 3; ++r)
+      for (int q = 0; q < 3; ++q) {
+        cx<double> zrq = (1.0 / 8.0) * W[3 * r + q], zqr = (1.0 / 8.0) * W[3 * q + r];
+        if (r == q) {
+          zrq -= (1.0 / 24.0) * tr;
+          zqr -= (1.0 / 24.0) * tr;
+        }
+        const cx<double> v = c * (zrq - conj(zqr));
+        out[3 * r + q] = make_double2(v.re, v.im);
+      }
+  }
+}
+
+TP_DEV void load_y(const double2* Y, const Geom& g, int64_t V, int pl, int x, int y, int z, int t,
+                   cx<double>* m) {
+  x = (x + g.Lx) % g.Lx;
+  y = (y + g.Ly) % g.Ly;
+  z = (z + g.Lz) % g.Lz;
+  t = (t + g.Lt) % g.Lt;
+  const int64_t n = (int64_t)x + (int64_t)g.Lx * (y + (int64_t)g.Ly * (z + (int64_t)g.Lz * t));
+  const double2* src = Y + ((int64_t)pl * V + n) * 9;
+  for (int k = 0; k < 9; ++k) m[k] = cx<double>{src[k].x, src[k].y};
+}
+
+TP_DEV void madd3(const cx<double>* a, const cx<double>* b, cx<double>* acc) {
+  cx<double> c[9];
+  mm3(a, b, c);
+  for (int k = 0; k < 9; ++k) acc[k] += c[k];
+}
+
+// R = Ya M1 M2 M3 + M1 Yb M2 M3 + M1 M2 Yc M3 + M1 M2 M3 Yd
+TP_DEV void insert4(const cx<double>* M1, const cx<double>* M2, const cx<double>* M3, const cx<double>* Ya,
+                    const cx<double>* Yb, const cx<double>* Yc, const cx<double>* Yd, cx<double>* R) {
+  cx<double> P23[9], P123[9], T[9], P12[9];
+  mm3(M2, M3, P23);
+  mm3(M1, P23, P123);
+  mm3(Ya, P123, R);
+  mm3(Yb, P23, T);
+  madd3(M1, T, R);
+  mm3(M1, M2, P12);
+  mm3(Yc, M3, T);
+  madd3(P12, T, R);
+  madd3(P123, Yd, R);
+}
+
+__global__ void __launch_bounds__(64) k_clover_force(const double2* __restrict__ canon,
+                                                      const double2* __restrict__ Y, double2* grad,
+                                                      Geom g, int64_t V, int projected) {
+  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int mu = blockIdx.y;
+  if (n >= V) return;
+  int c[4];
+  canon_coords(n, g, c[0], c[1], c[2], c[3]);
+  auto at = [&](int d1, int s1, int d2, int s2, int& X, int& Yy, int& Z, int& T) {
+    int q[4] = {c[0], c[1], c[2], c[3]};
+    if (d1 >= 0) q[d1] += s1;
+    if (d2 >= 0) q[d2] += s2;
+    X = q[0]; Yy = q[1]; Z = q[2]; T = q[3];
+  };
+  cx<double> G[9];
+  for (int k = 0; k < 9; ++k) G[k] = czero<double>();
+  for (int nu = 0; nu < 4; ++nu) {
+    if (nu == mu) continue;
+    const int a = mu < nu ? mu : nu, b = mu < nu ? nu : mu;
+    const int pl = plane_index(a, b);
+    cx<double> L0[9], L1[9], L2[9], L3[9], T[9], Ya[9], Yb[9], Yc[9], Yd[9], R[9];
+    int X, Yy, Z, Tt;
+    // plaquette(base): L0 = U_a(base), L1 = U_b(base+a), L2 = U_a(base+b)^dag, L3 = U_b(base)^dag
+    // corners c0 = base, c1 = base+a, c2 = base+a+b, c3 = base+b
+    auto load_plaq = [&](int d, int sd) {  // base = x + sd * e_d (d < 0: base = x)
+      at(d, sd, -1, 0, X, Yy, Z, Tt);
+      const int bx = X, by = Yy, bz = Z, bt = Tt;
+      int e[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
+      load_link(canon, g, V, a, bx, by, bz, bt, L0);
+      load_link(canon, g, V, b, bx + e[a][0], by + e[a][1], bz + e[a][2], bt + e[a][3], L1);
+      load_link(canon, g, V, a, bx + e[b][0], by + e[b][1], bz + e[b][2], bt + e[b][3], T);
+      dag3(T, L2);
+      load_link(canon, g, V, b, bx, by, bz, bt, T);
+      dag3(T, L3);
+      load_y(Y, g, V, pl, bx, by, bz, bt, Ya);                                              // c0
+      load_y(Y, g, V, pl, bx + e[a][0], by + e[a][1], bz + e[a][2], bt + e[a][3], Yb);      // c1
+      load_y(Y, g, V, pl, bx + e[a][0] + e[b][0], by + e[a][1] + e[b][1], bz + e[a][2] + e[b][2],
+             bt + e[a][3] + e[b][3], Yc);                                                   // c2
+      load_y(Y, g, V, pl, bx + e[b][0], by + e[b][1], bz + e[b][2], bt + e[b][3], Yd);      // c3
+    };
+    if (mu == a) {
+      // the link is L0 of the plaquette based at x, and L2 (daggered) of the one at x - b
+      load_plaq(-1, 0);
+      insert4(L1, L2, L3, Yb, Yc, Yd, Ya, R);  // R_0: corners c1 c2 c3 before L1 L2 L3, c0 last
+      dag3(R, T);
+      for (int k = 0; k < 9; ++k) G[k] += T[k];
+      load_plaq(b, -1);
+      insert4(L3, L0, L1, Yd, Ya, Yb, Yc, R);  // R_2
+      for (int k = 0; k < 9; ++k) G[k] += R[k];
+    } else {
+      // the link is L1 of the plaquette based at x - a, and L3 (daggered) of the one at x
+      load_plaq(a, -1);
+      insert4(L2, L3, L0, Yc, Yd, Ya, Yb, R);  // R_1
+      dag3(R, T);
+      for (int k = 0; k < 9; ++k) G[k] += T[k];
+      load_plaq(-1, 0);
+      insert4(L0, L1, L2, Ya, Yb, Yc, Yd, R);  // R_3
+      for (int k = 0; k < 9; ++k) G[k] += R[k];
+    }
+  }
+  double2* out = grad + ((int64_t)mu * V + n) * 9;
+  if (!projected) {
+    for (int k = 0; k < 9; ++k) out[k] = make_double2(out[k].x + G[k].re, out[k].y + G[k].im);
+    return;
+  }
+  // su(3) projection TH[i U G^dag]
+  cx<double> U[9], Gd[9], M[9];
+  load_link(canon, g, V, mu, c[0], c[1], c[2], c[3], U);
+  dag3(G, Gd);
+  mm3(U, Gd, M);
+  for (int k = 0; k < 9; ++k) M[k] = cx<double>{-M[k].im, M[k].re};  // i U G^dag
+  const double trh = (M[0].re + M[4].re + M[8].re) / 3.0;
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 3; ++q) {
+      cx<double> h = 0.5 * (M[3 * r + q] + conj(M[3 * q + r]));
+      if (r == q) h.re -= trh;
+      out[3 * r + q] = make_double2(out[3 * r + q].x + h.re, out[3 * r + q].y + h.im);
+    }
+}
+
 }  // namespace
 
 void launch_pack(tp_ctx ctx, const double2* canon, Field& dst, bool l4, bool g5, const double2* w) {
@@ -670,4 +837,29 @@ void launch_plaquette(tp_ctx ctx, tp_gauge g, double* part) {
   hipLaunchKernelGGL(k_plaquette, dim3(nblk(L.V)), dim3(kBlock), 0, ctx->stream, g->canon, L.g,
                      L.V, part);
   LAUNCH_CHECK();
+}
+
+void launch_clover_force(tp_op op, const Field& x, const Field& lam, double2* grad, bool projected,
+                         const double sig[6][4][4][2]) {
+  tp_ctx ctx = op->g->ctx;
+  const Lattice& L = ctx->lat;
+  SigmaTab t;
+  for (int p = 0; p < 6; ++p)
+    for (int r = 0; r < 4; ++r)
+      for (int q = 0; q < 4; ++q) t.s[p][r][q] = make_double2(sig[p][r][q][0], sig[p][r][q][1]);
+  double2* Y = static_cast<double2*>(dev_alloc(size_t(6) * L.V * 9 * sizeof(double2)));
+  try {
+    hipLaunchKernelGGL(k_clover_Y, dim3(nblk(L.V, 128)), dim3(128), 0, ctx->stream, x.par<double2>(0),
+                       x.par<double2>(1), lam.par<double2>(0), lam.par<double2>(1), Y, L.g, L.V, t,
+                       op->c->cs, op->c->ct);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_clover_force, dim3(nblk(L.V, 64), 4), dim3(64), 0, ctx->stream, op->g->canon, Y,
+                       grad, L.g, L.V, projected ? 1 : 0);
+    LAUNCH_CHECK();
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  } catch (...) {
+    dev_free(Y);
+    throw;
+  }
+  dev_free(Y);
 }

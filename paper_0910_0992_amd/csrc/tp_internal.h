@@ -292,6 +292,9 @@ void blas_multi(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list
 double finish_norm(tp_ctx ctx, int nblocks);
 
 // ---------------------------------------------------------------- force
+// SW-term part of the link gradient (added to grad), sig = sigma_{mu nu} of planes 03 13 23 01 02 12
+void launch_clover_force(tp_op op, const Field& x, const Field& lam, double2* grad, bool projected,
+                         const double sig[6][4][4][2]);
 void launch_force(tp_op op, const Field& x, const Field& lam, double2* grad, bool projected);
 
 // ---------------------------------------------------------------- composite operators (ops.cpp)

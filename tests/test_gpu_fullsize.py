@@ -10,8 +10,9 @@ benchmark uses, against the oracle evaluated at sampled sites and time lines
 * 24^3x128: the 12 spin-colour point sources at the origin, FP32 and FP16+norm inner
   solves, each to 1e-10, one at a time and as one batch, against the FP64 even-odd
   solution;
-* 12^3x64: the gradient of |M^-1 eta|^2 against central finite differences
-  (h = 1e-6, 32 random su(3) directions) with FP64 solves to 1e-13.
+* 12^3x64: the gradient of |M^-1 eta|^2 (hopping and SW-term link dependence) against
+  central finite differences (h = 1e-6, 32 random su(3) directions) with FP64 solves to
+  1e-13, with and without the clover term.
 """
 import numpy as np
 import pytest
@@ -159,19 +160,21 @@ def test_point_sources_24x128():
         g.close()
 
 
-def test_gradient_fd_12x64():
-    """d|M^-1 eta|^2 / dh for U -> exp(i h omega) U against the autograd link gradient, and
-    the source gradient.  The link gradient holds the SW term fixed, so the check runs at
-    csw = 0, where that is the whole derivative."""
+@pytest.mark.parametrize("clover", [False, True])
+def test_gradient_fd_12x64(clover):
+    """d|M^-1 eta|^2 / dh for U -> exp(i h omega) U against the autograd link gradient
+    (hopping and SW-term parts; the clover term is rebuilt from the perturbed links), and the
+    source gradient."""
     from paper_0910_0992_amd import Operator
     from paper_0910_0992_amd.api import SolveFn
     cfg = synth.WORKLOADS["clover_12x64"]
     dims, xi, m0 = cfg["dims"], cfg["xi"], cfg["m0"]
+    c_s, c_t = (cfg["csw_s"] / xi, cfg["csw_t"]) if clover else (0.0, 0.0)
     U = synth.make_links(dims, cfg["eps_s"], cfg["eps_t"], cfg["seed"])
     eta = synth.make_source(dims, 2000)
 
     def loss(Uh):
-        g = Operator(torch.from_numpy(Uh).cuda(), m0, xi, 0.0, 0.0, -1)
+        g = Operator(torch.from_numpy(Uh).cuda(), m0, xi, c_s, c_t, -1)
         try:
             x, info = g.solve(torch.from_numpy(eta).cuda(), scheme="TEMPORAL_SCHUR", prec="F64", tol=1e-13)
             return torch.vdot(x.flatten(), x.flatten()).real.item()
@@ -180,7 +183,7 @@ def test_gradient_fd_12x64():
 
     links = torch.from_numpy(U).cuda().requires_grad_(True)
     te = torch.from_numpy(eta).cuda().requires_grad_(True)
-    x = SolveFn.apply(links, te, m0, xi, 0.0, 0.0, -1, "TEMPORAL_SCHUR", "F64", 1e-13)
+    x = SolveFn.apply(links, te, m0, xi, c_s, c_t, -1, "TEMPORAL_SCHUR", "F64", 1e-13)
     L = torch.vdot(x.flatten(), x.flatten()).real
     L.backward()
     gU = _np(links.grad)
@@ -198,13 +201,13 @@ def test_gradient_fd_12x64():
             print(f"[fullsize] FD direction {k}: worst relative deviation {worst:.2e}", flush=True)
     assert worst < 5e-6, worst
     d = synth.make_source(dims, 2001)
-    fd = (loss_eta(U, eta + h * d, m0, xi) - loss_eta(U, eta - h * d, m0, xi)) / (2 * h)
+    fd = (loss_eta(U, eta + h * d, m0, xi, c_s, c_t) - loss_eta(U, eta - h * d, m0, xi, c_s, c_t)) / (2 * h)
     assert abs(fd - np.vdot(gE, d).real) < 5e-6 * L0
 
 
-def loss_eta(U, eta, m0, xi):
+def loss_eta(U, eta, m0, xi, c_s, c_t):
     from paper_0910_0992_amd import Operator
-    g = Operator(torch.from_numpy(U).cuda(), m0, xi, 0.0, 0.0, -1)
+    g = Operator(torch.from_numpy(U).cuda(), m0, xi, c_s, c_t, -1)
     try:
         x, _ = g.solve(torch.from_numpy(eta).cuda(), scheme="TEMPORAL_SCHUR", prec="F64", tol=1e-13)
         return torch.vdot(x.flatten(), x.flatten()).real.item()

@@ -202,14 +202,18 @@ def test_solve_schur4d_f32_mixed(case):
 
 
 def test_force_matches_oracle(case):
+    """Link gradient: the hopping part alone (TP_FORCE_HOPPING_ONLY) and the whole gradient
+    with the SW term's link dependence, raw and su(3)-projected."""
     o, g = case["oop"], case["gop"]
     x = synth.make_source(case["dims"], 2001)
     lam = synth.make_source(case["dims"], 2002)
-    raw_o, G_o = oforce.link_gradient(o, x, lam)
-    raw = _np(g.force(torch.from_numpy(x).cuda(), torch.from_numpy(lam).cuda(), projected=False))
-    G = _np(g.force(torch.from_numpy(x).cuda(), torch.from_numpy(lam).cuda(), projected=True))
-    _close(raw, raw_o, 1e-12, 'raw, raw_o')
-    _close(G, G_o, 1e-12, 'G, G_o')
+    tx, tl = torch.from_numpy(x).cuda(), torch.from_numpy(lam).cuda()
+    raw_h, G_h = oforce.link_gradient(o, x, lam)
+    _close(_np(g.force(tx, tl, projected=False, hopping_only=True)), raw_h, 1e-12, "hopping raw")
+    _close(_np(g.force(tx, tl, projected=True, hopping_only=True)), G_h, 1e-12, "hopping projected")
+    raw_o, G_o = oforce.full_link_gradient(o, x, lam)
+    _close(_np(g.force(tx, tl, projected=False)), raw_o, 1e-12, "full raw")
+    _close(_np(g.force(tx, tl, projected=True)), G_o, 1e-12, "full projected")
 
 
 def test_plaquette(case):

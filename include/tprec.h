@@ -164,7 +164,7 @@ typedef struct {
   int32_t reserved;
   double tol;              /* target true relative residual |eta - M x| / |eta|     */
   double inner_tol;        /* BiCGStab in F32/F16N: reliable-update threshold delta
-                              (0 = default 1e-3 F32, 0.02 F16N); CGNR: relative
+                              (0 = default 1e-3 F32, 0.01 F16N); CGNR: relative
                               reduction per inner solve (0 = 1e-6 F32, 2e-3 F16N)   */
 } tp_solve_params;
 

@@ -699,7 +699,7 @@ tp_status op_solve(tp_op op, const tp_solve_params& P, Field& x64, const Field& 
   int failures = 0;  // cycles rolled back
   if (pr != TP_F64 && solver == TP_BICGSTAB && sqrt(r2 / eta2) > tol) {
     // reliable updates; on a stall the defect-correction loop below continues with CGNR
-    double delta = P.inner_tol > 0 ? P.inner_tol : (pr == TP_F32 ? 1e-3 : 0.02);
+    double delta = P.inner_tol > 0 ? P.inner_tol : (pr == TP_F32 ? 1e-3 : 0.01);
     if (!bicgstab_reliable(op, P, A, l4, sub, delta, x64, eta64, r64, eta2, r2, tol, max_iter, info))
       solver = TP_CGNR;
   }
@@ -789,7 +789,7 @@ tp_status op_solve_multi(tp_op op, const tp_solve_params& P, int nr, Field& x64,
     return worst;
   }
   const double tol = P.tol > 0 ? P.tol : 1e-10;
-  const double delta = P.inner_tol > 0 ? P.inner_tol : (pr == TP_F32 ? 1e-3 : 0.02);
+  const double delta = P.inner_tol > 0 ? P.inner_tol : (pr == TP_F32 ? 1e-3 : 0.01);
   const int max_iter = P.max_iter > 0 ? P.max_iter : 100000;
   const int max_upd = P.max_restarts > 0 ? P.max_restarts : 200;
   KrylovOp A{op, P.scheme, pr, 0, 2, nr};

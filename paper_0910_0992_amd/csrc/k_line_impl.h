@@ -249,6 +249,7 @@ struct LineArgs {
   int par, LPB, NCH;
   int lds_table;  // complex elements of LDS used by the chunk combine (the rest follows it)
   int nr;         // right-hand sides: block b works on field b % nr of each batch
+  int lds_extra;  // LDS bytes after the table and the parked complex values
 };
 
 // Selects this block's right-hand side in every spinor argument; returns the block index
@@ -394,77 +395,206 @@ __global__ void __launch_bounds__(1024) k_line(LineArgs<S> a) {
 // registers per thread.
 template <int CH> constexpr int mid_threads() { return CH == 1 ? 1024 : 512; }
 
-template <typename S, int CH>
+// A half spinor in the storage form of its field (FP16 pairs and the FP32 scale for the FP16
+// form, else six complex values of the arithmetic precision), as parked in LDS by the middle
+// kernel: one per thread and time slice.
+template <typename S>
+struct RawHalf {
+  using R = typename Prec<S>::R;
+  static constexpr bool half = Prec<S>::half;
+  static constexpr int bytes = half ? 6 * 4 + 4 : 6 * int(sizeof(cx<R>));  // LDS per thread and slice
+  typename std::conditional<half, Half2x2, cx<R>>::type e[half ? 3 : 6];
+  float s;
+
+  TP_DEV void load(const SpinorF<S>& f, int h, int64_t i) {
+    if constexpr (half) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) e[q] = *reinterpret_cast<const Half2x2*>(f.p[h] + (int64_t)(2 * q) * f.stride + 2 * i);
+      s = f.nrm[h][i];
+    } else {
+      load_half<S, R>(f, h, i, e);
+    }
+  }
+  TP_DEV void zero() {
+    if constexpr (half) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) e[q] = Half2x2{__half2{}, __half2{}};
+      s = 0.f;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) e[c] = czero<R>();
+    }
+  }
+  TP_DEV void unpack(cx<R>* v) const {
+    if constexpr (half) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const float2 fa = __half22float2(e[q].a), fb = __half22float2(e[q].b);
+        v[2 * q] = {s * fa.x, s * fa.y};
+        v[2 * q + 1] = {s * fb.x, s * fb.y};
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[c] = e[c];
+    }
+  }
+  // LDS slot `k` of the region at `base` ([CH][3][n] pairs then [CH][n] scales for FP16,
+  // [CH][6][n] complex values otherwise; n threads, consecutive threads adjacent)
+  TP_DEV void put(char* base, int CH, int n, int k) const {
+    if constexpr (half) {
+      Half2x2* pr = reinterpret_cast<Half2x2*>(base);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) pr[(k * 3 + q) * n + threadIdx.x] = e[q];
+      reinterpret_cast<float*>(pr + 3 * CH * n)[k * n + threadIdx.x] = s;
+    } else {
+      cx<R>* pr = reinterpret_cast<cx<R>*>(base);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) pr[(k * 6 + c) * n + threadIdx.x] = e[c];
+    }
+  }
+  TP_DEV void get(const char* base, int CH, int n, int k) {
+    if constexpr (half) {
+      const Half2x2* pr = reinterpret_cast<const Half2x2*>(base);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) e[q] = pr[(k * 3 + q) * n + threadIdx.x];
+      s = reinterpret_cast<const float*>(pr + 3 * CH * n)[k * n + threadIdx.x];
+    } else {
+      const cx<R>* pr = reinterpret_cast<const cx<R>*>(base);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) e[c] = pr[(k * 6 + c) * n + threadIdx.x];
+    }
+  }
+};
+
+// The ILU middle step on the even sites of each tile (App. B sequence, steps 2-5):
+//   b = T^-1 u_lo, f = T^dag^-1 (u_up + psi_up), y = A (f, b + psi_lo),
+//   chi = (psi_up + y_up, psi_lo + T^-1 y_lo), n = (T^dag^-1 (y_up - u_up), T^-1 y_lo - b).
+// b waits in LDS from the first scans to the end.  NP inputs are parked in LDS in storage
+// form instead of being held in registers or read twice from HBM: NP = 2 parks u_up and
+// psi_up, psi_lo taking u_up's slot once the clover product has consumed it; NP = 3 gives
+// psi_lo its own slot, parked before the product.  Each thread touches only its own slots,
+// so no barrier guards them.
+template <typename S, int CH, int NP>
 __global__ void __launch_bounds__(mid_threads<CH>()) k_ilu_mid(LineArgs<S> a) {
   using R = typename Prec<S>::R;
   using Lk = typename Prec<S>::L;
+  using Raw = RawHalf<S>;
   extern __shared__ char smem_raw[];
   cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
-  // b = T^-1 u_lo is needed again only at the end: it waits in LDS ([CH][6][threads],
-  // consecutive threads adjacent) instead of registers while y and the second scans run
-  cx<R>* park = lds + a.lds_table;
   const int nthr = blockDim.x;
+  cx<R>* park_b = lds + a.lds_table;  // [CH][6][threads]
+  char* raw0 = reinterpret_cast<char*>(park_b + 6 * CH * nthr);
+  char* park_u = raw0;                                           // u_up, then (NP = 2) psi_lo
+  char* park_p = raw0 + size_t(Raw::bytes) * CH * nthr;          // psi_up
+  char* park_l = raw0 + size_t(Raw::bytes) * CH * nthr * 2;      // psi_lo (NP = 3)
+  auto bslot = [&](int k, int c) -> cx<R>& { return park_b[(k * 6 + c) * nthr + threadIdx.x]; };
   const uint32_t blk = batch_select(a);
   ScanCtx<R> sc = make_ctx<S>(a, CH, blk);
   const int s = sc.active ? sc.s : 0;
-  cx<R> b[CH][6], f[CH][6], uup[CH][6];
+  cx<R> b[CH][6], f[CH][6], uup[NP ? 1 : CH][6];
 #pragma unroll
   for (int k = 0; k < CH; ++k) {
     const int64_t i = p3_idx(a.g, sc.t0 + k, s);
-    if (sc.active) {
-      cx<R> ps[6];
-      load_half<S, R>(a.aux, 0, i, uup[k]);
-      load_half<S, R>(a.aux, 1, i, b[k]);
-      load_half<S, R>(a.in, 0, i, ps);
+    cx<R> u[6], ps[6];
+    if constexpr (NP > 0) {
+      Raw ru, rp;
+      if (sc.active) {
+        ru.load(a.aux, 0, i);
+        rp.load(a.in, 0, i);
+        load_half<S, R>(a.aux, 1, i, b[k]);
+      } else {
+        ru.zero();
+        rp.zero();
 #pragma unroll
-      for (int c = 0; c < 6; ++c) f[k][c] = uup[k][c] + ps[c];
+        for (int c = 0; c < 6; ++c) b[k][c] = czero<R>();
+      }
+      ru.put(park_u, CH, nthr, k);
+      rp.put(park_p, CH, nthr, k);
+      ru.unpack(u);
+      rp.unpack(ps);
     } else {
+      if (sc.active) {
+        load_half<S, R>(a.aux, 0, i, u);
+        load_half<S, R>(a.aux, 1, i, b[k]);
+        load_half<S, R>(a.in, 0, i, ps);
+      } else {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) { b[k][c] = czero<R>(); f[k][c] = czero<R>(); uup[k][c] = czero<R>(); }
+        for (int c = 0; c < 6; ++c) { u[c] = czero<R>(); b[k][c] = czero<R>(); ps[c] = czero<R>(); }
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) uup[k][c] = u[c];
     }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) f[k][c] = u[c] + ps[c];
   }
   scan_core<R, CH, 6, true>(b, lds, sc);
   scan_core<R, CH, 6, false>(f, lds, sc);
 #pragma unroll
   for (int k = 0; k < CH; ++k)
 #pragma unroll
-    for (int c = 0; c < 6; ++c) park[(k * 6 + c) * nthr + threadIdx.x] = b[k][c];
-  // y = A w; write chi_up; second-phase inputs y_lo (backward) and y_up - u_up (forward)
+    for (int c = 0; c < 6; ++c) bslot(k, c) = b[k][c];
+  // y = A w; write chi_up; second-phase inputs y_lo (backward, kept in b) and y_up - u_up
+  // (forward, kept in f)
 #pragma unroll
   for (int k = 0; k < CH; ++k) {
     const int64_t i = p3_idx(a.g, sc.t0 + k, s);
     if (sc.active) {
       cx<R> w[12], y[12], pl[6], ps[6];
-      load_half<S, R>(a.in, 1, i, pl);
+      Raw rl;
+      if constexpr (NP > 0) {
+        rl.load(a.in, 1, i);
+        rl.unpack(pl);
+        if constexpr (NP == 3) rl.put(park_l, CH, nthr, k);
+      } else {
+        load_half<S, R>(a.in, 1, i, pl);
+      }
 #pragma unroll
-      for (int c = 0; c < 6; ++c) { w[c] = f[k][c]; w[6 + c] = park[(k * 6 + c) * nthr + threadIdx.x] + pl[c]; }
+      for (int c = 0; c < 6; ++c) { w[c] = f[k][c]; w[6 + c] = bslot(k, c) + pl[c]; }
       clover_apply<R, Lk>(a.clov, a.g.V2, i, w, y);
-      load_half<S, R>(a.in, 0, i, ps);
+      cx<R> u[6];
+      if constexpr (NP > 0) {
+        Raw rp, ru;
+        rp.get(park_p, CH, nthr, k);
+        rp.unpack(ps);
+        ru.get(park_u, CH, nthr, k);
+        ru.unpack(u);
+        if constexpr (NP == 2) rl.put(park_u, CH, nthr, k);
+      } else {
+        load_half<S, R>(a.in, 0, i, ps);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) u[c] = uup[k][c];
+      }
 #pragma unroll
       for (int c = 0; c < 6; ++c) ps[c] += y[c];
       store_half<S, R>(a.out, 0, i, ps);
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        f[k][c] = y[c] - uup[k][c];
-        uup[k][c] = y[6 + c];
+        f[k][c] = y[c] - u[c];
+        b[k][c] = y[6 + c];
       }
     } else {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) { f[k][c] = czero<R>(); uup[k][c] = czero<R>(); }
+      for (int c = 0; c < 6; ++c) { f[k][c] = czero<R>(); b[k][c] = czero<R>(); }
     }
   }
-  scan_core<R, CH, 6, true>(uup, lds, sc);   // T^-1 y_lo
-  scan_core<R, CH, 6, false>(f, lds, sc);    // T^dag^-1 (y_up - u_up)
+  scan_core<R, CH, 6, true>(b, lds, sc);   // T^-1 y_lo
+  scan_core<R, CH, 6, false>(f, lds, sc);  // T^dag^-1 (y_up - u_up)
   if (!sc.active) return;
 #pragma unroll
   for (int k = 0; k < CH; ++k) {
     const int64_t i = p3_idx(a.g, sc.t0 + k, s);
     cx<R> pl[6], n[6];
-    load_half<S, R>(a.in, 1, i, pl);
+    if constexpr (NP > 0) {
+      Raw rl;
+      rl.get(NP == 3 ? park_l : park_u, CH, nthr, k);
+      rl.unpack(pl);
+    } else {
+      load_half<S, R>(a.in, 1, i, pl);
+    }
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      pl[c] += uup[k][c];
-      n[c] = uup[k][c] - park[(k * 6 + c) * nthr + threadIdx.x];
+      pl[c] += b[k][c];
+      n[c] = b[k][c] - bslot(k, c);
     }
     store_half<S, R>(a.out, 1, i, pl);
     store_half<S, R>(a.base, 0, i, f[k]);
@@ -530,6 +660,13 @@ constexpr int max_threads() { return sizeof(typename Prec<S>::R) == 8 ? 512 : 10
 
 // LDS of a line kernel: the chunk-combine table (shuffle path: [tile][16 segments][4 lines][6];
 // LDS path: [chunk][line][6]) followed by `park` complex values per thread.
+int lds_table_of(Shape sh) { return sh.NCH % 16 == 0 ? sh.LPB * 16 * 6 : sh.LPB * sh.NCH * 6; }
+
+template <typename S>
+size_t lds_bytes(Shape sh, int park) {
+  return (size_t(lds_table_of(sh)) + size_t(park) * sh.LPB * sh.NCH) * sizeof(cx<typename Prec<S>::R>);
+}
+
 template <typename S, typename K>
 void go(tp_op op, K kern, LineArgs<S>& a, Shape sh, int park = 0) {
   tp_ctx ctx = op->g->ctx;
@@ -537,9 +674,8 @@ void go(tp_op op, K kern, LineArgs<S>& a, Shape sh, int park = 0) {
   a.LPB = sh.LPB;
   a.NCH = sh.NCH;
   a.f = pow(op->mu, -double(sh.CH));
-  const bool fast = sh.NCH % 16 == 0;
-  a.lds_table = fast ? sh.LPB * 16 * 6 : sh.LPB * sh.NCH * 6;
-  size_t lds = (size_t(a.lds_table) + size_t(park) * sh.LPB * sh.NCH) * sizeof(cx<typename Prec<S>::R>);
+  a.lds_table = lds_table_of(sh);
+  const size_t lds = lds_bytes<S>(sh, park) + size_t(a.lds_extra);
   dim3 grid((unsigned)((L.Vs2 + sh.LPB - 1) / sh.LPB * a.nr));
   hipLaunchKernelGGL(kern, grid, dim3(sh.LPB * sh.NCH), lds, ctx->stream, a);
   LAUNCH_CHECK();
@@ -606,7 +742,26 @@ void mid_t(tp_op op, const Field& psi, const Field& u, Field& chi, Field& n) {
     break;
   }
   if (sh.CH == 0) TP_THROW(TP_EDIMS, "time extent not supported by the line kernels");
-  TP_CH_DISPATCH(sh.CH, go<S>(op, k_ilu_mid<S, CH>, a, sh, 6 * CH))
+  // park as many inputs in LDS as the workgroup's LDS allows (each costs RawHalf bytes)
+  auto bytes = [&](int np) {
+    return lds_bytes<S>(sh, 6 * sh.CH) + size_t(np) * RawHalf<S>::bytes * sh.CH * sh.LPB * sh.NCH;
+  };
+  const int park = 6 * sh.CH;
+  // FP64 scans already fill the register file: they park only b
+  if constexpr (sizeof(typename Prec<S>::R) == 4) {
+    const size_t cap = op->g->ctx->lds_max;
+    if (bytes(3) <= cap) {
+      a.lds_extra = int(bytes(3) - lds_bytes<S>(sh, park));
+      TP_CH_DISPATCH(sh.CH, go<S>(op, k_ilu_mid<S, CH, 3>, a, sh, park))
+      return;
+    }
+    if (bytes(2) <= cap) {
+      a.lds_extra = int(bytes(2) - lds_bytes<S>(sh, park));
+      TP_CH_DISPATCH(sh.CH, go<S>(op, k_ilu_mid<S, CH, 2>, a, sh, park))
+      return;
+    }
+  }
+  TP_CH_DISPATCH(sh.CH, go<S>(op, k_ilu_mid<S, CH, 0>, a, sh, park))
 }
 
 }  // namespace

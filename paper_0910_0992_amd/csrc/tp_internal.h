@@ -98,6 +98,7 @@ struct tp_ctx_s {
   Lattice lat;
   int bc = -1;
   int device = 0;
+  size_t lds_max = 65536;  // LDS bytes a workgroup may allocate on this device
   hipStream_t stream = nullptr;
   bool prof = false;
   ProfSlot prof_slots[KID_COUNT];

@@ -316,8 +316,15 @@ template <int MODE> TP_DEV constexpr bool passes(int h) {
 
 // out = c_out MODE(in) + c_base base  (BASE), else c_out MODE(in).
 // Halves that MODE does not scan pass through (PASS), or are left untouched.
+// One-slice FP32-arithmetic scans of one half spinor fit in 64 VGPRs: two 1024-thread
+// workgroups per CU, so one workgroup's loads overlap the other's barriers.
+template <typename S, int CH, int MODE> constexpr int line_waves() {
+  return (CH == 1 && sizeof(typename Prec<S>::R) == 4 && ModeT<MODE>::nb + ModeT<MODE>::nf == 6) ? 8 : 1;
+}
+
 template <typename S, int CH, int MODE, bool BASE, bool PASS>
-__global__ void __launch_bounds__(1024) k_line(LineArgs<S> a) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(line_waves<S, CH, MODE>())))
+k_line(LineArgs<S> a) {
   using R = typename Prec<S>::R;
   using M = ModeT<MODE>;
   extern __shared__ char smem_raw[];
@@ -469,12 +476,12 @@ struct RawHalf {
 // The ILU middle step on the even sites of each tile (App. B sequence, steps 2-5):
 //   b = T^-1 u_lo, f = T^dag^-1 (u_up + psi_up), y = A (f, b + psi_lo),
 //   chi = (psi_up + y_up, psi_lo + T^-1 y_lo), n = (T^dag^-1 (y_up - u_up), T^-1 y_lo - b).
-// b waits in LDS from the first scans to the end.  NP inputs are parked in LDS in storage
+// b waits in LDS from the first scans to the end (in registers when PB is false).  NP inputs are parked in LDS in storage
 // form instead of being held in registers or read twice from HBM: NP = 2 parks u_up and
 // psi_up, psi_lo taking u_up's slot once the clover product has consumed it; NP = 3 gives
 // psi_lo its own slot, parked before the product.  Each thread touches only its own slots,
 // so no barrier guards them.
-template <typename S, int CH, int NP>
+template <typename S, int CH, int NP, bool PB = true>
 __global__ void __launch_bounds__(mid_threads<CH>()) k_ilu_mid(LineArgs<S> a) {
   using R = typename Prec<S>::R;
   using Lk = typename Prec<S>::L;
@@ -487,7 +494,12 @@ __global__ void __launch_bounds__(mid_threads<CH>()) k_ilu_mid(LineArgs<S> a) {
   char* park_u = raw0;                                           // u_up, then (NP = 2) psi_lo
   char* park_p = raw0 + size_t(Raw::bytes) * CH * nthr;          // psi_up
   char* park_l = raw0 + size_t(Raw::bytes) * CH * nthr * 2;      // psi_lo (NP = 3)
-  auto bslot = [&](int k, int c) -> cx<R>& { return park_b[(k * 6 + c) * nthr + threadIdx.x]; };
+  // PB = false (FP64 on lines too long for its LDS): b stays in registers
+  cx<R> bkeep[PB ? 1 : CH][6];
+  auto bslot = [&](int k, int c) -> cx<R>& {
+    if constexpr (PB) return park_b[(k * 6 + c) * nthr + threadIdx.x];
+    else return bkeep[k][c];
+  };
   const uint32_t blk = batch_select(a);
   ScanCtx<R> sc = make_ctx<S>(a, CH, blk);
   const int s = sc.active ? sc.s : 0;
@@ -676,6 +688,7 @@ void go(tp_op op, K kern, LineArgs<S>& a, Shape sh, int park = 0) {
   a.f = pow(op->mu, -double(sh.CH));
   a.lds_table = lds_table_of(sh);
   const size_t lds = lds_bytes<S>(sh, park) + size_t(a.lds_extra);
+  if (lds > ctx->lds_max) TP_THROW(TP_EDIMS, "time extent too long for the line kernels' LDS");
   dim3 grid((unsigned)((L.Vs2 + sh.LPB - 1) / sh.LPB * a.nr));
   hipLaunchKernelGGL(kern, grid, dim3(sh.LPB * sh.NCH), lds, ctx->stream, a);
   LAUNCH_CHECK();
@@ -761,7 +774,11 @@ void mid_t(tp_op op, const Field& psi, const Field& u, Field& chi, Field& n) {
       return;
     }
   }
-  TP_CH_DISPATCH(sh.CH, go<S>(op, k_ilu_mid<S, CH, 0>, a, sh, park))
+  if (lds_bytes<S>(sh, park) <= op->g->ctx->lds_max) {
+    TP_CH_DISPATCH(sh.CH, go<S>(op, k_ilu_mid<S, CH, 0>, a, sh, park))
+  } else {
+    TP_CH_DISPATCH(sh.CH, go<S>(op, k_ilu_mid<S, CH, 0, false>, a, sh, 0))
+  }
 }
 
 }  // namespace

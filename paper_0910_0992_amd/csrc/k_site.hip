@@ -11,6 +11,50 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Order in which the blocks of a one-block-per-chunk launch visit the tiles.  Workgroups go to
+// the 8 XCDs (each with its own L2) in turn, so block b runs on XCD b % 8.  A tile of 4 lines
+// spans Q = Lt / 64 blocks; XCD x takes the time range x % Q of the tiles in part x / Q of a
+// z-blocked tile sequence (x fastest, then z inside blocks of BZ planes, then y, then the z
+// block), so that the tiles holding a site's x, y and z neighbours were visited by the same
+// XCD 1, TX*BZ and TX blocks earlier.  off = identity.
+struct TileOrder {
+  uint32_t Q, TX, Ly, BZ, per_part;
+  int on;
+};
+
+TP_DEV uint32_t ordered_block(const TileOrder& o, uint32_t b) {
+  const uint32_t x = b & 7u, n = b >> 3;
+  const uint32_t q = (x / o.Q) * o.per_part + n;
+  const uint32_t tx = q % o.TX;
+  uint32_t r = q / o.TX;
+  const uint32_t zi = r % o.BZ;
+  r /= o.BZ;
+  const uint32_t y = r % o.Ly, zb = r / o.Ly;
+  const uint32_t tile = tx + o.TX * (y + o.Ly * (zb * o.BZ + zi));
+  return tile * o.Q + x % o.Q;
+}
+
+// The XCD-aware order where the launch shape allows it (one block per chunk of 256 sites,
+// whole tiles per block group, tiles inside x rows), else off.
+TileOrder tile_order(const Lattice& L, int64_t nblocks, int nr, bool half) {
+  TileOrder o{1, 1, 1, 1, 0, 0};
+  const Geom& g = L.g;
+  if (nr != 1 || int64_t(nblocks) * kBlock != g.V2) return o;
+  if (g.Lt % 64 || (8 % (g.Lt / 64)) || g.Lxh % kTile) return o;
+  const uint32_t Q = uint32_t(g.Lt / 64), tiles = uint32_t(g.Vs2 / kTile);
+  if ((uint64_t(tiles) * Q) % 8) return o;
+  o.Q = Q;
+  o.TX = uint32_t(g.Lxh / kTile);
+  o.Ly = uint32_t(g.Ly);
+  o.BZ = g.Lz % 8 == 0 ? 8u : g.Lz % 4 == 0 ? 4u : g.Lz % 2 == 0 ? 2u : 1u;
+  o.per_part = tiles * Q / 8;
+  o.on = 1;
+  // measured: with FP16 storage and four blocks per tile (256-slice lines) the identity
+  // order was 2.7% faster; everywhere else this order was 4-19% faster
+  o.on = !(half && Q >= 4);
+  return o;
+}
+
 template <typename S>
 struct SiteArgsP3 {
   // for output parity p: self[p] (parity p operand of mu, A, D_t), nb[p] (parity 1-p
@@ -23,6 +67,7 @@ struct SiteArgsP3 {
   int par;  // output parity of this launch
   int nr;   // right-hand sides: block b works on field b % nr of each batch
   double* partial;
+  TileOrder ord;
 };
 
 // DS: 0 = no spatial hop, 3 = spatial links read whole, 2 = read as two rows (SU(3))
@@ -36,7 +81,8 @@ __global__ void __launch_bounds__(kBlock) k_site_p3(SiteArgsP3<S> a) {
   const uint32_t nr = uint32_t(a.nr), rhs = blockIdx.x % nr, blk = blockIdx.x / nr, nblk = gridDim.x / nr;
   const SpinorF<S> self = rhs_view(a.self[p], rhs), nbf = rhs_view(a.nb[p], rhs);
   const SpinorF<S> in2 = rhs_view(a.in2[p], rhs), dst = rhs_view(a.dst[p], rhs);
-  for (uint32_t i = blk * blockDim.x + threadIdx.x; i < uint32_t(a.g.V2); i += nblk * blockDim.x) {
+  const uint32_t first = a.ord.on ? ordered_block(a.ord, blk) : blk;
+  for (uint32_t i = first * blockDim.x + threadIdx.x; i < uint32_t(a.g.V2); i += nblk * blockDim.x) {
     int t, s;
     p3_ts32(a.g, i, t, s);
     cx<R> out[12];
@@ -351,6 +397,7 @@ int site_t(tp_op op, const SiteIO& io, Field& dst, SiteCoef cf, int ck, int par0
   if (norm && a.nr != 1) TP_THROW(TP_EINVAL, "a fused norm needs a single right-hand side");
   int64_t nb = (L.V2 + kBlock - 1) / kBlock;
   if (norm) nb = std::min<int64_t>(nb, kRedBlocks / 2);
+  a.ord = tile_order(L, nb, a.nr, Prec<S>::half);
   bool dt = cf.c_t != 0.0, ds = cf.c_s != 0.0;
   bool i2 = in2 != nullptr;
   // reduced-precision spatial hops read SU(3) links as two rows

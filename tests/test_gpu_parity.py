@@ -245,3 +245,31 @@ def test_gauge_rejects_nonunitary_time_links():
     U = synth.make_links(dims, 0.3, 0.1, 5)
     U[3] *= np.exp(0.3j)
     Operator(torch.from_numpy(U).cuda(), -0.05, 3.0, 0.5, 1.0, -1).close()
+
+
+# Shapes on which the site kernels visit tiles in their XCD-aware order (time extent a
+# multiple of 64 up to 512, Lx/2 a multiple of 4): 1, 2, 4 and 8 blocks per tile, two tiles
+# per x row and several z blocks.
+ORDER_SHAPES = [(16, 2, 12, 64), (16, 2, 12, 128), (8, 4, 4, 256), (8, 2, 2, 512)]
+
+
+@pytest.mark.parametrize("dims", ORDER_SHAPES)
+def test_site_kernels_in_tile_order(dims):
+    from paper_0910_0992_amd import Operator
+    xi, m0, cs, ct = 3.5, -0.05, 1.6, 1.0
+    U = synth.make_links(dims, 0.35, 0.12, 1000)
+    oop = OOp(U, m0, xi, -1.0, cs / xi, ct)
+    gop = Operator(torch.from_numpy(U).cuda(), m0, xi, cs / xi, ct, -1)
+    eta = synth.make_source(dims, 2000)
+    teta = torch.from_numpy(eta).cuda()
+    print(f"[order] dims={dims}", flush=True)
+    try:
+        m = oop.M(eta)
+        ts = oop.tschur(eta)
+        for prec in ("F64", "F32", "F16N"):
+            _close(_np(gop.apply_M(teta, prec)), m, TOL[prec][0] * 2, f"M {prec}")
+            _close(_np(gop.apply_Ds(teta, prec)), oop.Ds(eta), TOL[prec][0] * 2, f"D_s {prec}")
+            _close(_np(gop.apply_prec(teta, "TEMPORAL_SCHUR", prec=prec)), ts, TOL[prec][1],
+                   f"TEMPORAL_SCHUR {prec}")
+    finally:
+        gop.close()

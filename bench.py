@@ -29,7 +29,7 @@ TRAFFIC = {
     ("clover_32x256", "F16N", "hop_site"): {
         "bytes_per_launch": 2.206e9,
         "sources": ["k_site.hip", "tp_hop.h", "tp_device.h"],
-        "sha256": "4be8527cbf123ac2b517b39c9ec2d9e8385d17dbba2cd24d357787fbd1a02b47",
+        "sha256": "9c4f4f04a416a9eecb496212dea9d6624bec635f46d3d07a200fe2682644d648",
     },
 }
 

@@ -282,7 +282,9 @@ tp_status tp_ctx_create(const int32_t dims[4], int32_t bc_t, int32_t device, tp_
       HIP_CHECK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
       c->lds_max = size_t(lds);
       c->red_partial = static_cast<double*>(dev_alloc(sizeof(double) * 8 * kRedBlocks));
-      c->red_result = static_cast<double*>(dev_alloc(sizeof(double) * 8 * kMaxRhs));
+      c->red_result = static_cast<double*>(dev_alloc(sizeof(double) * (8 * kMaxRhs + BS_COUNT)));
+      c->bicg = c->red_result + 8 * kMaxRhs;
+      HIP_CHECK(hipMemset(c->bicg, 0, sizeof(double) * BS_COUNT));
       HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&c->red_host), sizeof(double) * 8 * kMaxRhs,
                               hipHostMallocDefault));
     } catch (...) {

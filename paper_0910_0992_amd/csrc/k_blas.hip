@@ -23,7 +23,9 @@ struct BlasK {
   int nr;                      // right-hand sides: block b works on field b % nr of each batch
   double coef[kMaxRhs][8];     // nr > 1: per right-hand side a, b, c (complex) and a skip flag
   double* partial;             // [nr][blocks per right-hand side][8]
+  const double* dcoef;         // single right-hand side: a, b, c read from device memory
 };
+static_assert(BS_COUNT <= 8 * kMaxRhs, "pinned staging buffer too small for the solver scalars");
 
 TP_DEV void block_reduce(double (&acc)[8], int nred, double* partial, uint32_t blk) {
   __shared__ double sh[kBlock / 64][8];
@@ -57,9 +59,26 @@ __global__ void __launch_bounds__(kBlock) k_blas(BlasK<S> k) {
   using R = typename Prec<S>::R;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const uint32_t nr = uint32_t(k.nr), rhs = blockIdx.x % nr, blk = blockIdx.x / nr, nblk = gridDim.x / nr;
-  const double* cf = nr > 1 ? k.coef[rhs] : nullptr;
-  const cx<R> A = cc<R>(cf ? cf : k.a), B = cc<R>(cf ? cf + 2 : k.b), C = cc<R>(cf ? cf + 4 : k.c);
-  const int npar = (cf && cf[6] != 0.0) ? 0 : k.npar;  // a skipped right-hand side is left untouched
+  // coefficients from the kernel arguments (one set, or one per right-hand side) or from
+  // device memory; separate branches, so that no pointer mixes the two address spaces (a
+  // pointer that may point into the by-value arguments makes the compiler copy them to
+  // scratch in every thread)
+  cx<R> A, B, C;
+  if (k.dcoef) {
+    A = cc<R>(k.dcoef);
+    B = cc<R>(k.dcoef + 2);
+    C = cc<R>(k.dcoef + 4);
+  } else if (nr > 1) {
+    A = cc<R>(k.coef[rhs]);
+    B = cc<R>(k.coef[rhs] + 2);
+    C = cc<R>(k.coef[rhs] + 4);
+  } else {
+    A = cc<R>(k.a);
+    B = cc<R>(k.b);
+    C = cc<R>(k.c);
+  }
+  // a skipped right-hand side is left untouched
+  const int npar = (nr > 1 && k.coef[rhs][6] != 0.0) ? 0 : k.npar;
   for (int q = 0; q < npar; ++q)
 #pragma unroll
   for (int h = 0; h < 2; ++h)
@@ -173,9 +192,57 @@ __global__ void __launch_bounds__(kBlock) k_convert(SpinorF<SX> x0, SpinorF<SX> 
   }
 }
 
-// Block r sums the `nblocks` partials of right-hand side r into result[r][0..nred).
-__global__ void k_finish(const double* partial, int nblocks, int nred, double* result) {
+// BiCGStab's scalar steps on the device (single right-hand side), from the reduced values v
+// of the op just finished; the same formulas as the host-side solver.
+TP_DEV void bicg_post(int post, const double* v, double* st) {
+  if (post == BP_RHO) {
+    st[BS_RHO] = v[0];
+    st[BS_RHO + 1] = v[1];
+  } else if (post == BP_ALPHA) {  // v = <rhat, v>
+    const double den = v[0] * v[0] + v[1] * v[1];
+    const double rr = st[BS_RHO], ri = st[BS_RHO + 1];
+    const double ar = (rr * v[0] + ri * v[1]) / den, ai = (ri * v[0] - rr * v[1]) / den;
+    st[BS_ALPHA] = ar;
+    st[BS_ALPHA + 1] = ai;
+    st[BS_AXPY] = -ar;
+    st[BS_AXPY + 1] = -ai;
+    for (int q = 2; q < 6; ++q) st[BS_AXPY + q] = 0.0;
+  } else if (post == BP_S2) {
+    st[BS_S2] = v[0];
+  } else if (post == BP_OMEGA) {  // v = <t, s>, |t|^2, <rhat, s>, <rhat, t>
+    const double om_r = v[0] / v[2], om_i = v[1] / v[2];
+    const double rn_r = v[3] - (om_r * v[5] - om_i * v[6]);
+    const double rn_i = v[4] - (om_r * v[6] + om_i * v[5]);
+    const double rho_r = st[BS_RHO], rho_i = st[BS_RHO + 1];
+    const double al_r = st[BS_ALPHA], al_i = st[BS_ALPHA + 1];
+    const double rr = rho_r * rho_r + rho_i * rho_i, oo = om_r * om_r + om_i * om_i;
+    const double q_r = (rn_r * rho_r + rn_i * rho_i) / rr, q_i = (rn_i * rho_r - rn_r * rho_i) / rr;
+    const double w_r = (al_r * om_r + al_i * om_i) / oo, w_i = (al_i * om_r - al_r * om_i) / oo;
+    const double be_r = q_r * w_r - q_i * w_i, be_i = q_r * w_i + q_i * w_r;
+    st[BS_BREAK] = (v[2] == 0.0 || !isfinite(oo) || oo == 0.0 || rr == 0.0) ? 1.0 : 0.0;
+    st[BS_OMEGA] = om_r;
+    st[BS_OMEGA + 1] = om_i;
+    st[BS_BETA] = be_r;
+    st[BS_BETA + 1] = be_i;
+    st[BS_FUSED] = al_r;
+    st[BS_FUSED + 1] = al_i;
+    st[BS_FUSED + 2] = om_r;
+    st[BS_FUSED + 3] = om_i;
+    st[BS_FUSED + 4] = be_r;
+    st[BS_FUSED + 5] = be_i;
+    st[BS_RHO] = rn_r;
+    st[BS_RHO + 1] = rn_i;
+  } else if (post == BP_R2) {
+    st[BS_R2] = v[0];
+  }
+}
+
+// Block r sums the `nblocks` partials of right-hand side r into result[r][0..nred); with
+// `post`, block 0 then updates the solver scalars st.
+__global__ void k_finish(const double* partial, int nblocks, int nred, double* result, int post,
+                         double* st) {
   __shared__ double sh[kBlock];
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   partial += (int64_t)blockIdx.x * nblocks * 8;
   result += (int64_t)blockIdx.x * 8;
   for (int k = 0; k < nred; ++k) {
@@ -187,9 +254,10 @@ __global__ void k_finish(const double* partial, int nblocks, int nred, double* r
       if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
       __syncthreads();
     }
-    if (threadIdx.x == 0) result[k] = sh[0];
+    if (threadIdx.x == 0) result[k] = v[k] = sh[0];
     __syncthreads();
   }
+  if (post != BP_NONE && blockIdx.x == 0 && threadIdx.x == 0) bicg_post(post, v, st);
 }
 
 template <typename S>
@@ -208,6 +276,7 @@ struct BlasCall {
   int nr;
   const BlasArgs* per;
   const bool* skip;
+  const double* dcoef;
 };
 
 template <typename S, int OP>
@@ -232,6 +301,7 @@ int blas_go(tp_ctx ctx, int par0, int npar, const Field* const* fs, const BlasCa
   a.npar = npar;
   a.V2 = uint32_t(ctx->lat.V2);
   a.partial = ctx->red_partial;
+  a.dcoef = c.dcoef;
   // blocks per right-hand side: the whole grid stays near kBlasBlocks
   int64_t nb = ((int64_t)npar * 2 * a.V2 + kBlock - 1) / kBlock;
   nb = std::min<int64_t>(nb, std::max(1, kBlasBlocks / c.nr));
@@ -285,8 +355,34 @@ void blas(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<const
   blas_multi(ctx, op, par0, npar, fl, nullptr, nullptr, red_out, k);
 }
 
+namespace {
+void blas_impl(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<const Field*> fl,
+               const BlasArgs* per, const bool* skip, double* red_out, BlasArgs k, const double* dcoef,
+               int post, bool dev);
+}  // namespace
+
 void blas_multi(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<const Field*> fl,
                 const BlasArgs* per, const bool* skip, double* red_out, BlasArgs k) {
+  blas_impl(ctx, op, par0, npar, fl, per, skip, red_out, k, nullptr, BP_NONE, false);
+}
+
+void blas_dev(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<const Field*> fl,
+              const double* dcoef, int post) {
+  blas_impl(ctx, op, par0, npar, fl, nullptr, nullptr, nullptr, BlasArgs{}, dcoef, post, true);
+}
+
+void bicg_state(tp_ctx ctx, double* out) {
+  HIP_CHECK(hipMemcpyAsync(ctx->red_host, ctx->bicg, sizeof(double) * BS_COUNT, hipMemcpyDeviceToHost,
+                           ctx->stream));
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  prof_flush(ctx);
+  for (int q = 0; q < BS_COUNT; ++q) out[q] = ctx->red_host[q];
+}
+
+namespace {
+void blas_impl(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<const Field*> fl,
+               const BlasArgs* per, const bool* skip, double* red_out, BlasArgs k, const double* dcoef,
+               int post, bool dev) {
   const Field* fs[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   int nr = 0;
   {
@@ -300,7 +396,8 @@ void blas_multi(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list
     }
   }
   if (nr < 1 || nr > kMaxRhs) TP_THROW(TP_EINVAL, "blas: batch size");
-  const BlasCall call{k, nr, per, skip};
+  if (dev && nr != 1) TP_THROW(TP_EINVAL, "blas: device-side coefficients take single fields");
+  const BlasCall call{k, nr, per, skip, dcoef};
   const Field* x = fs[0];
   const Field* y = fs[1];
   int prec = x ? x->prec : y->prec;
@@ -345,9 +442,10 @@ void blas_multi(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list
     {
       ProfScope ps(ctx, KID_REDUCE, double(nb) * nr * 8 * 8);
       hipLaunchKernelGGL(k_finish, dim3(nr), dim3(kBlock), 0, ctx->stream, ctx->red_partial, nb, nred,
-                         ctx->red_result);
+                         ctx->red_result, post, ctx->bicg);
       LAUNCH_CHECK();
     }
+    if (dev) return;
     HIP_CHECK(hipMemcpyAsync(ctx->red_host, ctx->red_result, sizeof(double) * 8 * nr,
                              hipMemcpyDeviceToHost, ctx->stream));
     HIP_CHECK(hipStreamSynchronize(ctx->stream));
@@ -355,11 +453,12 @@ void blas_multi(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list
     for (int q = 0; q < 8 * (nr - 1) + nred; ++q) red_out[q] = ctx->red_host[q];
   }
 }
+}  // namespace
 
 // Sum of the first `nblocks` partials written by a norm-producing site kernel.
 double finish_norm(tp_ctx ctx, int nblocks) {
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, ctx->stream, ctx->red_partial, nblocks, 1,
-                     ctx->red_result);
+                     ctx->red_result, int(BP_NONE), ctx->bicg);
   LAUNCH_CHECK();
   HIP_CHECK(hipMemcpyAsync(ctx->red_host, ctx->red_result, sizeof(double), hipMemcpyDeviceToHost,
                            ctx->stream));

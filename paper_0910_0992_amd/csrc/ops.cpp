@@ -568,61 +568,51 @@ bool bicgstab_reliable(tp_op op, const tp_solve_params& P, const KrylovOp& A, bo
   double seg_r2 = r2, seg_rr2 = rr2;
   blas(ctx, B_COPY, p0, np, {&r, &rh});
   blas(ctx, B_COPY, p0, np, {&r, &p});
-  blas(ctx, B_DOT, p0, np, {&rh, &r}, BlasArgs{}, red);
-  double rho_r = red[0], rho_i = red[1];
+  double rho_r = 0, rho_i = 0;
   double rmax2 = rr2;
   double best2 = r2;
   int since_best = 0;
   // stall / divergence guard on the recursive residual within a segment
   double seg_best = rr2;
   int seg_start = info.iters, seg_best_it = info.iters;
+  // one iteration runs without host round trips: the reductions turn into the next op's
+  // coefficients on the device (BicgPost), and the host reads the scalars once at its end
+  double* st = ctx->bicg;
+  double S[BS_COUNT];
+  auto set_rho = [&]() {
+    blas_dev(ctx, B_DOT, p0, np, {&rh, &r}, nullptr, BP_RHO);
+    bicg_state(ctx, S);
+    rho_r = S[BS_RHO];
+    rho_i = S[BS_RHO + 1];
+  };
+  set_rho();
   while (true) {
     const double tgt2 = 0.25 * tol * tol * eta2 / seg_r2 * seg_rr2;
     if (info.iters >= max_iter) return give_up();
     A.apply(p, v, false);
-    info.applies++;
-    blas(ctx, B_DOT, p0, np, {&rh, &v}, BlasArgs{}, red);
-    double den = red[0] * red[0] + red[1] * red[1];
-    if (den == 0.0 || !isfinite(den)) return give_up();
-    double al_r = (rho_r * red[0] + rho_i * red[1]) / den;
-    double al_i = (rho_i * red[0] - rho_r * red[1]) / den;
-    blas(ctx, B_AXPYZ_NORM, p0, np, {&v, &r, &s}, cplx(-al_r, -al_i), red);
-    double s2 = red[0];
+    blas_dev(ctx, B_DOT, p0, np, {&rh, &v}, nullptr, BP_ALPHA);              // alpha
+    blas_dev(ctx, B_AXPYZ_NORM, p0, np, {&v, &r, &s}, st + BS_AXPY, BP_S2);  // s = r - alpha v
+    A.apply(s, t, false);
+    // <t,s>, |t|^2, <rhat,s>, <rhat,t>: omega, rho_new = <rhat, s - omega t> and beta before r
+    // exists, so the x, r and p updates share one pass over the fields
+    blas_dev(ctx, B_DOT4_TS, p0, np, {&t, &s, &rh}, nullptr, BP_OMEGA);
+    blas_dev(ctx, B_BICG_FUSED, p0, np, {&y, &p, &s, &t, &v, &r}, st + BS_FUSED, BP_R2);
+    info.applies += 2;
     info.iters++;
-    bool upd = false;
-    if (s2 <= tgt2) {
-      blas(ctx, B_AXPY, p0, np, {&p, &y}, cplx(al_r, al_i));
-      blas(ctx, B_COPY, p0, np, {&s, &r});
-      rr2 = s2;
-      upd = true;
-    } else {
-      A.apply(s, t, false);
-      info.applies++;
-      blas(ctx, B_DOT4_TS, p0, np, {&t, &s, &rh}, BlasArgs{}, red);
-      double om_r = red[0] / red[2], om_i = red[1] / red[2];
-      double rn_r = red[3] - (om_r * red[5] - om_i * red[6]);
-      double rn_i = red[4] - (om_r * red[6] + om_i * red[5]);
-      double rr = rho_r * rho_r + rho_i * rho_i;
-      double oo = om_r * om_r + om_i * om_i;
-      if (red[2] == 0.0 || !isfinite(oo) || oo == 0.0 || rr == 0.0) return give_up();
-      double q_r = (rn_r * rho_r + rn_i * rho_i) / rr, q_i = (rn_i * rho_r - rn_r * rho_i) / rr;
-      double w_r = (al_r * om_r + al_i * om_i) / oo, w_i = (al_i * om_r - al_r * om_i) / oo;
-      double be_r = q_r * w_r - q_i * w_i, be_i = q_r * w_i + q_i * w_r;
-      blas(ctx, B_BICG_FUSED, p0, np, {&y, &p, &s, &t, &v, &r},
-           cplx(al_r, al_i, om_r, om_i, be_r, be_i), red);
-      rr2 = red[0];
-      if (!isfinite(rr2)) return give_up();
-      if (rr2 < seg_best) {
-        seg_best = rr2;
-        seg_best_it = info.iters;
-      }
-      if (rr2 > 1e8 * seg_best || info.iters - seg_best_it > std::max(500, 2 * (seg_best_it - seg_start)))
-        return give_up();
-      rho_r = rn_r;
-      rho_i = rn_i;
-      rmax2 = std::max(rmax2, rr2);
-      upd = rr2 <= tgt2 || rr2 <= delta * delta * rmax2;
+    bicg_state(ctx, S);
+    // a vanishing <rhat, v> makes alpha and everything after it non-finite
+    rr2 = S[BS_R2];
+    if (S[BS_BREAK] != 0.0 || !isfinite(rr2)) return give_up();
+    if (rr2 < seg_best) {
+      seg_best = rr2;
+      seg_best_it = info.iters;
     }
+    if (rr2 > 1e8 * seg_best || info.iters - seg_best_it > std::max(500, 2 * (seg_best_it - seg_start)))
+      return give_up();
+    rho_r = S[BS_RHO];
+    rho_i = S[BS_RHO + 1];
+    rmax2 = std::max(rmax2, rr2);
+    const bool upd = rr2 <= tgt2 || rr2 <= delta * delta * rmax2;
     if (!upd) continue;
     fold();
     if (getenv("TPREC_VERBOSE"))
@@ -643,15 +633,12 @@ bool bicgstab_reliable(tp_op op, const tp_solve_params& P, const KrylovOp& A, bo
     rmax2 = rr2;
     seg_best = rr2;
     seg_start = seg_best_it = info.iters;
-    blas(ctx, B_DOT, p0, np, {&rh, &r}, BlasArgs{}, red);
-    rho_r = red[0];
-    rho_i = red[1];
+    set_rho();
     if (rho_r * rho_r + rho_i * rho_i < 1e-24 * rr2 * rr2) {
       // the shadow residual has become orthogonal to the new residual: restart it
       blas(ctx, B_COPY, p0, np, {&r, &rh});
       blas(ctx, B_COPY, p0, np, {&r, &p});
-      rho_r = rr2;
-      rho_i = 0;
+      set_rho();
       info.restarts++;
     }
   }

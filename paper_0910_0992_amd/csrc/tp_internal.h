@@ -110,6 +110,8 @@ struct tp_ctx_s {
   double* red_partial = nullptr;  // [kRedBlocks][8]
   double* red_result = nullptr;   // [8]
   double* red_host = nullptr;     // pinned [8]
+  // BiCGStab scalars kept on the device (inside red_result's allocation): see BicgSlot
+  double* bicg = nullptr;
 };
 
 struct tp_gauge_s {
@@ -276,6 +278,22 @@ enum BlasOp {
   B_G5,           // y = gamma5 x
   B_MIXED_ACC     // y(F64) += x(any)
 };
+// Device-resident BiCGStab scalars (doubles in tp_ctx_s::bicg): the reduction that ends a
+// level-1 op can turn its results into the next op's coefficients without a host round trip.
+enum BicgSlot {
+  BS_RHO = 0,      // rho = <rhat, r> (complex)
+  BS_ALPHA = 2,    // alpha = rho / <rhat, v>
+  BS_OMEGA = 4,    // omega = <t, s> / |t|^2
+  BS_BETA = 6,     // beta = (rho_new / rho) (alpha / omega)
+  BS_S2 = 8,       // |s|^2
+  BS_R2 = 9,       // |r|^2 after the fused update
+  BS_BREAK = 10,   // nonzero: |t|^2, omega or rho vanished or is not finite
+  BS_AXPY = 16,    // coefficients (a, b, c) of s = r - alpha v
+  BS_FUSED = 24,   // coefficients (alpha, omega, beta) of the fused update
+  BS_COUNT = 32
+};
+enum BicgPost { BP_NONE, BP_RHO, BP_ALPHA, BP_S2, BP_OMEGA, BP_R2 };
+
 struct BlasArgs {
   double a[2], b[2], c[2];  // complex coefficients
 };
@@ -289,6 +307,13 @@ void blas(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<const
 // [nr][8] values.
 void blas_multi(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<const Field*> fs,
                 const BlasArgs* per, const bool* skip, double* red_out, BlasArgs k = BlasArgs{});
+// The same op with its coefficients (a, b, c as six doubles) read from device memory when
+// dcoef is not null, and its reductions post-processed on the device by `post` (BicgPost);
+// nothing is copied to the host and the host does not wait.
+void blas_dev(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<const Field*> fs,
+              const double* dcoef, int post);
+// Copies the BS_COUNT device scalars to out and waits for the stream.
+void bicg_state(tp_ctx ctx, double* out);
 // Sum of the first nblocks per-block partials written by a site kernel with want_norm.
 double finish_norm(tp_ctx ctx, int nblocks);
 

@@ -170,6 +170,22 @@ def test_solve_mixed(case, prec, scheme):
 
 
 @pytest.mark.parametrize("prec", ["F32", "F16N"])
+def test_solve_iteration_limit(case, prec):
+    """A mixed solve cut off after a few iterations reports non-convergence and returns the
+    best FP64 iterate it has: finite, and no worse than x = 0."""
+    from paper_0910_0992_amd import _lib as L
+    o, g = case["oop"], case["gop"]
+    x, info = g.solve(case["teta"], scheme="TEMPORAL_SCHUR", prec=prec, tol=1e-10, max_iter=4,
+                      raise_on_noconv=False)
+    assert info["status"] == L.TP_ENOCONV, info
+    xn = _np(x)
+    assert np.all(np.isfinite(xn))
+    true = np.linalg.norm(case["eta"] - o.M(xn)) / np.linalg.norm(case["eta"])
+    assert true <= 1.0 + 1e-12, (info, true)
+    assert info["iters"] <= 4 + 1, info
+
+
+@pytest.mark.parametrize("prec", ["F32", "F16N"])
 @pytest.mark.parametrize("scheme", ["TEMPORAL_SCHUR", "TEMPORAL", "UNPREC", "SCHUR4D"])
 def test_solve_multi(case, prec, scheme):
     """Batched right-hand sides (lockstep BiCGStab, or one after another where the scheme

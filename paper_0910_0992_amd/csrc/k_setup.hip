@@ -349,10 +349,11 @@ TP_DEV void chain4(const cx<double>* a, const cx<double>* b, const cx<double>* c
 // F_{mu nu}(x) = (Q - Q^dag)/8 - tr/3 with Q the four leaves, all oriented mu -> nu.
 TP_DEV void field_strength(const double2* canon, const Geom& g, int64_t V, int mu, int nu, int x,
                            int y, int z, int t, cx<double>* F) {
-  int e[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
-  auto L = [&](int d, int am, int an, cx<double>* u) {  // U_d(x + am*mu + an*nu)
-    load_link(canon, g, V, d, x + am * e[mu][0] + an * e[nu][0], y + am * e[mu][1] + an * e[nu][1],
-              z + am * e[mu][2] + an * e[nu][2], t + am * e[mu][3] + an * e[nu][3], u);
+  // U_d(x + am*mu + an*nu); the offsets are formed arithmetically (a direction table indexed
+  // by mu and nu would live in scratch memory)
+  auto L = [&](int d, int am, int an, cx<double>* u) {
+    load_link(canon, g, V, d, x + am * (mu == 0) + an * (nu == 0), y + am * (mu == 1) + an * (nu == 1),
+              z + am * (mu == 2) + an * (nu == 2), t + am * (mu == 3) + an * (nu == 3), u);
   };
   cx<double> a[9], b[9], c[9], d[9], cd[9], dd[9], leaf[9], Q[9];
   for (int k = 0; k < 9; ++k) Q[k] = cx<double>{0, 0};
@@ -378,148 +379,192 @@ TP_DEV void field_strength(const double2* canon, const Geom& g, int64_t V, int m
   F[0] -= tr; F[4] -= tr; F[8] -= tr;
 }
 
-TP_DEV void store_herm6(const cx<double>* m /*36 row-major*/, double2* d3, float2* f3, int64_t st,
-                        int64_t i3, double2* d4, int64_t i4, float2* f4 = nullptr) {
-  // slots 0..2: diagonal pairs, 3..17: lower triangle row-major
-  int slot = 0;
-  for (int k = 0; k < 3; ++k, ++slot) {
-    double2 v = make_double2(m[(2 * k) * 7].re, m[(2 * k + 1) * 7].re);
-    if (d3) d3[(int64_t)slot * st + i3] = v;
-    if (f3) f3[comp_off<float2>(slot, 18, st, i3)] = make_float2(float(v.x), float(v.y));
-    if (d4) d4[(int64_t)slot * st + i4] = v;
-    if (f4) f4[comp_off<float2>(slot, 18, st, i4)] = make_float2(float(v.x), float(v.y));
-  }
-  for (int r = 1; r < 6; ++r)
-    for (int c = 0; c < r; ++c, ++slot) {
-      double2 v = make_double2(m[6 * r + c].re, m[6 * r + c].im);
-      if (d3) d3[(int64_t)slot * st + i3] = v;
-      if (f3) f3[comp_off<float2>(slot, 18, st, i3)] = make_float2(float(v.x), float(v.y));
-      if (d4) d4[(int64_t)slot * st + i4] = v;
-      if (f4) f4[comp_off<float2>(slot, 18, st, i4)] = make_float2(float(v.x), float(v.y));
-    }
-}
-
-__global__ void k_clover_build(const double2* __restrict__ canon, double2* a3d, float2* a3f,
-                               double2* a4d, float2* a4f, Geom g, int64_t V, SigTab sig) {
+// One chiral block C of the clover term at every site: the sum over the six planes of the
+// sigma-table coefficients times F_{mu nu}, accumulated only into the stored entries of the
+// hermitian 6x6 block (6 real diagonal, 15 complex below it), all at compile-time indices so
+// that they stay in registers.
+template <int C>
+__global__ void __launch_bounds__(64) k_clover_build(const double2* __restrict__ canon, double2* a3d,
+                                                     float2* a3f, double2* a4d, float2* a4f, Geom g,
+                                                     int64_t V, SigTab sig) {
   int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= V) return;
   int x, y, z, t;
   canon_coords(n, g, x, y, z, t);
-  const int planes[6][2] = {{0, 3}, {1, 3}, {2, 3}, {0, 1}, {0, 2}, {1, 2}};
-  cx<double> B[2][36];
-  for (int c = 0; c < 2; ++c)
-    for (int k = 0; k < 36; ++k) B[c][k] = cx<double>{0, 0};
+  double dg[6];
+  cx<double> lo[15];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) dg[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 15; ++k) lo[k] = cx<double>{0, 0};
+#pragma unroll
   for (int pl = 0; pl < 6; ++pl) {
-    double2 nz = sig.s[pl][0][0][0];
-    double mag = fabs(nz.x) + fabs(nz.y) + fabs(sig.s[pl][0][0][1].x) + fabs(sig.s[pl][0][0][1].y) +
-                 fabs(sig.s[pl][1][0][0].x) + fabs(sig.s[pl][1][0][0].y) +
-                 fabs(sig.s[pl][1][0][1].x) + fabs(sig.s[pl][1][0][1].y);
-    if (mag == 0.0) continue;  // coefficient zero
+    // planes 03 13 23 01 02 12
+    const int mu = pl < 3 ? pl : (pl == 5 ? 1 : 0);
+    const int nu = pl < 3 ? 3 : (pl == 3 ? 1 : 2);
+    const double2 w00 = sig.s[pl][C][0][0], w01 = sig.s[pl][C][0][1];
+    const double2 w10 = sig.s[pl][C][1][0], w11 = sig.s[pl][C][1][1];
+    if (fabs(w00.x) + fabs(w00.y) + fabs(w01.x) + fabs(w01.y) + fabs(w10.x) + fabs(w10.y) +
+            fabs(w11.x) + fabs(w11.y) == 0.0)
+      continue;  // coefficient zero
     cx<double> F[9];
-    field_strength(canon, g, V, planes[pl][0], planes[pl][1], x, y, z, t, F);
-    for (int c = 0; c < 2; ++c)
-      for (int s = 0; s < 2; ++s)
-        for (int sp = 0; sp < 2; ++sp) {
-          cx<double> w = cx<double>{sig.s[pl][c][s][sp].x, sig.s[pl][c][s][sp].y};
-          for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) B[c][(3 * s + a) * 6 + 3 * sp + b] += cmul(w, F[3 * a + b]);
-        }
+    field_strength(canon, g, V, mu, nu, x, y, z, t, F);
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int q = 0; q <= r; ++q) {
+        const int sr = r / 3, a = r % 3, sq = q / 3, bb = q % 3;
+        const double2 wv = sr == 0 ? (sq == 0 ? w00 : w01) : (sq == 0 ? w10 : w11);
+        const cx<double> v = cmul(cx<double>{wv.x, wv.y}, F[3 * a + bb]);
+        if (r == q) dg[r] += v.re;
+        else lo[r * (r - 1) / 2 + q] += v;
+      }
   }
   int p3, p4;
   int64_t i3, i4;
   site_pi(g, false, x, y, z, t, p3, i3);
   site_pi(g, true, x, y, z, t, p4, i4);
-  int64_t V2 = V / 2;
-  for (int c = 0; c < 2; ++c) {
-    double2* d3 = a3d ? a3d + ((int64_t)p3 * 36 + 18 * c) * V2 : nullptr;
-    float2* f3 = a3f ? a3f + ((int64_t)p3 * 36 + 18 * c) * V2 : nullptr;
-    double2* d4 = a4d ? a4d + ((int64_t)p4 * 36 + 18 * c) * V2 : nullptr;
-    float2* f4 = a4f ? a4f + ((int64_t)p4 * 36 + 18 * c) * V2 : nullptr;
-    store_herm6(B[c], d3, f3, V2, i3, d4, i4, f4);
+  const int64_t V2 = V / 2;
+  double2* d3 = a3d ? a3d + ((int64_t)p3 * 36 + 18 * C) * V2 : nullptr;
+  float2* f3 = a3f ? a3f + ((int64_t)p3 * 36 + 18 * C) * V2 : nullptr;
+  double2* d4 = a4d ? a4d + ((int64_t)p4 * 36 + 18 * C) * V2 : nullptr;
+  float2* f4 = a4f ? a4f + ((int64_t)p4 * 36 + 18 * C) * V2 : nullptr;
+  // slots 0..2: diagonal pairs, 3..17: lower triangle row-major (the layout of store_herm6_parts)
+#pragma unroll
+  for (int slot = 0; slot < 18; ++slot) {
+    const double2 v = slot < 3 ? make_double2(dg[2 * slot], dg[2 * slot + 1])
+                               : make_double2(lo[slot - 3].re, lo[slot - 3].im);
+    if (d3) d3[(int64_t)slot * V2 + i3] = v;
+    if (f3) f3[comp_off<float2>(slot, 18, V2, i3)] = make_float2(float(v.x), float(v.y));
+    if (d4) d4[(int64_t)slot * V2 + i4] = v;
+    if (f4) f4[comp_off<float2>(slot, 18, V2, i4)] = make_float2(float(v.x), float(v.y));
   }
 }
 
-TP_DEV void load_herm6(const double2* base, int64_t st, int64_t i, cx<double>* m) {
-  int slot = 0;
-  for (int k = 0; k < 3; ++k, ++slot) {
-    double2 v = base[(int64_t)slot * st + i];
-    m[(2 * k) * 7] = cx<double>{v.x, 0};
-    m[(2 * k + 1) * 7] = cx<double>{v.y, 0};
-  }
-  for (int r = 1; r < 6; ++r)
-    for (int c = 0; c < r; ++c, ++slot) {
-      double2 v = base[(int64_t)slot * st + i];
-      m[6 * r + c] = cx<double>{v.x, v.y};
-      m[6 * c + r] = cx<double>{v.x, -v.y};
-    }
-}
-
-// Gauss-Jordan with partial pivoting on a 6x6 complex matrix (FP64).
-TP_DEV bool inv6(cx<double>* a, cx<double>* inv) {
-  for (int i = 0; i < 36; ++i) inv[i] = cx<double>{(i % 7 == 0) ? 1.0 : 0.0, 0.0};
+// Inverse of a hermitian 6x6 block from its stored form (real diagonal dg, lower triangle lo
+// row-major), by H = L D L^dag with L unit lower triangular and D real: H^-1 = L^-dag D^-1 L^-1.
+// Every loop has fixed bounds, so all entries stay in registers.  Returns false when a pivot
+// falls below 1e-13 of the largest diagonal entry (the block is then reported singular).
+TP_DEV bool inv_herm6(const double* dg, const cx<double>* lo, double* idg, cx<double>* ilo) {
+  auto T = [](int r, int c) { return r * (r - 1) / 2 + c; };  // lower-triangle index, r > c
   double scale = 0;
-  for (int i = 0; i < 6; ++i) scale = fmax(scale, sqrt(norm2(a[7 * i])));
-  for (int col = 0; col < 6; ++col) {
-    int piv = col;
-    double best = norm2(a[6 * col + col]);
-    for (int r = col + 1; r < 6; ++r) {
-      double v = norm2(a[6 * r + col]);
-      if (v > best) { best = v; piv = r; }
-    }
-    if (!(sqrt(best) > 1e-13 * scale)) return false;
-    if (piv != col)
-      for (int k = 0; k < 6; ++k) {
-        cx<double> t1 = a[6 * col + k]; a[6 * col + k] = a[6 * piv + k]; a[6 * piv + k] = t1;
-        cx<double> t2 = inv[6 * col + k]; inv[6 * col + k] = inv[6 * piv + k]; inv[6 * piv + k] = t2;
-      }
-    cx<double> d = a[6 * col + col];
-    double dn = norm2(d);
-    cx<double> id = cx<double>{d.re / dn, -d.im / dn};
-    for (int k = 0; k < 6; ++k) {
-      a[6 * col + k] = cmul(a[6 * col + k], id);
-      inv[6 * col + k] = cmul(inv[6 * col + k], id);
-    }
-    for (int r = 0; r < 6; ++r) {
-      if (r == col) continue;
-      cx<double> f = a[6 * r + col];
-      for (int k = 0; k < 6; ++k) {
-        a[6 * r + k] -= cmul(f, a[6 * col + k]);
-        inv[6 * r + k] -= cmul(f, inv[6 * col + k]);
-      }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) scale = fmax(scale, fabs(dg[k]));
+  double d[6];
+  cx<double> L[15];
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    double dj = dg[j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) dj -= norm2(L[T(j, k)]) * d[k];
+    d[j] = dj;
+    if (!(fabs(dj) > 1e-13 * scale)) ok = false;
+    const double id = 1.0 / dj;
+#pragma unroll
+    for (int i = j + 1; i < 6; ++i) {
+      cx<double> v = lo[T(i, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= d[k] * cmul(L[T(i, k)], conj(L[T(j, k)]));
+      L[T(i, j)] = id * v;
     }
   }
-  return true;
+  // M = L^-1 (unit lower triangular), by forward substitution
+  cx<double> M[15];
+#pragma unroll
+  for (int i = 1; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < i; ++j) {
+      cx<double> v = -L[T(i, j)];
+#pragma unroll
+      for (int k = j + 1; k < i; ++k) v -= cmul(L[T(i, k)], M[T(k, j)]);
+      M[T(i, j)] = v;
+    }
+  // H^-1[i][j] = sum_{k >= i} conj(M[k][i]) M[k][j] / d[k]  (i >= j; M[k][k] = 1)
+  double id[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) id[k] = 1.0 / d[k];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double v = id[i];
+#pragma unroll
+    for (int k = i + 1; k < 6; ++k) v += norm2(M[T(k, i)]) * id[k];
+    idg[i] = v;
+  }
+#pragma unroll
+  for (int i = 1; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < i; ++j) {
+      cx<double> v = id[i] * M[T(i, j)];
+#pragma unroll
+      for (int k = i + 1; k < 6; ++k) v += id[k] * cmul(conj(M[T(k, i)]), M[T(k, j)]);
+      ilo[T(i, j)] = v;
+    }
+  return ok;
+}
+
+// Stored form of a hermitian block: slots 0..2 diagonal pairs, 3..17 the lower triangle
+// row-major.  The clover kernels read this form (clover_apply, herm6_from_slots).
+TP_DEV void load_herm6_parts(const double2* base, int64_t st, int64_t i, double* dg, cx<double>* lo) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double2 v = base[(int64_t)k * st + i];
+    dg[2 * k] = v.x;
+    dg[2 * k + 1] = v.y;
+  }
+#pragma unroll
+  for (int k = 0; k < 15; ++k) {
+    const double2 v = base[(int64_t)(3 + k) * st + i];
+    lo[k] = cx<double>{v.x, v.y};
+  }
+}
+TP_DEV void store_herm6_parts(const double* dg, const cx<double>* lo, double2* d, float2* f, int64_t st,
+                              int64_t i) {
+#pragma unroll
+  for (int slot = 0; slot < 18; ++slot) {
+    const double2 v = slot < 3 ? make_double2(dg[2 * slot], dg[2 * slot + 1])
+                               : make_double2(lo[slot - 3].re, lo[slot - 3].im);
+    d[(int64_t)slot * st + i] = v;
+    if (f) f[comp_off<float2>(slot, 18, st, i)] = make_float2(float(v.x), float(v.y));
+  }
 }
 
 // From the stored A/2 blocks (layout p3 or p4), write (A+mu)/2 and (A+mu)^-1/2 blocks.
-__global__ void k_clover_derived(const double2* __restrict__ a, double2* amu, double2* ainv,
-                                 float2* amu_f, float2* ainv_f, int64_t V2, double mu, int* bad) {
+__global__ void __launch_bounds__(64) k_clover_derived(const double2* __restrict__ a, double2* amu,
+                                                       double2* ainv, float2* amu_f, float2* ainv_f,
+                                                       int64_t V2, double mu, int* bad) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int p = blockIdx.y;
   if (i >= V2) return;
+#pragma unroll
   for (int c = 0; c < 2; ++c) {
-    int64_t off = ((int64_t)p * 36 + 18 * c) * V2;
-    cx<double> m[36], inv[36];
+    const int64_t off = ((int64_t)p * 36 + 18 * c) * V2;
+    double dg[6], idg[6];
+    cx<double> lo[15], ilo[15];
     if (a) {
-      load_herm6(a + off, V2, i, m);
+      load_herm6_parts(a + off, V2, i, dg, lo);
     } else {
-      for (int k = 0; k < 36; ++k) m[k] = cx<double>{0, 0};
+#pragma unroll
+      for (int k = 0; k < 6; ++k) dg[k] = 0.0;
+#pragma unroll
+      for (int k = 0; k < 15; ++k) lo[k] = cx<double>{0, 0};
     }
-    for (int k = 0; k < 6; ++k) m[7 * k].re += 0.5 * mu;  // (A + mu)/2
-    store_herm6(m, amu + off, amu_f ? amu_f + off : nullptr, V2, i, nullptr, 0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) dg[k] += 0.5 * mu;  // (A + mu)/2
+    store_herm6_parts(dg, lo, amu + off, amu_f ? amu_f + off : nullptr, V2, i);
     // (A+mu)^-1/2 = [(A+mu)/2]^-1 / 4
-    if (!inv6(m, inv)) {
+    if (!inv_herm6(dg, lo, idg, ilo)) {
       bad[0] = 1;
-      for (int k = 0; k < 36; ++k) inv[k] = cx<double>{0, 0};
+#pragma unroll
+      for (int k = 0; k < 6; ++k) idg[k] = 0.0;
+#pragma unroll
+      for (int k = 0; k < 15; ++k) ilo[k] = cx<double>{0, 0};
     }
-    for (int k = 0; k < 36; ++k) inv[k] = 0.25 * inv[k];
-    // symmetrise (hermitian up to rounding)
-    for (int r = 0; r < 6; ++r)
-      for (int cc = 0; cc < r; ++cc) {
-        cx<double> l = 0.5 * (inv[6 * r + cc] + conj(inv[6 * cc + r]));
-        inv[6 * r + cc] = l;
-      }
-    store_herm6(inv, ainv + off, ainv_f ? ainv_f + off : nullptr, V2, i, nullptr, 0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) idg[k] *= 0.25;
+#pragma unroll
+    for (int k = 0; k < 15; ++k) ilo[k] = 0.25 * ilo[k];
+    store_herm6_parts(idg, ilo, ainv + off, ainv_f ? ainv_f + off : nullptr, V2, i);
   }
 }
 
@@ -531,14 +576,16 @@ __global__ void k_plaquette(const double2* __restrict__ canon, Geom g, int64_t V
   if (n < V) {
     int x, y, z, t;
     canon_coords(n, g, x, y, z, t);
-    const int planes[6][2] = {{0, 1}, {0, 2}, {1, 2}, {0, 3}, {1, 3}, {2, 3}};
-    int e[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
+    // planes 01 02 12 03 13 23; offsets formed arithmetically, not from a table indexed by
+    // the plane (which would live in scratch memory)
+#pragma unroll 1
     for (int pl = 0; pl < 6; ++pl) {
-      int mu = planes[pl][0], nu = planes[pl][1];
+      const int mu = pl == 2 || pl == 4 ? 1 : (pl == 5 ? 2 : 0);
+      const int nu = pl < 3 ? (pl == 0 ? 1 : 2) : 3;
       cx<double> a[9], b[9], c[9], d[9], cd[9], dd[9], leaf[9];
       load_link(canon, g, V, mu, x, y, z, t, a);
-      load_link(canon, g, V, nu, x + e[mu][0], y + e[mu][1], z + e[mu][2], t + e[mu][3], b);
-      load_link(canon, g, V, mu, x + e[nu][0], y + e[nu][1], z + e[nu][2], t + e[nu][3], c);
+      load_link(canon, g, V, nu, x + (mu == 0), y + (mu == 1), z + (mu == 2), t + (mu == 3), b);
+      load_link(canon, g, V, mu, x + (nu == 0), y + (nu == 1), z + (nu == 2), t + (nu == 3), c);
       load_link(canon, g, V, nu, x, y, z, t, d);
       dag3(c, cd);
       dag3(d, dd);
@@ -812,10 +859,16 @@ void launch_clover_build(tp_ctx ctx, tp_clover c, const double sig[6][2][2][2][2
     for (int ch = 0; ch < 2; ++ch)
       for (int r = 0; r < 2; ++r)
         for (int q = 0; q < 2; ++q) t.s[p][ch][r][q] = make_double2(sig[p][ch][r][q][0], sig[p][ch][r][q][1]);
-  hipLaunchKernelGGL(k_clover_build, dim3(nblk(L.V, 64)), dim3(64), 0, ctx->stream, c->g->canon_ax,
+  hipLaunchKernelGGL(k_clover_build<0>, dim3(nblk(L.V, 64)), dim3(64), 0, ctx->stream, c->g->canon_ax,
                      c->a3_d, c->a3_f, (double2*)nullptr, (float2*)nullptr, L.g, L.V, t);
   LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_clover_build, dim3(nblk(L.V, 64)), dim3(64), 0, ctx->stream, c->g->canon,
+  hipLaunchKernelGGL(k_clover_build<1>, dim3(nblk(L.V, 64)), dim3(64), 0, ctx->stream, c->g->canon_ax,
+                     c->a3_d, c->a3_f, (double2*)nullptr, (float2*)nullptr, L.g, L.V, t);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_clover_build<0>, dim3(nblk(L.V, 64)), dim3(64), 0, ctx->stream, c->g->canon,
+                     (double2*)nullptr, (float2*)nullptr, c->a4_d, c->a4_f, L.g, L.V, t);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_clover_build<1>, dim3(nblk(L.V, 64)), dim3(64), 0, ctx->stream, c->g->canon,
                      (double2*)nullptr, (float2*)nullptr, c->a4_d, c->a4_f, L.g, L.V, t);
   LAUNCH_CHECK();
 }

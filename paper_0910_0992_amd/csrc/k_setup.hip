@@ -656,16 +656,28 @@ __global__ void __launch_bounds__(128) k_clover_Y(SpinorF<double2> x0, SpinorF<d
   cx<double> xs[12], ls[12];
   load_spinor<double2, double>(p ? x1 : x0, i, xs);
   load_spinor<double2, double>(p ? l1 : l0, i, ls);
+  // W_ba = sum_s v_sb conj(lambda_sa) with v_sb = sum_s' sigma_ss' x_s'b; every loop is
+  // unrolled so that the spinor components and the table are read at constant indices (arrays
+  // indexed by a loop variable would live in scratch memory)
+#pragma unroll
   for (int pl = 0; pl < 6; ++pl) {
     cx<double> W[9];
+#pragma unroll
     for (int k = 0; k < 9; ++k) W[k] = czero<double>();
-    for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      cx<double> v[3] = {czero<double>(), czero<double>(), czero<double>()};
+#pragma unroll
       for (int sp = 0; sp < 4; ++sp) {
         const cx<double> sg = cx<double>{sig.s[pl][s][sp].x, sig.s[pl][s][sp].y};
-        if (sg.re == 0.0 && sg.im == 0.0) continue;
-        for (int b = 0; b < 3; ++b)
-          for (int a = 0; a < 3; ++a) W[3 * b + a] += cmul(sg, cmul(xs[3 * sp + b], conj(ls[3 * s + a])));
+#pragma unroll
+        for (int b = 0; b < 3; ++b) v[b] += cmul(sg, xs[3 * sp + b]);
       }
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) W[3 * b + a] += cmul(v[b], conj(ls[3 * s + a]));
+    }
     const cx<double> tr = W[0] + W[4] + W[8];
     const double c = 0.5 * (pl < 3 ? c_t : c_s);
     double2* out = Y + ((int64_t)pl * V + n) * 9;

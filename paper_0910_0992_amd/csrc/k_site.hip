@@ -209,21 +209,23 @@ TP_DEV void proj_full(int mu, bool minus, const cx<double>* x, cx<double>* out) 
   }
 }
 
-__global__ void k_force(SpinorF<double2> x0, SpinorF<double2> x1, SpinorF<double2> l0,
-                        SpinorF<double2> l1, const double2* __restrict__ canon, double2* grad,
-                        Geom g, int64_t V, double inv_gf, double b, int projected) {
-  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int mu = blockIdx.y;
-  if (n >= V) return;
+// One direction mu (a compile-time constant, so that no array is indexed by it: such arrays
+// would live in scratch memory).
+template <int mu>
+TP_DEV void force_site(SpinorF<double2> x0, SpinorF<double2> x1, SpinorF<double2> l0,
+                       SpinorF<double2> l1, const double2* __restrict__ canon, double2* grad,
+                       const Geom& g, int64_t V, double inv_gf, double b, int projected, int64_t n) {
   int x = int(n % g.Lx);
   int64_t r = n / g.Lx;
   int y = int(r % g.Ly);
   r /= g.Ly;
   int z = int(r % g.Lz);
   int t = int(r / g.Lz);
-  int xs[4] = {x, y, z, t};
-  int ls[4] = {g.Lx, g.Ly, g.Lz, g.Lt};
-  xs[mu] = xs[mu] + 1 == ls[mu] ? 0 : xs[mu] + 1;
+  // s + mu
+  const int xn = mu == 0 ? (x + 1 == g.Lx ? 0 : x + 1) : x;
+  const int yn = mu == 1 ? (y + 1 == g.Ly ? 0 : y + 1) : y;
+  const int zn = mu == 2 ? (z + 1 == g.Lz ? 0 : z + 1) : z;
+  const int tn = mu == 3 ? (t + 1 == g.Lt ? 0 : t + 1) : t;
   auto p3 = [&](int X, int Y, int Z, int T, int& p, int64_t& i) {
     p = (X + Y + Z) & 1;
     i = p3_idx(g, T, (X + g.Lx * (Y + g.Ly * Z)) >> 1);
@@ -231,7 +233,7 @@ __global__ void k_force(SpinorF<double2> x0, SpinorF<double2> x1, SpinorF<double
   int pa, pb;
   int64_t ia, ib;
   p3(x, y, z, t, pa, ia);
-  p3(xs[0], xs[1], xs[2], xs[3], pb, ib);
+  p3(xn, yn, zn, tn, pb, ib);
   cx<double> xa[12], xb[12], la[12], lb[12], px[12];
   load_spinor<double2, double>(pa ? x1 : x0, ia, xa);
   load_spinor<double2, double>(pb ? x1 : x0, ib, xb);
@@ -279,6 +281,19 @@ __global__ void k_force(SpinorF<double2> x0, SpinorF<double2> x1, SpinorF<double
       if (i == j) h.re -= tr;
       out[3 * i + j] = make_double2(fac * h.re, fac * h.im);
     }
+}
+
+__global__ void __launch_bounds__(128) k_force(SpinorF<double2> x0, SpinorF<double2> x1, SpinorF<double2> l0,
+                        SpinorF<double2> l1, const double2* __restrict__ canon, double2* grad,
+                        Geom g, int64_t V, double inv_gf, double b, int projected) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= V) return;
+  switch (blockIdx.y) {
+    case 0: force_site<0>(x0, x1, l0, l1, canon, grad, g, V, inv_gf, b, projected, n); break;
+    case 1: force_site<1>(x0, x1, l0, l1, canon, grad, g, V, inv_gf, b, projected, n); break;
+    case 2: force_site<2>(x0, x1, l0, l1, canon, grad, g, V, inv_gf, b, projected, n); break;
+    default: force_site<3>(x0, x1, l0, l1, canon, grad, g, V, inv_gf, b, projected, n); break;
+  }
 }
 
 template <typename S>

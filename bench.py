@@ -29,7 +29,7 @@ TRAFFIC = {
     ("clover_32x256", "F16N", "hop_site"): {
         "bytes_per_launch": 2.206e9,
         "sources": ["k_site.hip", "tp_hop.h", "tp_device.h"],
-        "sha256": "9c4f4f04a416a9eecb496212dea9d6624bec635f46d3d07a200fe2682644d648",
+        "sha256": "d96cc61d9b769d058ba7c01e6ebe74d886243271732c3dac36491dbba396c756",
     },
 }
 

@@ -222,8 +222,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the multi-GPU path is a design note only)", file=sys.stderr)
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported: the library has "
+              "no multi-GPU path (spatial sharding is described as a design only)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -316,6 +316,11 @@ template <int MODE> TP_DEV constexpr bool passes(int h) {
 
 // out = c_out MODE(in) + c_base base  (BASE), else c_out MODE(in).
 // Halves that MODE does not scan pass through (PASS), or are left untouched.
+// Largest workgroup of the line kernels: FP64 lines take at most 512 threads, which also
+// lets the compiler give each FP64 thread up to 256 VGPRs.
+template <typename S>
+constexpr int max_threads() { return sizeof(typename Prec<S>::R) == 8 ? 512 : 1024; }
+
 // One-slice FP32-arithmetic scans of one half spinor fit in 64 VGPRs: two 1024-thread
 // workgroups per CU, so one workgroup's loads overlap the other's barriers.
 template <typename S, int CH, int MODE> constexpr int line_waves() {
@@ -323,7 +328,7 @@ template <typename S, int CH, int MODE> constexpr int line_waves() {
 }
 
 template <typename S, int CH, int MODE, bool BASE, bool PASS>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(line_waves<S, CH, MODE>())))
+__global__ void __launch_bounds__(max_threads<S>()) __attribute__((amdgpu_waves_per_eu(line_waves<S, CH, MODE>())))
 k_line(LineArgs<S> a) {
   using R = typename Prec<S>::R;
   using M = ModeT<MODE>;
@@ -482,7 +487,8 @@ struct RawHalf {
 // psi_lo its own slot, parked before the product.  Each thread touches only its own slots,
 // so no barrier guards them.
 template <typename S, int CH, int NP, bool PB = true>
-__global__ void __launch_bounds__(mid_threads<CH>()) k_ilu_mid(LineArgs<S> a) {
+__global__ void __launch_bounds__(mid_threads<CH>() < max_threads<S>() ? mid_threads<CH>() : max_threads<S>())
+k_ilu_mid(LineArgs<S> a) {
   using R = typename Prec<S>::R;
   using Lk = typename Prec<S>::L;
   using Raw = RawHalf<S>;
@@ -667,8 +673,6 @@ SpinorF<S> pv(const Field* f, int p) {
   return f->template par<S>(p);
 }
 
-template <typename S>
-constexpr int max_threads() { return sizeof(typename Prec<S>::R) == 8 ? 512 : 1024; }
 
 // LDS of a line kernel: the chunk-combine table (shuffle path: [tile][16 segments][4 lines][6];
 // LDS path: [chunk][line][6]) followed by `park` complex values per thread.

@@ -228,6 +228,10 @@ const char* tp_status_string(tp_status s);
 const char* tp_last_error(void);
 /* Per-kernel timing with HIP events on the bound stream. */
 tp_status tp_prof_enable(tp_ctx ctx, int32_t on);
+/* Time only the kernel groups whose bit (1 << id) is set in mask (all groups until this is
+ * called); launches of the other groups record no events, so timing one group costs the
+ * others nothing.  EINVAL for a null context. */
+tp_status tp_prof_select(tp_ctx ctx, uint32_t mask);
 tp_status tp_prof_reset(tp_ctx ctx);
 /* id in [0, tp_prof_count()): launches, summed milliseconds, algorithmic bytes. */
 int32_t tp_prof_count(void);

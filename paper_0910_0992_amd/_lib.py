@@ -72,6 +72,7 @@ SIGNATURES = [
     ("tp_status_string", [_I], C.c_char_p),
     ("tp_last_error", [], C.c_char_p),
     ("tp_prof_enable", [_P, _I], _I),
+    ("tp_prof_select", [_P, C.c_uint32], _I),
     ("tp_prof_reset", [_P], _I),
     ("tp_prof_count", [], _I),
     ("tp_prof_name", [_I], C.c_char_p),

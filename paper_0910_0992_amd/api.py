@@ -215,7 +215,16 @@ class Operator:
         return ps.value, pt.value
 
     # ---- per-kernel timing --------------------------------------------------------------
-    def profile(self, on=True):
+    def profile(self, on=True, only=None):
+        """Per-kernel-group HIP-event timing; `only`: names of the groups to time (all if None)."""
+        mask = 0xFFFFFFFF
+        if only is not None:
+            names = [self._lib.tp_prof_name(k).decode() for k in range(self._lib.tp_prof_count())]
+            unknown = set(only) - set(names)
+            if unknown:
+                raise ValueError(f"unknown kernel groups {sorted(unknown)}; known: {names}")
+            mask = sum(1 << names.index(n) for n in only)
+        self._call(self._lib.tp_prof_select, self._ctx, mask)
         self._call(self._lib.tp_prof_enable, self._ctx, int(on))
 
     def profile_reset(self):

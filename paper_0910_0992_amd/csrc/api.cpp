@@ -178,7 +178,8 @@ void field_free(Field& f) {
   f.nrm = nullptr;
 }
 
-ProfScope::ProfScope(tp_ctx c, int k, double b) : ctx(c), kid(k), bytes(b), slot(0), on(c && c->prof) {
+ProfScope::ProfScope(tp_ctx c, int k, double b)
+    : ctx(c), kid(k), bytes(b), slot(0), on(c && c->prof && ((c->prof_mask >> k) & 1u)) {
   if (!on) return;
   if (ctx->ev_used >= 4096) prof_flush(ctx);
   if (ctx->ev_used == ctx->ev_pool.size()) {
@@ -754,6 +755,14 @@ tp_status tp_prof_enable(tp_ctx ctx, int32_t on) {
     need(ctx, "ctx");
     prof_flush(ctx);
     ctx->prof = on != 0;
+  });
+}
+
+tp_status tp_prof_select(tp_ctx ctx, uint32_t mask) {
+  return guard([&] {
+    need(ctx, "ctx");
+    prof_flush(ctx);
+    ctx->prof_mask = mask;
   });
 }
 

@@ -101,6 +101,7 @@ struct tp_ctx_s {
   size_t lds_max = 65536;  // LDS bytes a workgroup may allocate on this device
   hipStream_t stream = nullptr;
   bool prof = false;
+  uint32_t prof_mask = 0xffffffffu;  // kernel groups that record events while prof is on
   ProfSlot prof_slots[KID_COUNT];
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   struct EvRec { int kid; double bytes; bool done; };

@@ -170,6 +170,42 @@ def test_solve_mixed(case, prec, scheme):
 
 
 @pytest.mark.parametrize("prec", ["F32", "F16N"])
+def test_solve_from_initial_guess(case, prec):
+    """A mixed solve started from x0 (use_x0) reaches the target from there: from a slightly
+    perturbed solution in fewer iterations than from zero, from the solution itself at once."""
+    o, g = case["oop"], case["gop"]
+    x_ref, i_ref = g.solve(case["teta"], scheme="TEMPORAL_SCHUR", prec=prec, tol=1e-10)
+    rng = np.random.default_rng(5)
+    noise = rng.standard_normal(x_ref.shape) + 1j * rng.standard_normal(x_ref.shape)
+    xr = _np(x_ref)
+    x0 = xr + 1e-6 * np.linalg.norm(xr) / np.linalg.norm(noise) * noise
+    x, info = g.solve(case["teta"], scheme="TEMPORAL_SCHUR", prec=prec, tol=1e-10,
+                      x0=torch.from_numpy(x0).cuda())
+    true = np.linalg.norm(case["eta"] - o.M(_np(x))) / np.linalg.norm(case["eta"])
+    assert true <= 1.05e-10, (info, true)
+    assert info["iters"] < i_ref["iters"], (info, i_ref)
+    x2, info2 = g.solve(case["teta"], scheme="TEMPORAL_SCHUR", prec=prec, tol=1e-10, x0=x_ref)
+    assert info2["iters"] <= 2, info2
+    true2 = np.linalg.norm(case["eta"] - o.M(_np(x2))) / np.linalg.norm(case["eta"])
+    assert true2 <= 1.05e-10
+
+
+@pytest.mark.parametrize("delta", [0.005, 0.05])
+def test_solve_reliable_update_threshold(case, delta):
+    """Any reliable-update threshold reaches the FP64 target.  An update follows a drop of the
+    recursive residual to delta times its running maximum, so a larger delta folds the
+    correction into FP64 at least as often."""
+    o, g = case["oop"], case["gop"]
+    x, info = g.solve(case["teta"], scheme="TEMPORAL_SCHUR", prec="F16N", tol=1e-10, inner_tol=delta)
+    true = np.linalg.norm(case["eta"] - o.M(_np(x))) / np.linalg.norm(case["eta"])
+    assert true <= 1.05e-10, (info, true)
+    if delta == 0.05:
+        _, tight = g.solve(case["teta"], scheme="TEMPORAL_SCHUR", prec="F16N", tol=1e-10,
+                           inner_tol=0.005)
+        assert info["outer_iters"] >= tight["outer_iters"], (info, tight)
+
+
+@pytest.mark.parametrize("prec", ["F32", "F16N"])
 def test_solve_iteration_limit(case, prec):
     """A mixed solve cut off after a few iterations reports non-convergence and returns the
     best FP64 iterate it has: finite, and no worse than x = 0."""

@@ -246,6 +246,30 @@ def test_solve_multi(case, prec, scheme):
     _close(xs[1], _np(x1), 1e-7, "batched vs single solve")
 
 
+@pytest.mark.parametrize("prec", ["F32", "F16N"])
+def test_solve_mixed_cgnr(case, prec):
+    """CGNR with FP64 defect correction in the reduced precision reaches the FP64 target."""
+    o, g = case["oop"], case["gop"]
+    x, info = g.solve(case["teta"], scheme="TEMPORAL_SCHUR", solver="CGNR", prec=prec, tol=1e-10)
+    true = np.linalg.norm(case["eta"] - o.M(_np(x))) / np.linalg.norm(case["eta"])
+    assert true <= 1.05e-10, (info, true)
+    assert info["outer_iters"] >= 2
+
+
+def test_solve_multi_from_initial_guess(case):
+    """A batch started from its own solutions needs almost no work and stays converged."""
+    o, g = case["oop"], case["gop"]
+    etas = [torch.from_numpy(case["eta"]).cuda(),
+            torch.from_numpy(synth.make_source(case["dims"], 2004)).cuda()]
+    xs, _ = g.solve_multi(etas, scheme="TEMPORAL_SCHUR", prec="F16N", tol=1e-10)
+    xs2, infos = g.solve_multi(etas, scheme="TEMPORAL_SCHUR", prec="F16N", tol=1e-10, x0=xs)
+    for k in range(2):
+        assert infos[k]["iters"] <= 2, infos[k]
+        e = _np(etas[k])
+        true = np.linalg.norm(e - o.M(_np(xs2[k]))) / np.linalg.norm(e)
+        assert true <= 1.05e-10, (k, infos[k], true)
+
+
 def test_solve_schur4d_f32_mixed(case):
     o, g = case["oop"], case["gop"]
     x, info = g.solve(case["teta"], scheme="SCHUR4D", prec="F32", tol=1e-10)

@@ -29,7 +29,9 @@
  *   All GPU work is enqueued on the stream set with tp_ctx_set_stream (default:
  *   the null stream).  Apply entry points do not synchronise.  tp_solve and
  *   the create functions synchronise the stream (they need scalars on the host).
- *   A handle may be used by one host thread at a time.
+ *   A context, together with the gauge, clover and operator handles created from
+ *   it, may be used by one host thread at a time: they share the context's
+ *   reduction buffers and the solver's device-side scalars.
  *
  * Errors
  *   Every entry point returns a tp_status.  On failure a message is available

@@ -32,20 +32,6 @@ template <typename R> TP_DEV cx<R> cmul(cx<R> a, cx<R> b) {
 template <typename R> TP_DEV cx<R> cmulc(cx<R> a, cx<R> b) {
   return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
 }
-// acc += a b and acc += conj(a) b as four multiply-adds each (a product formed first and
-// then added costs two more instructions)
-template <typename R> TP_DEV void cmac(cx<R>& acc, cx<R> a, cx<R> b) {
-  acc.re += a.re * b.re;
-  acc.re -= a.im * b.im;
-  acc.im += a.re * b.im;
-  acc.im += a.im * b.re;
-}
-template <typename R> TP_DEV void cmacc(cx<R>& acc, cx<R> a, cx<R> b) {
-  acc.re += a.re * b.re;
-  acc.re += a.im * b.im;
-  acc.im += a.re * b.im;
-  acc.im -= a.im * b.re;
-}
 template <typename R> TP_DEV cx<R> conj(cx<R> a) { return {a.re, -a.im}; }
 template <typename R> TP_DEV cx<R> ti(cx<R> a) { return {-a.im, a.re}; }   // i a
 template <typename R> TP_DEV cx<R> tmi(cx<R> a) { return {a.im, -a.re}; }  // -i a
@@ -63,8 +49,8 @@ template <typename R> TP_DEV void mv(const su3<R>& u, const cx<R>* v, cx<R>* out
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     cx<R> s = cmul(u.e[3 * a], v[0]);
-    cmac(s, u.e[3 * a + 1], v[1]);
-    cmac(s, u.e[3 * a + 2], v[2]);
+    s += cmul(u.e[3 * a + 1], v[1]);
+    s += cmul(u.e[3 * a + 2], v[2]);
     out[a] = s;
   }
 }
@@ -73,8 +59,8 @@ template <typename R> TP_DEV void mvd(const su3<R>& u, const cx<R>* v, cx<R>* ou
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     cx<R> s = cmulc(u.e[a], v[0]);
-    cmacc(s, u.e[3 + a], v[1]);
-    cmacc(s, u.e[6 + a], v[2]);
+    s += cmulc(u.e[3 + a], v[1]);
+    s += cmulc(u.e[6 + a], v[2]);
     out[a] = s;
   }
 }
@@ -370,8 +356,8 @@ TP_DEV void herm6_from_slots(const cx<R>* sl, const cx<R>* v, cx<R>* out) {
   for (int r = 1; r < 6; ++r) {
 #pragma unroll
     for (int c = 0; c < r; ++c) {
-      cmac(out[r], sl[slot], v[c]);
-      cmacc(out[c], sl[slot], v[r]);
+      out[r] += cmul(sl[slot], v[c]);
+      out[c] += cmulc(sl[slot], v[r]);
       ++slot;
     }
   }

@@ -67,6 +67,7 @@ def test_null_handles_rejected(lib):
     assert lib.tp_solve(None, None, None, None, None) == -1
     assert lib.tp_solve_multi(None, None, 2, None, None, None) == -1
     assert lib.tp_force(None, None, None, None, 1) == -1
+    assert lib.tp_prof_select(None, 0xFFFFFFFF) == -1
     # destroy of a null handle is a no-op
     assert lib.tp_op_destroy(None) == 0
 

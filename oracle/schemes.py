@@ -13,6 +13,13 @@ TEMPORAL_SCHUR  3D parity p3 = (-1)^(x+y+z); M^ee = A + mu - D_t on even sites,
                 matrices of Sec. II.B; Mt3 = S_L M S_R.  For Wilson fermions this
                 is eq:TPrecFull; for clover with the Wilson C_L, C_R ("partial SW
                 temporal preconditioning") it is eq:TPrecPartial, the 3D ILU scheme.
+TEMPORAL_SCHUR3D  the same p3 blocks with the even block inverted exactly (temporal
+                preconditioning combined with 3D-Schur, Sec. II.B and App. A):
+                S_o = M^oo - M^oe (M^ee)^-1 M^eo and Mt = diag(1, C_L^o S_o C_R^o),
+                S_L = diag((M^ee)^-1, C_L^o) L^-1, S_R = U^-1 diag(1, C_R^o).  Here
+                (M^ee)^-1 is a sparse direct solve of the assembled even block;
+                for Wilson fermions M^ee = mu - D_t = (C_R C_L)^-1 and the scheme is
+                eq:TPrecFull again.
 
 Blocks are formed literally: K^{ab} psi = mask_a * K(mask_b * psi) on the full
 lattice, so every identity below can be checked by eye against the paper.
@@ -22,12 +29,14 @@ triangularity is swapped); they are not needed, because the solution is
 recovered as x = S_R y.
 """
 import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
-from .dirac import GAMMA5, spin_apply
+from .dirac import GAMMA5, PT_MINUS, PT_PLUS, spin_apply
 from . import wilson as W
 from .temporal import Temporal
 
-SCHEMES = ("UNPREC", "SCHUR4D", "TEMPORAL", "TEMPORAL_SCHUR")
+SCHEMES = ("UNPREC", "SCHUR4D", "TEMPORAL", "TEMPORAL_SCHUR", "TEMPORAL_SCHUR3D")
 
 
 def parity_masks(dims, four_d: bool):
@@ -57,6 +66,7 @@ class Operator:
         self.e3, self.o3 = parity_masks(self.dims, False)
         self.e4, self.o4 = parity_masks(self.dims, True)
         self._Amu_inv = None
+        self._mee = None
 
     # ---- the unpreconditioned pieces -------------------------------------------------
     def M(self, psi):
@@ -159,6 +169,71 @@ class Operator:
         chi_o = po + self.Abar(po) + self.Dbar_oe(t2 - t1) / g
         return e * chi_e + o * chi_o
 
+    # ---- temporal + 3D Schur with the exact even block (p3) --------------------------
+    def _mee_factor(self):
+        """Sparse LU of M^ee = A + mu - D_t on the even p3 sites (identity on odd sites).
+
+        Assembled from the definitions (Sec. II.B; D_t of Sec. II.A with the boundary phase b
+        on the wrapping hops): diagonal blocks A(x) + mu, and the temporal hops
+        -P_- (x) U_t(x) to t+1 and -P_+ (x) U_t(x - t)^dagger to t-1, index spin*3 + colour.
+        M^ee keeps the spatial site, so the matrix is block diagonal over time lines."""
+        lx, ly, lz, lt = self.dims
+        n = lx * ly * lz * lt * 12
+        idx = np.arange(n).reshape(lt, lz, ly, lx, 12)
+        even = self.e3[..., 0, 0] > 0.5
+        diag = np.broadcast_to(self.mu * np.eye(12), (lt, lz, ly, lx, 12, 12)).copy()
+        if self.clover:
+            diag = diag + self.A
+        diag[~even] = np.eye(12)
+        ut = self.U[3]
+        fwd = -np.einsum("st,...ab->...satb", PT_MINUS, ut).reshape(ut.shape[:4] + (12, 12))
+        fwd[-1] *= self.b
+        ubk = np.roll(ut, 1, axis=0).conj().swapaxes(-1, -2)
+        bwd = -np.einsum("st,...ab->...satb", PT_PLUS, ubk).reshape(ut.shape[:4] + (12, 12))
+        bwd[0] *= self.b
+        rows, cols, vals = [], [], []
+        for blk, col_idx, mask in ((diag, idx, np.ones_like(even)),
+                                   (fwd, np.roll(idx, -1, axis=0), even),
+                                   (bwd, np.roll(idx, 1, axis=0), even)):
+            r = np.broadcast_to(idx[..., :, None], blk.shape)[mask]
+            c = np.broadcast_to(col_idx[..., None, :], blk.shape)[mask]
+            rows.append(r.ravel())
+            cols.append(c.ravel())
+            vals.append(blk[mask].ravel())
+        m = sp.csc_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                          shape=(n, n))
+        return spla.splu(m)
+
+    def Mee_inv(self, psi):
+        """(M^ee)^-1 on the even p3 sites."""
+        if self._mee is None:
+            self._mee = self._mee_factor()
+        out = self._mee.solve(np.ascontiguousarray((self.e3 * psi).ravel()))
+        return self.e3 * out.reshape(psi.shape)
+
+    def schur3d_S(self, psi):
+        """S_o = M^oo - M^oe (M^ee)^-1 M^eo on the odd p3 sites (blocks cut from M)."""
+        e, o = self.e3, self.o3
+        po = o * psi
+        return o * self.M(po) - o * self.M(e * self.Mee_inv(e * self.M(po)))
+
+    def tschur3d(self, psi):
+        """diag(1, C_L^o S_o C_R^o)."""
+        e, o = self.e3, self.o3
+        return e * psi + o * self.tmp.CL(self.schur3d_S(o * self.tmp.CR(o * psi)))
+
+    def tschur3d_SL(self, eta):
+        """((M^ee)^-1 eta_e,  C_L^o [eta_o - M^oe (M^ee)^-1 eta_e])."""
+        e, o = self.e3, self.o3
+        f = self.Mee_inv(e * eta)
+        return f + o * self.tmp.CL(o * eta - o * self.M(f))
+
+    def tschur3d_SR(self, y):
+        """(y_e - (M^ee)^-1 M^eo x_o,  x_o = C_R^o y_o)."""
+        e, o = self.e3, self.o3
+        xo = o * self.tmp.CR(o * y)
+        return e * y - self.Mee_inv(e * self.M(xo)) + xo
+
     # ---- scheme dispatch -------------------------------------------------------------
     def prec(self, scheme, psi):
         if scheme == "UNPREC":
@@ -169,6 +244,8 @@ class Operator:
             return self.temporal(psi)
         if scheme == "TEMPORAL_SCHUR":
             return self.tschur(psi)
+        if scheme == "TEMPORAL_SCHUR3D":
+            return self.tschur3d(psi)
         raise ValueError(scheme)
 
     def prec_dag(self, scheme, psi):
@@ -184,6 +261,8 @@ class Operator:
             return self.tmp.CL(eta)
         if scheme == "TEMPORAL_SCHUR":
             return self.tschur_SL(eta)
+        if scheme == "TEMPORAL_SCHUR3D":
+            return self.tschur3d_SL(eta)
         raise ValueError(scheme)
 
     def reconstruct(self, scheme, y):
@@ -195,16 +274,18 @@ class Operator:
             return self.tmp.CR(y)
         if scheme == "TEMPORAL_SCHUR":
             return self.tschur_SR(y)
+        if scheme == "TEMPORAL_SCHUR3D":
+            return self.tschur3d_SR(y)
         raise ValueError(scheme)
 
     def solve_subspace(self, scheme):
         """Mask of the sites the Krylov solver works on, and how the rest of y is fixed.
 
         SCHUR4D: Mt = diag(A+mu, S-hat): y_e = (A+mu)^-1 eta~_e, Krylov on odd p4 sites.
-        TEMPORAL_SCHUR, Wilson: Mt3 = diag(1, S_o): y_e = eta~_e, Krylov on odd p3 sites.
-        Otherwise: the whole lattice."""
+        TEMPORAL_SCHUR, Wilson, and TEMPORAL_SCHUR3D: Mt3 = diag(1, .): y_e = eta~_e,
+        Krylov on odd p3 sites.  Otherwise: the whole lattice."""
         if scheme == "SCHUR4D":
             return self.o4, lambda et: self.e4 * self.Amu_inv(self.e4 * et)
-        if scheme == "TEMPORAL_SCHUR" and not self.clover:
+        if (scheme == "TEMPORAL_SCHUR" and not self.clover) or scheme == "TEMPORAL_SCHUR3D":
             return self.o3, lambda et: self.e3 * et
         return None, None

@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-prof", action="store_true", help="no per-kernel events in the timed region")
     ap.add_argument("--schemes", action="store_true",
-                    help="only compare the four schemes in FP64 on the workload: BiCGStab iterations "
+                    help="only compare the schemes in FP64 on the workload: BiCGStab iterations "
                          "and time, CGNR iterations and the Lanczos condition number")
     ap.add_argument("--point-sources", action="store_true",
                     help="only time the 12 spin-colour point sources at the origin: one after "
@@ -130,7 +130,8 @@ def cpu_baseline(cfg, applies):
 def compare_schemes(args):
     """FP64 solves of the workload's Gaussian source with each scheme: BiCGStab (iterations,
     time) and CGNR with the Lanczos estimate of kappa(A^dagger A) of the preconditioned
-    operator.  One JSON line."""
+    operator, and the kernel groups of one more BiCGStab solve, timed per launch.  One JSON
+    line."""
     import torch
 
     import synth
@@ -143,7 +144,7 @@ def compare_schemes(args):
     op = Operator(torch.from_numpy(U).cuda(), cfg["m0"], xi, cfg["csw_s"] / xi, cfg["csw_t"], -1)
     del U
     out = {}
-    for scheme in ("UNPREC", "SCHUR4D", "TEMPORAL", "TEMPORAL_SCHUR"):
+    for scheme in ("UNPREC", "SCHUR4D", "TEMPORAL", "TEMPORAL_SCHUR", "TEMPORAL_SCHUR3D"):
         op.solve(eta, scheme=scheme, solver="BICGSTAB", prec="F64", tol=1e-10)  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -151,7 +152,14 @@ def compare_schemes(args):
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
         _, ic = op.solve(eta, scheme=scheme, solver="CGNR", prec="F64", tol=1e-10, estimate_kappa=True)
-        out[scheme] = {"bicgstab_iters": ib["iters"], "bicgstab_s": tb,
+        op.profile(True)
+        op.profile_reset()
+        op.solve(eta, scheme=scheme, solver="BICGSTAB", prec="F64", tol=1e-10)
+        groups = {k: {"launches": v["launches"], "ms": v["ms"],
+                      "GB_per_s": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None}
+                  for k, v in op.profile_stats().items() if v["launches"] > 0}
+        op.profile(False)
+        out[scheme] = {"bicgstab_iters": ib["iters"], "bicgstab_s": tb, "kernel_groups": groups,
                        "bicgstab_true_rel_resid": ib["true_rel_resid"], "cgnr_iters": ic["iters"],
                        "kappa": ic["kappa_est"], "lambda_min": ic["lambda_min"],
                        "lambda_max": ic["lambda_max"], "cgnr_true_rel_resid": ic["true_rel_resid"]}

@@ -66,8 +66,14 @@ enum {
   TP_UNPREC = 0,          /* M itself                                              */
   TP_SCHUR4D = 1,         /* 4D even-odd Schur: diag(A+mu, S-hat) with p4 parity  */
   TP_TEMPORAL = 2,        /* C_L M C_R  (eq:ContaminatedUnprec for clover)        */
-  TP_TEMPORAL_SCHUR = 3   /* S_L M S_R with p3 parity: eq:TPrecFull (Wilson),
+  TP_TEMPORAL_SCHUR = 3,  /* S_L M S_R with p3 parity: eq:TPrecFull (Wilson),
                              eq:TPrecPartial = 3D ILU (clover)                    */
+  TP_TEMPORAL_SCHUR3D = 4 /* temporal preconditioning combined with 3D-Schur
+                             (Sec. II.B, App. A): the even block M^ee = A + mu - D_t
+                             is inverted exactly, Mt = diag(1, C_L^o S_o C_R^o) with
+                             S_o = M^oo - M^oe (M^ee)^-1 M^eo.  F64 only; the first use
+                             on an operator factors M^ee (FP64, 2304 bytes per even
+                             site, kept until tp_op_destroy)                       */
 };
 
 enum { TP_CGNR = 0, TP_BICGSTAB = 1 };
@@ -145,18 +151,21 @@ tp_status tp_apply_CL(tp_op op, int32_t prec, void* dst, const void* src);
 tp_status tp_apply_CR(tp_op op, int32_t prec, void* dst, const void* src);
 /* The preconditioned operator Mt of `scheme` on the full lattice:
  *   UNPREC M; SCHUR4D diag(A+mu, (A+mu) - D_w^oe (A+mu)^-1 D_w^eo) in p4 parity;
- *   TEMPORAL C_L M C_R; TEMPORAL_SCHUR S_L M S_R in p3 parity. */
+ *   TEMPORAL C_L M C_R; TEMPORAL_SCHUR S_L M S_R in p3 parity; TEMPORAL_SCHUR3D
+ *   diag(1, C_L^o S_o C_R^o) in p3 parity. */
 tp_status tp_apply_prec(tp_op op, int32_t scheme, int32_t prec, void* dst, const void* src,
                         int32_t dagger);
 /* eta~ = S_L eta and x = S_R y, with M = S_L^-1 Mt S_R^-1 for `scheme`
- * (SCHUR4D: S_L = L^-1, S_R = U^-1 of the LDU factorisation, Sec. II.B). */
+ * (SCHUR4D: S_L = L^-1, S_R = U^-1 of the LDU factorisation, Sec. II.B;
+ * TEMPORAL_SCHUR3D: S_L = diag((M^ee)^-1, C_L^o) L^-1, S_R = U^-1 diag(1, C_R^o) with the
+ * p3 LDU factorisation). */
 tp_status tp_prepare_source(tp_op op, int32_t scheme, int32_t prec, void* eta_tilde,
                             const void* eta);
 tp_status tp_reconstruct(tp_op op, int32_t scheme, int32_t prec, void* x, const void* y);
 
 /* ---- solve ------------------------------------------------------------------------ */
 typedef struct {
-  int32_t scheme;          /* TP_UNPREC ... TP_TEMPORAL_SCHUR                       */
+  int32_t scheme;          /* TP_UNPREC ... TP_TEMPORAL_SCHUR3D                     */
   int32_t solver;          /* TP_CGNR or TP_BICGSTAB                                */
   int32_t prec;            /* inner precision: TP_F64, TP_F32, TP_F16N              */
   int32_t max_iter;        /* cap on inner Krylov iterations summed over restarts  */

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtprec.so")
 SOURCES = ["k_setup.hip", "k_site.hip", "k_line.hip", "k_line_f64.hip", "k_line_f32.hip",
-           "k_line_f16.hip", "k_blas.hip", "ops.cpp", "api.cpp"]
+           "k_line_f16.hip", "k_blas.hip", "k_schur3d.hip", "ops.cpp", "api.cpp"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = [

@@ -17,7 +17,8 @@ tp_status op_solve_multi(tp_op op, const tp_solve_params& P, int nr, Field& x64,
 
 const char* const kKernelNames[KID_COUNT] = {
     "pack_unpack", "site_p3",  "schur4d_eo_clover_inv", "schur4d_oe_clover", "line_scan",
-    "ilu_mid",     "hop_site", "blas",                  "reduce_finish",     "force"};
+    "ilu_mid",     "hop_site", "blas",                  "reduce_finish",     "force",
+    "schur3d_mee"};
 
 namespace {
 thread_local std::string g_last_error;
@@ -41,7 +42,7 @@ void check_prec(int prec) {
   if (prec != TP_F64 && prec != TP_F32 && prec != TP_F16N) TP_THROW(TP_EINVAL, "bad precision");
 }
 void check_scheme(int s) {
-  if (s < TP_UNPREC || s > TP_TEMPORAL_SCHUR) TP_THROW(TP_EINVAL, "bad scheme");
+  if (s < TP_UNPREC || s > TP_TEMPORAL_SCHUR3D) TP_THROW(TP_EINVAL, "bad scheme");
 }
 void need(const void* p, const char* what) {
   if (!p) TP_THROW(TP_EINVAL, std::string("null pointer: ") + what);
@@ -547,6 +548,7 @@ tp_status tp_op_destroy(tp_op op) {
     (void)hipSetDevice(op->g->ctx->device);
     (void)hipStreamSynchronize(op->g->ctx->stream);
     ws_free(op);
+    schur3d_free(op);
     dev_free(op->gclos);
     dev_free(op->gclos_f);
     dev_free(op->a4_mu);
@@ -615,6 +617,8 @@ tp_status tp_apply_prec(tp_op op, int32_t scheme, int32_t prec, void* dst, const
   return guard([&] {
     check_scheme(scheme);
     if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
+    if (scheme == TP_TEMPORAL_SCHUR3D && prec != TP_F64)
+      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64");
     tp_status s = apply_wrap(op, prec, dst, src, scheme_layout4(scheme), dagger != 0,
                              [&](Field& a, Field& b) { op_apply_prec(op, scheme, prec, a, b, false); });
     if (s != TP_OK) TP_THROW(s, g_last_error);
@@ -625,6 +629,8 @@ tp_status tp_prepare_source(tp_op op, int32_t scheme, int32_t prec, void* et, co
   return guard([&] {
     check_scheme(scheme);
     if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
+    if (scheme == TP_TEMPORAL_SCHUR3D && prec != TP_F64)
+      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64");
     tp_status s = apply_wrap(op, prec, et, eta, scheme_layout4(scheme), false,
                              [&](Field& a, Field& b) { op_prepare(op, scheme, prec, a, b); });
     if (s != TP_OK) TP_THROW(s, g_last_error);
@@ -635,6 +641,8 @@ tp_status tp_reconstruct(tp_op op, int32_t scheme, int32_t prec, void* x, const 
   return guard([&] {
     check_scheme(scheme);
     if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
+    if (scheme == TP_TEMPORAL_SCHUR3D && prec != TP_F64)
+      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64");
     tp_status s = apply_wrap(op, prec, x, y, scheme_layout4(scheme), false,
                              [&](Field& a, Field& b) { op_reconstruct(op, scheme, prec, a, b); });
     if (s != TP_OK) TP_THROW(s, g_last_error);
@@ -656,6 +664,8 @@ tp_status tp_solve(tp_op op, const tp_solve_params* params, void* x, const void*
     check_prec(P.prec);
     if (P.solver != TP_CGNR && P.solver != TP_BICGSTAB) TP_THROW(TP_EINVAL, "bad solver");
     if (P.scheme == TP_SCHUR4D && P.prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
+    if (P.scheme == TP_TEMPORAL_SCHUR3D && P.prec != TP_F64)
+      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64");
     if (!(P.tol >= 0) || !(P.inner_tol >= 0)) TP_THROW(TP_EINVAL, "tolerances");
     tp_ctx ctx = op->g->ctx;
     set_device(ctx);
@@ -699,6 +709,8 @@ tp_status tp_solve_multi(tp_op op, const tp_solve_params* params, int32_t nrhs, 
     check_prec(P.prec);
     if (P.solver != TP_CGNR && P.solver != TP_BICGSTAB) TP_THROW(TP_EINVAL, "bad solver");
     if (P.scheme == TP_SCHUR4D && P.prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
+    if (P.scheme == TP_TEMPORAL_SCHUR3D && P.prec != TP_F64)
+      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64");
     if (!(P.tol >= 0) || !(P.inner_tol >= 0)) TP_THROW(TP_EINVAL, "tolerances");
     tp_ctx ctx = op->g->ctx;
     set_device(ctx);

@@ -15,6 +15,12 @@
 //                     chi_o = psi_o + C_L^o v                      (scan)
 //                   which is the appendix's ILU sequence with t1 = C_L u, t2 = C_L y,
 //                   C_R(t2 - t1) = C_R C_L (y - u) and the Dbar/Abar products expanded.
+//   TEMPORAL_SCHUR3D  p3 parity with the even block inverted exactly (temporal
+//                   preconditioning combined with 3D-Schur):
+//                     Mt = diag(1, C_L^o S_o C_R^o),  S_o = M^oo - M^oe (M^ee)^-1 M^eo,
+//                   applied as a_o = C_R^o psi_o, u = D_s^eo a_o, f = (M^ee)^-1 u,
+//                   v = A^oo a_o - D_s^oe f / gamma_f^2, chi_o = psi_o + C_L^o v
+//                   (M^oo = C_L^-1 C_R^-1 + A^oo on odd sites); FP64.
 // All p3 operators act in the axial gauge (interior time links = 1), see k_line_impl.h.
 #include <math.h>
 #include <stdio.h>
@@ -53,6 +59,12 @@ void ws_free(tp_op op) {
 
 bool scheme_layout4(int scheme) { return scheme == TP_SCHUR4D; }
 
+// Schemes whose even block is solved directly, so the Krylov solver runs on the odd sites.
+bool scheme_sub(tp_op op, int scheme) {
+  return scheme == TP_SCHUR4D || (scheme == TP_TEMPORAL_SCHUR && !op->c) ||
+         scheme == TP_TEMPORAL_SCHUR3D;
+}
+
 namespace {
 
 // workspace slot numbers
@@ -60,7 +72,8 @@ enum {
   W_T1 = 0, W_T2, W_T3, W_T4, W_G5A, W_G5B, W_PREP, W_PREP2,
   // solver vectors
   W_R = 16, W_RHAT, W_P, W_V, W_S, W_T, W_X, W_B, W_Y, W_Z, W_D,
-  W_X64 = 40, W_R64, W_ETA64, W_TMP64
+  W_X64 = 40, W_R64, W_ETA64, W_TMP64,
+  W_S3W = 48, W_S3F
 };
 
 BlasArgs cplx(double ar, double ai, double br = 0, double bi = 0, double cr = 0, double ci = 0) {
@@ -121,6 +134,26 @@ void ilu_full(tp_op op, int prec, const Field& src, Field& dst) {
   launch_line(op, prec, LM_CL, 1, lio(&v, &src), dst);                      // chi_o
 }
 
+// C_L^o S_o C_R^o on the odd p3 parity (FP64):
+//   dst_o = src_o + C_L^o [A^oo a_o - D_s^oe (M^ee)^-1 D_s^eo a_o / gamma_f^2],  a_o = C_R^o src_o
+void schur3d_so_odd(tp_op op, int prec, const Field& src, Field& dst) {
+  Field& aup = ws_get(op, prec, W_T1);
+  Field& u = ws_get(op, prec, W_T2);
+  Field& f = ws_get(op, prec, W_T3);
+  Field& v = ws_get(op, prec, W_T4);
+  launch_line(op, prec, LM_CR, 1, lio(&src, nullptr, false), aup);          // a_o upper
+  launch_site(op, prec, sio_nb(&aup, &src), u, SiteCoef{0, 0, 0, 1.0, 0}, 0, 0, 1, false);
+  launch_mee_inv(op, u, f, ws_get(op, TP_F64, W_S3W));
+  SiteIO io3;
+  io3.self_up = &aup;
+  io3.self_lo = &src;
+  io3.nb_up = io3.nb_lo = &f;
+  const double ig2 = 1.0 / (op->gf * op->gf);
+  launch_site(op, prec, io3, v, SiteCoef{0, op->c ? 1.0 : 0.0, 0, -ig2, 0}, op->c ? 1 : 0, 1, 1,
+              false);
+  launch_line(op, prec, LM_CL, 1, lio(&v, &src), dst);                      // chi_o
+}
+
 void temporal_full(tp_op op, int prec, const Field& src, Field& dst) {
   // C_L M C_R = 1 + C_L (A - D_s / gamma_f) C_R
   Field& a = ws_get(op, prec, W_T1);
@@ -165,6 +198,10 @@ void prec_noalias(tp_op op, int scheme, int prec, const Field& src, Field& dst) 
         blas(op->g->ctx, B_COPY, 0, 1, {&src, &dst});
       }
       break;
+    case TP_TEMPORAL_SCHUR3D:
+      schur3d_so_odd(op, prec, src, dst);
+      blas(op->g->ctx, B_COPY, 0, 1, {&src, &dst});
+      break;
     default:
       TP_THROW(TP_EINVAL, "unknown scheme");
   }
@@ -197,6 +234,7 @@ struct KrylovOp {
     }
     if (npar == 1) {
       if (scheme == TP_SCHUR4D) schur4d_odd(op, prec, *in, *out);
+      else if (scheme == TP_TEMPORAL_SCHUR3D) schur3d_so_odd(op, prec, *in, *out);
       else wilson_so_odd(op, prec, *in, *out);
     } else {
       prec_noalias(op, scheme, prec, *in, *out);
@@ -263,6 +301,16 @@ void op_prepare(tp_op op, int scheme, int prec, const Field& eta, Field& et) {
       launch_line(op, prec, LM_CL, 1, lio(&v), et);
       break;
     }
+    case TP_TEMPORAL_SCHUR3D: {
+      // eta~_e = (M^ee)^-1 eta_e ; eta~_o = C_L^o [eta_o + D_s^oe eta~_e / gamma_f]
+      Field& v = ws_get(op, prec, W_PREP);
+      launch_mee_inv(op, eta, et, ws_get(op, TP_F64, W_S3W));
+      SiteIO io = sio_nb(&et, &et);
+      io.in2 = &eta;
+      launch_site(op, prec, io, v, SiteCoef{0, 0, 0, 1.0 / op->gf, 1.0}, 0, 1, 1, false);
+      launch_line(op, prec, LM_CL, 1, lio(&v), et);
+      break;
+    }
     default:
       TP_THROW(TP_EINVAL, "unknown scheme");
   }
@@ -294,6 +342,17 @@ void op_reconstruct(tp_op op, int scheme, int prec, const Field& y, Field& x) {
       launch_site(op, prec, sio_nb(&x, &x), v, SiteCoef{0, 0, 0, 1.0 / op->gf, 0}, 0, 0, 1, false);
       launch_line(op, prec, LM_CL, 0, lio(&v, &y), t);
       launch_line(op, prec, LM_CR, 0, lio(&t), x);
+      break;
+    }
+    case TP_TEMPORAL_SCHUR3D: {
+      // x_o = C_R^o y_o ; x_e = y_e + (M^ee)^-1 D_s^eo x_o / gamma_f
+      Field& t = ws_get(op, prec, W_PREP);
+      Field& f = ws_get(op, prec, W_S3F);
+      launch_line(op, prec, LM_CR, 1, lio(&y), x);
+      launch_site(op, prec, sio_nb(&x, &x), t, SiteCoef{0, 0, 0, 1.0 / op->gf, 0}, 0, 0, 1, false);
+      launch_mee_inv(op, t, f, ws_get(op, TP_F64, W_S3W));
+      blas(ctx, B_COPY, 0, 1, {&y, &x});
+      blas(ctx, B_AXPY, 0, 1, {&f, &x}, cplx(1, 0));
       break;
     }
     default:
@@ -671,7 +730,7 @@ tp_status op_solve(tp_op op, const tp_solve_params& P, Field& x64, const Field& 
   int max_iter = P.max_iter > 0 ? P.max_iter : 100000;
   int max_restarts = P.max_restarts > 0 ? P.max_restarts : 50;
   KrylovOp A{op, P.scheme, pr, 0, 2};
-  bool sub = (P.scheme == TP_SCHUR4D) || (P.scheme == TP_TEMPORAL_SCHUR && !op->c);
+  bool sub = scheme_sub(op, P.scheme);
   if (sub) {
     A.par0 = 1;
     A.npar = 1;
@@ -762,7 +821,7 @@ tp_status op_solve_multi(tp_op op, const tp_solve_params& P, int nr, Field& x64,
   tp_ctx ctx = op->g->ctx;
   auto t0 = std::chrono::steady_clock::now();
   const bool l4 = scheme_layout4(P.scheme);
-  const bool sub = (P.scheme == TP_SCHUR4D) || (P.scheme == TP_TEMPORAL_SCHUR && !op->c);
+  const bool sub = scheme_sub(op, P.scheme);
   const int pr = P.prec;
   tp_status worst = TP_OK;
   auto merge = [&](tp_status st) {

@@ -5,8 +5,9 @@ benchmark uses, against the oracle evaluated at sampled sites and time lines
 * M (every precision) at 48 sampled sites, T^-1 and T^dagger^-1 on 8 sampled time lines;
 * the preconditioned operators: S_L M S_R y against prepare(M(reconstruct(y))) and
   gamma5-hermiticity, at the full shape;
-* the benchmark solve (temporal+3D-ILU, mixed FP32): the oracle's residual at sampled
-  sites is bounded by the library's FP64 true residual, which must be <= 1e-10;
+* the benchmark solve (temporal+3D-ILU, mixed FP32) and the exact temporal+3D-Schur FP64
+  solve: the oracle's residual at sampled sites is bounded by the library's FP64 true
+  residual, which must be <= 1e-10;
 * 24^3x128: the 12 spin-colour point sources at the origin, FP32 and FP16+norm inner
   solves, each to 1e-10, one at a time and as one batch, against the FP64 even-odd
   solution;
@@ -82,7 +83,7 @@ def test_Tinv_sampled_lines(big, prec, dagger):
     assert _rel(got, ref) < TOL[prec], (b["name"], prec, _rel(got, ref))
 
 
-@pytest.mark.parametrize("scheme", ["TEMPORAL", "TEMPORAL_SCHUR"])
+@pytest.mark.parametrize("scheme", ["TEMPORAL", "TEMPORAL_SCHUR", "TEMPORAL_SCHUR3D"])
 def test_prec_is_SL_M_SR(big, scheme):
     """The fused preconditioned apply equals the composition of the separately
     parity-checked maps: S_L M S_R y = prepare(M(reconstruct(y)))."""
@@ -91,11 +92,13 @@ def test_prec_is_SL_M_SR(big, scheme):
     a = _np(g.apply_prec(y, scheme, "F64"))
     c = _np(g.prepare_source(g.apply_M(g.reconstruct(y, scheme, "F64"), "F64"), scheme, "F64"))
     assert _rel(a, c) < 1e-12
+    if scheme == "TEMPORAL_SCHUR3D":
+        return  # F64 only
     a32 = _np(g.apply_prec(y, scheme, "F32"))
     assert _rel(a32, c) < 2e-5
 
 
-@pytest.mark.parametrize("scheme", ["TEMPORAL_SCHUR", "SCHUR4D"])
+@pytest.mark.parametrize("scheme", ["TEMPORAL_SCHUR", "SCHUR4D", "TEMPORAL_SCHUR3D"])
 def test_prec_gamma5_hermiticity(big, scheme):
     g = big["gop"]
     phi = torch.from_numpy(synth.make_source(big["dims"], 2003)).cuda()
@@ -109,6 +112,18 @@ def test_bench_solve_residual_sampled(big):
     """The benchmark's solve; the oracle's residual on 48 sites cannot exceed the global one."""
     b = big
     x, info = b["gop"].solve(b["teta"], scheme="TEMPORAL_SCHUR", prec="F32", tol=1e-10)
+    assert info["true_rel_resid"] <= 1e-10, info
+    xs = _np(x)
+    r = _at(b["eta"], b["sites"]) - sampled.M_at_sites(b["U"], xs, b["sites"], b["m0"], b["xi"], -1.0,
+                                                      b["c_s"], b["c_t"])
+    assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(b["eta"]), (np.linalg.norm(r), info)
+
+
+def test_schur3d_solve_residual_sampled(big):
+    """The exact 3D-Schur scheme's FP64 solve; the oracle's residual on 48 sites cannot exceed
+    the global one."""
+    b = big
+    x, info = b["gop"].solve(b["teta"], scheme="TEMPORAL_SCHUR3D", prec="F64", tol=1e-10)
     assert info["true_rel_resid"] <= 1e-10, info
     xs = _np(x)
     r = _at(b["eta"], b["sites"]) - sampled.M_at_sites(b["U"], xs, b["sites"], b["m0"], b["xi"], -1.0,

@@ -135,6 +135,8 @@ def test_point_source_reduced_precision(case, prec):
 def test_apply_prec(case, scheme, prec):
     if scheme == "SCHUR4D" and prec == "F16N":
         pytest.skip("the 4D Schur baseline runs in F64/F32")
+    if scheme == "TEMPORAL_SCHUR3D" and prec != "F64":
+        pytest.skip("the exact even-block inverse runs in F64")
     o, g = case["oop"], case["gop"]
     e, te = case["eta"], case["teta"]
     tol = TOL[prec][1]
@@ -349,3 +351,23 @@ def test_site_kernels_in_tile_order(dims):
                    f"TEMPORAL_SCHUR {prec}")
     finally:
         gop.close()
+
+
+@pytest.mark.parametrize("prec", ["F32", "F16N"])
+def test_schur3d_rejects_reduced_precision(case, prec):
+    from paper_0910_0992_amd._lib import TprecError
+    g = case["gop"]
+    with pytest.raises(TprecError, match="F64"):
+        g.apply_prec(case["teta"], "TEMPORAL_SCHUR3D", prec)
+    with pytest.raises(TprecError, match="F64"):
+        g.solve(case["teta"], scheme="TEMPORAL_SCHUR3D", prec=prec, tol=1e-10)
+
+
+def test_schur3d_even_block_inverse(case):
+    """The even half of the prepared source is (M^ee)^-1 eta_e: M^ee applied to it (the even
+    block of M, from the separately checked M apply) returns eta_e."""
+    o, g = case["oop"], case["gop"]
+    e = o.e3
+    f = _np(g.prepare_source(case["teta"], "TEMPORAL_SCHUR3D", "F64"))
+    back = _np(g.apply_M(torch.from_numpy(e * f).cuda(), "F64"))
+    _close(e * back, e * case["eta"], 1e-12, "M^ee (M^ee)^-1 eta_e")

@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--schemes", action="store_true",
                     help="only compare the schemes in FP64 on the workload: BiCGStab iterations "
                          "and time, CGNR iterations and the Lanczos condition number")
+    ap.add_argument("--only", default=None,
+                    help="with --schemes: a comma-separated subset of the schemes")
     ap.add_argument("--point-sources", action="store_true",
                     help="only time the 12 spin-colour point sources at the origin: one after "
                          "another, as one batch, and with FP64 even-odd")
@@ -144,7 +146,10 @@ def compare_schemes(args):
     op = Operator(torch.from_numpy(U).cuda(), cfg["m0"], xi, cfg["csw_s"] / xi, cfg["csw_t"], -1)
     del U
     out = {}
-    for scheme in ("UNPREC", "SCHUR4D", "TEMPORAL", "TEMPORAL_SCHUR", "TEMPORAL_SCHUR3D"):
+    schemes = ("UNPREC", "SCHUR4D", "TEMPORAL", "TEMPORAL_SCHUR", "TEMPORAL_SCHUR3D")
+    if args.only:
+        schemes = tuple(s.strip().upper() for s in args.only.split(","))
+    for scheme in schemes:
         op.solve(eta, scheme=scheme, solver="BICGSTAB", prec="F64", tol=1e-10)  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -164,6 +164,17 @@ def compare_schemes(args):
                       "GB_per_s": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None}
                   for k, v in op.profile_stats().items() if v["launches"] > 0}
         op.profile(False)
+        if scheme == "TEMPORAL_SCHUR3D":
+            # its production form: FP32 inner BiCGStab with FP64 reliable updates
+            op.solve(eta, scheme=scheme, prec="F32", tol=1e-10)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, im = op.solve(eta, scheme=scheme, prec="F32", tol=1e-10)
+            torch.cuda.synchronize()
+            groups["mixed_f32"] = {"s": time.perf_counter() - t0, "iters": im["iters"],
+                                   "true_rel_resid": im["true_rel_resid"]}
+            print(f"[bench] {scheme} mixed F32: {im['iters']} its {groups['mixed_f32']['s']:.3f} s",
+                  file=sys.stderr, flush=True)
         out[scheme] = {"bicgstab_iters": ib["iters"], "bicgstab_s": tb, "kernel_groups": groups,
                        "bicgstab_true_rel_resid": ib["true_rel_resid"], "cgnr_iters": ic["iters"],
                        "kappa": ic["kappa_est"], "lambda_min": ic["lambda_min"],

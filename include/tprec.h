@@ -71,9 +71,10 @@ enum {
   TP_TEMPORAL_SCHUR3D = 4 /* temporal preconditioning combined with 3D-Schur
                              (Sec. II.B, App. A): the even block M^ee = A + mu - D_t
                              is inverted exactly, Mt = diag(1, C_L^o S_o C_R^o) with
-                             S_o = M^oo - M^oe (M^ee)^-1 M^eo.  F64 only; the first use
-                             on an operator factors M^ee (FP64, 2304 bytes per even
-                             site, kept until tp_op_destroy)                       */
+                             S_o = M^oo - M^oe (M^ee)^-1 M^eo.  F64 and F32 (not
+                             F16N); the first use on an operator factors M^ee (FP64,
+                             2304 bytes per even site, plus an FP32 copy of 1152 bytes
+                             on the first F32 use, kept until tp_op_destroy)       */
 };
 
 enum { TP_CGNR = 0, TP_BICGSTAB = 1 };

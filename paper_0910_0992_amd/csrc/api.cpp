@@ -617,8 +617,8 @@ tp_status tp_apply_prec(tp_op op, int32_t scheme, int32_t prec, void* dst, const
   return guard([&] {
     check_scheme(scheme);
     if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
-    if (scheme == TP_TEMPORAL_SCHUR3D && prec != TP_F64)
-      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64");
+    if (scheme == TP_TEMPORAL_SCHUR3D && prec == TP_F16N)
+      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
     tp_status s = apply_wrap(op, prec, dst, src, scheme_layout4(scheme), dagger != 0,
                              [&](Field& a, Field& b) { op_apply_prec(op, scheme, prec, a, b, false); });
     if (s != TP_OK) TP_THROW(s, g_last_error);
@@ -629,8 +629,8 @@ tp_status tp_prepare_source(tp_op op, int32_t scheme, int32_t prec, void* et, co
   return guard([&] {
     check_scheme(scheme);
     if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
-    if (scheme == TP_TEMPORAL_SCHUR3D && prec != TP_F64)
-      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64");
+    if (scheme == TP_TEMPORAL_SCHUR3D && prec == TP_F16N)
+      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
     tp_status s = apply_wrap(op, prec, et, eta, scheme_layout4(scheme), false,
                              [&](Field& a, Field& b) { op_prepare(op, scheme, prec, a, b); });
     if (s != TP_OK) TP_THROW(s, g_last_error);
@@ -641,8 +641,8 @@ tp_status tp_reconstruct(tp_op op, int32_t scheme, int32_t prec, void* x, const 
   return guard([&] {
     check_scheme(scheme);
     if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
-    if (scheme == TP_TEMPORAL_SCHUR3D && prec != TP_F64)
-      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64");
+    if (scheme == TP_TEMPORAL_SCHUR3D && prec == TP_F16N)
+      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
     tp_status s = apply_wrap(op, prec, x, y, scheme_layout4(scheme), false,
                              [&](Field& a, Field& b) { op_reconstruct(op, scheme, prec, a, b); });
     if (s != TP_OK) TP_THROW(s, g_last_error);
@@ -664,8 +664,8 @@ tp_status tp_solve(tp_op op, const tp_solve_params* params, void* x, const void*
     check_prec(P.prec);
     if (P.solver != TP_CGNR && P.solver != TP_BICGSTAB) TP_THROW(TP_EINVAL, "bad solver");
     if (P.scheme == TP_SCHUR4D && P.prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
-    if (P.scheme == TP_TEMPORAL_SCHUR3D && P.prec != TP_F64)
-      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64");
+    if (P.scheme == TP_TEMPORAL_SCHUR3D && P.prec == TP_F16N)
+      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
     if (!(P.tol >= 0) || !(P.inner_tol >= 0)) TP_THROW(TP_EINVAL, "tolerances");
     tp_ctx ctx = op->g->ctx;
     set_device(ctx);
@@ -709,8 +709,8 @@ tp_status tp_solve_multi(tp_op op, const tp_solve_params* params, int32_t nrhs, 
     check_prec(P.prec);
     if (P.solver != TP_CGNR && P.solver != TP_BICGSTAB) TP_THROW(TP_EINVAL, "bad solver");
     if (P.scheme == TP_SCHUR4D && P.prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
-    if (P.scheme == TP_TEMPORAL_SCHUR3D && P.prec != TP_F64)
-      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64");
+    if (P.scheme == TP_TEMPORAL_SCHUR3D && P.prec == TP_F16N)
+      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
     if (!(P.tol >= 0) || !(P.inner_tol >= 0)) TP_THROW(TP_EINVAL, "tolerances");
     tp_ctx ctx = op->g->ctx;
     set_device(ctx);

@@ -195,46 +195,46 @@ __device__ SweepLane sweep_lane() {
   return q;
 }
 
-// Row r of an even-parity FP64 spinor field: half r / 6, component r % 6.
-__device__ const double2* row_plane(const double2* up, const double2* lo, int64_t V2, int r) {
-  return (r < 6 ? up : lo) + (int64_t)(r < 6 ? r : r - 6) * V2;
-}
-__device__ double2* row_plane(double2* up, double2* lo, int64_t V2, int r) {
-  return (r < 6 ? up : lo) + (int64_t)(r < 6 ? r : r - 6) * V2;
+// Element (row r, site i) of an even-parity spinor field of storage T: half r / 6,
+// component r % 6 (FP32 planes are paired).
+template <typename T>
+__device__ int64_t row_off(int r, int64_t V2, int64_t i) {
+  return comp_off<T>(r < 6 ? r : r - 6, 6, V2, i);
 }
 
-// Forward sweep: w(t) = S(t)^-1 (eta(t) + P_+ w(t-1) + c(beta)(t)).
-// eta: even-parity planes, or null for eta = 0.  beta per line: K q when kmat is given,
+// Forward sweep: w(t) = S(t)^-1 (eta(t) + P_+ w(t-1) + c(beta)(t)), storage T (double2:
+// FP64; float2: FP32 factors and spinors, FP32 arithmetic).
+// eta: even-parity halves, or null for eta = 0.  beta per line: K q when kmat is given,
 // the unit vector `unit` when unit >= 0, else no corner term.
-// link_t: planes [9][V2] of the even-parity axial time links (P at t = Lt-1).
-__global__ __launch_bounds__(64) void k_s3_forward(const double2* __restrict__ eta_up,
-                                                   const double2* __restrict__ eta_lo,
-                                                   int64_t V2, Geom g,
-                                                   const double2* __restrict__ sinv,
+// link_t: FP64 planes [9][V2] of the even-parity axial time links (P at t = Lt-1).
+template <typename T>
+__global__ __launch_bounds__(64) void k_s3_forward(const T* __restrict__ eta_up,
+                                                   const T* __restrict__ eta_lo, int64_t V2,
+                                                   Geom g, const T* __restrict__ sinv,
                                                    const double2* __restrict__ link_t,
-                                                   const double2* __restrict__ kmat,
-                                                   const double2* __restrict__ q, int unit,
-                                                   double2* __restrict__ w_up,
-                                                   double2* __restrict__ w_lo) {
-  __shared__ cx<double> zb[4][12];
-  __shared__ cx<double> db[4][12];
+                                                   const T* __restrict__ kmat,
+                                                   const T* __restrict__ q, int unit,
+                                                   T* __restrict__ w_up, T* __restrict__ w_lo) {
+  using R = typename Prec<T>::R;
+  __shared__ cx<R> zb[4][12];
+  __shared__ cx<R> db[4][12];
   const SweepLane ln = sweep_lane();
   const bool corner = kmat != nullptr || unit >= 0;
   if (ln.active && corner) {
-    cx<double> d = czero<double>();
+    cx<R> d = czero<R>();
     if (kmat) {
-      const double2* kr = kmat + (int64_t)ln.s * 144 + ln.r * 12;
-      const double2* qs = q + (int64_t)ln.s * 12;
+      const T* kr = kmat + (int64_t)ln.s * 144 + ln.r * 12;
+      const T* qs = q + (int64_t)ln.s * 12;
 #pragma unroll
-      for (int c = 0; c < 12; ++c) d += cmul(cx<double>{kr[c].x, kr[c].y}, cx<double>{qs[c].x, qs[c].y});
+      for (int c = 0; c < 12; ++c) d += cmul(ld<R, T>(kr + c), ld<R, T>(qs + c));
     } else if (ln.r == unit) {
-      d = cx<double>{1.0, 0.0};
+      d = cx<R>{R(1), R(0)};
     }
     db[ln.l][ln.r] = d;
   }
   __syncthreads();
   // this lane's corner term: rows 0-5 at t = 0, rows 6-11 at t = Lt-1
-  cx<double> corr = czero<double>();
+  cx<R> corr = czero<R>();
   if (ln.active && corner) {
     const int64_t ib = p3_idx(g, g.Lt - 1, ln.s);
     const int rr = ln.r < 6 ? ln.r : ln.r - 6;
@@ -243,23 +243,23 @@ __global__ __launch_bounds__(64) void k_s3_forward(const double2* __restrict__ e
     for (int b = 0; b < 3; ++b) {
       if (ln.r < 6) {
         double2 u = link_t[(int64_t)(b * 3 + a) * V2 + ib];  // (P^dag)_{ab} = conj(P_{ba})
-        corr += cmulc(cx<double>{u.x, u.y}, db[ln.l][sp * 3 + b]);
+        corr += cmulc(cx<R>{R(u.x), R(u.y)}, db[ln.l][sp * 3 + b]);
       } else {
         double2 u = link_t[(int64_t)(a * 3 + b) * V2 + ib];
-        corr += cmul(cx<double>{u.x, u.y}, db[ln.l][6 + sp * 3 + b]);
+        corr += cmul(cx<R>{R(u.x), R(u.y)}, db[ln.l][6 + sp * 3 + b]);
       }
     }
   }
-  const double2* ep = ln.active && eta_up ? row_plane(eta_up, eta_lo, V2, ln.r) : nullptr;
-  double2* wp = ln.active ? row_plane(w_up, w_lo, V2, ln.r) : nullptr;
-  const double2* sbase = sinv + (int64_t)ln.tile * g.Lt * 576 + ln.lane;
-  cx<double> wprev = czero<double>();
+  const T* ep = ln.active && eta_up ? (ln.r < 6 ? eta_up : eta_lo) : nullptr;
+  T* wp = ln.active ? (ln.r < 6 ? w_up : w_lo) : nullptr;
+  const T* sbase = sinv + (int64_t)ln.tile * g.Lt * 576 + ln.lane;
+  cx<R> wprev = czero<R>();
 #pragma unroll 1
   for (int t = 0; t < g.Lt; ++t) {
     const int64_t i = p3_idx(g, t, ln.s);
     if (ln.active) {
-      cx<double> z = czero<double>();
-      if (ep) z = cx<double>{ep[i].x, ep[i].y};
+      cx<R> z = czero<R>();
+      if (ep) z = ld<R, T>(ep + row_off<T>(ln.r, V2, i));
       if (ln.r < 6) {
         z += wprev;
         if (t == 0) z += corr;
@@ -270,14 +270,11 @@ __global__ __launch_bounds__(64) void k_s3_forward(const double2* __restrict__ e
     }
     __syncthreads();
     if (ln.active) {
-      const double2* sc = sbase + (int64_t)t * 576;
-      cx<double> w = czero<double>();
+      const T* sc = sbase + (int64_t)t * 576;
+      cx<R> w = czero<R>();
 #pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        double2 e = sc[c * 48];
-        w += cmul(cx<double>{e.x, e.y}, zb[ln.l][c]);
-      }
-      wp[i] = make_double2(w.re, w.im);
+      for (int c = 0; c < 12; ++c) w += cmul(ld<R, T>(sc + c * 48), zb[ln.l][c]);
+      st(wp + row_off<T>(ln.r, V2, i), w);
       wprev = w;
     }
     __syncthreads();
@@ -286,42 +283,44 @@ __global__ __launch_bounds__(64) void k_s3_forward(const double2* __restrict__ e
 
 // Backward sweep: x(t) = w(t) + S(t)^-1 P_- x(t+1).  x (optional) receives the solution;
 // qout (optional) receives W^dag x = (rows 0-5 of x(Lt-1), rows 6-11 of x(0)) per line.
-__global__ __launch_bounds__(64) void k_s3_backward(const double2* __restrict__ w_up,
-                                                    const double2* __restrict__ w_lo,
-                                                    int64_t V2, Geom g,
-                                                    const double2* __restrict__ sinv,
-                                                    double2* __restrict__ x_up,
-                                                    double2* __restrict__ x_lo,
-                                                    double2* __restrict__ qout) {
-  __shared__ cx<double> xb[4][12];
+template <typename T>
+__global__ __launch_bounds__(64) void k_s3_backward(const T* __restrict__ w_up,
+                                                    const T* __restrict__ w_lo, int64_t V2,
+                                                    Geom g, const T* __restrict__ sinv,
+                                                    T* __restrict__ x_up, T* __restrict__ x_lo,
+                                                    T* __restrict__ qout) {
+  using R = typename Prec<T>::R;
+  __shared__ cx<R> xb[4][12];
   const SweepLane ln = sweep_lane();
-  const double2* wp = ln.active ? row_plane(w_up, w_lo, V2, ln.r) : nullptr;
-  double2* xp = ln.active && x_up ? row_plane(x_up, x_lo, V2, ln.r) : nullptr;
-  const double2* sbase = sinv + (int64_t)ln.tile * g.Lt * 576 + ln.lane;
+  const T* wp = ln.active ? (ln.r < 6 ? w_up : w_lo) : nullptr;
+  T* xp = ln.active && x_up ? (ln.r < 6 ? x_up : x_lo) : nullptr;
+  const T* sbase = sinv + (int64_t)ln.tile * g.Lt * 576 + ln.lane;
 #pragma unroll 1
   for (int t = g.Lt - 1; t >= 0; --t) {
     const int64_t i = p3_idx(g, t, ln.s);
-    cx<double> x = czero<double>();
+    cx<R> x = czero<R>();
     if (ln.active) {
-      x = cx<double>{wp[i].x, wp[i].y};
+      x = ld<R, T>(wp + row_off<T>(ln.r, V2, i));
       if (t < g.Lt - 1) {
-        const double2* sc = sbase + (int64_t)t * 576;
+        const T* sc = sbase + (int64_t)t * 576;
 #pragma unroll
-        for (int c = 6; c < 12; ++c) {
-          double2 e = sc[c * 48];
-          x += cmul(cx<double>{e.x, e.y}, xb[ln.l][c]);
-        }
+        for (int c = 6; c < 12; ++c) x += cmul(ld<R, T>(sc + c * 48), xb[ln.l][c]);
       }
     }
     __syncthreads();  // every lane has read x(t+1)
     if (ln.active) {
       if (ln.r >= 6) xb[ln.l][ln.r] = x;
-      if (xp) xp[i] = make_double2(x.re, x.im);
+      if (xp) st(xp + row_off<T>(ln.r, V2, i), x);
       if (qout && ((t == g.Lt - 1 && ln.r < 6) || (t == 0 && ln.r >= 6)))
-        qout[(int64_t)ln.s * 12 + ln.r] = make_double2(x.re, x.im);
+        st(qout + (int64_t)ln.s * 12 + ln.r, x);
     }
     __syncthreads();
   }
+}
+
+__global__ void k_s3_round(const double2* __restrict__ src, float2* __restrict__ dst, int64_t n) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) dst[k] = make_float2(float(src[k].x), float(src[k].y));
 }
 
 size_t factor_lds() { return size_t(kFacThreads) * (180 * sizeof(double2) + 12 * sizeof(int)); }
@@ -354,11 +353,14 @@ void schur3d_setup(tp_op op) {
     const double2* link_t = op->g->u3_d + (int64_t)(3 * 2 + 0) * 9 * L.V2;
     SpinorF<double2> wf = w.par<double2>(0);
     for (int j = 0; j < 12; ++j) {
-      hipLaunchKernelGGL(k_s3_forward, dim3(nlines / 4), dim3(64), 0, ctx->stream, nullptr,
-                         nullptr, L.V2, L.g, sinv, link_t, nullptr, nullptr, j, wf.p[0], wf.p[1]);
+      hipLaunchKernelGGL(k_s3_forward<double2>, dim3(nlines / 4), dim3(64), 0, ctx->stream,
+                         (const double2*)nullptr, (const double2*)nullptr, L.V2, L.g,
+                         (const double2*)sinv, link_t, (const double2*)nullptr,
+                         (const double2*)nullptr, j, wf.p[0], wf.p[1]);
       LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_s3_backward, dim3(nlines / 4), dim3(64), 0, ctx->stream, wf.p[0],
-                         wf.p[1], L.V2, L.g, sinv, nullptr, nullptr,
+      hipLaunchKernelGGL(k_s3_backward<double2>, dim3(nlines / 4), dim3(64), 0, ctx->stream,
+                         (const double2*)wf.p[0], (const double2*)wf.p[1], L.V2, L.g,
+                         (const double2*)sinv, (double2*)nullptr, (double2*)nullptr,
                          qbuf + (int64_t)j * nlines * 12);
       LAUNCH_CHECK();
     }
@@ -385,42 +387,96 @@ void schur3d_setup(tp_op op) {
   op->s3_q = qbuf;  // the first 12 complex per line serve the applies
 }
 
+// FP32 copies of the factors for the FP32 operator (rounded from the FP64 factorisation).
+void schur3d_setup_f32(tp_op op) {
+  schur3d_setup(op);
+  if (op->s3_inv_f) return;
+  tp_ctx ctx = op->g->ctx;
+  const Lattice& L = ctx->lat;
+  const int64_t ni = L.V2 * 144, nk = int64_t(L.Vs2) * 144;
+  float2* fi = static_cast<float2*>(dev_alloc(size_t(ni) * sizeof(float2)));
+  float2* fk = nullptr;
+  float2* fq = nullptr;
+  try {
+    fk = static_cast<float2*>(dev_alloc(size_t(nk) * sizeof(float2)));
+    fq = static_cast<float2*>(dev_alloc(size_t(L.Vs2) * 12 * sizeof(float2)));
+    hipLaunchKernelGGL(k_s3_round, dim3(unsigned((ni + 255) / 256)), dim3(256), 0, ctx->stream,
+                       op->s3_inv, fi, ni);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_s3_round, dim3(unsigned((nk + 255) / 256)), dim3(256), 0, ctx->stream,
+                       op->s3_k, fk, nk);
+    LAUNCH_CHECK();
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  } catch (...) {
+    dev_free(fq);
+    dev_free(fk);
+    dev_free(fi);
+    throw;
+  }
+  op->s3_inv_f = fi;
+  op->s3_k_f = fk;
+  op->s3_q_f = fq;
+}
+
 void schur3d_free(tp_op op) {
   dev_free(op->s3_inv);
   dev_free(op->s3_k);
   dev_free(op->s3_q);
+  dev_free(op->s3_inv_f);
+  dev_free(op->s3_k_f);
+  dev_free(op->s3_q_f);
   op->s3_inv = op->s3_k = op->s3_q = nullptr;
+  op->s3_inv_f = op->s3_k_f = op->s3_q_f = nullptr;
 }
 
-// dst_e = (M^ee)^-1 src_e for each right-hand side of the batch (FP64).  dst may alias src;
-// w is an FP64 work field of the same batch size.
-void launch_mee_inv(tp_op op, const Field& src, Field& dst, Field& w) {
-  schur3d_setup(op);
+namespace {
+template <typename T>
+void mee_inv_impl(tp_op op, const Field& src, Field& dst, Field& w, const T* sinv, const T* kmat,
+                  T* q) {
   tp_ctx ctx = op->g->ctx;
   const Lattice& L = ctx->lat;
-  if (src.prec != TP_F64 || dst.prec != TP_F64 || w.prec != TP_F64)
-    TP_THROW(TP_EINVAL, "the exact M^ee inverse runs in F64");
   const int nlines = L.Vs2;
   const double2* link_t = op->g->u3_d + (int64_t)(3 * 2 + 0) * 9 * L.V2;
-  ProfScope ps(ctx, KID_SCHUR3D_MEE,
-               double(L.V2) * (2 * (144 + 72) * 16.0 + 7 * spinor_bytes(TP_F64)) * src.nr);
   for (int r = 0; r < src.nr; ++r) {
-    SpinorF<double2> sf = src.view(r).par<double2>(0);
-    SpinorF<double2> df = dst.view(r).par<double2>(0);
-    SpinorF<double2> wf = w.view(r).par<double2>(0);
-    hipLaunchKernelGGL(k_s3_forward, dim3(nlines / 4), dim3(64), 0, ctx->stream, sf.p[0],
-                       sf.p[1], L.V2, L.g, op->s3_inv, link_t, nullptr, nullptr, -1, wf.p[0],
-                       wf.p[1]);
+    SpinorF<T> sf = src.view(r).template par<T>(0);
+    SpinorF<T> df = dst.view(r).template par<T>(0);
+    SpinorF<T> wf = w.view(r).template par<T>(0);
+    hipLaunchKernelGGL(k_s3_forward<T>, dim3(nlines / 4), dim3(64), 0, ctx->stream,
+                       (const T*)sf.p[0], (const T*)sf.p[1], L.V2, L.g, sinv, link_t,
+                       (const T*)nullptr, (const T*)nullptr, -1, wf.p[0], wf.p[1]);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_s3_backward, dim3(nlines / 4), dim3(64), 0, ctx->stream, wf.p[0],
-                       wf.p[1], L.V2, L.g, op->s3_inv, nullptr, nullptr, op->s3_q);
+    hipLaunchKernelGGL(k_s3_backward<T>, dim3(nlines / 4), dim3(64), 0, ctx->stream,
+                       (const T*)wf.p[0], (const T*)wf.p[1], L.V2, L.g, sinv, (T*)nullptr,
+                       (T*)nullptr, q);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_s3_forward, dim3(nlines / 4), dim3(64), 0, ctx->stream, sf.p[0],
-                       sf.p[1], L.V2, L.g, op->s3_inv, link_t, op->s3_k, op->s3_q, -1, wf.p[0],
-                       wf.p[1]);
+    hipLaunchKernelGGL(k_s3_forward<T>, dim3(nlines / 4), dim3(64), 0, ctx->stream,
+                       (const T*)sf.p[0], (const T*)sf.p[1], L.V2, L.g, sinv, link_t, kmat,
+                       (const T*)q, -1, wf.p[0], wf.p[1]);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_s3_backward, dim3(nlines / 4), dim3(64), 0, ctx->stream, wf.p[0],
-                       wf.p[1], L.V2, L.g, op->s3_inv, df.p[0], df.p[1], nullptr);
+    hipLaunchKernelGGL(k_s3_backward<T>, dim3(nlines / 4), dim3(64), 0, ctx->stream,
+                       (const T*)wf.p[0], (const T*)wf.p[1], L.V2, L.g, sinv, df.p[0], df.p[1],
+                       (T*)nullptr);
     LAUNCH_CHECK();
+  }
+}
+}  // namespace
+
+// dst_e = (M^ee)^-1 src_e for each right-hand side of the batch, in the fields' precision
+// (F64, or F32 with the rounded factors).  dst may alias src; w is a work field of the same
+// precision and batch size.
+void launch_mee_inv(tp_op op, const Field& src, Field& dst, Field& w) {
+  tp_ctx ctx = op->g->ctx;
+  const Lattice& L = ctx->lat;
+  if (src.prec != dst.prec || src.prec != w.prec || src.prec == TP_F16N)
+    TP_THROW(TP_EINVAL, "the exact M^ee inverse runs in F64 or F32");
+  const double fb = src.prec == TP_F64 ? 16.0 : 8.0;
+  ProfScope ps(ctx, KID_SCHUR3D_MEE,
+               double(L.V2) * (2 * (144 + 72) * fb + 7 * spinor_bytes(src.prec)) * src.nr);
+  if (src.prec == TP_F64) {
+    schur3d_setup(op);
+    mee_inv_impl<double2>(op, src, dst, w, op->s3_inv, op->s3_k, op->s3_q);
+  } else {
+    schur3d_setup_f32(op);
+    mee_inv_impl<float2>(op, src, dst, w, op->s3_inv_f, op->s3_k_f, op->s3_q_f);
   }
 }

@@ -20,7 +20,7 @@
 //                     Mt = diag(1, C_L^o S_o C_R^o),  S_o = M^oo - M^oe (M^ee)^-1 M^eo,
 //                   applied as a_o = C_R^o psi_o, u = D_s^eo a_o, f = (M^ee)^-1 u,
 //                   v = A^oo a_o - D_s^oe f / gamma_f^2, chi_o = psi_o + C_L^o v
-//                   (M^oo = C_L^-1 C_R^-1 + A^oo on odd sites); FP64.
+//                   (M^oo = C_L^-1 C_R^-1 + A^oo on odd sites); F64 or F32.
 // All p3 operators act in the axial gauge (interior time links = 1), see k_line_impl.h.
 #include <math.h>
 #include <stdio.h>
@@ -134,7 +134,7 @@ void ilu_full(tp_op op, int prec, const Field& src, Field& dst) {
   launch_line(op, prec, LM_CL, 1, lio(&v, &src), dst);                      // chi_o
 }
 
-// C_L^o S_o C_R^o on the odd p3 parity (FP64):
+// C_L^o S_o C_R^o on the odd p3 parity (F64 or F32):
 //   dst_o = src_o + C_L^o [A^oo a_o - D_s^oe (M^ee)^-1 D_s^eo a_o / gamma_f^2],  a_o = C_R^o src_o
 void schur3d_so_odd(tp_op op, int prec, const Field& src, Field& dst) {
   Field& aup = ws_get(op, prec, W_T1);
@@ -143,7 +143,7 @@ void schur3d_so_odd(tp_op op, int prec, const Field& src, Field& dst) {
   Field& v = ws_get(op, prec, W_T4);
   launch_line(op, prec, LM_CR, 1, lio(&src, nullptr, false), aup);          // a_o upper
   launch_site(op, prec, sio_nb(&aup, &src), u, SiteCoef{0, 0, 0, 1.0, 0}, 0, 0, 1, false);
-  launch_mee_inv(op, u, f, ws_get(op, TP_F64, W_S3W));
+  launch_mee_inv(op, u, f, ws_get(op, prec, W_S3W));
   SiteIO io3;
   io3.self_up = &aup;
   io3.self_lo = &src;
@@ -304,7 +304,7 @@ void op_prepare(tp_op op, int scheme, int prec, const Field& eta, Field& et) {
     case TP_TEMPORAL_SCHUR3D: {
       // eta~_e = (M^ee)^-1 eta_e ; eta~_o = C_L^o [eta_o + D_s^oe eta~_e / gamma_f]
       Field& v = ws_get(op, prec, W_PREP);
-      launch_mee_inv(op, eta, et, ws_get(op, TP_F64, W_S3W));
+      launch_mee_inv(op, eta, et, ws_get(op, prec, W_S3W));
       SiteIO io = sio_nb(&et, &et);
       io.in2 = &eta;
       launch_site(op, prec, io, v, SiteCoef{0, 0, 0, 1.0 / op->gf, 1.0}, 0, 1, 1, false);
@@ -350,7 +350,7 @@ void op_reconstruct(tp_op op, int scheme, int prec, const Field& y, Field& x) {
       Field& f = ws_get(op, prec, W_S3F);
       launch_line(op, prec, LM_CR, 1, lio(&y), x);
       launch_site(op, prec, sio_nb(&x, &x), t, SiteCoef{0, 0, 0, 1.0 / op->gf, 0}, 0, 0, 1, false);
-      launch_mee_inv(op, t, f, ws_get(op, TP_F64, W_S3W));
+      launch_mee_inv(op, t, f, ws_get(op, prec, W_S3W));
       blas(ctx, B_COPY, 0, 1, {&y, &x});
       blas(ctx, B_AXPY, 0, 1, {&f, &x}, cplx(1, 0));
       break;

@@ -167,6 +167,9 @@ struct tp_op_s {
   double2* s3_inv = nullptr;  // block-LU S(t)^-1 [even tile][t][12 col][12 row][4 line]
   double2* s3_k = nullptr;    // Woodbury capacitance K per even line [Vs2][12][12]
   double2* s3_q = nullptr;    // boundary values W^dag T0^-1 eta [Vs2][12] (set-up: [12][Vs2][12])
+  float2* s3_inv_f = nullptr;  // the factors rounded to FP32 for the FP32 operator
+  float2* s3_k_f = nullptr;
+  float2* s3_q_f = nullptr;
   Workspace* ws = nullptr;
   int batch_nr = 1;  // right-hand sides of the batched apply in progress (workspace size)
 };
@@ -246,10 +249,11 @@ void launch_line(tp_op op, int prec, int mode, int par, const LineIO& io, Field&
 // u = D_s^eo a_o / gamma_f, chi_e = psi_e + C_L y and n_e = C_R C_L (y - u) with
 // y = A C_R (C_L u + psi_e).
 void launch_ilu_mid(tp_op op, int prec, const Field& psi, const Field& u, Field& chi, Field& n);
-// Exact (M^ee)^-1, M^ee = A + mu - D_t on the even p3 sites (FP64): block LU of each even
-// time line plus a rank-12 Woodbury correction for the wrapping hops.  schur3d_setup builds
-// the factors once per operator (TP_ESINGULAR on a zero pivot); launch_mee_inv writes
-// dst_e = (M^ee)^-1 src_e per right-hand side (w: FP64 work field of the same batch size).
+// Exact (M^ee)^-1, M^ee = A + mu - D_t on the even p3 sites: block LU of each even time line
+// plus a rank-12 Woodbury correction for the wrapping hops.  schur3d_setup builds the FP64
+// factors once per operator (TP_ESINGULAR on a zero pivot); launch_mee_inv writes
+// dst_e = (M^ee)^-1 src_e per right-hand side in F64, or in F32 with the factors rounded to
+// FP32 on first use (w: work field of the same precision and batch size).
 void schur3d_setup(tp_op op);
 void schur3d_free(tp_op op);
 void launch_mee_inv(tp_op op, const Field& src, Field& dst, Field& w);

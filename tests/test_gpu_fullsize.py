@@ -92,8 +92,6 @@ def test_prec_is_SL_M_SR(big, scheme):
     a = _np(g.apply_prec(y, scheme, "F64"))
     c = _np(g.prepare_source(g.apply_M(g.reconstruct(y, scheme, "F64"), "F64"), scheme, "F64"))
     assert _rel(a, c) < 1e-12
-    if scheme == "TEMPORAL_SCHUR3D":
-        return  # F64 only
     a32 = _np(g.apply_prec(y, scheme, "F32"))
     assert _rel(a32, c) < 2e-5
 
@@ -119,11 +117,12 @@ def test_bench_solve_residual_sampled(big):
     assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(b["eta"]), (np.linalg.norm(r), info)
 
 
-def test_schur3d_solve_residual_sampled(big):
-    """The exact 3D-Schur scheme's FP64 solve; the oracle's residual on 48 sites cannot exceed
-    the global one."""
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+def test_schur3d_solve_residual_sampled(big, prec):
+    """The exact 3D-Schur scheme's FP64 and mixed FP32 solves; the oracle's residual on 48
+    sites cannot exceed the global one."""
     b = big
-    x, info = b["gop"].solve(b["teta"], scheme="TEMPORAL_SCHUR3D", prec="F64", tol=1e-10)
+    x, info = b["gop"].solve(b["teta"], scheme="TEMPORAL_SCHUR3D", prec=prec, tol=1e-10)
     assert info["true_rel_resid"] <= 1e-10, info
     xs = _np(x)
     r = _at(b["eta"], b["sites"]) - sampled.M_at_sites(b["U"], xs, b["sites"], b["m0"], b["xi"], -1.0,

@@ -135,8 +135,8 @@ def test_point_source_reduced_precision(case, prec):
 def test_apply_prec(case, scheme, prec):
     if scheme == "SCHUR4D" and prec == "F16N":
         pytest.skip("the 4D Schur baseline runs in F64/F32")
-    if scheme == "TEMPORAL_SCHUR3D" and prec != "F64":
-        pytest.skip("the exact even-block inverse runs in F64")
+    if scheme == "TEMPORAL_SCHUR3D" and prec == "F16N":
+        pytest.skip("the exact even-block inverse runs in F64 and F32")
     o, g = case["oop"], case["gop"]
     e, te = case["eta"], case["teta"]
     tol = TOL[prec][1]
@@ -353,14 +353,23 @@ def test_site_kernels_in_tile_order(dims):
         gop.close()
 
 
-@pytest.mark.parametrize("prec", ["F32", "F16N"])
-def test_schur3d_rejects_reduced_precision(case, prec):
+def test_schur3d_rejects_f16n(case):
     from paper_0910_0992_amd._lib import TprecError
     g = case["gop"]
-    with pytest.raises(TprecError, match="F64"):
-        g.apply_prec(case["teta"], "TEMPORAL_SCHUR3D", prec)
-    with pytest.raises(TprecError, match="F64"):
-        g.solve(case["teta"], scheme="TEMPORAL_SCHUR3D", prec=prec, tol=1e-10)
+    with pytest.raises(TprecError, match="F64 and F32"):
+        g.apply_prec(case["teta"], "TEMPORAL_SCHUR3D", "F16N")
+    with pytest.raises(TprecError, match="F64 and F32"):
+        g.solve(case["teta"], scheme="TEMPORAL_SCHUR3D", prec="F16N", tol=1e-10)
+
+
+def test_schur3d_solve_mixed_f32(case):
+    """FP32 inner solves with the FP32-rounded factors, FP64 reliable updates, to 1e-10."""
+    o, g = case["oop"], case["gop"]
+    x, info = g.solve(case["teta"], scheme="TEMPORAL_SCHUR3D", prec="F32", tol=1e-10)
+    xn = _np(x)
+    true = np.linalg.norm(case["eta"] - o.M(xn)) / np.linalg.norm(case["eta"])
+    assert true <= 1.05e-10, (info, true)
+    assert info["outer_iters"] >= 2
 
 
 def test_schur3d_even_block_inverse(case):

@@ -1,6 +1,7 @@
 // Exact inverse of the even p3 block M^ee = A + mu - D_t: the even-site solve of temporal
 // preconditioning combined with 3D-Schur (Sec. II.B; App. A writes the block as a
-// tridiagonal matrix plus a corner term).  FP64.
+// tridiagonal matrix plus a corner term).  The factors are computed in FP64; the sweeps run
+// in FP64, or in FP32 on a rounded copy of the factors for the FP32 operator.
 //
 // In the axial frame every interior time link is the identity, so on an even time line
 //   (M^ee psi)(t) = B(t) psi(t) - P_- psi(t+1) - P_+ psi(t-1),   B(t) = A(t) + mu,
@@ -21,7 +22,7 @@
 //
 // Storage: S(t)^-1 for every even site as [tile][t][column][row][line of the tile], so the
 // 48 lanes (row, line) of one wavefront that handle a tile read one column in a single
-// contiguous 768-byte load.  K is [line][row][column].
+// contiguous load (768 bytes in FP64).  K is [line][row][column].
 #include "tp_internal.h"
 
 namespace {

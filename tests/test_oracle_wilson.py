@@ -169,3 +169,46 @@ def test_clover_small_field_is_linear_in_F():
     a1 = W.clover_field(synth.make_links(dims, 1e-4, 1e-4, 7), 1.0, 1.0)
     a2 = W.clover_field(synth.make_links(dims, 2e-4, 2e-4, 7), 1.0, 1.0)
     assert np.linalg.norm(a2 - 2 * a1) < 1e-3 * np.linalg.norm(a2)
+
+
+def _colour0_low_mode(dims, mu, nu, m0, c):
+    """Smallest real part among the near-real eigenvalues of M restricted to colour 0, in
+    the constant abelian field of the (mu, nu) plane (one flux quantum per L_nu), with
+    gamma_f = 1, periodic time and the SW coefficient c on that plane (c_s for a spatial
+    plane, c_t for a plane with t).  Extents of 1 in the other two directions leave them
+    at zero momentum, so M is the 2D Wilson operator of the plane plus m0 (and the SW term)."""
+    U = synth.abelian_plane_links(dims, mu, nu, 1)
+    spatial = mu < 3 and nu < 3
+    A = W.clover_field(U, c if spatial else 0.0, 0.0 if spatial else c) if c else None
+    lx, ly, lz, lt = dims
+    n = lx * ly * lz * lt
+    M = np.zeros((4 * n, 4 * n), complex)
+    for k in range(4 * n):
+        e = np.zeros((n, 4, 3), complex)
+        e[k // 4, k % 4, 0] = 1.0
+        out = W.apply_M(U, e.reshape(lt, lz, ly, lx, 4, 3), m0, 1.0, 1.0, A).reshape(n, 4, 3)
+        assert np.abs(out[..., 1:]).max() < 1e-14  # colour 0 decouples (diagonal links)
+        M[:, k] = out[..., 0].ravel()
+    ev = np.linalg.eigvals(M)
+    near_real = ev[np.abs(ev.imag) < 1e-8]
+    return near_real.real.min()
+
+
+@pytest.mark.parametrize("dims,mu,nu", [((8, 8, 1, 1), 0, 1), ((8, 1, 1, 8), 0, 3),
+                                        ((16, 16, 1, 1), 0, 1)])
+def test_clover_sign_removes_wilson_mass_shift(dims, mu, nu):
+    """The sign of the SW term (Sec. II, the definition of A), pinned by the tree-level
+    O(a) improvement it exists for.  In a constant abelian field of flux f per plaquette
+    the lowest Landau level of the continuum Dirac operator is a set of exact zero modes.
+    The Wilson term lifts them to m0 + f/2 + O(f^2) (its Laplacian equals the squared
+    Dirac operator minus the spin-field coupling, which is -|F| on those modes); the SW
+    term with coefficient 1 cancels that shift to O(f^2), and with the opposite sign it
+    doubles it.  Checked for a spatial plane (c_s) and a plane with t (c_t)."""
+    m0 = 0.1
+    f = 2 * np.pi / dims[nu]
+    wilson = _colour0_low_mode(dims, mu, nu, m0, 0.0) - m0
+    improved = _colour0_low_mode(dims, mu, nu, m0, 1.0) - m0
+    # Wilson: the O(a) shift f/2 (to within its O(f^2) lattice corrections)
+    assert abs(wilson - 0.5 * np.sin(f)) < 0.05 * wilson
+    # SW term: the O(a) shift is gone; a flipped sign would give about 2x the Wilson shift
+    assert abs(improved) < 0.05 * wilson

@@ -22,16 +22,13 @@ sys.path.insert(0, ROOT)
 METRIC = "time-to-solution @1e-10 resid (mixed vs FP64 even-odd); operator HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE + WRITE_SIZE runs scaled
-# by a 1 GiB copy (FETCH x2.0000, WRITE x1.0000), for the sources whose hash is recorded; any
-# change to those sources makes the figure stale and it is reported as null.
-TRAFFIC = {
-    ("clover_32x256", "F16N", "hop_site"): {
-        "bytes_per_launch": 2.206e9,
-        "sources": ["k_site.hip", "tp_hop.h", "tp_device.h"],
-        "sha256": "d96cc61d9b769d058ba7c01e6ebe74d886243271732c3dac36491dbba396c756",
-    },
-}
+# HBM bytes per launch, from rocprofv3 FETCH_SIZE + WRITE_SIZE runs scaled by a 1 GiB copy
+# (FETCH x2.0000, WRITE x1.0000), for the kernel sources whose hash is recorded; any change to
+# those sources makes the figure stale and it is reported as null.
+TRAFFIC = {}
+
+# The five kernels of one temporal + 3D-ILU apply (App. B sequence), in launch order.
+ILU_APPLY = ("scan_cr", "hop_ds", "ilu_mid", "hop_clover", "scan_cl")
 
 
 def measured_traffic(workload, prec, kernel):
@@ -93,11 +90,21 @@ def copy_calibration():
                       "GBs": 8 * n / (ms * 1e-3) / 1e9}))
 
 
-def cpu_baseline(cfg, applies):
-    """The FP64 oracle's preconditioned operator timed on a 16^3x16 slab of the workload
-    (same anisotropy, mass, clover and link ensemble parameters); one apply costs the
-    same per site, so the solve time is extrapolated by volume and by the GPU solve's
-    apply count."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_worker(args):
+    """One oracle process: builds the operator on its own 16^3x16 slab and times applies of
+    S_L M S_R for about `seconds`; returns the apply times."""
+    cfg, seed, seconds = args
     import numpy as np
 
     import synth
@@ -105,27 +112,63 @@ def cpu_baseline(cfg, applies):
 
     sample = (16, 16, 16, 16)
     xi = cfg["xi"]
-    U = synth.make_links(sample, cfg["eps_s"], cfg["eps_t"], cfg["seed"])
+    U = synth.make_links(sample, cfg["eps_s"], cfg["eps_t"], seed)
     eta = synth.make_source(sample, 2000)
     op = Operator(U, cfg["m0"], xi, -1.0, cfg["csw_s"] / xi, cfg["csw_t"])
     op.prec("TEMPORAL_SCHUR", eta)  # warm-up
     ts = []
-    t_end = time.perf_counter() + 12.0
+    t_end = time.perf_counter() + seconds
     while time.perf_counter() < t_end or len(ts) < 2:
         t0 = time.perf_counter()
         op.prec("TEMPORAL_SCHUR", eta)
         ts.append(time.perf_counter() - t0)
-    t_apply = float(np.median(ts))
+    return ts
+
+
+def cpu_oracle_times(cfg):
+    """The FP64 oracle's preconditioned operator on the host cores: one process per core
+    (the oracle's NumPy element-wise work is single-threaded, so each core applies S_L M S_R
+    to its own 16^3x16 slab of the workload, with the same anisotropy, mass, clover and link
+    ensemble parameters, and the slabs run side by side).  Runs before anything touches the
+    GPU: the workers are forked, never exec'd, from a process without GPU state."""
+    import multiprocessing as mp
+
+    nproc = os.cpu_count() or 1
+    cores = max(1, min(nproc, 16))  # the box's CPU share is 16 cores
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"  # one thread per worker process, `cores` processes
+    with mp.get_context("fork").Pool(cores) as pool:
+        runs = pool.map(_oracle_worker, [(cfg, cfg["seed"] + 100 * k, 8.0) for k in range(cores)])
+    return {"nproc": nproc, "cores": cores, "runs": runs}
+
+
+def cpu_baseline(cfg, timing, applies):
+    """One apply costs the same per site, so the oracle's solve time is extrapolated by volume
+    and by the GPU solve's apply count from the all-core site throughput; the one-core figure
+    is reported beside it."""
+    import numpy as np
+
+    runs, cores = timing["runs"], timing["cores"]
+    sample_sites = 16 ** 4
     lx, ly, lz, lt = cfg["dims"]
-    scale = (lx * ly * lz * lt) / float(np.prod(sample))
+    V = lx * ly * lz * lt
+    per_core = [float(np.median(ts)) for ts in runs]
+    agg_sites_per_s = sum(sample_sites / t for t in per_core)
+    t_all = V * applies / agg_sites_per_s
+    t_one = V * applies * float(np.median(per_core)) / sample_sites
     return {
-        "value": t_apply * scale * applies,
+        "value": t_all,
         "unit": "s",
-        "cores": 1,
+        "cores": cores,
         "kind": "oracle",
-        "sample": (f"{len(ts)} oracle applies of S_L M S_R on a 16^3x16 slab of the workload, "
-                   f"median {t_apply:.3f} s, x{scale:.0f} volume x{applies} applies of the GPU "
-                   f"solve (extrapolated; NumPy single-threaded element-wise work)"),
+        "nproc": timing["nproc"],
+        "cpu_model": _cpu_model(),
+        "per_core_value": t_one,
+        "sample": (f"{cores} oracle processes (one thread each), each timing S_L M S_R on its own "
+                   f"16^3x16 slab of the workload ({sum(len(r) for r in runs)} applies, median "
+                   f"{float(np.median(per_core)):.3f} s per apply per core); time-to-solution "
+                   f"extrapolated from the all-core site throughput to {V} sites x {applies} applies "
+                   f"of the GPU solve; per_core_value is the same from one core"),
     }
 
 
@@ -249,13 +292,20 @@ def main():
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported: the library has "
               "no multi-GPU path (spatial sharding is described as a design only)", file=sys.stderr)
         sys.exit(2)
+    import synth
+
+    cfg = synth.WORKLOADS[args.workload]
+    cpu_timing = None
+    if not args.no_cpu:
+        t0 = time.perf_counter()
+        cpu_timing = cpu_oracle_times(cfg)
+        print(f"[bench] oracle CPU baseline timed on {cpu_timing['cores']} cores in "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     import numpy as np
     import torch
 
-    import synth
     from paper_0910_0992_amd import Operator
 
-    cfg = synth.WORKLOADS[args.workload]
     dims, xi, m0 = cfg["dims"], cfg["xi"], cfg["m0"]
     c_s, c_t = cfg["csw_s"] / xi, cfg["csw_t"]
     dev = torch.device("cuda", 0)
@@ -295,8 +345,8 @@ def main():
             print(f"[bench] warm-up {scheme}/{prec} done", file=sys.stderr, flush=True)
         dom = None
         if prof:
-            ops = {k: v for k, v in breakdown.items() if k not in ("blas", "reduce_finish", "pack_unpack")}
-            dom = max(ops, key=lambda k: ops[k]["ms"])
+            # the largest single kernel of the untimed breakdown, nothing excluded
+            dom = max(breakdown, key=lambda k: breakdown[k]["ms"])
             op.profile(True, only=[dom])
             op.profile_reset()
         torch.cuda.synchronize()
@@ -339,6 +389,18 @@ def main():
             "solver": "BiCGStab with FP64 reliable updates",
             "inner_prec": args.prec,
         },
+        "readings": [
+            f"m0 = {m0}: no mass is given for this workload; the lightest mass at which every "
+            "scheme's BiCGStab converges on the synthetic field (a heavier, better-conditioned "
+            "system than m0 = -0.05)",
+            "F16N stores links and clover in FP16 as well as the spinors (per-site FP32 scale "
+            "on spinors only)",
+            "the reduced-precision scans apply the FP64-formed Polyakov-loop closure in FP32",
+        ] if args.prec == "F16N" else [
+            f"m0 = {m0}: no mass is given for this workload; the lightest mass at which every "
+            "scheme's BiCGStab converges on the synthetic field",
+            "the FP32 scans apply the FP64-formed Polyakov-loop closure in FP32",
+        ],
         "iters": infos[-1]["iters"],
         "applies": infos[-1]["applies"],
         "outer_cycles": infos[-1]["outer_iters"],
@@ -347,7 +409,7 @@ def main():
         "plaquette_s_t": plaq,
     }
     if stats:
-        # the dominant kernel group, timed live on the library's stream over the timed solves
+        # the largest single kernel, timed live on the library's stream over the timed solves
         d = stats[dom]
         avg_ms = d["ms"] / d["launches"]
         bytes_per = d["bytes"] / d["launches"]
@@ -356,11 +418,18 @@ def main():
                            "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                            "traffic": measured_traffic(args.workload, args.prec, dom),
                            "avg_ms": avg_ms, "bytes_per_launch": bytes_per, "launches": d["launches"]}
-        # every group, from the last untimed solve
+        # every kernel, from the last untimed solve
+        tot = sum(s["ms"] for s in breakdown.values())
         res["kernels"] = {k: {"launches": v["launches"], "avg_ms": v["ms"] / v["launches"],
                               "GBs": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None,
-                              "share": v["ms"] / sum(s["ms"] for s in breakdown.values())}
+                              "share": v["ms"] / tot}
                           for k, v in breakdown.items()}
+        # the whole preconditioned apply: its five kernels' algorithmic bytes over their time
+        ap = [breakdown[k] for k in ILU_APPLY if k in breakdown]
+        if ap:
+            by, ms = sum(v["bytes"] for v in ap), sum(v["ms"] for v in ap)
+            res["roofline"]["ilu_apply_frac"] = by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+            res["roofline"]["ilu_apply_GBs"] = by / (ms * 1e-3) / 1e9
     if not args.no_alt:
         alt = "F32" if args.prec == "F16N" else "F16N"
         k = alt.lower()
@@ -379,7 +448,7 @@ def main():
         res["speedup_vs_fp64_even_odd"] = btts / tts
         rel = (torch.linalg.vector_norm(x - xb) / torch.linalg.vector_norm(xb)).item()
         res["rel_diff_vs_fp64_even_odd_solution"] = rel
-    res["cpu_baseline"] = None if args.no_cpu else cpu_baseline(cfg, res["applies"])
+    res["cpu_baseline"] = None if cpu_timing is None else cpu_baseline(cfg, cpu_timing, res["applies"])
     op.close()
     print(json.dumps(res))
 

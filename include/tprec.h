@@ -93,6 +93,13 @@ typedef struct tp_gauge_s* tp_gauge;
 typedef struct tp_clover_s* tp_clover;
 typedef struct tp_op_s* tp_op;
 
+/* Device allocator hooks (tp_ctx_set_allocator).  alloc returns `bytes` bytes of device
+ * memory of the context's device, aligned to at least 256 bytes and usable on `stream`, or
+ * NULL if it cannot; free releases a pointer that alloc returned, given the size asked for
+ * and the stream bound to the context at the time of the free.  `user` is passed through. */
+typedef void* (*tp_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*tp_free_fn)(void* ptr, size_t bytes, void* stream, void* user);
+
 /* ---- context ------------------------------------------------------------- */
 
 /* Lattice geometry (dims = {Lx, Ly, Lz, Lt}), fermion time boundary phase
@@ -102,6 +109,16 @@ tp_status tp_ctx_create(const int32_t dims[4], int32_t bc_t, int32_t device, tp_
 tp_status tp_ctx_destroy(tp_ctx ctx);
 /* hip_stream is a hipStream_t (NULL = default stream). */
 tp_status tp_ctx_set_stream(tp_ctx ctx, void* hip_stream);
+/* Routes every device allocation of the context and of the gauge, clover and operator
+ * handles created from it (fields, workspaces, set-up temporaries) through alloc_fn and
+ * free_fn, e.g. a framework's caching allocator, so that the caller owns all device memory.
+ * Both NULL: back to hipMalloc / hipFree.  Must be called before the first tp_gauge_create
+ * on the context (else TP_EINVAL); the context's own buffers move to the new allocator.
+ * Every allocation made through the hooks is freed through them by the destroy calls.
+ * Pinned host memory for reduction read-back is not device memory and stays hipHostMalloc. */
+tp_status tp_ctx_set_allocator(tp_ctx ctx, tp_alloc_fn alloc_fn, tp_free_fn free_fn, void* user);
+/* Device bytes currently held by the context and its handles. */
+tp_status tp_ctx_device_bytes(tp_ctx ctx, size_t* bytes);
 
 /* ---- gauge field ------------------------------------------------------------
  * Copies the canonical links (host or device pointer, per `where`) into the
@@ -112,7 +129,8 @@ tp_status tp_ctx_set_stream(tp_ctx ctx, void* hip_stream);
  * work in the axial frame rotated by W^dag (Sec. II.C), a gauge rotation only for
  * unitary W.  Spatial links may be any complex 3x3 matrices; when all of them are
  * SU(3) to 1e-9, the FP32 and FP16 kernels read their first two rows and rebuild
- * the third (FP64 kernels always read all nine entries). */
+ * the third (FP64 kernels always read all nine entries).  Links containing NaN or
+ * Inf are refused with TP_EINVAL. */
 tp_status tp_gauge_create(tp_ctx ctx, const void* links, int32_t where, tp_gauge* out);
 tp_status tp_gauge_destroy(tp_gauge g);
 /* Mean plaquette diagnostics: spatial and temporal (1/3 Re tr) averages. */
@@ -133,6 +151,8 @@ tp_status tp_clover_destroy(tp_clover c);
  * factorises (A + mu) per site for SCHUR4D (TP_ESINGULAR on a zero pivot). */
 tp_status tp_op_create(tp_gauge g, tp_clover c, double m0, double gamma_f, tp_op* out);
 tp_status tp_op_destroy(tp_op op);
+/* The diagonal mass term mu = m0 + 1 + 3/gamma_f of M (Sec. II, a_t = 1). */
+tp_status tp_op_mass(tp_op op, double* mu);
 
 /* ---- applies (canonical device spinors in and out, dst != src) -----------------
  * `prec` selects the precision of the internal apply (TP_F64/F32/F16N); input
@@ -173,7 +193,8 @@ typedef struct {
   int32_t max_restarts;    /* cap on FP64 corrections (updates or cycles)           */
   int32_t use_x0;          /* 1: x holds the initial guess on entry                 */
   int32_t estimate_kappa;  /* 1 (CGNR only): Lanczos estimate of kappa(Mt^dag Mt)  */
-  int32_t reserved;
+  int32_t dagger;          /* 1: solve M^dagger x = eta instead (as M (g5 x) = g5 eta,
+                              M^dagger = g5 M g5, with the same preconditioned solver) */
   double tol;              /* target true relative residual |eta - M x| / |eta|     */
   double inner_tol;        /* BiCGStab in F32/F16N: reliable-update threshold delta
                               (0 = default 1e-3 F32, 0.01 F16N); CGNR: relative
@@ -192,7 +213,8 @@ typedef struct {
   double ms;               /* wall time of the solve                                */
 } tp_solve_info;
 
-/* Solves M x = eta (canonical device spinors) to the FP64 true relative
+/* Solves M x = eta (or M^dagger x = eta with params->dagger; canonical device
+ * spinors) to the FP64 true relative
  * residual `tol` with the preconditioned operator Mt = S_L M S_R of `scheme`
  * (eta~ = S_L r, Krylov on Mt y = eta~ in `prec`, x += S_R y, r = eta - M x in
  * FP64).  F64: one Krylov solve.  F32/F16N BiCGStab: reliable updates (Sleijpen
@@ -205,7 +227,8 @@ typedef struct {
 tp_status tp_solve(tp_op op, const tp_solve_params* params, void* x, const void* eta,
                    tp_solve_info* info);
 
-/* Solves M x[k] = eta[k] for k < nrhs (1..16) with the same parameters.  For
+/* Solves M x[k] = eta[k] (M^dagger with params->dagger) for k < nrhs (1..16) with the
+ * same parameters.  For
  * mixed-precision BiCGStab on the full-lattice schemes (UNPREC, TEMPORAL, and
  * TEMPORAL_SCHUR with clover) the right-hand sides iterate in lockstep: every
  * operator application is one launch per kernel for all of them, so links and

@@ -21,7 +21,7 @@ PRECS = {"F64": 0, "F32": 1, "F16N": 2}
 class SolveParams(C.Structure):
     _fields_ = [("scheme", C.c_int32), ("solver", C.c_int32), ("prec", C.c_int32),
                 ("max_iter", C.c_int32), ("max_restarts", C.c_int32), ("use_x0", C.c_int32),
-                ("estimate_kappa", C.c_int32), ("reserved", C.c_int32),
+                ("estimate_kappa", C.c_int32), ("dagger", C.c_int32),
                 ("tol", C.c_double), ("inner_tol", C.c_double)]
 
 
@@ -45,11 +45,17 @@ _P = C.c_void_p
 _I = C.c_int32
 _D = C.c_double
 
+# tp_alloc_fn and tp_free_fn
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
 # (name, argtypes, restype)
 SIGNATURES = [
     ("tp_ctx_create", [C.POINTER(C.c_int32), _I, _I, C.POINTER(_P)], _I),
     ("tp_ctx_destroy", [_P], _I),
     ("tp_ctx_set_stream", [_P, _P], _I),
+    ("tp_ctx_set_allocator", [_P, ALLOC_FN, FREE_FN, _P], _I),
+    ("tp_ctx_device_bytes", [_P, C.POINTER(C.c_size_t)], _I),
     ("tp_gauge_create", [_P, _P, _I, C.POINTER(_P)], _I),
     ("tp_gauge_destroy", [_P], _I),
     ("tp_gauge_plaquette", [_P, C.POINTER(_D), C.POINTER(_D)], _I),
@@ -57,6 +63,7 @@ SIGNATURES = [
     ("tp_clover_destroy", [_P], _I),
     ("tp_op_create", [_P, _P, _D, _D, C.POINTER(_P)], _I),
     ("tp_op_destroy", [_P], _I),
+    ("tp_op_mass", [_P, C.POINTER(_D)], _I),
     ("tp_apply_M", [_P, _I, _P, _P, _I], _I),
     ("tp_apply_Ds", [_P, _I, _P, _P], _I),
     ("tp_apply_clover", [_P, _I, _P, _P, _I], _I),

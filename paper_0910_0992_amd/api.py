@@ -23,6 +23,21 @@ def _prec(p):
     return int(key)
 
 
+def _torch_allocator(device):
+    """tp_alloc_fn / tp_free_fn callbacks over torch's caching allocator on `device`."""
+
+    def alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=device, stream=int(stream or 0))
+        except Exception:  # out of memory: the library reports TP_ENOMEM
+            return None
+
+    def free(ptr, nbytes, stream, user):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    return L.ALLOC_FN(alloc), L.FREE_FN(free)
+
+
 def _scheme(s):
     if isinstance(s, str):
         if s.upper() not in L.SCHEMES:
@@ -37,9 +52,11 @@ class Operator:
     links: complex128 tensor [4, Lt, Lz, Ly, Lx, 3, 3] (CPU or CUDA).
     c_s, c_t: the literal SW coefficients (both 0 for Wilson fermions).
     bc_t: +1 periodic or -1 antiperiodic in time.
+    allocator: "torch" (default) hands every device allocation of the library to torch's
+    caching allocator (tp_ctx_set_allocator); "hip" leaves it to hipMalloc.
     """
 
-    def __init__(self, links, m0, gamma_f, c_s=0.0, c_t=0.0, bc_t=-1, device=0):
+    def __init__(self, links, m0, gamma_f, c_s=0.0, c_t=0.0, bc_t=-1, device=0, allocator="torch"):
         self._lib = L.load()
         lib = self._lib
         if links.dtype != torch.complex128 or links.dim() != 7 or links.shape[0] != 4:
@@ -48,7 +65,6 @@ class Operator:
         self.dims = (lx, ly, lz, lt)
         self.device = torch.device("cuda", device)
         self.m0, self.gamma_f, self.c_s, self.c_t, self.bc_t = m0, gamma_f, c_s, c_t, bc_t
-        self.mu = m0 + 1.0 + 3.0 / gamma_f
         self._ctx = C.c_void_p()
         self._gauge = C.c_void_p()
         self._clover = C.c_void_p()
@@ -56,6 +72,12 @@ class Operator:
         d = (C.c_int32 * 4)(*self.dims)
         L.check(lib.tp_ctx_create(d, int(bc_t), int(device), C.byref(self._ctx)))
         self._bind_stream()
+        self._alloc_cb = None
+        if allocator == "torch":
+            self._alloc_cb = _torch_allocator(device)
+            L.check(lib.tp_ctx_set_allocator(self._ctx, self._alloc_cb[0], self._alloc_cb[1], None))
+        elif allocator != "hip":
+            raise ValueError(f"allocator {allocator!r}: 'torch' or 'hip'")
         links = links.contiguous()
         where = L.TP_DEVICE if links.is_cuda else L.TP_HOST
         L.check(lib.tp_gauge_create(self._ctx, C.c_void_p(links.data_ptr()), where,
@@ -64,6 +86,15 @@ class Operator:
             L.check(lib.tp_clover_create(self._gauge, float(c_s), float(c_t), C.byref(self._clover)))
         L.check(lib.tp_op_create(self._gauge, self._clover, float(m0), float(gamma_f),
                                  C.byref(self._op)))
+        mu = C.c_double()
+        L.check(lib.tp_op_mass(self._op, C.byref(mu)))
+        self.mu = mu.value
+
+    def device_bytes(self):
+        """Device memory held by the library for this operator (context and handles)."""
+        n = C.c_size_t()
+        L.check(self._lib.tp_ctx_device_bytes(self._ctx, C.byref(n)))
+        return n.value
 
     # ---- plumbing --------------------------------------------------------------
     def _bind_stream(self):
@@ -157,14 +188,14 @@ class Operator:
     # ---- solve -----------------------------------------------------------------------
     def solve(self, eta, scheme="TEMPORAL_SCHUR", solver="BICGSTAB", prec="F64", tol=1e-10,
               inner_tol=0.0, max_iter=0, max_restarts=0, x0=None, estimate_kappa=False,
-              raise_on_noconv=True):
-        """x with |eta - M x| <= tol |eta|; returns (x, info dict)."""
+              dagger=False, raise_on_noconv=True):
+        """x with |eta - M x| <= tol |eta| (M^dagger with dagger); returns (x, info dict)."""
         src = self._in(eta)
         x = self._in(x0).clone() if x0 is not None else self._out()
         P = L.SolveParams(scheme=_scheme(scheme), solver=L.SOLVERS[solver.upper()], prec=_prec(prec),
                           max_iter=int(max_iter), max_restarts=int(max_restarts),
                           use_x0=int(x0 is not None), estimate_kappa=int(estimate_kappa),
-                          reserved=0, tol=float(tol), inner_tol=float(inner_tol))
+                          dagger=int(bool(dagger)), tol=float(tol), inner_tol=float(inner_tol))
         info = L.SolveInfo()
         self._bind_stream()
         st = self._lib.tp_solve(self._op, C.byref(P), C.c_void_p(x.data_ptr()),
@@ -176,7 +207,8 @@ class Operator:
         return x, d
 
     def solve_multi(self, etas, scheme="TEMPORAL_SCHUR", solver="BICGSTAB", prec="F64", tol=1e-10,
-                    inner_tol=0.0, max_iter=0, max_restarts=0, x0=None, raise_on_noconv=True):
+                    inner_tol=0.0, max_iter=0, max_restarts=0, x0=None, dagger=False,
+                    raise_on_noconv=True):
         """x[k] with |eta[k] - M x[k]| <= tol |eta[k]| for a batch of up to 16 sources solved
         together (tp_solve_multi); etas: [n, Lt, Lz, Ly, Lx, 4, 3].  Returns (x, [info])."""
         n = len(etas)
@@ -185,7 +217,7 @@ class Operator:
         P = L.SolveParams(scheme=_scheme(scheme), solver=L.SOLVERS[solver.upper()], prec=_prec(prec),
                           max_iter=int(max_iter), max_restarts=int(max_restarts),
                           use_x0=int(x0 is not None), estimate_kappa=0,
-                          reserved=0, tol=float(tol), inner_tol=float(inner_tol))
+                          dagger=int(bool(dagger)), tol=float(tol), inner_tol=float(inner_tol))
         infos = (L.SolveInfo * n)()
         xp = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
         ep = (C.c_void_p * n)(*[e.data_ptr() for e in srcs])
@@ -242,11 +274,6 @@ class Operator:
         return out
 
 
-def _g5(v):
-    """gamma5 = [[0,-1],[-1,0]] on (upper, lower) spin pairs (Dirac-Pauli basis)."""
-    return -torch.cat([v[..., 2:, :], v[..., :2, :]], dim=-2)
-
-
 def solve(links, eta, m0, gamma_f, c_s=0.0, c_t=0.0, bc_t=-1, **kw):
     op = Operator(links, m0, gamma_f, c_s, c_t, bc_t)
     try:
@@ -258,8 +285,8 @@ def solve(links, eta, m0, gamma_f, c_s=0.0, c_t=0.0, bc_t=-1, **kw):
 class SolveFn(torch.autograd.Function):
     """x = M(U)^-1 eta with a hand-written backward.
 
-    Backward: lambda solves M^dagger lambda = g (as M (g5 lambda) = g5 g, with the
-    same preconditioned solver), grad_eta = lambda, and grad_U is the link gradient
+    Backward: lambda solves M^dagger lambda = g (tp_solve with dagger, the same
+    preconditioned solver), grad_eta = lambda, and grad_U is the link gradient
     (tp_force, raw form), including the SW term's dependence on the links.
     Conventions follow torch: dL = Re <grad, dz>.
     """
@@ -278,8 +305,7 @@ class SolveFn(torch.autograd.Function):
     def backward(ctx, g):
         (x,) = ctx.saved_tensors
         op = ctx.op
-        y, _ = op.solve(_g5(g.contiguous()), **ctx.opts)
-        lam = _g5(y)
+        lam, _ = op.solve(g.contiguous(), dagger=True, **ctx.opts)
         grad_links = op.force(x, lam, projected=False) if ctx.needs_input_grad[0] else None
         op.close()
         ctx.op = None

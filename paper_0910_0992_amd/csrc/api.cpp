@@ -16,9 +16,10 @@ tp_status op_solve_multi(tp_op op, const tp_solve_params& P, int nr, Field& x64,
                          tp_solve_info* info);
 
 const char* const kKernelNames[KID_COUNT] = {
-    "pack_unpack", "site_p3",  "schur4d_eo_clover_inv", "schur4d_oe_clover", "line_scan",
-    "ilu_mid",     "hop_site", "blas",                  "reduce_finish",     "force",
-    "schur3d_mee"};
+    "pack_unpack", "site_p3",   "schur4d_eo_clover_inv", "schur4d_oe_clover", "scan_cr",
+    "scan_cl",     "scan_other", "ilu_mid",              "hop_ds",            "hop_clover",
+    "blas_dot",    "blas_axpyz_norm", "blas_dot4",       "blas_bicg_fused",   "blas_other",
+    "reduce_finish", "force",   "schur3d_mee"};
 
 namespace {
 thread_local std::string g_last_error;
@@ -139,41 +140,58 @@ Field& tmp_field(tp_op op, int prec, int k) { return ws_get(op, prec, 100 + k); 
 // ---------------------------------------------------------------- memory / profiling helpers
 void tp_set_error(const std::string& m) { g_last_error = m; }
 
-void* dev_alloc(size_t bytes) {
-  void* p = nullptr;
+void* dev_alloc(tp_ctx ctx, size_t bytes) {
   if (bytes == 0) return nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    TP_THROW(e == hipErrorOutOfMemory ? TP_ENOMEM : TP_EHIP,
-             std::string("hipMalloc: ") + hipGetErrorString(e));
+  void* p = nullptr;
+  if (ctx->alloc_fn) {
+    p = ctx->alloc_fn(bytes, ctx->stream, ctx->alloc_user);
+    if (!p) TP_THROW(TP_ENOMEM, "registered allocator returned no memory");
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      TP_THROW(e == hipErrorOutOfMemory ? TP_ENOMEM : TP_EHIP,
+               std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
   }
+  ctx->live[p] = bytes;
+  ctx->live_bytes += bytes;
   return p;
 }
-void dev_free(void* p) {
-  if (p) (void)hipFree(p);
+void dev_free(tp_ctx ctx, void* p) {
+  if (!p) return;
+  size_t n = 0;
+  auto it = ctx->live.find(p);
+  if (it != ctx->live.end()) {
+    n = it->second;
+    ctx->live.erase(it);
+    ctx->live_bytes -= n;
+  }
+  if (ctx->free_fn) ctx->free_fn(p, n, ctx->stream, ctx->alloc_user);
+  else (void)hipFree(p);
 }
 
-Field field_alloc(const Lattice& lat, int prec, int nr) {
+Field field_alloc(tp_ctx ctx, int prec, int nr) {
+  const Lattice& lat = ctx->lat;
   Field f;
   f.prec = prec;
   f.V2 = lat.V2;
   f.nr = nr;
   const size_t db = size_t(nr) * 2 * 12 * lat.V2 * f.elem_bytes();
-  f.data = dev_alloc(db);
-  HIP_CHECK(hipMemset(f.data, 0, db));
+  f.data = dev_alloc(ctx, db);
+  f.owned = true;
+  HIP_CHECK(hipMemsetAsync(f.data, 0, db, ctx->stream));
   if (prec == TP_F16N) {
     const size_t nb = size_t(nr) * 2 * 2 * lat.V2 * sizeof(float);
-    f.nrm = static_cast<float*>(dev_alloc(nb));
-    HIP_CHECK(hipMemset(f.nrm, 0, nb));
+    f.nrm = static_cast<float*>(dev_alloc(ctx, nb));
+    HIP_CHECK(hipMemsetAsync(f.nrm, 0, nb, ctx->stream));
   }
-  f.owned = true;
   return f;
 }
-void field_free(Field& f) {
+void field_free(tp_ctx ctx, Field& f) {
   if (f.owned) {
-    dev_free(f.data);
-    dev_free(f.nrm);
+    dev_free(ctx, f.data);
+    dev_free(ctx, f.nrm);
   }
   f.data = nullptr;
   f.nrm = nullptr;
@@ -216,6 +234,20 @@ void prof_flush(tp_ctx ctx) {
     s.bytes += ctx->ev_pending[k].bytes;
   }
   ctx->ev_used = 0;
+}
+
+// The context's own device buffers: reduction partials and results, and the solver's
+// device-side scalars.
+void ctx_buffers_alloc(tp_ctx c) {
+  c->red_partial = static_cast<double*>(dev_alloc(c, sizeof(double) * 8 * kRedBlocks));
+  c->red_result = static_cast<double*>(dev_alloc(c, sizeof(double) * (8 * kMaxRhs + BS_COUNT)));
+  c->bicg = c->red_result + 8 * kMaxRhs;
+  HIP_CHECK(hipMemsetAsync(c->bicg, 0, sizeof(double) * BS_COUNT, c->stream));
+}
+void ctx_buffers_free(tp_ctx c) {
+  dev_free(c, c->red_partial);
+  dev_free(c, c->red_result);
+  c->red_partial = c->red_result = c->bicg = nullptr;
 }
 
 // Canonical-in / canonical-out wrapper for the internal applies.
@@ -283,15 +315,11 @@ tp_status tp_ctx_create(const int32_t dims[4], int32_t bc_t, int32_t device, tp_
       int lds = 0;
       HIP_CHECK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
       c->lds_max = size_t(lds);
-      c->red_partial = static_cast<double*>(dev_alloc(sizeof(double) * 8 * kRedBlocks));
-      c->red_result = static_cast<double*>(dev_alloc(sizeof(double) * (8 * kMaxRhs + BS_COUNT)));
-      c->bicg = c->red_result + 8 * kMaxRhs;
-      HIP_CHECK(hipMemset(c->bicg, 0, sizeof(double) * BS_COUNT));
+      ctx_buffers_alloc(c);
       HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&c->red_host), sizeof(double) * 8 * kMaxRhs,
                               hipHostMallocDefault));
     } catch (...) {
-      dev_free(c->red_partial);
-      dev_free(c->red_result);
+      ctx_buffers_free(c);
       delete c;
       throw;
     }
@@ -308,10 +336,34 @@ tp_status tp_ctx_destroy(tp_ctx ctx) {
       (void)hipEventDestroy(e.first);
       (void)hipEventDestroy(e.second);
     }
-    dev_free(ctx->red_partial);
-    dev_free(ctx->red_result);
+    ctx_buffers_free(ctx);
     if (ctx->red_host) (void)hipHostFree(ctx->red_host);
     delete ctx;
+  });
+}
+
+tp_status tp_ctx_set_allocator(tp_ctx ctx, tp_alloc_fn alloc_fn, tp_free_fn free_fn, void* user) {
+  return guard([&] {
+    need(ctx, "ctx");
+    if ((alloc_fn == nullptr) != (free_fn == nullptr))
+      TP_THROW(TP_EINVAL, "alloc_fn and free_fn must both be set or both be null");
+    if (ctx->nchildren) TP_THROW(TP_EINVAL, "set the allocator before the first tp_gauge_create");
+    set_device(ctx);
+    if (ctx->stream) HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    ctx_buffers_free(ctx);
+    ctx->alloc_fn = alloc_fn;
+    ctx->free_fn = free_fn;
+    ctx->alloc_user = user;
+    ctx_buffers_alloc(ctx);
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+tp_status tp_ctx_device_bytes(tp_ctx ctx, size_t* bytes) {
+  return guard([&] {
+    need(ctx, "ctx");
+    need(bytes, "bytes");
+    *bytes = ctx->live_bytes;
   });
 }
 
@@ -334,35 +386,37 @@ tp_status tp_gauge_create(tp_ctx ctx, const void* links, int32_t where, tp_gauge
     const Lattice& L = ctx->lat;
     tp_gauge g = new tp_gauge_s();
     g->ctx = ctx;
+    ctx->nchildren++;
     try {
       size_t lb = size_t(4) * L.V * 9 * sizeof(double2);
-      g->canon = static_cast<double2*>(dev_alloc(lb));
+      g->canon = static_cast<double2*>(dev_alloc(ctx, lb));
       HIP_CHECK(hipMemcpyAsync(g->canon, links, lb,
                                where == TP_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
                                ctx->stream));
-      g->u3_d = static_cast<double2*>(dev_alloc(lb));
-      g->u3_f = static_cast<float2*>(dev_alloc(lb / 2));
-      g->u3_h = static_cast<__half2*>(dev_alloc(lb / 4));
-      g->u4_d = static_cast<double2*>(dev_alloc(lb));
-      g->u4_f = static_cast<float2*>(dev_alloc(lb / 2));
-      g->w_d = static_cast<double2*>(dev_alloc(size_t(2) * 9 * L.V2 * sizeof(double2)));
-      g->poly = static_cast<double2*>(dev_alloc(size_t(2) * 9 * L.Vs2 * sizeof(double2)));
-      g->canon_ax = static_cast<double2*>(dev_alloc(lb));
-      int* flags = static_cast<int*>(dev_alloc(2 * sizeof(int)));
-      int hf[2] = {1, 1};
+      g->u3_d = static_cast<double2*>(dev_alloc(ctx, lb));
+      g->u3_f = static_cast<float2*>(dev_alloc(ctx, lb / 2));
+      g->u3_h = static_cast<__half2*>(dev_alloc(ctx, lb / 4));
+      g->u4_d = static_cast<double2*>(dev_alloc(ctx, lb));
+      g->u4_f = static_cast<float2*>(dev_alloc(ctx, lb / 2));
+      g->w_d = static_cast<double2*>(dev_alloc(ctx, size_t(2) * 9 * L.V2 * sizeof(double2)));
+      g->poly = static_cast<double2*>(dev_alloc(ctx, size_t(2) * 9 * L.Vs2 * sizeof(double2)));
+      g->canon_ax = static_cast<double2*>(dev_alloc(ctx, lb));
+      int* flags = static_cast<int*>(dev_alloc(ctx, 3 * sizeof(int)));
+      int hf[3] = {1, 1, 1};
       try {
-        HIP_CHECK(hipMemsetAsync(flags, 0, 2 * sizeof(int), ctx->stream));
+        HIP_CHECK(hipMemsetAsync(flags, 0, 3 * sizeof(int), ctx->stream));
         launch_wline(ctx, g);
         launch_axial_links(ctx, g, flags);
         launch_to_half(ctx, g->u3_f, g->u3_h, int64_t(lb / sizeof(double2)));
         launch_pack_links(ctx, g);
-        HIP_CHECK(hipMemcpyAsync(hf, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_CHECK(hipMemcpyAsync(hf, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
         HIP_CHECK(hipStreamSynchronize(ctx->stream));
       } catch (...) {
-        dev_free(flags);
+        dev_free(ctx, flags);
         throw;
       }
-      dev_free(flags);
+      dev_free(ctx, flags);
+      if (hf[2]) TP_THROW(TP_EINVAL, "links contain NaN or Inf");
       if (hf[1]) TP_THROW(TP_EINVAL, "time links must be unitary (U U^dag = 1 to 1e-10)");
       g->su3_spatial = hf[0] == 0;
     } catch (...) {
@@ -376,17 +430,19 @@ tp_status tp_gauge_create(tp_ctx ctx, const void* links, int32_t where, tp_gauge
 tp_status tp_gauge_destroy(tp_gauge g) {
   return guard([&] {
     if (!g) return;
-    (void)hipSetDevice(g->ctx->device);
+    tp_ctx ctx = g->ctx;
+    (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(g->ctx->stream);
-    dev_free(g->canon);
-    dev_free(g->u3_d);
-    dev_free(g->u3_f);
-    dev_free(g->u3_h);
-    dev_free(g->u4_d);
-    dev_free(g->u4_f);
-    dev_free(g->w_d);
-    dev_free(g->canon_ax);
-    dev_free(g->poly);
+    dev_free(ctx, g->canon);
+    dev_free(ctx, g->u3_d);
+    dev_free(ctx, g->u3_f);
+    dev_free(ctx, g->u3_h);
+    dev_free(ctx, g->u4_d);
+    dev_free(ctx, g->u4_f);
+    dev_free(ctx, g->w_d);
+    dev_free(ctx, g->canon_ax);
+    dev_free(ctx, g->poly);
+    ctx->nchildren--;
     delete g;
   });
 }
@@ -400,7 +456,7 @@ tp_status tp_gauge_plaquette(tp_gauge g, double* ps, double* pt) {
     set_device(ctx);
     const Lattice& L = ctx->lat;
     int64_t nb = (L.V + 255) / 256;
-    double* part = static_cast<double*>(dev_alloc(sizeof(double) * 2 * nb));
+    double* part = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * nb));
     std::vector<double> h(2 * nb);
     try {
       launch_plaquette(ctx, g, part);
@@ -408,10 +464,10 @@ tp_status tp_gauge_plaquette(tp_gauge g, double* ps, double* pt) {
                                ctx->stream));
       HIP_CHECK(hipStreamSynchronize(ctx->stream));
     } catch (...) {
-      dev_free(part);
+      dev_free(ctx, part);
       throw;
     }
-    dev_free(part);
+    dev_free(ctx, part);
     double s = 0, t = 0;
     for (int64_t b = 0; b < nb; ++b) {
       s += h[2 * b];
@@ -437,11 +493,11 @@ tp_status tp_clover_create(tp_gauge g, double c_s, double c_t, tp_clover* out) {
     c->ct = c_t;
     try {
       size_t cb = size_t(2) * 36 * L.V2;
-      c->a3_d = static_cast<double2*>(dev_alloc(cb * sizeof(double2)));
-      c->a3_f = static_cast<float2*>(dev_alloc(cb * sizeof(float2)));
-      c->a3_h = static_cast<__half2*>(dev_alloc(cb * sizeof(__half2)));
-      c->a4_d = static_cast<double2*>(dev_alloc(cb * sizeof(double2)));
-      c->a4_f = static_cast<float2*>(dev_alloc(cb * sizeof(float2)));
+      c->a3_d = static_cast<double2*>(dev_alloc(ctx, cb * sizeof(double2)));
+      c->a3_f = static_cast<float2*>(dev_alloc(ctx, cb * sizeof(float2)));
+      c->a3_h = static_cast<__half2*>(dev_alloc(ctx, cb * sizeof(__half2)));
+      c->a4_d = static_cast<double2*>(dev_alloc(ctx, cb * sizeof(double2)));
+      c->a4_f = static_cast<float2*>(dev_alloc(ctx, cb * sizeof(float2)));
       double sig[6][2][2][2][2];
       clover_sigma_table(c_s, c_t, sig);
       launch_clover_build(ctx, c, sig);
@@ -458,13 +514,14 @@ tp_status tp_clover_create(tp_gauge g, double c_s, double c_t, tp_clover* out) {
 tp_status tp_clover_destroy(tp_clover c) {
   return guard([&] {
     if (!c) return;
-    (void)hipSetDevice(c->g->ctx->device);
+    tp_ctx ctx = c->g->ctx;
+    (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(c->g->ctx->stream);
-    dev_free(c->a3_d);
-    dev_free(c->a3_f);
-    dev_free(c->a3_h);
-    dev_free(c->a4_d);
-    dev_free(c->a4_f);
+    dev_free(ctx, c->a3_d);
+    dev_free(ctx, c->a3_f);
+    dev_free(ctx, c->a3_h);
+    dev_free(ctx, c->a4_d);
+    dev_free(ctx, c->a4_f);
     delete c;
   });
 }
@@ -489,31 +546,31 @@ tp_status tp_op_create(tp_gauge g, tp_clover c, double m0, double gamma_f, tp_op
     int* bad = nullptr;
     try {
       if (!(op->mu > 0)) TP_THROW(TP_EINVAL, "mass term mu = m0 + 1 + 3/gamma_f must be positive");
-      op->gclos = static_cast<double2*>(dev_alloc(size_t(2) * 9 * L.Vs2 * sizeof(double2)));
-      op->gclos_f = static_cast<float2*>(dev_alloc(size_t(2) * 9 * L.Vs2 * sizeof(float2)));
+      op->gclos = static_cast<double2*>(dev_alloc(ctx, size_t(2) * 9 * L.Vs2 * sizeof(double2)));
+      op->gclos_f = static_cast<float2*>(dev_alloc(ctx, size_t(2) * 9 * L.Vs2 * sizeof(float2)));
       size_t cb = size_t(2) * 36 * L.V2;
-      op->a4_mu = static_cast<double2*>(dev_alloc(cb * sizeof(double2)));
-      op->a4_inv = static_cast<double2*>(dev_alloc(cb * sizeof(double2)));
-      op->a4_mu_f = static_cast<float2*>(dev_alloc(cb * sizeof(float2)));
-      op->a4_inv_f = static_cast<float2*>(dev_alloc(cb * sizeof(float2)));
-      op->a3_mu = static_cast<double2*>(dev_alloc(cb * sizeof(double2)));
-      op->a3_inv = static_cast<double2*>(dev_alloc(cb * sizeof(double2)));
-      op->a3_mu_f = static_cast<float2*>(dev_alloc(cb * sizeof(float2)));
-      op->a3_inv_f = static_cast<float2*>(dev_alloc(cb * sizeof(float2)));
-      op->a3_mu_h = static_cast<__half2*>(dev_alloc(cb * sizeof(__half2)));
-      op->a3_inv_h = static_cast<__half2*>(dev_alloc(cb * sizeof(__half2)));
+      op->a4_mu = static_cast<double2*>(dev_alloc(ctx, cb * sizeof(double2)));
+      op->a4_inv = static_cast<double2*>(dev_alloc(ctx, cb * sizeof(double2)));
+      op->a4_mu_f = static_cast<float2*>(dev_alloc(ctx, cb * sizeof(float2)));
+      op->a4_inv_f = static_cast<float2*>(dev_alloc(ctx, cb * sizeof(float2)));
+      op->a3_mu = static_cast<double2*>(dev_alloc(ctx, cb * sizeof(double2)));
+      op->a3_inv = static_cast<double2*>(dev_alloc(ctx, cb * sizeof(double2)));
+      op->a3_mu_f = static_cast<float2*>(dev_alloc(ctx, cb * sizeof(float2)));
+      op->a3_inv_f = static_cast<float2*>(dev_alloc(ctx, cb * sizeof(float2)));
+      op->a3_mu_h = static_cast<__half2*>(dev_alloc(ctx, cb * sizeof(__half2)));
+      op->a3_inv_h = static_cast<__half2*>(dev_alloc(ctx, cb * sizeof(__half2)));
       std::vector<double> pw(L.L[3] + 1);
       std::vector<float> pwf(L.L[3] + 1);
       for (int k = 0; k <= L.L[3]; ++k) {
         pw[k] = pow(op->mu, -double(k));
         pwf[k] = float(pw[k]);
       }
-      op->mupow_d = static_cast<double*>(dev_alloc(sizeof(double) * pw.size()));
-      op->mupow_f = static_cast<float*>(dev_alloc(sizeof(float) * pwf.size()));
+      op->mupow_d = static_cast<double*>(dev_alloc(ctx, sizeof(double) * pw.size()));
+      op->mupow_f = static_cast<float*>(dev_alloc(ctx, sizeof(float) * pwf.size()));
       HIP_CHECK(hipMemcpy(op->mupow_d, pw.data(), sizeof(double) * pw.size(), hipMemcpyHostToDevice));
       HIP_CHECK(hipMemcpy(op->mupow_f, pwf.data(), sizeof(float) * pwf.size(), hipMemcpyHostToDevice));
-      cond = static_cast<double*>(dev_alloc(sizeof(double) * 2 * L.Vs2));
-      bad = static_cast<int*>(dev_alloc(sizeof(int)));
+      cond = static_cast<double*>(dev_alloc(ctx, sizeof(double) * 2 * L.Vs2));
+      bad = static_cast<int*>(dev_alloc(ctx, sizeof(int)));
       HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
       launch_closure(ctx, op, cond);
       launch_clover_derived(ctx, op, bad);
@@ -531,13 +588,13 @@ tp_status tp_op_create(tp_gauge g, tp_clover c, double m0, double gamma_f, tp_op
         TP_THROW(TP_ESINGULAR, "closure (I - mu^-Lt P) is singular or ill-conditioned");
       if (hb) TP_THROW(TP_ESINGULAR, "(A + mu) has a numerically singular 6x6 block");
     } catch (...) {
-      dev_free(cond);
-      dev_free(bad);
+      dev_free(ctx, cond);
+      dev_free(ctx, bad);
       tp_op_destroy(op);
       throw;
     }
-    dev_free(cond);
-    dev_free(bad);
+    dev_free(ctx, cond);
+    dev_free(ctx, bad);
     *out = op;
   });
 }
@@ -545,25 +602,34 @@ tp_status tp_op_create(tp_gauge g, tp_clover c, double m0, double gamma_f, tp_op
 tp_status tp_op_destroy(tp_op op) {
   return guard([&] {
     if (!op) return;
-    (void)hipSetDevice(op->g->ctx->device);
+    tp_ctx ctx = op->g->ctx;
+    (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(op->g->ctx->stream);
     ws_free(op);
     schur3d_free(op);
-    dev_free(op->gclos);
-    dev_free(op->gclos_f);
-    dev_free(op->a4_mu);
-    dev_free(op->a4_inv);
-    dev_free(op->a4_mu_f);
-    dev_free(op->a4_inv_f);
-    dev_free(op->a3_mu);
-    dev_free(op->a3_inv);
-    dev_free(op->a3_mu_f);
-    dev_free(op->a3_inv_f);
-    dev_free(op->a3_mu_h);
-    dev_free(op->a3_inv_h);
-    dev_free(op->mupow_d);
-    dev_free(op->mupow_f);
+    dev_free(ctx, op->gclos);
+    dev_free(ctx, op->gclos_f);
+    dev_free(ctx, op->a4_mu);
+    dev_free(ctx, op->a4_inv);
+    dev_free(ctx, op->a4_mu_f);
+    dev_free(ctx, op->a4_inv_f);
+    dev_free(ctx, op->a3_mu);
+    dev_free(ctx, op->a3_inv);
+    dev_free(ctx, op->a3_mu_f);
+    dev_free(ctx, op->a3_inv_f);
+    dev_free(ctx, op->a3_mu_h);
+    dev_free(ctx, op->a3_inv_h);
+    dev_free(ctx, op->mupow_d);
+    dev_free(ctx, op->mupow_f);
     delete op;
+  });
+}
+
+tp_status tp_op_mass(tp_op op, double* mu) {
+  return guard([&] {
+    need(op, "op");
+    need(mu, "mu");
+    *mu = op->mu;
   });
 }
 
@@ -663,6 +729,7 @@ tp_status tp_solve(tp_op op, const tp_solve_params* params, void* x, const void*
     check_scheme(P.scheme);
     check_prec(P.prec);
     if (P.solver != TP_CGNR && P.solver != TP_BICGSTAB) TP_THROW(TP_EINVAL, "bad solver");
+    if (P.dagger != 0 && P.dagger != 1) TP_THROW(TP_EINVAL, "dagger must be 0 or 1");
     if (P.scheme == TP_SCHUR4D && P.prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
     if (P.scheme == TP_TEMPORAL_SCHUR3D && P.prec == TP_F16N)
       TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
@@ -674,10 +741,12 @@ tp_status tp_solve(tp_op op, const tp_solve_params* params, void* x, const void*
     Field& eta64 = ws_get(op, TP_F64, 60);
     Field& x64 = ws_get(op, TP_F64, 61);
     const double2* w = l4 ? nullptr : op->g->w_d;  // p3 schemes solve in the axial frame
-    launch_pack(ctx, static_cast<const double2*>(eta), eta64, l4, false, w);
-    if (P.use_x0) launch_pack(ctx, static_cast<const double2*>(x), x64, l4, false, w);
+    // M^dagger x = eta  <=>  M (g5 x) = g5 eta: g5 on the way in and out
+    const bool g5 = P.dagger != 0;
+    launch_pack(ctx, static_cast<const double2*>(eta), eta64, l4, g5, w);
+    if (P.use_x0) launch_pack(ctx, static_cast<const double2*>(x), x64, l4, g5, w);
     st = op_solve(op, P, x64, eta64, *info);
-    launch_unpack(ctx, x64, static_cast<double2*>(x), l4, false, w);
+    launch_unpack(ctx, x64, static_cast<double2*>(x), l4, g5, w);
     HIP_CHECK(hipStreamSynchronize(ctx->stream));
     prof_flush(ctx);
     if (st != TP_OK)
@@ -708,6 +777,7 @@ tp_status tp_solve_multi(tp_op op, const tp_solve_params* params, int32_t nrhs, 
     check_scheme(P.scheme);
     check_prec(P.prec);
     if (P.solver != TP_CGNR && P.solver != TP_BICGSTAB) TP_THROW(TP_EINVAL, "bad solver");
+    if (P.dagger != 0 && P.dagger != 1) TP_THROW(TP_EINVAL, "dagger must be 0 or 1");
     if (P.scheme == TP_SCHUR4D && P.prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
     if (P.scheme == TP_TEMPORAL_SCHUR3D && P.prec == TP_F16N)
       TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
@@ -719,15 +789,16 @@ tp_status tp_solve_multi(tp_op op, const tp_solve_params* params, int32_t nrhs, 
     Field& eta64 = ws_get_n(op, TP_F64, 62, nrhs);
     Field& x64 = ws_get_n(op, TP_F64, 63, nrhs);
     const double2* w = l4 ? nullptr : op->g->w_d;  // p3 schemes solve in the axial frame
+    const bool g5 = P.dagger != 0;  // M^dagger x = eta  <=>  M (g5 x) = g5 eta
     for (int q = 0; q < nrhs; ++q) {
       Field e = eta64.view(q), xq = x64.view(q);
-      launch_pack(ctx, static_cast<const double2*>(eta[q]), e, l4, false, w);
-      if (P.use_x0) launch_pack(ctx, static_cast<const double2*>(x[q]), xq, l4, false, w);
+      launch_pack(ctx, static_cast<const double2*>(eta[q]), e, l4, g5, w);
+      if (P.use_x0) launch_pack(ctx, static_cast<const double2*>(x[q]), xq, l4, g5, w);
     }
     st = op_solve_multi(op, P, nrhs, x64, eta64, info);
     for (int q = 0; q < nrhs; ++q) {
       Field xq = x64.view(q);
-      launch_unpack(ctx, xq, static_cast<double2*>(x[q]), l4, false, w);
+      launch_unpack(ctx, xq, static_cast<double2*>(x[q]), l4, g5, w);
     }
     HIP_CHECK(hipStreamSynchronize(ctx->stream));
     prof_flush(ctx);

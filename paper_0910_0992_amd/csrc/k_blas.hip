@@ -408,7 +408,7 @@ void blas_impl(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<
   double n = double(npar) * ctx->lat.V2 * nr;
   if (op == B_CONVERT || op == B_MIXED_ACC) {
     if (nr != 1) TP_THROW(TP_EINVAL, "blas: conversions take single fields");
-    ProfScope ps(ctx, KID_BLAS, n * (S + double(y->elem_bytes()) * 12 * (op == B_MIXED_ACC ? 2 : 1)));
+    ProfScope ps(ctx, KID_BLAS_OTHER, n * (S + double(y->elem_bytes()) * 12 * (op == B_MIXED_ACC ? 2 : 1)));
     if (op == B_CONVERT) conv<false>(ctx, par0, npar, *x, *y);
     else conv<true>(ctx, par0, npar, *x, *y);
     return;
@@ -424,7 +424,11 @@ void blas_impl(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<
       case B_ZERO: passes = 1; break;
       default: break;
     }
-    ProfScope ps(ctx, KID_BLAS, n * S * passes);
+    const int kid = op == B_DOT ? KID_BLAS_DOT
+                    : op == B_AXPYZ_NORM ? KID_BLAS_AXPYZ
+                    : op == B_DOT4_TS ? KID_BLAS_DOT4
+                    : op == B_BICG_FUSED ? KID_BLAS_FUSED : KID_BLAS_OTHER;
+    ProfScope ps(ctx, kid, n * S * passes);
     switch (op) {
       case B_ZERO: nb = blas_prec<B_ZERO>(ctx, prec, par0, npar, fs, call); break;
       case B_COPY: nb = blas_prec<B_COPY>(ctx, prec, par0, npar, fs, call); break;

@@ -26,7 +26,8 @@ void launch_line(tp_op op, int prec, int mode, int par, const LineIO& io, Field&
   int nscan = (mode == LM_CRCL || mode == LM_TINV || mode == LM_TDINV) ? 2 : 1;
   int nio = io.pass ? 2 : nscan;  // halves read and written
   double per = nio * 2 * hs + (io.base ? nio * hs : 0);
-  ProfScope ps(op->g->ctx, KID_LINE_CR, double(L.V2) * per * dst.nr);
+  const int kid = mode == LM_CR ? KID_SCAN_CR : (mode == LM_CL ? KID_SCAN_CL : KID_SCAN_OTHER);
+  ProfScope ps(op->g->ctx, kid, double(L.V2) * per * dst.nr);
   TP_DISPATCH(prec, line_, op, mode, par, io, dst)
 }
 

@@ -336,16 +336,16 @@ void schur3d_setup(tp_op op) {
   if (factor_lds() > ctx->lds_max) TP_THROW(TP_EDIMS, "device LDS too small for the M^ee factorisation");
   const int nlines = L.Vs2;
   const int nblk = (nlines + kFacThreads - 1) / kFacThreads;
-  double2* sinv = static_cast<double2*>(dev_alloc(size_t(L.V2) * 144 * sizeof(double2)));
+  double2* sinv = static_cast<double2*>(dev_alloc(ctx, size_t(L.V2) * 144 * sizeof(double2)));
   double2* kmat = nullptr;
   double2* qbuf = nullptr;
   int* bad = nullptr;
   Field w;
   try {
-    kmat = static_cast<double2*>(dev_alloc(size_t(nlines) * 144 * sizeof(double2)));
-    qbuf = static_cast<double2*>(dev_alloc(size_t(nlines) * 144 * sizeof(double2)));
-    bad = static_cast<int*>(dev_alloc(sizeof(int)));
-    w = field_alloc(L, TP_F64);
+    kmat = static_cast<double2*>(dev_alloc(ctx, size_t(nlines) * 144 * sizeof(double2)));
+    qbuf = static_cast<double2*>(dev_alloc(ctx, size_t(nlines) * 144 * sizeof(double2)));
+    bad = static_cast<int*>(dev_alloc(ctx, sizeof(int)));
+    w = field_alloc(ctx, TP_F64);
     HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
     const double2* cl = op->c ? op->c->a3_d : nullptr;  // even parity first
     hipLaunchKernelGGL(k_s3_factor, dim3(nblk), dim3(kFacThreads), factor_lds(), ctx->stream, cl,
@@ -374,15 +374,15 @@ void schur3d_setup(tp_op op) {
     HIP_CHECK(hipStreamSynchronize(ctx->stream));
     if (hb) TP_THROW(TP_ESINGULAR, "M^ee factorisation: zero pivot");
   } catch (...) {
-    field_free(w);
-    dev_free(bad);
-    dev_free(qbuf);
-    dev_free(kmat);
-    dev_free(sinv);
+    field_free(ctx, w);
+    dev_free(ctx, bad);
+    dev_free(ctx, qbuf);
+    dev_free(ctx, kmat);
+    dev_free(ctx, sinv);
     throw;
   }
-  field_free(w);
-  dev_free(bad);
+  field_free(ctx, w);
+  dev_free(ctx, bad);
   op->s3_inv = sinv;
   op->s3_k = kmat;
   op->s3_q = qbuf;  // the first 12 complex per line serve the applies
@@ -395,12 +395,12 @@ void schur3d_setup_f32(tp_op op) {
   tp_ctx ctx = op->g->ctx;
   const Lattice& L = ctx->lat;
   const int64_t ni = L.V2 * 144, nk = int64_t(L.Vs2) * 144;
-  float2* fi = static_cast<float2*>(dev_alloc(size_t(ni) * sizeof(float2)));
+  float2* fi = static_cast<float2*>(dev_alloc(ctx, size_t(ni) * sizeof(float2)));
   float2* fk = nullptr;
   float2* fq = nullptr;
   try {
-    fk = static_cast<float2*>(dev_alloc(size_t(nk) * sizeof(float2)));
-    fq = static_cast<float2*>(dev_alloc(size_t(L.Vs2) * 12 * sizeof(float2)));
+    fk = static_cast<float2*>(dev_alloc(ctx, size_t(nk) * sizeof(float2)));
+    fq = static_cast<float2*>(dev_alloc(ctx, size_t(L.Vs2) * 12 * sizeof(float2)));
     hipLaunchKernelGGL(k_s3_round, dim3(unsigned((ni + 255) / 256)), dim3(256), 0, ctx->stream,
                        op->s3_inv, fi, ni);
     LAUNCH_CHECK();
@@ -409,9 +409,9 @@ void schur3d_setup_f32(tp_op op) {
     LAUNCH_CHECK();
     HIP_CHECK(hipStreamSynchronize(ctx->stream));
   } catch (...) {
-    dev_free(fq);
-    dev_free(fk);
-    dev_free(fi);
+    dev_free(ctx, fq);
+    dev_free(ctx, fk);
+    dev_free(ctx, fi);
     throw;
   }
   op->s3_inv_f = fi;
@@ -420,12 +420,13 @@ void schur3d_setup_f32(tp_op op) {
 }
 
 void schur3d_free(tp_op op) {
-  dev_free(op->s3_inv);
-  dev_free(op->s3_k);
-  dev_free(op->s3_q);
-  dev_free(op->s3_inv_f);
-  dev_free(op->s3_k_f);
-  dev_free(op->s3_q_f);
+  tp_ctx ctx = op->g->ctx;
+  dev_free(ctx, op->s3_inv);
+  dev_free(ctx, op->s3_k);
+  dev_free(ctx, op->s3_q);
+  dev_free(ctx, op->s3_inv_f);
+  dev_free(ctx, op->s3_k_f);
+  dev_free(ctx, op->s3_q_f);
   op->s3_inv = op->s3_k = op->s3_q = nullptr;
   op->s3_inv_f = op->s3_k_f = op->s3_q_f = nullptr;
 }

@@ -202,7 +202,9 @@ __global__ void k_axial_links(const double2* __restrict__ canon, const double2* 
   cx<double> U[9], Wa[9], Wb[9], T1[9], T2[9];
   double ph = (mu == 3 && t == g.Lt - 1) ? b : 1.0;
   const double2* src = canon + ((int64_t)mu * V + n) * 9;
+  bool finite = true;
   for (int k = 0; k < 9; ++k) {
+    finite = finite && isfinite(src[k].x) && isfinite(src[k].y);
     U[k] = cx<double>{ph * src[k].x, ph * src[k].y};
     double2 ea = wd[((int64_t)pa * 9 + k) * V2 + ia];
     double2 eb = wd[((int64_t)pb * 9 + k) * V2 + ib];
@@ -235,6 +237,7 @@ __global__ void k_axial_links(const double2* __restrict__ canon, const double2* 
     } else if (!(dev <= 1e-10)) {
       flags[1] = 1;
     }
+    if (!finite) flags[2] = 1;
   }
   double2* d3 = u3d + ((int64_t)(mu * 2 + pa) * 9) * V2 + ia;
   float2* f3 = u3f + ((int64_t)(mu * 2 + pa) * 9) * V2;
@@ -912,7 +915,7 @@ void launch_clover_force(tp_op op, const Field& x, const Field& lam, double2* gr
   for (int p = 0; p < 6; ++p)
     for (int r = 0; r < 4; ++r)
       for (int q = 0; q < 4; ++q) t.s[p][r][q] = make_double2(sig[p][r][q][0], sig[p][r][q][1]);
-  double2* Y = static_cast<double2*>(dev_alloc(size_t(6) * L.V * 9 * sizeof(double2)));
+  double2* Y = static_cast<double2*>(dev_alloc(ctx, size_t(6) * L.V * 9 * sizeof(double2)));
   try {
     hipLaunchKernelGGL(k_clover_Y, dim3(nblk(L.V, 128)), dim3(128), 0, ctx->stream, x.par<double2>(0),
                        x.par<double2>(1), lam.par<double2>(0), lam.par<double2>(1), Y, L.g, L.V, t,
@@ -923,8 +926,8 @@ void launch_clover_force(tp_op op, const Field& x, const Field& lam, double2* gr
     LAUNCH_CHECK();
     HIP_CHECK(hipStreamSynchronize(ctx->stream));
   } catch (...) {
-    dev_free(Y);
+    dev_free(ctx, Y);
     throw;
   }
-  dev_free(Y);
+  dev_free(ctx, Y);
 }

@@ -492,7 +492,8 @@ int launch_site(tp_op op, int prec, const SiteIO& io, Field& dst, SiteCoef cf, i
   double lk = (cf.c_s != 0 ? 6 * Ls : 0) + (cf.c_t != 0 ? 2 * Lb : 0) + (ck && cf.c_A != 0 ? C : 0);
   double bytes = double(npar) * L.V2 * (dst.nr * sp + lk);
   // the time-line pipeline's stencils are accounted separately from M / residual applies
-  ProfScope ps(ctx, cf.c_t != 0 || io.in2 ? KID_SITE_P3 : KID_HOP, bytes);
+  const int kid = cf.c_t != 0 || io.in2 ? KID_SITE_P3 : (ck && cf.c_A != 0 ? KID_HOP_CLOVER : KID_HOP_DS);
+  ProfScope ps(ctx, kid, bytes);
   switch (prec) {
     case TP_F64: return site_t<double2>(op, io, dst, cf, ck, par0, npar, norm);
     case TP_F32: return site_t<float2>(op, io, dst, cf, ck, par0, npar, norm);

@@ -44,7 +44,7 @@ Field& ws_get_n(tp_op op, int prec, int slot, int nr) {
   auto key = std::make_tuple(prec, slot, nr);
   auto it = op->ws->f.find(key);
   if (it != op->ws->f.end()) return it->second;
-  Field nf = field_alloc(op->g->ctx->lat, prec, nr);
+  Field nf = field_alloc(op->g->ctx, prec, nr);
   return op->ws->f.emplace(key, nf).first->second;
 }
 
@@ -52,7 +52,7 @@ Field& ws_get(tp_op op, int prec, int slot) { return ws_get_n(op, prec, slot, op
 
 void ws_free(tp_op op) {
   if (!op->ws) return;
-  for (auto& kv : op->ws->f) field_free(kv.second);
+  for (auto& kv : op->ws->f) field_free(op->g->ctx, kv.second);
   delete op->ws;
   op->ws = nullptr;
 }

@@ -6,6 +6,7 @@
 
 #include <initializer_list>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "tp_device.h"
@@ -28,18 +29,26 @@ struct TpError {
 #define LAUNCH_CHECK() HIP_CHECK(hipGetLastError())
 
 // ---------------------------------------------------------------- profiling ids
+// One slot per kernel (or per pair of sweep kernels for KID_SCHUR3D_MEE).
 enum KernelId {
   KID_PACK = 0,
   KID_SITE_P3,      // M / D_s / clover / residual on the p3 layout
   KID_SCHUR4D_EO,   // (A+mu)^-1 D_w^eo
-  KID_SCHUR4D_OE,   // (A+mu) psi_o - D_w^oe t_e
-  KID_LINE_CR,      // C_R / C_L / C_R C_L / T^-1 scans
+  KID_SCHUR4D_OE,   // (A+mu) psi_o - D_w^oe t_e (and the other p4 site kernels)
+  KID_SCAN_CR,      // C_R scans
+  KID_SCAN_CL,      // C_L scans
+  KID_SCAN_OTHER,   // C_R C_L, T^-1 and T^dag^-1 scans
   KID_ILU_MID,      // fused scans + clover of the 3D ILU operator (even parity)
-  KID_HOP,          // D_s / clover site kernels feeding the scans
-  KID_BLAS,
+  KID_HOP_DS,       // D_s hop feeding the scans (no clover)
+  KID_HOP_CLOVER,   // A self + D_s hop feeding the scans
+  KID_BLAS_DOT,     // <x, y>
+  KID_BLAS_AXPYZ,   // z = y + a x with |z|^2
+  KID_BLAS_DOT4,    // <t,s>, |t|^2, <rhat,s>, <rhat,t>
+  KID_BLAS_FUSED,   // BiCGStab x, r, p update with |r|^2
+  KID_BLAS_OTHER,   // every other level-1 kernel
   KID_REDUCE,
   KID_FORCE,
-  KID_SCHUR3D_MEE,  // exact (M^ee)^-1 sweeps of the 3D-Schur scheme
+  KID_SCHUR3D_MEE,  // exact (M^ee)^-1: forward and backward sweeps of the 3D-Schur scheme
   KID_COUNT
 };
 extern const char* const kKernelNames[KID_COUNT];
@@ -114,6 +123,13 @@ struct tp_ctx_s {
   double* red_host = nullptr;     // pinned [8]
   // BiCGStab scalars kept on the device (inside red_result's allocation): see BicgSlot
   double* bicg = nullptr;
+  // device memory: registered allocator (null: hipMalloc), live allocations and their sizes
+  tp_alloc_fn alloc_fn = nullptr;
+  tp_free_fn free_fn = nullptr;
+  void* alloc_user = nullptr;
+  std::unordered_map<void*, size_t> live;
+  size_t live_bytes = 0;
+  int nchildren = 0;  // gauge fields created from this context and not yet destroyed
 };
 
 struct tp_gauge_s {
@@ -175,10 +191,13 @@ struct tp_op_s {
 };
 
 // ---------------------------------------------------------------- memory helpers
-void* dev_alloc(size_t bytes);
-void dev_free(void* p);
-Field field_alloc(const Lattice& lat, int prec, int nr = 1);
-void field_free(Field& f);
+// Device memory of a context and of the handles created from it: through the allocator
+// registered with tp_ctx_set_allocator, else hipMalloc / hipFree.  Fields are zeroed on the
+// context's stream.
+void* dev_alloc(tp_ctx ctx, size_t bytes);
+void dev_free(tp_ctx ctx, void* p);
+Field field_alloc(tp_ctx ctx, int prec, int nr = 1);
+void field_free(tp_ctx ctx, Field& f);
 
 // ---------------------------------------------------------------- profiling helpers
 struct ProfScope {
@@ -201,9 +220,9 @@ void launch_unpack(tp_ctx ctx, const Field& src, double2* canon, bool layout4, b
                    const double2* w);
 void launch_pack_links(tp_ctx ctx, tp_gauge g);   // p4 layout (original frame)
 void launch_wline(tp_ctx ctx, tp_gauge g);        // W(t), P from the canonical links
-// p3 layout, axial frame.  flags: two device ints zeroed by the caller; [0] is set when an
+// p3 layout, axial frame.  flags: three device ints zeroed by the caller; [0] is set when an
 // axial-frame spatial link deviates from SU(3) by more than 1e-9, [1] when a time link
-// deviates from unitarity by more than 1e-10
+// deviates from unitarity by more than 1e-10, [2] when an input entry is NaN or Inf
 void launch_axial_links(tp_ctx ctx, tp_gauge g, int* flags);
 // dst = src rounded to FP16 (n complex values)
 void launch_to_half(tp_ctx ctx, const float2* src, __half2* dst, int64_t n);

@@ -4,7 +4,12 @@
  *   c_client --host-checks   argument checks that need no GPU
  *   c_client                 a temporally preconditioned clover solve on a free-field
  *                            lattice, FP16 and FP32 inner precision, whose FP64 residual is
- *                            recomputed here from tp_apply_M
+ *                            recomputed here from tp_apply_M; a dagger solve checked the same
+ *                            way; links with a NaN refused
+ *   c_client --allocator     every device allocation of the library goes through a counting
+ *                            allocator registered with tp_ctx_set_allocator: the device's free
+ *                            memory drops by what the allocator handed out, and the destroy
+ *                            calls free all of it
  */
 #include <hip/hip_runtime_api.h>
 #include <math.h>
@@ -23,6 +28,100 @@
     }                                                                                     \
   } while (0)
 
+/* Counting allocator over hipMalloc. */
+typedef struct {
+  long n_alloc, n_free;
+  size_t live, peak;
+} counter_t;
+
+static void* count_alloc(size_t bytes, void* stream, void* user) {
+  counter_t* c = (counter_t*)user;
+  void* p = NULL;
+  (void)stream;
+  if (hipMalloc(&p, bytes) != hipSuccess) return NULL;
+  c->n_alloc++;
+  c->live += bytes;
+  if (c->live > c->peak) c->peak = c->live;
+  return p;
+}
+
+static void count_free(void* p, size_t bytes, void* stream, void* user) {
+  counter_t* c = (counter_t*)user;
+  (void)stream;
+  c->n_free++;
+  c->live -= bytes;
+  hipFree(p);
+}
+
+/* One clover solve on a 16^3x16 free field with the counting allocator; with `measure`, the
+ * device's free memory before and after the set-up and solve is compared with the allocator. */
+static int allocator_pass(int measure) {
+  const int32_t dims[4] = {16, 16, 16, 16};
+  const size_t V = 16 * 16 * 16 * 16;
+  const size_t nsp = V * 12, nlk = 4 * V * 9;
+  double* links = (double*)calloc(2 * nlk, sizeof(double));
+  double* eta = (double*)calloc(2 * nsp, sizeof(double));
+  for (size_t l = 0; l < 4 * V; ++l)
+    for (int a = 0; a < 3; ++a) links[2 * (l * 9 + 4 * a)] = 1.0;
+  eta[2 * 7] = 1.0;
+  void *d_eta, *d_x;
+  if (hipMalloc(&d_eta, 2 * nsp * sizeof(double)) != hipSuccess) return 1;
+  if (hipMalloc(&d_x, 2 * nsp * sizeof(double)) != hipSuccess) return 1;
+  if (hipMemcpy(d_eta, eta, 2 * nsp * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) return 1;
+  if (hipDeviceSynchronize() != hipSuccess) return 1;
+  size_t free0 = 0, free1 = 0, total = 0;
+  if (hipMemGetInfo(&free0, &total) != hipSuccess) return 1;
+  counter_t cnt = {0, 0, 0, 0};
+  tp_ctx ctx;
+  tp_gauge g;
+  tp_clover c;
+  tp_op op;
+  CHECK(tp_ctx_create(dims, -1, 0, &ctx));
+  CHECK(tp_ctx_set_allocator(ctx, count_alloc, count_free, &cnt));
+  CHECK(tp_gauge_create(ctx, links, TP_HOST, &g));
+  if (tp_ctx_set_allocator(ctx, NULL, NULL, NULL) != TP_EINVAL) return 1; /* too late */
+  CHECK(tp_clover_create(g, 0.5, 1.0, &c));
+  CHECK(tp_op_create(g, c, -0.05, 2.0, &op));
+  tp_solve_params P;
+  memset(&P, 0, sizeof P);
+  P.scheme = TP_TEMPORAL_SCHUR;
+  P.solver = TP_BICGSTAB;
+  P.prec = TP_F16N;
+  P.tol = 1e-10;
+  tp_solve_info info;
+  CHECK(tp_solve(op, &P, d_x, d_eta, &info));
+  P.scheme = TP_SCHUR4D;
+  P.prec = TP_F64;
+  CHECK(tp_solve(op, &P, d_x, d_eta, &info));
+  if (hipDeviceSynchronize() != hipSuccess) return 1;
+  if (hipMemGetInfo(&free1, &total) != hipSuccess) return 1;
+  size_t lib_bytes = 0;
+  CHECK(tp_ctx_device_bytes(ctx, &lib_bytes));
+  const double drop = (double)free0 - (double)free1;
+  if (measure)
+    printf("allocator: %ld allocations, %.1f MB live (library reports %.1f MB), device free memory "
+           "dropped by %.1f MB\n", cnt.n_alloc, cnt.live / 1e6, lib_bytes / 1e6, drop / 1e6);
+  if (lib_bytes != cnt.live || cnt.n_alloc == 0) return 1;
+  /* everything the device lost went through the allocator (up to page rounding) */
+  if (measure && (drop < 0.99 * (double)cnt.live || drop > (double)cnt.live + 4.0 * (1 << 20))) {
+    printf("device memory not accounted for by the allocator\n");
+    return 1;
+  }
+  CHECK(tp_op_destroy(op));
+  CHECK(tp_clover_destroy(c));
+  CHECK(tp_gauge_destroy(g));
+  CHECK(tp_ctx_destroy(ctx));
+  if (cnt.live != 0 || cnt.n_free != cnt.n_alloc) {
+    printf("allocator: %ld allocations, %ld frees, %zu bytes left\n", cnt.n_alloc, cnt.n_free, cnt.live);
+    return 1;
+  }
+  hipFree(d_eta);
+  hipFree(d_x);
+  free(links);
+  free(eta);
+  return 0;
+}
+
 static int host_checks(void) {
   tp_ctx ctx = NULL;
   const int32_t odd[4] = {3, 4, 4, 8};
@@ -31,6 +130,8 @@ static int host_checks(void) {
   if (tp_ctx_create(ok, 0, 0, &ctx) != TP_EINVAL) return 1;
   if (tp_solve(NULL, NULL, NULL, NULL, NULL) != TP_EINVAL) return 1;
   if (tp_force(NULL, NULL, NULL, NULL, 0) != TP_EINVAL) return 1;
+  if (tp_ctx_set_allocator(NULL, count_alloc, count_free, NULL) != TP_EINVAL) return 1;
+  if (tp_op_mass(NULL, NULL) != TP_EINVAL) return 1;
   if (strcmp(tp_status_string(TP_ENOCONV), "solver did not converge") != 0) return 1;
   printf("host checks ok\n");
   return 0;
@@ -38,6 +139,12 @@ static int host_checks(void) {
 
 int main(int argc, char** argv) {
   if (argc > 1 && strcmp(argv[1], "--host-checks") == 0) return host_checks();
+  if (argc > 1 && strcmp(argv[1], "--allocator") == 0) {
+    /* the first pass loads the code objects; the second is measured */
+    if (allocator_pass(0) || allocator_pass(1)) return 1;
+    printf("allocator ok\n");
+    return 0;
+  }
   const int32_t dims[4] = {4, 4, 4, 8};
   const size_t V = 4 * 4 * 4 * 8;
   const size_t nsp = V * 12, nlk = 4 * V * 9;
@@ -56,6 +163,9 @@ int main(int argc, char** argv) {
   CHECK(tp_gauge_create(ctx, links, TP_HOST, &g));
   CHECK(tp_clover_create(g, 0.5, 1.0, &c));
   CHECK(tp_op_create(g, c, -0.05, 2.0, &op));
+  double mu = 0;
+  CHECK(tp_op_mass(op, &mu));
+  if (fabs(mu - (-0.05 + 1.0 + 3.0 / 2.0)) > 1e-15) return 1;
   void *d_eta, *d_x, *d_mx;
   if (hipMalloc(&d_eta, 2 * nsp * sizeof(double)) != hipSuccess) return 1;
   if (hipMalloc(&d_x, 2 * nsp * sizeof(double)) != hipSuccess) return 1;
@@ -83,6 +193,24 @@ int main(int argc, char** argv) {
     printf("prec %d: %d iterations, reported %.3e, recomputed %.3e\n", (int)precs[k], (int)info.iters,
            info.true_rel_resid, rel);
     if (!(info.true_rel_resid <= 1e-10) || !(rel <= 1.05e-10)) return 1;
+    /* M^dagger x = eta, checked with tp_apply_M(dagger = 1) */
+    P.dagger = 1;
+    CHECK(tp_solve(op, &P, d_x, d_eta, &info));
+    CHECK(tp_apply_M(op, TP_F64, d_mx, d_x, 1));
+    if (hipDeviceSynchronize() != hipSuccess) return 1;
+    if (hipMemcpy(out, d_mx, 2 * nsp * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return 1;
+    r2 = 0;
+    for (size_t q = 0; q < 2 * nsp; ++q) r2 += (eta[q] - out[q]) * (eta[q] - out[q]);
+    printf("prec %d dagger: %d iterations, recomputed %.3e\n", (int)precs[k], (int)info.iters,
+           sqrt(r2 / e2));
+    if (!(sqrt(r2 / e2) <= 1.05e-10)) return 1;
+  }
+  {
+    /* links with a NaN are refused */
+    tp_gauge gbad = NULL;
+    links[2 * (9 * 17 + 4) + 1] = NAN;
+    if (tp_gauge_create(ctx, links, TP_HOST, &gbad) != TP_EINVAL || gbad) return 1;
+    links[2 * (9 * 17 + 4) + 1] = 0.0;
   }
   hipFree(d_eta);
   hipFree(d_x);

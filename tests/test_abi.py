@@ -75,4 +75,4 @@ def test_null_handles_rejected(lib):
 def test_kernel_profile_names(lib):
     n = lib.tp_prof_count()
     names = [lib.tp_prof_name(k).decode() for k in range(n)]
-    assert "ilu_mid" in names and "line_scan" in names and len(set(names)) == n
+    assert "ilu_mid" in names and "scan_cr" in names and "hop_ds" in names and len(set(names)) == n

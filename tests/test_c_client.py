@@ -38,3 +38,11 @@ def test_c_client_solve(client):
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "solve ok" in r.stdout
+
+
+@pytest.mark.gpu
+def test_c_client_allocator(client):
+    r = subprocess.run([client, "--allocator"], capture_output=True, text=True, timeout=180)
+    print(r.stdout)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "allocator ok" in r.stdout

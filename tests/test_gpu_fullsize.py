@@ -174,11 +174,17 @@ def test_point_sources_24x128():
         g.close()
 
 
-@pytest.mark.parametrize("clover", [False, True])
-def test_gradient_fd_12x64(clover):
+_GRAD_F64 = {}
+
+
+@pytest.mark.parametrize("clover,prec", [(False, "F64"), (True, "F64"), (True, "F32")])
+def test_gradient_fd_12x64(clover, prec):
     """d|M^-1 eta|^2 / dh for U -> exp(i h omega) U against the autograd link gradient
     (hopping and SW-term parts; the clover term is rebuilt from the perturbed links), and the
-    source gradient."""
+    source gradient.  prec is the inner precision of the autograd solves: FP64, or FP32 with
+    FP64 reliable updates ("FP32-refined", to the same 1e-13 true residual); the finite
+    differences always use FP64 solves.  The FP32-refined gradients must also agree with the
+    FP64 ones."""
     from paper_0910_0992_amd import Operator
     from paper_0910_0992_amd.api import SolveFn
     cfg = synth.WORKLOADS["clover_12x64"]
@@ -197,12 +203,19 @@ def test_gradient_fd_12x64(clover):
 
     links = torch.from_numpy(U).cuda().requires_grad_(True)
     te = torch.from_numpy(eta).cuda().requires_grad_(True)
-    x = SolveFn.apply(links, te, m0, xi, c_s, c_t, -1, "TEMPORAL_SCHUR", "F64", 1e-13)
+    x = SolveFn.apply(links, te, m0, xi, c_s, c_t, -1, "TEMPORAL_SCHUR", prec, 1e-13)
     L = torch.vdot(x.flatten(), x.flatten()).real
     L.backward()
     gU = _np(links.grad)
     gE = _np(te.grad)
     L0 = L.item()
+    if prec == "F64":
+        _GRAD_F64[clover] = (gU, gE)
+    elif clover in _GRAD_F64:
+        rU = np.linalg.norm(gU - _GRAD_F64[clover][0]) / np.linalg.norm(_GRAD_F64[clover][0])
+        rE = np.linalg.norm(gE - _GRAD_F64[clover][1]) / np.linalg.norm(_GRAD_F64[clover][1])
+        print(f"[fullsize] {prec}-refined gradients vs FP64: links {rU:.2e}, source {rE:.2e}", flush=True)
+        assert rU < 1e-9 and rE < 1e-9, (rU, rE)
     assert abs(loss(U) - L0) < 1e-12 * L0
     h = 1e-6
     worst = 0.0

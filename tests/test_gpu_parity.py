@@ -5,6 +5,10 @@ Tolerances (relative l2 over the whole field):
   F32  3e-6 single kernels, 2e-5 composites   (FP32 rounding, ~2^-24 per op times depth)
   F16N 4e-3 single kernels, 1.5e-2 composites (FP16 storage, 2^-11 relative per stored half
        spinor, scaled by its largest component)
+Beside the global l2, every comparison bounds the worst site: max over sites of |error(x)|
+divided by max over sites of |reference(x)| must stay below twice the same tolerance, so an
+error confined to a few sites (which the global l2 dilutes by the square root of the volume)
+fails as well.
 Lattices span several workgroups, ragged line counts, time extents that are not
 powers of two, and the scan's fast path (time extents that are multiples of 16,
 up to 16 wavefront segments of 16 chunks per line).
@@ -53,9 +57,22 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def _site_rel(a, b):
+    """max_x |a(x) - b(x)| / max_x |b(x)| over sites (the last two axes are one site's
+    spin-colour components, or one link's colour matrix)."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    n = a.shape[-1] * a.shape[-2]
+    da = np.linalg.norm((a - b).reshape(-1, n), axis=1)
+    nb = np.linalg.norm(b.reshape(-1, n), axis=1)
+    return float(da.max() / nb.max())
+
+
 def _close(a, b, tol, what=""):
     err = _rel(a, b)
     assert err < tol, f"{what}: relative error {err:.3e} >= {tol:.1e}"
+    serr = _site_rel(a, b)
+    assert serr < 2 * tol, f"{what}: worst-site relative error {serr:.3e} >= {2 * tol:.1e}"
 
 
 @pytest.fixture(scope="module", params=list(CASES))
@@ -81,7 +98,7 @@ def _np(t):
 @pytest.mark.parametrize("prec", ["F64", "F32", "F16N"])
 def test_apply_M(case, prec):
     o, g = case["oop"], case["gop"]
-    tol = TOL[prec][0] * 2
+    tol = TOL[prec][0] * (1 if prec == "F64" else 2)
     _close(_np(g.apply_M(case["teta"], prec)), o.M(case["eta"]), tol, '_np(g.apply_M(case["teta"], prec)), o.M(')
     _close(_np(g.apply_M(case["teta"], prec, dagger=True)), o.Mdag(case["eta"]), tol, '_np(g.apply_M(case["teta"], prec, dagger')
 
@@ -89,13 +106,13 @@ def test_apply_M(case, prec):
 @pytest.mark.parametrize("prec", ["F64", "F32", "F16N"])
 def test_apply_Ds(case, prec):
     o, g = case["oop"], case["gop"]
-    _close(_np(g.apply_Ds(case["teta"], prec)), o.Ds(case["eta"]), TOL[prec][0] * 2, '_np(g.apply_Ds(case["teta"], prec)), o.D')
+    _close(_np(g.apply_Ds(case["teta"], prec)), o.Ds(case["eta"]), TOL[prec][0] * (1 if prec == "F64" else 2), '_np(g.apply_Ds(case["teta"], prec)), o.D')
 
 
 @pytest.mark.parametrize("prec", ["F64", "F32"])
 def test_apply_clover(case, prec):
     o, g = case["oop"], case["gop"]
-    tol = TOL[prec][0] * 2
+    tol = TOL[prec][0] * (1 if prec == "F64" else 2)
     if o.clover:
         _close(_np(g.apply_clover(case["teta"], prec, 0)), o.Aop(case["eta"]), tol, '_np(g.apply_clover(case["teta"], prec, 0')
     _close(_np(g.apply_clover(case["teta"], prec, 1)), o.Amu(case["eta"]), tol, '_np(g.apply_clover(case["teta"], prec, 1')
@@ -345,8 +362,9 @@ def test_site_kernels_in_tile_order(dims):
         m = oop.M(eta)
         ts = oop.tschur(eta)
         for prec in ("F64", "F32", "F16N"):
-            _close(_np(gop.apply_M(teta, prec)), m, TOL[prec][0] * 2, f"M {prec}")
-            _close(_np(gop.apply_Ds(teta, prec)), oop.Ds(eta), TOL[prec][0] * 2, f"D_s {prec}")
+            t1 = TOL[prec][0] * (1 if prec == "F64" else 2)
+            _close(_np(gop.apply_M(teta, prec)), m, t1, f"M {prec}")
+            _close(_np(gop.apply_Ds(teta, prec)), oop.Ds(eta), t1, f"D_s {prec}")
             _close(_np(gop.apply_prec(teta, "TEMPORAL_SCHUR", prec=prec)), ts, TOL[prec][1],
                    f"TEMPORAL_SCHUR {prec}")
     finally:
@@ -380,3 +398,95 @@ def test_schur3d_even_block_inverse(case):
     f = _np(g.prepare_source(case["teta"], "TEMPORAL_SCHUR3D", "F64"))
     back = _np(g.apply_M(torch.from_numpy(e * f).cuda(), "F64"))
     _close(e * back, e * case["eta"], 1e-12, "M^ee (M^ee)^-1 eta_e")
+
+
+@pytest.mark.parametrize("scheme,prec", [("TEMPORAL_SCHUR", "F16N"), ("TEMPORAL_SCHUR", "F64"),
+                                         ("SCHUR4D", "F64"), ("TEMPORAL_SCHUR3D", "F32")])
+def test_solve_dagger(case, scheme, prec):
+    """M^dagger x = eta (tp_solve with dagger): the oracle's M^dagger residual of the solution,
+    single and batched."""
+    o, g = case["oop"], case["gop"]
+    x, info = g.solve(case["teta"], scheme=scheme, prec=prec, tol=1e-10, dagger=True)
+    true = np.linalg.norm(case["eta"] - o.Mdag(_np(x))) / np.linalg.norm(case["eta"])
+    assert info["true_rel_resid"] <= 1e-10 and true <= 1.05e-10, (info, true)
+    e2 = synth.make_source(case["dims"], 2004)
+    xs, infos = g.solve_multi([case["teta"], torch.from_numpy(e2).cuda()], scheme=scheme, prec=prec,
+                              tol=1e-10, dagger=True)
+    xs = _np(xs)
+    for k, e in enumerate([case["eta"], e2]):
+        true = np.linalg.norm(e - o.Mdag(xs[k])) / np.linalg.norm(e)
+        assert true <= 1.05e-10, (k, infos[k], true)
+
+
+def test_allocator_accounting(case):
+    """With torch's caching allocator registered (the binding's default) every device byte
+    the library holds is torch memory, and closing the operator returns all of it; an
+    operator on hipMalloc gives bit-identical results."""
+    from paper_0910_0992_amd import Operator
+    dims, xi, bc = case["dims"], case["xi"], case["bc"]
+    o = case["oop"]
+    torch.cuda.synchronize()
+    m0 = torch.cuda.memory_allocated()
+    gt = Operator(torch.from_numpy(case["U"]).cuda(), case["m0"], xi, o.c_s, o.c_t, bc)
+    gh = Operator(torch.from_numpy(case["U"]).cuda(), case["m0"], xi, o.c_s, o.c_t, bc, allocator="hip")
+    try:
+        yt = gt.apply_prec(case["teta"], "TEMPORAL_SCHUR", "F16N")
+        yh = gh.apply_prec(case["teta"], "TEMPORAL_SCHUR", "F16N")
+        assert torch.equal(yt, yh)
+        torch.cuda.synchronize()
+        lib = gt.device_bytes()
+        held = torch.cuda.memory_allocated() - m0 - 2 * yt.numel() * yt.element_size()
+        assert lib > 0 and lib <= held <= lib + 512 * 1024, (lib, held)
+    finally:
+        gt.close()
+        gh.close()
+    del yt, yh
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == m0
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_kappa_free_field(scheme):
+    """The library's Lanczos estimate of kappa(Mt^dag Mt) from its CGNR coefficients, on the
+    free field 4^3x16 (xi = 3, m0 = -0.05), against the momentum-space closed form."""
+    import _momentum as mom
+    from paper_0910_0992_amd import Operator
+    dims = (4, 4, 4, 16)
+    g = Operator(torch.from_numpy(synth.unit_links(dims)).cuda(), -0.05, 3.0, 0.0, 0.0, -1)
+    try:
+        eta = torch.from_numpy(synth.make_source(dims, 2009)).cuda()
+        _, info = g.solve(eta, scheme=scheme, solver="CGNR", prec="F64", tol=1e-12, estimate_kappa=True)
+    finally:
+        g.close()
+    ref = mom.kappa_free(dims, -0.05, 3.0, -1.0, scheme)
+    assert abs(info["kappa_est"] / ref - 1) < 0.01, (scheme, info["kappa_est"], ref)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_kappa_interacting(scheme):
+    """kappa on random clover links (4^3x16): the library's estimate against the oracle's
+    Lanczos estimate from its own CGNR on the same prepared source."""
+    from paper_0910_0992_amd import Operator
+    dims, xi, m0 = (4, 4, 4, 16), 3.0, -0.05
+    U = synth.make_links(dims, 0.35, 0.12, 1000)
+    oop = OOp(U, m0, xi, -1.0, 1.6 / xi, 1.0)
+    eta = synth.make_source(dims, 2000)
+    g = Operator(torch.from_numpy(U).cuda(), m0, xi, 1.6 / xi, 1.0, -1)
+    try:
+        _, info = g.solve(torch.from_numpy(eta).cuda(), scheme=scheme, solver="CGNR", prec="F64",
+                          tol=1e-12, estimate_kappa=True)
+    finally:
+        g.close()
+    et = oop.prepare_source(scheme, eta)
+    mask, _ = oop.solve_subspace(scheme)
+    if mask is None:
+        A = lambda v: oop.prec(scheme, v)
+        Ad = lambda v: oop.prec_dag(scheme, v)
+    else:
+        A = lambda v: mask * oop.prec(scheme, mask * v)
+        Ad = lambda v: mask * oop.prec_dag(scheme, mask * v)
+        et = mask * et
+    _, oi = krylov.cgnr(A, Ad, et, 1e-12)
+    lmin, lmax, kap = krylov.lanczos_kappa(oi["alphas"], oi["betas"])
+    assert abs(info["kappa_est"] / kap - 1) < 0.01, (scheme, info["kappa_est"], kap)
+    assert abs(info["lambda_max"] / lmax - 1) < 0.01 and abs(info["lambda_min"] / lmin - 1) < 0.01

@@ -176,6 +176,19 @@ tp_status tp_apply_CR(tp_op op, int32_t prec, void* dst, const void* src);
  *   diag(1, C_L^o S_o C_R^o) in p3 parity. */
 tp_status tp_apply_prec(tp_op op, int32_t scheme, int32_t prec, void* dst, const void* src,
                         int32_t dagger);
+/* tp_apply_prec for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation).  Same arguments, same
+ * result; its work fields come from a fixed 64 MiB device array of the library (held by
+ * every device the library runs on until the process ends) instead of the allocator, and it
+ * calls no allocation routine.  Takes (fields of the apply's precision) x V x field bytes:
+ * 2 (UNPREC), 3 (SCHUR4D), 4 (TEMPORAL), 6 (TEMPORAL_SCHUR), 7 (TEMPORAL_SCHUR3D), with
+ * V x 192 bytes per F64 field, V x 96 per F32 and V x 56 per F16N; a lattice that needs more
+ * than 64 MiB is refused with TP_EINVAL, as is TEMPORAL_SCHUR3D before a tp_apply_prec of
+ * that scheme and precision has built its factors.  All calls on one device share the
+ * array: calls that overlap on one device (other streams, threads or contexts) race, and
+ * the caller serialises them.  No per-kernel timing events are recorded. */
+tp_status tp_apply_prec_noalloc(tp_op op, int32_t scheme, int32_t prec, void* dst, const void* src,
+                                int32_t dagger);
 /* eta~ = S_L eta and x = S_R y, with M = S_L^-1 Mt S_R^-1 for `scheme`
  * (SCHUR4D: S_L = L^-1, S_R = U^-1 of the LDU factorisation, Sec. II.B;
  * TEMPORAL_SCHUR3D: S_L = diag((M^ee)^-1, C_L^o) L^-1, S_R = U^-1 diag(1, C_R^o) with the

@@ -71,6 +71,7 @@ SIGNATURES = [
     ("tp_apply_CL", [_P, _I, _P, _P], _I),
     ("tp_apply_CR", [_P, _I, _P, _P], _I),
     ("tp_apply_prec", [_P, _I, _I, _P, _P, _I], _I),
+    ("tp_apply_prec_noalloc", [_P, _I, _I, _P, _P, _I], _I),
     ("tp_prepare_source", [_P, _I, _I, _P, _P], _I),
     ("tp_reconstruct", [_P, _I, _I, _P, _P], _I),
     ("tp_solve", [_P, C.POINTER(SolveParams), _P, _P, C.POINTER(SolveInfo)], _I),

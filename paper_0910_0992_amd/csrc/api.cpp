@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <complex>
+#include <mutex>
 #include <vector>
 
 #include "tp_internal.h"
@@ -171,6 +172,13 @@ void dev_free(tp_ctx ctx, void* p) {
   else (void)hipFree(p);
 }
 
+size_t field_bytes(const Lattice& lat, int prec, int nr) {
+  const size_t eb = prec == TP_F64 ? 16 : (prec == TP_F32 ? 8 : 4);
+  size_t db = (size_t(nr) * 2 * 12 * lat.V2 * eb + 255) & ~size_t(255);
+  if (prec == TP_F16N) db += (size_t(nr) * 2 * 2 * lat.V2 * sizeof(float) + 255) & ~size_t(255);
+  return db;
+}
+
 Field field_alloc(tp_ctx ctx, int prec, int nr) {
   const Lattice& lat = ctx->lat;
   Field f;
@@ -234,6 +242,45 @@ void prof_flush(tp_ctx ctx) {
     s.bytes += ctx->ev_pending[k].bytes;
   }
   ctx->ev_used = 0;
+}
+
+// ---------------------------------------------------------------- fixed scratch
+// Device memory of tp_apply_prec_noalloc: a file-scope array that every device the library
+// runs on holds from the library's first use on it until the process ends.  Host code
+// never uses the array's name as an address: its device address is taken once per device
+// with hipGetSymbolAddress (with that device current) at context creation, and kept.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+char* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+// Device address of `scratch` on `device`, which must be the current device.
+char* scratch_address(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) TP_THROW(TP_EINVAL, "device ordinal");
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) TP_THROW(TP_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_dev[device] = static_cast<char*>(p);
+  }
+  return g_scratch_dev[device];
+}
+
+// Workspace fields an apply of `scheme` takes (the packed input and output, and the composite
+// operator's temporaries), all of the apply's precision.
+int noalloc_fields(int scheme) {
+  switch (scheme) {
+    case TP_UNPREC: return 2;
+    case TP_SCHUR4D: return 3;
+    case TP_TEMPORAL: return 4;
+    case TP_TEMPORAL_SCHUR: return 6;
+    default: return 7;  // TP_TEMPORAL_SCHUR3D
+  }
 }
 
 // The context's own device buffers: reduction partials and results, and the solver's
@@ -315,6 +362,7 @@ tp_status tp_ctx_create(const int32_t dims[4], int32_t bc_t, int32_t device, tp_
       int lds = 0;
       HIP_CHECK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
       c->lds_max = size_t(lds);
+      c->scratch = scratch_address(device);
       ctx_buffers_alloc(c);
       HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&c->red_host), sizeof(double) * 8 * kMaxRhs,
                               hipHostMallocDefault));
@@ -685,6 +733,49 @@ tp_status tp_apply_prec(tp_op op, int32_t scheme, int32_t prec, void* dst, const
     if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
     if (scheme == TP_TEMPORAL_SCHUR3D && prec == TP_F16N)
       TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
+    tp_status s = apply_wrap(op, prec, dst, src, scheme_layout4(scheme), dagger != 0,
+                             [&](Field& a, Field& b) { op_apply_prec(op, scheme, prec, a, b, false); });
+    if (s != TP_OK) TP_THROW(s, g_last_error);
+  });
+}
+
+tp_status tp_apply_prec_noalloc(tp_op op, int32_t scheme, int32_t prec, void* dst, const void* src,
+                                int32_t dagger) {
+  return guard([&] {
+    need(op, "op");
+    check_scheme(scheme);
+    check_prec(prec);
+    if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
+    if (scheme == TP_TEMPORAL_SCHUR3D && prec == TP_F16N)
+      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
+    if (scheme == TP_TEMPORAL_SCHUR3D &&
+        !(prec == TP_F64 ? static_cast<const void*>(op->s3_inv) : static_cast<const void*>(op->s3_inv_f)))
+      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D: its factors are built (and allocated) by the first "
+                          "tp_apply_prec of the scheme in this precision");
+    tp_ctx ctx = op->g->ctx;
+    const size_t needb = size_t(noalloc_fields(scheme)) * field_bytes(ctx->lat, prec);
+    if (needb > kScratchBytes)
+      TP_THROW(TP_EINVAL, "lattice too large for the no-allocation scratch (" +
+                              std::to_string(needb >> 20) + " MiB needed, " +
+                              std::to_string(kScratchBytes >> 20) + " MiB available)");
+    if (!ctx->scratch) TP_THROW(TP_EHIP, "no scratch address on this device");
+    // workspace fields from the scratch array; no profiling events (they would be created)
+    struct Scope {
+      tp_op op;
+      bool prof;
+      Scope(tp_op o, char* base) : op(o), prof(o->g->ctx->prof) {
+        op->arena = base;
+        op->arena_cap = kScratchBytes;
+        op->arena_top = 0;
+        op->arena_n = 0;
+        op->g->ctx->prof = false;
+      }
+      ~Scope() {
+        op->arena = nullptr;
+        op->arena_n = 0;
+        op->g->ctx->prof = prof;
+      }
+    } scope(op, ctx->scratch);
     tp_status s = apply_wrap(op, prec, dst, src, scheme_layout4(scheme), dagger != 0,
                              [&](Field& a, Field& b) { op_apply_prec(op, scheme, prec, a, b, false); });
     if (s != TP_OK) TP_THROW(s, g_last_error);

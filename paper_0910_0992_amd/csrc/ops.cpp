@@ -39,7 +39,39 @@ struct Workspace {
   std::map<std::tuple<int, int, int>, Field> f;
 };
 
+// A workspace field carved from the no-allocation arena (one per (prec, slot, nr) and call),
+// cleared by a fill kernel on first use.
+Field& arena_get(tp_op op, int prec, int slot, int nr) {
+  for (int k = 0; k < op->arena_n; ++k) {
+    auto& a = op->arena_slots[k];
+    if (a.prec == prec && a.slot == slot && a.nr == nr) return a.f;
+  }
+  const Lattice& lat = op->g->ctx->lat;
+  const size_t need = field_bytes(lat, prec, nr);
+  if (op->arena_n == tp_op_s::kArenaSlots || op->arena_top + need > op->arena_cap)
+    TP_THROW(TP_EINVAL, "no-allocation scratch exhausted");
+  Field f;
+  f.prec = prec;
+  f.V2 = lat.V2;
+  f.nr = nr;
+  f.data = op->arena + op->arena_top;
+  if (prec == TP_F16N) {
+    const size_t db = size_t(nr) * 2 * 12 * lat.V2 * f.elem_bytes();
+    f.nrm = reinterpret_cast<float*>(op->arena + op->arena_top + ((db + 255) & ~size_t(255)));
+  }
+  f.owned = false;
+  op->arena_top += need;
+  auto& a = op->arena_slots[op->arena_n++];
+  a.prec = prec;
+  a.slot = slot;
+  a.nr = nr;
+  a.f = f;
+  blas(op->g->ctx, B_ZERO, 0, 2, {nullptr, &a.f});
+  return a.f;
+}
+
 Field& ws_get_n(tp_op op, int prec, int slot, int nr) {
+  if (op->arena) return arena_get(op, prec, slot, nr);
   if (!op->ws) op->ws = new Workspace();
   auto key = std::make_tuple(prec, slot, nr);
   auto it = op->ws->f.find(key);

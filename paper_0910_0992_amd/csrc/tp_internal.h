@@ -130,6 +130,9 @@ struct tp_ctx_s {
   std::unordered_map<void*, size_t> live;
   size_t live_bytes = 0;
   int nchildren = 0;  // gauge fields created from this context and not yet destroyed
+  // device address of the library's fixed scratch array on this context's device
+  // (tp_apply_prec_noalloc)
+  char* scratch = nullptr;
 };
 
 struct tp_gauge_s {
@@ -188,6 +191,18 @@ struct tp_op_s {
   float2* s3_q_f = nullptr;
   Workspace* ws = nullptr;
   int batch_nr = 1;  // right-hand sides of the batched apply in progress (workspace size)
+  // No-allocation mode (tp_apply_prec_noalloc): while arena is set, workspace fields are
+  // carved from that fixed device region for the duration of one call instead of being
+  // allocated; at most kArenaSlots distinct fields.
+  struct ArenaSlot {
+    int prec, slot, nr;
+    Field f;
+  };
+  static constexpr int kArenaSlots = 16;
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_top = 0;
+  ArenaSlot arena_slots[kArenaSlots];
+  int arena_n = 0;
 };
 
 // ---------------------------------------------------------------- memory helpers
@@ -198,6 +213,8 @@ void* dev_alloc(tp_ctx ctx, size_t bytes);
 void dev_free(tp_ctx ctx, void* p);
 Field field_alloc(tp_ctx ctx, int prec, int nr = 1);
 void field_free(tp_ctx ctx, Field& f);
+// Device bytes of one field of `prec` (data, and the FP32 scales of F16N), 256-byte aligned.
+size_t field_bytes(const Lattice& lat, int prec, int nr = 1);
 
 // ---------------------------------------------------------------- profiling helpers
 struct ProfScope {

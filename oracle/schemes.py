@@ -52,7 +52,7 @@ def parity_masks(dims, four_d: bool):
 class Operator:
     """M = A + mu - D_t - D_s/gamma_f bound to links, mass, anisotropy, clover and BC."""
 
-    def __init__(self, U, m0, gamma_f, b=-1.0, c_s=0.0, c_t=0.0):
+    def __init__(self, U, m0, gamma_f, b=-1.0, c_s=0.0, c_t=0.0, cutoff_eps=0.0):
         self.U = U
         self.m0 = m0
         self.gamma_f = gamma_f
@@ -62,7 +62,9 @@ class Operator:
         self.dims = (U.shape[4], U.shape[3], U.shape[2], U.shape[1])
         self.clover = (c_s != 0.0) or (c_t != 0.0)
         self.A = W.clover_field(U, c_s, c_t) if self.clover else None
-        self.tmp = Temporal(U, self.mu, b)
+        # cutoff_eps > 0: the cutoff trick in every T^-1 and T^dagger^-1 (C_L, C_R, and so the
+        # App. B sequence, S_L and S_R of TEMPORAL_SCHUR built from them)
+        self.tmp = Temporal(U, self.mu, b, cutoff_eps)
         self.e3, self.o3 = parity_masks(self.dims, False)
         self.e4, self.o4 = parity_masks(self.dims, True)
         self._Amu_inv = None

@@ -21,6 +21,11 @@ substitution from t=0, V' = -b U_t(Nt-1)^dagger in time slice 0 and W' selecting
 time slice Nt-1, so X'(Nt-1) builds up to the adjoint Polyakov loop.
 
 C_L = P+ + P- T^-1 and C_R = P- + P+ T^dagger^-1 with P+- = (1 +- gamma_t)/2.
+
+The cutoff trick (Sec. II.A, eq:cutoff): X(t) is a product of unitary time links divided by
+mu^(Nt-t), so ||X(t)||_F = sqrt(3) mu^-(Nt-t); where that bound is below a threshold eps the
+correction X(t) q is dropped (X(t) set to zero).  For T^dagger the suppression runs the other
+way, ||X'(t)||_F = sqrt(3) mu^-(t+1).  eps = 0 keeps the exact inverse.
 """
 import numpy as np
 
@@ -66,8 +71,17 @@ def smw_setup_dag(Ut, mu, b=-1.0):
     return X, lam
 
 
-def apply_Tinv(Ut, eta, mu, b=-1.0, setup=None):
-    """psi = T^-1 eta on every spin component of eta [Lt,Lz,Ly,Lx,4,3]."""
+def cutoff_slices(nt, mu, eps, dagger=False):
+    """Time slices whose Woodbury vector the cutoff trick drops: where the eq:cutoff bound
+    sqrt(3) mu^-(Nt-t) (T^-1) or sqrt(3) mu^-(t+1) (T^dagger^-1) is below eps."""
+    t = np.arange(nt)
+    bound = np.sqrt(3.0) * float(mu) ** -((t + 1) if dagger else (nt - t)).astype(np.float64)
+    return bound < eps
+
+
+def apply_Tinv(Ut, eta, mu, b=-1.0, setup=None, eps=0.0):
+    """psi = T^-1 eta on every spin component of eta [Lt,Lz,Ly,Lx,4,3]; with eps > 0 the
+    cutoff trick zeroes X(t) where its norm bound is below eps."""
     X, lam = setup if setup is not None else smw_setup(Ut, mu, b)
     nt = Ut.shape[0]
     chi = np.empty_like(eta)
@@ -75,11 +89,13 @@ def apply_Tinv(Ut, eta, mu, b=-1.0, setup=None):
     for t in range(nt - 2, -1, -1):
         chi[t] = (eta[t] + _matvec(Ut[t], chi[t + 1])) / mu
     q = _matvec(lam, chi[0])
-    return chi - np.stack([_matvec(X[t], q) for t in range(nt)])
+    drop = cutoff_slices(nt, mu, eps)
+    return chi - np.stack([np.zeros_like(chi[t]) if drop[t] else _matvec(X[t], q) for t in range(nt)])
 
 
-def apply_Tdaginv(Ut, eta, mu, b=-1.0, setup=None):
-    """psi = (T^dagger)^-1 eta by forward substitution plus the mirrored Woodbury step."""
+def apply_Tdaginv(Ut, eta, mu, b=-1.0, setup=None, eps=0.0):
+    """psi = (T^dagger)^-1 eta by forward substitution plus the mirrored Woodbury step (with
+    the mirrored cutoff trick for eps > 0)."""
     X, lam = setup if setup is not None else smw_setup_dag(Ut, mu, b)
     nt = Ut.shape[0]
     dag = lambda m: np.conj(np.swapaxes(m, -1, -2))
@@ -88,24 +104,27 @@ def apply_Tdaginv(Ut, eta, mu, b=-1.0, setup=None):
     for t in range(1, nt):
         chi[t] = (eta[t] + _matvec(dag(Ut[t - 1]), chi[t - 1])) / mu
     q = _matvec(lam, chi[nt - 1])
-    return chi - np.stack([_matvec(X[t], q) for t in range(nt)])
+    drop = cutoff_slices(nt, mu, eps, dagger=True)
+    return chi - np.stack([np.zeros_like(chi[t]) if drop[t] else _matvec(X[t], q) for t in range(nt)])
 
 
 class Temporal:
-    """C_L, C_R and their inverses for one gauge field and mass (Sec. II.A)."""
+    """C_L, C_R and their inverses for one gauge field and mass (Sec. II.A); eps > 0 applies
+    the cutoff trick in T^-1 and T^dagger^-1 (so C_L, C_R are then approximate inverses)."""
 
-    def __init__(self, U, mu, b=-1.0):
+    def __init__(self, U, mu, b=-1.0, eps=0.0):
         self.Ut = U[3]
         self.mu = mu
         self.b = b
+        self.eps = eps
         self.fwd = smw_setup(self.Ut, mu, b)
         self.bwd = smw_setup_dag(self.Ut, mu, b)
 
     def Tinv(self, psi):
-        return apply_Tinv(self.Ut, psi, self.mu, self.b, self.fwd)
+        return apply_Tinv(self.Ut, psi, self.mu, self.b, self.fwd, self.eps)
 
     def Tdaginv(self, psi):
-        return apply_Tdaginv(self.Ut, psi, self.mu, self.b, self.bwd)
+        return apply_Tdaginv(self.Ut, psi, self.mu, self.b, self.bwd, self.eps)
 
     def T(self, psi):
         return apply_T(self.Ut, psi, self.mu, self.b)

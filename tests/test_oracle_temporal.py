@@ -127,3 +127,72 @@ def test_gauge_covariance_of_Tinv(setup):
     rot = lambda v: np.einsum("...ab,...sb->...sa", om, v)
     assert np.linalg.norm(tpg.Tinv(rot(psi)) - rot(tp.Tinv(psi))) < 1e-14 * np.linalg.norm(psi)
     assert np.linalg.norm(tpg.Tdaginv(rot(psi)) - rot(tp.Tdaginv(psi))) < 1e-14 * np.linalg.norm(psi)
+
+
+@pytest.mark.parametrize("b", [-1.0, 1.0])
+@pytest.mark.parametrize("eps", [1e-4, 1e-8])
+def test_cutoff_trick_drops_exactly_the_bounded_terms(b, eps):
+    """The cutoff trick (Sec. II.A, eq:cutoff) on a 40-slice line.  Kept slices equal the
+    exact inverse (a dense line inverse); on a dropped slice the difference is exactly the
+    omitted Woodbury term X(t) q, where q = Lambda chi(0) is the exact psi(0) and X(t) is
+    built here from the link products, so it is bounded by sqrt(3) mu^-(Nt-t) |psi(0)| < eps |psi(0)|.
+    The mirrored T^dagger^-1 drops X'(t) psi'(Nt-1) at the other end, with sqrt(3) mu^-(t+1)."""
+    dims = (2, 2, 2, 40)
+    nt = dims[3]
+    U = synth.make_links(dims, 0.4, 0.3, 1005)
+    mu = W.mass_term(-0.05, 3.0)
+    eta = synth.make_source(dims, 2010)
+    cut = Temporal(U, mu, b, eps)
+    got, gotd = cut.Tinv(eta), cut.Tdaginv(eta)
+    dag = lambda m: np.conj(np.swapaxes(m, -1, -2))
+    ndrop = 0
+    for (z, y, x) in [(0, 0, 0), (1, 0, 1)]:
+        T = np.zeros((3 * nt, 3 * nt), complex)
+        for t in range(nt):
+            T[3 * t:3 * t + 3, 3 * t:3 * t + 3] = mu * np.eye(3)
+            ph = b if t == nt - 1 else 1.0
+            T[3 * t:3 * t + 3, 3 * ((t + 1) % nt):3 * ((t + 1) % nt) + 3] -= ph * U[3, t, z, y, x]
+        Ti, Tdi = np.linalg.inv(T), np.linalg.inv(T.conj().T)
+        for s in range(4):
+            ex = (Ti @ eta[:, z, y, x, s, :].ravel()).reshape(nt, 3)
+            exd = (Tdi @ eta[:, z, y, x, s, :].ravel()).reshape(nt, 3)
+            for t in range(nt):
+                # X(t) = -b mu^-(Nt-t) U(t) ... U(Nt-1);  X'(t) = -b mu^-(t+1) U(t-1)^dag ... U(0)^dag U(Nt-1)^dag
+                Xt = np.eye(3, dtype=complex)
+                for j in range(t, nt):
+                    Xt = Xt @ U[3, j, z, y, x]
+                Xt *= -b * mu ** (-(nt - t))
+                Xd = dag(U[3, nt - 1, z, y, x])
+                for j in range(0, t):
+                    Xd = dag(U[3, j, z, y, x]) @ Xd
+                Xd *= -b * mu ** (-(t + 1))
+                d = got[t, z, y, x, s] - ex[t]
+                dd = gotd[t, z, y, x, s] - exd[t]
+                if np.sqrt(3) * mu ** (-(nt - t)) < eps:
+                    ndrop += 1
+                    assert np.abs(d - Xt @ ex[0]).max() < 1e-14
+                    assert np.linalg.norm(d) <= np.sqrt(3) * mu ** (-(nt - t)) * np.linalg.norm(ex[0]) * (1 + 1e-12)
+                else:
+                    assert np.abs(d).max() < 1e-14
+                if np.sqrt(3) * mu ** (-(t + 1)) < eps:
+                    assert np.abs(dd - Xd @ exd[nt - 1]).max() < 1e-14
+                else:
+                    assert np.abs(dd).max() < 1e-14
+    # mu = 1.95: sqrt(3) mu^-k < eps from k = 15 (1e-4) and k = 29 (1e-8) on, of 40 slices
+    assert ndrop == 2 * 4 * (nt - (15 if eps == 1e-4 else 29) + 1)
+
+
+def test_cutoff_trick_perturbs_the_ilu_operator_by_order_eps():
+    """The App. B sequence built from the cut C_L, C_R stays within a small multiple of eps
+    of the exact one, and eps = 0 reproduces it exactly."""
+    from oracle.schemes import Operator
+    dims = (4, 2, 2, 40)
+    U = synth.make_links(dims, 0.35, 0.12, 1000)
+    psi = synth.make_source(dims, 2011)
+    ex = Operator(U, -0.05, 3.0, -1.0, 1.6 / 3, 1.0)
+    ref = ex.tschur_ilu_sequence(psi)
+    assert np.array_equal(Operator(U, -0.05, 3.0, -1.0, 1.6 / 3, 1.0, 0.0).tschur_ilu_sequence(psi), ref)
+    for eps in (1e-6, 1e-10):
+        d = Operator(U, -0.05, 3.0, -1.0, 1.6 / 3, 1.0, eps).tschur_ilu_sequence(psi) - ref
+        rel = np.linalg.norm(d) / np.linalg.norm(ref)
+        assert 0 < rel < 10 * eps, (eps, rel)

@@ -151,6 +151,15 @@ tp_status tp_clover_destroy(tp_clover c);
  * factorises (A + mu) per site for SCHUR4D (TP_ESINGULAR on a zero pivot). */
 tp_status tp_op_create(tp_gauge g, tp_clover c, double m0, double gamma_f, tp_op* out);
 tp_status tp_op_destroy(tp_op op);
+/* The cutoff trick (Sec. II.A, eq:cutoff): every T^-1 and T^dagger^-1 of the operator's
+ * applies, in every precision, drops the Woodbury correction X(t) Lambda chi(0) on the time
+ * slices where its norm bound sqrt(3) mu^-(Lt-t) (T^-1) or sqrt(3) mu^-(t+1) (T^dagger^-1) is
+ * below eps, and skips computing it there.  C_L and C_R, and the preconditioned operators
+ * built from them, then differ from the exact ones by terms bounded that way; solves still
+ * reach their FP64 true-residual target, whose residual uses M itself.  eps = 0 (the default)
+ * restores the exact inverse.  dropped (may be NULL) receives the number of slices dropped
+ * at each line's suppressed end.  TP_EINVAL for a negative or non-finite eps. */
+tp_status tp_op_set_cutoff(tp_op op, double eps, int32_t* dropped);
 /* The diagonal mass term mu = m0 + 1 + 3/gamma_f of M (Sec. II, a_t = 1). */
 tp_status tp_op_mass(tp_op op, double* mu);
 

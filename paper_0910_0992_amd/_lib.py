@@ -64,6 +64,7 @@ SIGNATURES = [
     ("tp_op_create", [_P, _P, _D, _D, C.POINTER(_P)], _I),
     ("tp_op_destroy", [_P], _I),
     ("tp_op_mass", [_P, C.POINTER(_D)], _I),
+    ("tp_op_set_cutoff", [_P, _D, C.POINTER(C.c_int32)], _I),
     ("tp_apply_M", [_P, _I, _P, _P, _I], _I),
     ("tp_apply_Ds", [_P, _I, _P, _P], _I),
     ("tp_apply_clover", [_P, _I, _P, _P, _I], _I),

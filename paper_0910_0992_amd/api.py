@@ -90,6 +90,14 @@ class Operator:
         L.check(lib.tp_op_mass(self._op, C.byref(mu)))
         self.mu = mu.value
 
+    def set_cutoff(self, eps):
+        """The cutoff trick of Sec. II.A (tp_op_set_cutoff): the Woodbury correction of the
+        temporal inverses is dropped where its eq:cutoff bound is below eps (0: exact).
+        Returns the number of time slices dropped at each line's suppressed end."""
+        n = C.c_int32()
+        L.check(self._lib.tp_op_set_cutoff(self._op, float(eps), C.byref(n)))
+        return n.value
+
     def device_bytes(self):
         """Device memory held by the library for this operator (context and handles)."""
         n = C.c_size_t()

@@ -673,6 +673,21 @@ tp_status tp_op_destroy(tp_op op) {
   });
 }
 
+tp_status tp_op_set_cutoff(tp_op op, double eps, int32_t* dropped) {
+  return guard([&] {
+    need(op, "op");
+    if (!(eps >= 0) || !isfinite(eps)) TP_THROW(TP_EINVAL, "cutoff threshold must be finite and >= 0");
+    const int lt = op->g->ctx->lat.L[3];
+    // |X(t)|_F = sqrt(3) mu^-(Lt-t) (eq:cutoff) decreases towards t = 0: the dropped slices
+    // are t = 0 .. cut-1, and by symmetry t = Lt-cut .. Lt-1 for T^dagger
+    int cut = 0;
+    for (int t = 0; t < lt; ++t)
+      if (std::sqrt(3.0) * std::pow(op->mu, -double(lt - t)) < eps) cut = t + 1;
+    op->cut = cut;
+    if (dropped) *dropped = cut;
+  });
+}
+
 tp_status tp_op_mass(tp_op op, double* mu) {
   return guard([&] {
     need(op, "op");

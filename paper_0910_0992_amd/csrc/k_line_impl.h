@@ -18,7 +18,9 @@
 // chunks whose partial sums combine exactly through LDS (carry = mu^-k times
 // the neighbour chunk's head).  The closure G = (I - mu^-Lt P)^-1 P / mu is formed
 // in FP64 at set-up (mu^-Lt is far below FP32 range on long lines) and applied in the
-// kernel's arithmetic precision.
+// kernel's arithmetic precision.  With the cutoff trick (Sec. II.A, eq:cutoff) the closure
+// term is applied only on the slices whose Woodbury vector survives, t >= cut for T^-1 and
+// t < Lt - cut for T^dagger^-1; threads whose slices all fall outside skip the closure.
 //
 // Workgroup = LPB lines (whole tiles of 4 lines) x NCH chunks of CH consecutive
 // time slices.  Threads are numbered in memory order of the tiled p3 layout
@@ -36,6 +38,7 @@ template <> struct Cplx2<float> { using T = float2; };
 template <typename R>
 struct ScanCtx {
   int l, j, LPB, NCH, t0, Lt, CH;
+  int cut;      // cutoff trick: time slices (from the open end) without the closure term
   int s;
   int tile;     // tile of 4 lines within the workgroup
   bool active;
@@ -190,8 +193,10 @@ TP_DEV void scan_core(cx<R> (&v)[CH][NV], cx<R>* lds, const ScanCtx<R>& sc) {
     }
     __syncthreads();
     }
-    // closure: delta = G z (backward) or G^dagger z (forward), per colour vector
-    if (sc.active) {
+    // closure: delta = G z (backward) or G^dagger z (forward), per colour vector, on the
+    // slices the cutoff keeps (all of them when cut = 0)
+    const bool band = BWD ? (sc.t0 + CH - 1 >= sc.cut) : (sc.t0 < sc.Lt - sc.cut);
+    if (sc.active && band) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         cx<R> acc0 = czero<R>(), acc1 = czero<R>();
@@ -219,7 +224,8 @@ TP_DEV void scan_core(cx<R> (&v)[CH][NV], cx<R>* lds, const ScanCtx<R>& sc) {
     for (int k = 0; k < CH; ++k) {
       int t = sc.t0 + k;
       R ca = BWD ? sc.mupow[CH - k] : sc.mupow[k + 1];
-      R cb = BWD ? sc.mupow[sc.Lt - 1 - t] : sc.mupow[t];
+      const bool keep = BWD ? (t >= sc.cut) : (t < sc.Lt - sc.cut);
+      R cb = keep ? (BWD ? sc.mupow[sc.Lt - 1 - t] : sc.mupow[t]) : R(0);
 #pragma unroll
       for (int c = 0; c < 6; ++c) v[k][6 * g + c] += ca * C[c] + cb * D[c];
     }
@@ -245,6 +251,7 @@ struct LineArgs {
   const typename Cplx2<typename Prec<S>::R>::T* G;  // closure, FP64 or FP32
   const typename Prec<S>::R* mupow;
   double inv_mu, f, c_out, c_base;
+  int cut;        // cutoff trick: slices without the closure term (0: exact inverse)
   Geom g;
   int par, LPB, NCH;
   int lds_table;  // complex elements of LDS used by the chunk combine (the rest follows it)
@@ -283,6 +290,7 @@ TP_DEV ScanCtx<typename Prec<S>::R> make_ctx(const LineArgs<S>& a, int CH, uint3
   sc.s = int(blk) * a.LPB + sc.l;
   sc.active = sc.s < a.g.Vs2;
   sc.inv_mu = R(a.inv_mu);
+  sc.cut = a.cut;
   sc.f = R(a.f);
   sc.mupow = a.mupow;
   sc.G = a.G + (int64_t)a.par * 9 * a.g.Vs2;
@@ -659,6 +667,7 @@ LineArgs<S> base_args(tp_op op, int par) {
     a.mupow = (const typename Prec<S>::R*)op->mupow_f;
   }
   a.inv_mu = 1.0 / op->mu;
+  a.cut = op->cut;
   a.g = L.g;
   a.par = par;
   return a;

@@ -168,6 +168,9 @@ struct tp_op_s {
   tp_gauge g = nullptr;
   tp_clover c = nullptr;
   double m0 = 0, gf = 1, mu = 1;
+  // cutoff trick (tp_op_set_cutoff): time slices whose Woodbury correction the scans drop
+  // (T^-1: t < cut; T^dagger^-1: t >= Lt - cut); 0 keeps the exact inverse
+  int cut = 0;
   double2* gclos = nullptr;  // per line G = (I - mu^-Lt P)^-1 P / mu  [2 par][9][Vs2]
   float2* gclos_f = nullptr;  // the same, rounded to FP32 (for the FP32 and FP16 scans)
   double2* a4_mu = nullptr;     // p4 (A+mu)/2 chiral blocks [2][36][V2]

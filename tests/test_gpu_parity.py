@@ -491,3 +491,46 @@ def test_kappa_interacting(scheme):
     lmin, lmax, kap = krylov.lanczos_kappa(oi["alphas"], oi["betas"])
     assert abs(info["kappa_est"] / kap - 1) < 0.01, (scheme, info["kappa_est"], kap)
     assert abs(info["lambda_max"] / lmax - 1) < 0.01 and abs(info["lambda_min"] / lmin - 1) < 0.01
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32", "F16N"])
+def test_cutoff_trick(case, prec):
+    """The cutoff trick (tp_op_set_cutoff, Sec. II.A eq:cutoff) with a threshold that drops
+    about half of every line's Woodbury corrections: T^-1, T^dagger^-1, C_L, C_R and the
+    TEMPORAL_SCHUR apply, S_L and S_R against the oracle's cutoff variant (the App. B sequence
+    for clover, eq:TPrecFull for Wilson, built from the cut C_L and C_R); the cut operator
+    differs from the exact one.  A mixed solve with the production threshold (the FP32 unit
+    roundoff 2^-24) still reaches 1e-10; the half-line threshold drops terms of order 0.1, too
+    coarse for a consistent preconditioner."""
+    from oracle.temporal import cutoff_slices
+    o, g = case["oop"], case["gop"]
+    lt = case["dims"][3]
+    mu = o.mu
+    # 1.5x the bound at mid-line (no slice sits on the threshold: ln 1.5 / ln mu is not an
+    # integer), at least 1e-6 so that the dropped terms show in FP64 on long lines too
+    eps = max(1.5 * np.sqrt(3) * mu ** (-(lt // 2)), 1e-6)
+    oc = OOp(case["U"], case["m0"], case["xi"], float(case["bc"]), o.c_s, o.c_t, eps)
+    e, te = case["eta"], case["teta"]
+    try:
+        dropped = g.set_cutoff(eps)
+        assert dropped == int(cutoff_slices(lt, mu, eps).sum()) == int(cutoff_slices(lt, mu, eps, True).sum())
+        assert 0 < dropped < lt
+        t0, t1 = TOL[prec]
+        _close(_np(g.apply_Tinv(te, prec)), oc.tmp.Tinv(e), t0, "cut T^-1")
+        _close(_np(g.apply_Tinv(te, prec, dagger=True)), oc.tmp.Tdaginv(e), t0, "cut T^dag^-1")
+        _close(_np(g.apply_CL(te, prec)), oc.tmp.CL(e), t0, "cut C_L")
+        _close(_np(g.apply_CR(te, prec)), oc.tmp.CR(e), t0, "cut C_R")
+        want = oc.tschur_ilu_sequence(e) if o.clover else oc.tschur_closed_form(e)
+        got = _np(g.apply_prec(te, "TEMPORAL_SCHUR", prec))
+        _close(got, want, t1, "cut TEMPORAL_SCHUR")
+        _close(_np(g.prepare_source(te, "TEMPORAL_SCHUR", prec)), oc.tschur_SL(e), t1, "cut S_L")
+        _close(_np(g.reconstruct(te, "TEMPORAL_SCHUR", prec)), oc.tschur_SR(e), t1, "cut S_R")
+        if prec == "F64":
+            assert _rel(got, o.tschur_ilu_sequence(e) if o.clover else o.tschur_closed_form(e)) > 1e-12
+        else:
+            g.set_cutoff(2.0 ** -24)
+            x, info = g.solve(te, scheme="TEMPORAL_SCHUR", prec=prec, tol=1e-10)
+            true = np.linalg.norm(e - o.M(_np(x))) / np.linalg.norm(e)
+            assert true <= 1.05e-10, (info, true)
+    finally:
+        assert g.set_cutoff(0.0) == 0

@@ -404,11 +404,12 @@ void blas_impl(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<
   const Field* x = fs[0];
   const Field* y = fs[1];
   int prec = x ? x->prec : y->prec;
-  double S = double(x ? x->elem_bytes() : y->elem_bytes()) * 12;
+  // bytes per site and field: 12 components, plus the two FP32 half-spinor scales of F16N
+  double S = spinor_bytes(prec);
   double n = double(npar) * ctx->lat.V2 * nr;
   if (op == B_CONVERT || op == B_MIXED_ACC) {
     if (nr != 1) TP_THROW(TP_EINVAL, "blas: conversions take single fields");
-    ProfScope ps(ctx, KID_BLAS_OTHER, n * (S + double(y->elem_bytes()) * 12 * (op == B_MIXED_ACC ? 2 : 1)));
+    ProfScope ps(ctx, KID_BLAS_OTHER, n * (S + spinor_bytes(y->prec) * (op == B_MIXED_ACC ? 2 : 1)));
     if (op == B_CONVERT) conv<false>(ctx, par0, npar, *x, *y);
     else conv<true>(ctx, par0, npar, *x, *y);
     return;

@@ -206,6 +206,55 @@ tp_status tp_prepare_source(tp_op op, int32_t scheme, int32_t prec, void* eta_ti
                             const void* eta);
 tp_status tp_reconstruct(tp_op op, int32_t scheme, int32_t prec, void* x, const void* y);
 
+/* ---- fields in the library's layouts -----------------------------------------------
+ * The paper's flow is a one-off set-up, then per right-hand side a source preparation,
+ * applies of the preconditioned operator and a reconstruction (Sec. II.A-B).  A tp_field lets
+ * a caller (for example its own Krylov solver) keep fields in the library's internal layout
+ * and precision between calls instead of converting from and to canonical complex128 in every
+ * call.  Internal buffers are opaque device memory of tp_field_bytes() bytes per right-hand
+ * side, owned by the caller; the right-hand sides of a batch lie back to back.
+ *   TP_LAYOUT_CANONICAL  complex128 [Lt][Lz][Ly][Lx][4][3] (prec TP_F64, subset FULL only)
+ *   TP_LAYOUT_P3         3D-parity (x+y+z) layout in the axial frame of the gauge field: the
+ *                        layout of UNPREC, TEMPORAL, TEMPORAL_SCHUR and TEMPORAL_SCHUR3D
+ *   TP_LAYOUT_P4         4D-parity (x+y+z+t) layout: the layout of SCHUR4D
+ * Both internal layouts are unitary images of the canonical field (a permutation of sites
+ * and components, and for P3 a colour rotation per site), so inner products and norms of F64
+ * internal fields, read as complex128 vectors, equal those of the canonical fields.
+ * subset: TP_SUBSET_FULL, or one parity of the layout (TP_SUBSET_EVEN / TP_SUBSET_ODD),
+ * stored alone in half the memory. */
+enum { TP_LAYOUT_CANONICAL = 0, TP_LAYOUT_P3 = 1, TP_LAYOUT_P4 = 2 };
+enum { TP_SUBSET_FULL = 0, TP_SUBSET_EVEN = 1, TP_SUBSET_ODD = 2 };
+typedef struct {
+  void* data;      /* device pointer                                                   */
+  int32_t layout;  /* TP_LAYOUT_*                                                      */
+  int32_t prec;    /* TP_F64, TP_F32, TP_F16N (internal layouts); TP_F64 for canonical  */
+  int32_t subset;  /* TP_SUBSET_*                                                      */
+  int32_t nrhs;    /* right-hand sides stored back to back (1..16)                      */
+} tp_field;
+
+/* Bytes of one right-hand side of a field with this layout, precision and subset. */
+tp_status tp_field_bytes(tp_op op, int32_t layout, int32_t prec, int32_t subset, size_t* bytes);
+/* dst = src between layouts, precisions and subsets (same nrhs).  Canonical <-> internal
+ * converts (with the axial-frame rotation for P3); internal -> internal needs one layout and
+ * changes precision (FP16 storage rounds, with a scale per half spinor) and subset: a FULL
+ * source gives the chosen parity, a one-parity source fills the same parity, and the other
+ * parity of a FULL destination is set to zero. */
+tp_status tp_field_convert(tp_op op, const tp_field* dst, const tp_field* src);
+/* dst = Mt src (Mt^dagger with dagger = 1) on internal fields of `scheme`'s layout, one
+ * precision: FULL fields, or TP_SUBSET_ODD fields for the schemes whose even block is solved
+ * directly (SCHUR4D, TEMPORAL_SCHUR3D, TEMPORAL_SCHUR without clover), where the odd block is
+ * the operator a Krylov solver iterates on.  dst and src must not overlap. */
+tp_status tp_apply_prec_field(tp_op op, int32_t scheme, const tp_field* dst, const tp_field* src,
+                              int32_t dagger);
+/* eta_tilde = S_L eta and x = S_R y with fields: eta_tilde and y are FULL internal fields of
+ * the scheme's layout (their precision is the precision of the maps); eta and x may be
+ * canonical or FULL internal fields of that layout and precision.  For the schemes solved on
+ * the odd block the even part of y is eta_tilde's (TEMPORAL_SCHUR without clover,
+ * TEMPORAL_SCHUR3D) or (A + mu)^-1 eta_tilde_e (SCHUR4D). */
+tp_status tp_prepare_source_field(tp_op op, int32_t scheme, const tp_field* eta_tilde,
+                                  const tp_field* eta);
+tp_status tp_reconstruct_field(tp_op op, int32_t scheme, const tp_field* x, const tp_field* y);
+
 /* ---- solve ------------------------------------------------------------------------ */
 typedef struct {
   int32_t scheme;          /* TP_UNPREC ... TP_TEMPORAL_SCHUR3D                     */

@@ -12,7 +12,7 @@ Fields are torch complex128 CUDA tensors in the canonical layout:
 spinors [Lt][Lz][Ly][Lx][4][3] (Dirac-Pauli basis), links [4][Lt][Lz][Ly][Lx][3][3]
 with direction 0=x, 1=y, 2=z, 3=t.
 """
-from .api import Operator, SolveFn, solve
+from .api import Field, Operator, SolveFn, solve
 from ._lib import TprecError, SCHEMES, SOLVERS, PRECS
 
-__all__ = ["Operator", "SolveFn", "solve", "TprecError", "SCHEMES", "SOLVERS", "PRECS"]
+__all__ = ["Field", "Operator", "SolveFn", "solve", "TprecError", "SCHEMES", "SOLVERS", "PRECS"]

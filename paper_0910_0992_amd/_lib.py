@@ -16,6 +16,13 @@ TP_HOST, TP_DEVICE = 0, 1
 SCHEMES = {"UNPREC": 0, "SCHUR4D": 1, "TEMPORAL": 2, "TEMPORAL_SCHUR": 3, "TEMPORAL_SCHUR3D": 4}
 SOLVERS = {"CGNR": 0, "BICGSTAB": 1}
 PRECS = {"F64": 0, "F32": 1, "F16N": 2}
+LAYOUTS = {"CANONICAL": 0, "P3": 1, "P4": 2}
+SUBSETS = {"FULL": 0, "EVEN": 1, "ODD": 2}
+
+
+class TpField(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("layout", C.c_int32), ("prec", C.c_int32),
+                ("subset", C.c_int32), ("nrhs", C.c_int32)]
 
 
 class SolveParams(C.Structure):
@@ -75,6 +82,11 @@ SIGNATURES = [
     ("tp_apply_prec_noalloc", [_P, _I, _I, _P, _P, _I], _I),
     ("tp_prepare_source", [_P, _I, _I, _P, _P], _I),
     ("tp_reconstruct", [_P, _I, _I, _P, _P], _I),
+    ("tp_field_bytes", [_P, _I, _I, _I, C.POINTER(C.c_size_t)], _I),
+    ("tp_field_convert", [_P, C.POINTER(TpField), C.POINTER(TpField)], _I),
+    ("tp_apply_prec_field", [_P, _I, C.POINTER(TpField), C.POINTER(TpField), _I], _I),
+    ("tp_prepare_source_field", [_P, _I, C.POINTER(TpField), C.POINTER(TpField)], _I),
+    ("tp_reconstruct_field", [_P, _I, C.POINTER(TpField), C.POINTER(TpField)], _I),
     ("tp_solve", [_P, C.POINTER(SolveParams), _P, _P, C.POINTER(SolveInfo)], _I),
     ("tp_solve_multi", [_P, C.POINTER(SolveParams), _I, C.POINTER(_P), C.POINTER(_P), C.POINTER(SolveInfo)], _I),
     ("tp_force", [_P, _P, _P, _P, _I], _I),

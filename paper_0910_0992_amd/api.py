@@ -46,6 +46,24 @@ def _scheme(s):
     return int(s)
 
 
+class Field:
+    """A device buffer in one of the library's layouts (tp_field): `buf` holds nrhs right-hand
+    sides back to back.  Internal layouts are opaque; an F64 FULL internal field read as a
+    complex128 vector (as_complex) has the canonical field's inner products."""
+
+    def __init__(self, buf, layout, prec, subset, nrhs):
+        self.buf, self.layout, self.prec, self.subset, self.nrhs = buf, layout, prec, subset, nrhs
+
+    def desc(self):
+        return L.TpField(data=self.buf.data_ptr(), layout=L.LAYOUTS[self.layout], prec=L.PRECS[self.prec],
+                         subset=L.SUBSETS[self.subset], nrhs=self.nrhs)
+
+    def as_complex(self):
+        if self.prec != "F64" or self.subset != "FULL" or self.layout == "CANONICAL":
+            raise ValueError("as_complex: F64 FULL internal fields only")
+        return self.buf.view(torch.complex128).view(self.nrhs, -1)
+
+
 class Operator:
     """M = A + mu - D_t - D_s/gamma_f bound to a gauge field, on one GPU.
 
@@ -192,6 +210,65 @@ class Operator:
         self._call(self._lib.tp_reconstruct, self._op, _scheme(scheme), _prec(prec),
                    C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()))
         return dst
+
+    # ---- fields in the library's layouts ------------------------------------------------
+    def field_bytes(self, layout="P3", prec="F64", subset="FULL"):
+        n = C.c_size_t()
+        L.check(self._lib.tp_field_bytes(self._op, L.LAYOUTS[layout], _prec(prec), L.SUBSETS[subset],
+                                         C.byref(n)))
+        return n.value
+
+    def field(self, layout="P3", prec="F64", subset="FULL", nrhs=1):
+        """An uninitialised field (device memory from torch)."""
+        if layout == "CANONICAL":
+            t = torch.empty((nrhs,) + self.spinor_shape, dtype=torch.complex128, device=self.device)
+            return Field(t, layout, "F64", "FULL", nrhs)
+        per = self.field_bytes(layout, prec, subset)
+        return Field(torch.empty(nrhs * per, dtype=torch.uint8, device=self.device), layout, prec, subset, nrhs)
+
+    def _canonical(self, psi):
+        psi = psi.to(self.device).contiguous()
+        if psi.dtype != torch.complex128 or tuple(psi.shape[-6:]) != self.spinor_shape:
+            raise ValueError(f"spinor must be complex128 {self.spinor_shape} (or a batch of them)")
+        n = 1 if psi.dim() == 6 else psi.shape[0]
+        return Field(psi.view((n,) + self.spinor_shape), "CANONICAL", "F64", "FULL", n)
+
+    def convert_field(self, dst, src):
+        self._call(self._lib.tp_field_convert, self._op, C.byref(dst.desc()), C.byref(src.desc()))
+        return dst
+
+    def to_field(self, psi, layout="P3", prec="F64", subset="FULL"):
+        """A canonical spinor (or batch) converted into a field of the given layout."""
+        src = self._canonical(psi)
+        return self.convert_field(self.field(layout, prec, subset, src.nrhs), src)
+
+    def from_field(self, f):
+        """The canonical complex128 spinors [nrhs, Lt, Lz, Ly, Lx, 4, 3] of a field."""
+        out = self.field("CANONICAL", nrhs=f.nrhs)
+        self.convert_field(out, f)
+        return out.buf
+
+    def apply_prec_field(self, f, scheme, dagger=False, out=None):
+        out = out if out is not None else self.field(f.layout, f.prec, f.subset, f.nrhs)
+        self._call(self._lib.tp_apply_prec_field, self._op, _scheme(scheme), C.byref(out.desc()),
+                   C.byref(f.desc()), int(dagger))
+        return out
+
+    def prepare_source_field(self, eta, scheme, prec="F64"):
+        """eta~ = S_L eta as a FULL field of the scheme's layout; eta a canonical tensor or a field."""
+        src = eta if isinstance(eta, Field) else self._canonical(eta)
+        lay = "P4" if _scheme(scheme) == L.SCHEMES["SCHUR4D"] else "P3"
+        out = self.field(lay, prec, "FULL", src.nrhs)
+        self._call(self._lib.tp_prepare_source_field, self._op, _scheme(scheme), C.byref(out.desc()),
+                   C.byref(src.desc()))
+        return out
+
+    def reconstruct_field(self, y, scheme):
+        """x = S_R y as canonical spinors [nrhs, ...]."""
+        out = self.field("CANONICAL", nrhs=y.nrhs)
+        self._call(self._lib.tp_reconstruct_field, self._op, _scheme(scheme), C.byref(out.desc()),
+                   C.byref(y.desc()))
+        return out.buf
 
     # ---- solve -----------------------------------------------------------------------
     def solve(self, eta, scheme="TEMPORAL_SCHUR", solver="BICGSTAB", prec="F64", tol=1e-10,

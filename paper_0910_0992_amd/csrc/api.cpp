@@ -319,6 +319,96 @@ tp_status apply_wrap(tp_op op, int prec, void* dst, const void* src, bool l4, bo
 }
 
 
+// ---------------------------------------------------------------- fields in the library's layouts
+namespace {
+size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+void check_tpfield(tp_op op, const tp_field* f, const char* what) {
+  need(f, what);
+  need(f->data, what);
+  if (f->nrhs < 1 || f->nrhs > kMaxRhs) TP_THROW(TP_EINVAL, std::string(what) + ": nrhs must be 1..16");
+  if (f->layout < TP_LAYOUT_CANONICAL || f->layout > TP_LAYOUT_P4) TP_THROW(TP_EINVAL, std::string(what) + ": bad layout");
+  if (f->subset < TP_SUBSET_FULL || f->subset > TP_SUBSET_ODD) TP_THROW(TP_EINVAL, std::string(what) + ": bad subset");
+  if (f->layout == TP_LAYOUT_CANONICAL) {
+    if (f->prec != TP_F64 || f->subset != TP_SUBSET_FULL)
+      TP_THROW(TP_EINVAL, std::string(what) + ": canonical fields are F64 and FULL");
+  } else {
+    check_prec(f->prec);
+  }
+  if (f->layout == TP_LAYOUT_P4 && op->g->ctx->lat.L[3] % 2) TP_THROW(TP_EDIMS, "the P4 layout needs an even time extent");
+}
+
+size_t tpfield_bytes(const Lattice& L, int layout, int prec, int subset) {
+  if (layout == TP_LAYOUT_CANONICAL) return size_t(L.V) * 12 * sizeof(double2);
+  const size_t eb = prec == TP_F64 ? 16 : (prec == TP_F32 ? 8 : 4);
+  const size_t npar = subset == TP_SUBSET_FULL ? 2 : 1;
+  size_t b = al256(npar * 12 * L.V2 * eb);
+  if (prec == TP_F16N) b += al256(npar * 2 * L.V2 * sizeof(float));
+  return b;
+}
+
+// Right-hand side r of an internal field as a Field.  For a one-parity field, parity p of the
+// view is the caller's buffer; the view is only used with kernels restricted to parity p
+// (one-parity copies and conversions), so the other parity's addresses are never formed into
+// accesses.
+Field tpfield_view(const Lattice& L, const tp_field& f, int r) {
+  Field v;
+  v.prec = f.prec;
+  v.V2 = L.V2;
+  v.nr = 1;
+  v.owned = false;
+  const size_t per = tpfield_bytes(L, f.layout, f.prec, f.subset);
+  const uintptr_t base = reinterpret_cast<uintptr_t>(f.data) + size_t(r) * per;
+  const size_t npar = f.subset == TP_SUBSET_FULL ? 2 : 1;
+  const size_t dbytes = al256(npar * 12 * L.V2 * v.elem_bytes());
+  const int p = f.subset == TP_SUBSET_ODD ? 1 : 0;
+  const uintptr_t back = f.subset == TP_SUBSET_FULL ? 0 : uintptr_t(p);
+  v.data = reinterpret_cast<void*>(base - back * 12 * L.V2 * v.elem_bytes());
+  v.nrm = f.prec == TP_F16N ? reinterpret_cast<float*>(base + dbytes - back * 2 * L.V2 * sizeof(float)) : nullptr;
+  return v;
+}
+
+double2* tpfield_canon(const Lattice& L, const tp_field& f, int r) {
+  return static_cast<double2*>(f.data) + size_t(r) * L.V * 12;
+}
+
+int subset_par(int subset) { return subset == TP_SUBSET_ODD ? 1 : 0; }
+bool layout4_of(int layout) { return layout == TP_LAYOUT_P4; }
+int scheme_layout(int scheme) { return scheme == TP_SCHUR4D ? TP_LAYOUT_P4 : TP_LAYOUT_P3; }
+
+// One right-hand side: internal dst = internal src, same layout (precision and subset change).
+void convert_internal(tp_ctx ctx, const tp_field& dst, const Field& dv, const tp_field& src, const Field& sv) {
+  if (src.subset == TP_SUBSET_FULL) {
+    if (dst.subset == TP_SUBSET_FULL) blas(ctx, B_CONVERT, 0, 2, {&sv, &dv});
+    else blas(ctx, B_CONVERT, subset_par(dst.subset), 1, {&sv, &dv});
+    return;
+  }
+  const int p = subset_par(src.subset);
+  if (dst.subset != TP_SUBSET_FULL && subset_par(dst.subset) != p)
+    TP_THROW(TP_EINVAL, "field convert: one-parity fields of different parities");
+  blas(ctx, B_CONVERT, p, 1, {&sv, &dv});
+  if (dst.subset == TP_SUBSET_FULL) blas(ctx, B_ZERO, 1 - p, 1, {nullptr, &dv});
+}
+
+// One right-hand side of a field as a FULL internal Field of (layout, prec): the field itself
+// when it already is one, else a conversion into workspace slot `slot`.
+Field full_internal(tp_op op, const tp_field& f, int r, int layout, int prec, int slot) {
+  tp_ctx ctx = op->g->ctx;
+  const Lattice& L = ctx->lat;
+  if (f.layout == layout && f.prec == prec && f.subset == TP_SUBSET_FULL) return tpfield_view(L, f, r);
+  Field& w = tmp_field(op, prec, slot);
+  if (f.layout == TP_LAYOUT_CANONICAL) {
+    const double2* wd = layout4_of(layout) ? nullptr : op->g->w_d;
+    launch_pack(ctx, tpfield_canon(L, f, r), w, layout4_of(layout), false, wd);
+  } else {
+    if (f.layout != layout) TP_THROW(TP_EINVAL, "field in another internal layout");
+    tp_field full{nullptr, layout, prec, TP_SUBSET_FULL, 1};
+    convert_internal(ctx, full, w, f, tpfield_view(L, f, r));
+  }
+  return w;
+}
+}  // namespace
+
 // ---------------------------------------------------------------- C ABI
 extern "C" {
 
@@ -818,6 +908,153 @@ tp_status tp_reconstruct(tp_op op, int32_t scheme, int32_t prec, void* x, const 
     tp_status s = apply_wrap(op, prec, x, y, scheme_layout4(scheme), false,
                              [&](Field& a, Field& b) { op_reconstruct(op, scheme, prec, a, b); });
     if (s != TP_OK) TP_THROW(s, g_last_error);
+  });
+}
+
+tp_status tp_field_bytes(tp_op op, int32_t layout, int32_t prec, int32_t subset, size_t* bytes) {
+  return guard([&] {
+    need(op, "op");
+    need(bytes, "bytes");
+    tp_field f{bytes, layout, prec, subset, 1};
+    check_tpfield(op, &f, "field");
+    *bytes = tpfield_bytes(op->g->ctx->lat, layout, prec, subset);
+  });
+}
+
+tp_status tp_field_convert(tp_op op, const tp_field* dst, const tp_field* src) {
+  return guard([&] {
+    need(op, "op");
+    check_tpfield(op, dst, "dst");
+    check_tpfield(op, src, "src");
+    if (dst->nrhs != src->nrhs) TP_THROW(TP_EINVAL, "field convert: different nrhs");
+    if (dst->data == src->data) TP_THROW(TP_EINVAL, "field convert: dst and src must differ");
+    tp_ctx ctx = op->g->ctx;
+    set_device(ctx);
+    const Lattice& L = ctx->lat;
+    const bool dc = dst->layout == TP_LAYOUT_CANONICAL, sc = src->layout == TP_LAYOUT_CANONICAL;
+    if (!dc && !sc && dst->layout != src->layout)
+      TP_THROW(TP_EINVAL, "field convert: internal layouts differ (convert through the canonical layout)");
+    for (int r = 0; r < src->nrhs; ++r) {
+      if (dc && sc) {
+        HIP_CHECK(hipMemcpyAsync(tpfield_canon(L, *dst, r), tpfield_canon(L, *src, r), size_t(L.V) * 12 * sizeof(double2),
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+      } else if (sc) {  // canonical -> internal
+        const double2* wd = layout4_of(dst->layout) ? nullptr : op->g->w_d;
+        Field dv = tpfield_view(L, *dst, r);
+        if (dst->subset == TP_SUBSET_FULL) {
+          launch_pack(ctx, tpfield_canon(L, *src, r), dv, layout4_of(dst->layout), false, wd);
+        } else {
+          Field& w = tmp_field(op, dst->prec, 0);
+          launch_pack(ctx, tpfield_canon(L, *src, r), w, layout4_of(dst->layout), false, wd);
+          blas(ctx, B_COPY, subset_par(dst->subset), 1, {&w, &dv});
+        }
+      } else if (dc) {  // internal -> canonical
+        const double2* wd = layout4_of(src->layout) ? nullptr : op->g->w_d;
+        Field w = full_internal(op, *src, r, src->layout, src->prec, 0);
+        launch_unpack(ctx, w, tpfield_canon(L, *dst, r), layout4_of(src->layout), false, wd);
+      } else {
+        Field dv = tpfield_view(L, *dst, r);
+        convert_internal(ctx, *dst, dv, *src, tpfield_view(L, *src, r));
+      }
+    }
+  });
+}
+
+tp_status tp_apply_prec_field(tp_op op, int32_t scheme, const tp_field* dst, const tp_field* src,
+                              int32_t dagger) {
+  return guard([&] {
+    need(op, "op");
+    check_scheme(scheme);
+    check_tpfield(op, dst, "dst");
+    check_tpfield(op, src, "src");
+    const int lay = scheme_layout(scheme);
+    if (dst->layout != lay || src->layout != lay)
+      TP_THROW(TP_EINVAL, "apply_prec_field: fields must be in the scheme's internal layout");
+    if (dst->prec != src->prec || dst->subset != src->subset || dst->nrhs != src->nrhs)
+      TP_THROW(TP_EINVAL, "apply_prec_field: fields of different precision, subset or nrhs");
+    const int prec = src->prec;
+    if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
+    if (scheme == TP_TEMPORAL_SCHUR3D && prec == TP_F16N) TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
+    if (src->subset == TP_SUBSET_EVEN) TP_THROW(TP_EINVAL, "apply_prec_field: FULL or ODD fields");
+    if (src->subset == TP_SUBSET_ODD && !scheme_sub(op, scheme))
+      TP_THROW(TP_EINVAL, "apply_prec_field: ODD fields only for schemes solved on the odd block");
+    tp_ctx ctx = op->g->ctx;
+    set_device(ctx);
+    const Lattice& L = ctx->lat;
+    const size_t per = tpfield_bytes(L, src->layout, prec, src->subset);
+    const uintptr_t d0 = reinterpret_cast<uintptr_t>(dst->data), s0 = reinterpret_cast<uintptr_t>(src->data);
+    if (d0 < s0 + per * src->nrhs && s0 < d0 + per * dst->nrhs) TP_THROW(TP_EINVAL, "apply_prec_field: dst overlaps src");
+    for (int r = 0; r < src->nrhs; ++r) {
+      Field sv = tpfield_view(L, *src, r), dv = tpfield_view(L, *dst, r);
+      if (src->subset == TP_SUBSET_FULL) {
+        op_apply_prec(op, scheme, prec, sv, dv, dagger != 0);
+      } else {
+        // the odd block through full work fields: copy parity 1 in, apply, copy parity 1 out
+        Field& a = tmp_field(op, prec, 0);
+        Field& b = tmp_field(op, prec, 1);
+        blas(ctx, B_COPY, 1, 1, {&sv, &a});
+        op_apply_odd(op, scheme, prec, a, b, dagger != 0);
+        blas(ctx, B_COPY, 1, 1, {&b, &dv});
+      }
+    }
+  });
+}
+
+tp_status tp_prepare_source_field(tp_op op, int32_t scheme, const tp_field* et, const tp_field* eta) {
+  return guard([&] {
+    need(op, "op");
+    check_scheme(scheme);
+    check_tpfield(op, et, "eta_tilde");
+    check_tpfield(op, eta, "eta");
+    const int lay = scheme_layout(scheme);
+    if (et->layout != lay || et->subset != TP_SUBSET_FULL)
+      TP_THROW(TP_EINVAL, "prepare_source_field: eta_tilde must be a FULL field of the scheme's layout");
+    if (eta->nrhs != et->nrhs) TP_THROW(TP_EINVAL, "prepare_source_field: different nrhs");
+    if (eta->data == et->data) TP_THROW(TP_EINVAL, "prepare_source_field: eta_tilde and eta must differ");
+    const int prec = et->prec;
+    if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
+    if (scheme == TP_TEMPORAL_SCHUR3D && prec == TP_F16N) TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
+    tp_ctx ctx = op->g->ctx;
+    set_device(ctx);
+    for (int r = 0; r < et->nrhs; ++r) {
+      Field in = full_internal(op, *eta, r, lay, prec, 0);
+      Field ov = tpfield_view(ctx->lat, *et, r);
+      op_prepare(op, scheme, prec, in, ov);
+    }
+  });
+}
+
+tp_status tp_reconstruct_field(tp_op op, int32_t scheme, const tp_field* x, const tp_field* y) {
+  return guard([&] {
+    need(op, "op");
+    check_scheme(scheme);
+    check_tpfield(op, x, "x");
+    check_tpfield(op, y, "y");
+    const int lay = scheme_layout(scheme);
+    if (y->layout != lay || y->subset != TP_SUBSET_FULL)
+      TP_THROW(TP_EINVAL, "reconstruct_field: y must be a FULL field of the scheme's layout");
+    if (x->nrhs != y->nrhs) TP_THROW(TP_EINVAL, "reconstruct_field: different nrhs");
+    if (x->data == y->data) TP_THROW(TP_EINVAL, "reconstruct_field: x and y must differ");
+    const int prec = y->prec;
+    if (x->layout != TP_LAYOUT_CANONICAL && (x->layout != lay || x->prec != prec || x->subset != TP_SUBSET_FULL))
+      TP_THROW(TP_EINVAL, "reconstruct_field: x must be canonical or a FULL field like y");
+    if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
+    if (scheme == TP_TEMPORAL_SCHUR3D && prec == TP_F16N) TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
+    tp_ctx ctx = op->g->ctx;
+    set_device(ctx);
+    const Lattice& L = ctx->lat;
+    for (int r = 0; r < y->nrhs; ++r) {
+      Field yv = tpfield_view(L, *y, r);
+      if (x->layout == TP_LAYOUT_CANONICAL) {
+        Field& w = tmp_field(op, prec, 1);
+        op_reconstruct(op, scheme, prec, yv, w);
+        launch_unpack(ctx, w, tpfield_canon(L, *x, r), layout4_of(lay), false,
+                      layout4_of(lay) ? nullptr : op->g->w_d);
+      } else {
+        Field xv = tpfield_view(L, *x, r);
+        op_reconstruct(op, scheme, prec, yv, xv);
+      }
+    }
   });
 }
 

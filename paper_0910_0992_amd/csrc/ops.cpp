@@ -277,6 +277,13 @@ struct KrylovOp {
 
 }  // namespace
 
+// The odd block of a scheme whose even block is solved directly (scheme_sub): the operator
+// the Krylov solver iterates on, reading and writing parity 1 of src and dst only.
+void op_apply_odd(tp_op op, int scheme, int prec, const Field& src, Field& dst, bool dagger) {
+  KrylovOp A{op, scheme, prec, 1, 1};
+  A.apply(src, dst, dagger);
+}
+
 void op_apply_M(tp_op op, int prec, const Field& src, Field& dst, bool dagger) {
   tp_ctx ctx = op->g->ctx;
   if (!dagger) {

@@ -382,6 +382,8 @@ void launch_force(tp_op op, const Field& x, const Field& lam, double2* grad, boo
 // ---------------------------------------------------------------- composite operators (ops.cpp)
 void op_apply_M(tp_op op, int prec, const Field& src, Field& dst, bool dagger);
 void op_apply_prec(tp_op op, int scheme, int prec, const Field& src, Field& dst, bool dagger);
+void op_apply_odd(tp_op op, int scheme, int prec, const Field& src, Field& dst, bool dagger);
+bool scheme_sub(tp_op op, int scheme);
 void op_prepare(tp_op op, int scheme, int prec, const Field& eta, Field& et);
 void op_reconstruct(tp_op op, int scheme, int prec, const Field& y, Field& x);
 bool scheme_layout4(int scheme);

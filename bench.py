@@ -23,9 +23,36 @@ METRIC = "time-to-solution @1e-10 resid (mixed vs FP64 even-odd); operator HBM G
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch, from rocprofv3 FETCH_SIZE + WRITE_SIZE runs scaled by a 1 GiB copy
-# (FETCH x2.0000, WRITE x1.0000), for the kernel sources whose hash is recorded; any change to
-# those sources makes the figure stale and it is reported as null.
-TRAFFIC = {}
+# (FETCH x1.9999, WRITE x1.0000; the runs and their commands are summarised in
+# profiles/hbm_traffic_clover_32x256.md), for the kernel sources whose hash is recorded; any
+# change to those sources makes the figure stale and it is reported as null.
+TRAFFIC = {
+    ("clover_32x256", "F16N", "ilu_mid"): {
+        "bytes_per_launch": 1.5522e+09,
+        "sources": ["k_line_impl.h", "k_line_f16.hip", "k_line.hip", "tp_device.h"],
+        "sha256": "56aee1f3385ed15d0f570e8644d8b0956b4ab8716b63068b189194fbc89c9101",
+    },
+    ("clover_32x256", "F16N", "hop_clover"): {
+        "bytes_per_launch": 2.6012e+09,
+        "sources": ["k_site.hip", "tp_hop.h", "tp_device.h"],
+        "sha256": "1ceae9d98c228f96b34a58207ca05e08e53f2d79357e2a743abbde45db7954dc",
+    },
+    ("clover_32x256", "F16N", "hop_ds"): {
+        "bytes_per_launch": 1.7930e+09,
+        "sources": ["k_site.hip", "tp_hop.h", "tp_device.h"],
+        "sha256": "1ceae9d98c228f96b34a58207ca05e08e53f2d79357e2a743abbde45db7954dc",
+    },
+    ("clover_32x256", "F16N", "blas_bicg_fused"): {
+        "bytes_per_launch": 3.7582e+09,
+        "sources": ["k_blas.hip", "tp_device.h"],
+        "sha256": "e2f2a4d476761fba15de6e965f9202c1193f3ea59d1096a25dda0293644b84fe",
+    },
+    ("clover_32x256", "F16N", "scan_cl"): {
+        "bytes_per_launch": 7.0951e+08,
+        "sources": ["k_line_impl.h", "k_line_f16.hip", "k_line.hip", "tp_device.h"],
+        "sha256": "56aee1f3385ed15d0f570e8644d8b0956b4ab8716b63068b189194fbc89c9101",
+    },
+}
 
 # The five kernels of one temporal + 3D-ILU apply (App. B sequence), in launch order.
 ILU_APPLY = ("scan_cr", "hop_ds", "ilu_mid", "hop_clover", "scan_cl")

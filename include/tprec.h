@@ -74,7 +74,15 @@ enum {
                              S_o = M^oo - M^oe (M^ee)^-1 M^eo.  F64 and F32 (not
                              F16N); the first use on an operator factors M^ee (FP64,
                              2304 bytes per even site, plus an FP32 copy of 1152 bytes
-                             on the first F32 use, kept until tp_op_destroy)       */
+                             on the first F32 use, kept until tp_op_destroy)       */,
+  TP_TEMPORAL_FULLSW = 5  /* full SW temporal preconditioning on the whole lattice
+                             (Sec. II.A, App. A): T = A + mu - D_t inverted exactly,
+                             C_L = T^-1, C_R = 1, so Mt = 1 - T^-1 D_s / gamma_f,
+                             S_L = T^-1, S_R = 1.  Mt is not gamma5-hermitian
+                             (Mt^dagger = gamma5 (1 - D_s T^-1 / gamma_f) gamma5).
+                             F64 and F32 (not F16N); the first use factors T on
+                             both parities (2304 bytes per site, plus 1152 per site
+                             for FP32, kept until tp_op_destroy)                   */
 };
 
 enum { TP_CGNR = 0, TP_BICGSTAB = 1 };
@@ -182,7 +190,9 @@ tp_status tp_apply_CR(tp_op op, int32_t prec, void* dst, const void* src);
 /* The preconditioned operator Mt of `scheme` on the full lattice:
  *   UNPREC M; SCHUR4D diag(A+mu, (A+mu) - D_w^oe (A+mu)^-1 D_w^eo) in p4 parity;
  *   TEMPORAL C_L M C_R; TEMPORAL_SCHUR S_L M S_R in p3 parity; TEMPORAL_SCHUR3D
- *   diag(1, C_L^o S_o C_R^o) in p3 parity. */
+ *   diag(1, C_L^o S_o C_R^o) in p3 parity; TEMPORAL_FULLSW 1 - T^-1 D_s / gamma_f with
+ *   T = A + mu - D_t, in p3 parity.  dagger = 1 applies Mt^dagger: gamma5 Mt gamma5 for all
+ *   but TEMPORAL_FULLSW, whose adjoint is gamma5 (1 - D_s T^-1 / gamma_f) gamma5. */
 tp_status tp_apply_prec(tp_op op, int32_t scheme, int32_t prec, void* dst, const void* src,
                         int32_t dagger);
 /* tp_apply_prec for callers that cannot allocate device memory (code under HIP graph
@@ -190,10 +200,11 @@ tp_status tp_apply_prec(tp_op op, int32_t scheme, int32_t prec, void* dst, const
  * result; its work fields come from a fixed 64 MiB device array of the library (held by
  * every device the library runs on until the process ends) instead of the allocator, and it
  * calls no allocation routine.  Takes (fields of the apply's precision) x V x field bytes:
- * 2 (UNPREC), 3 (SCHUR4D), 4 (TEMPORAL), 6 (TEMPORAL_SCHUR), 7 (TEMPORAL_SCHUR3D), with
- * V x 192 bytes per F64 field, V x 96 per F32 and V x 56 per F16N; a lattice that needs more
- * than 64 MiB is refused with TP_EINVAL, as is TEMPORAL_SCHUR3D before a tp_apply_prec of
- * that scheme and precision has built its factors.  All calls on one device share the
+ * 2 (UNPREC), 3 (SCHUR4D), 4 (TEMPORAL), 6 (TEMPORAL_SCHUR), 7 (TEMPORAL_SCHUR3D),
+ * 4 (TEMPORAL_FULLSW), with V x 192 bytes per F64 field, V x 96 per F32 and V x 56 per F16N;
+ * a lattice that needs more than 64 MiB is refused with TP_EINVAL, as are TEMPORAL_SCHUR3D
+ * and TEMPORAL_FULLSW before a tp_apply_prec of that scheme and precision has built their
+ * factors.  All calls on one device share the
  * array: calls that overlap on one device (other streams, threads or contexts) race, and
  * the caller serialises them.  No per-kernel timing events are recorded. */
 tp_status tp_apply_prec_noalloc(tp_op op, int32_t scheme, int32_t prec, void* dst, const void* src,
@@ -201,7 +212,7 @@ tp_status tp_apply_prec_noalloc(tp_op op, int32_t scheme, int32_t prec, void* ds
 /* eta~ = S_L eta and x = S_R y, with M = S_L^-1 Mt S_R^-1 for `scheme`
  * (SCHUR4D: S_L = L^-1, S_R = U^-1 of the LDU factorisation, Sec. II.B;
  * TEMPORAL_SCHUR3D: S_L = diag((M^ee)^-1, C_L^o) L^-1, S_R = U^-1 diag(1, C_R^o) with the
- * p3 LDU factorisation). */
+ * p3 LDU factorisation; TEMPORAL_FULLSW: S_L = (A + mu - D_t)^-1, S_R = 1). */
 tp_status tp_prepare_source(tp_op op, int32_t scheme, int32_t prec, void* eta_tilde,
                             const void* eta);
 tp_status tp_reconstruct(tp_op op, int32_t scheme, int32_t prec, void* x, const void* y);
@@ -215,7 +226,8 @@ tp_status tp_reconstruct(tp_op op, int32_t scheme, int32_t prec, void* x, const 
  * side, owned by the caller; the right-hand sides of a batch lie back to back.
  *   TP_LAYOUT_CANONICAL  complex128 [Lt][Lz][Ly][Lx][4][3] (prec TP_F64, subset FULL only)
  *   TP_LAYOUT_P3         3D-parity (x+y+z) layout in the axial frame of the gauge field: the
- *                        layout of UNPREC, TEMPORAL, TEMPORAL_SCHUR and TEMPORAL_SCHUR3D
+ *                        layout of UNPREC, TEMPORAL, TEMPORAL_SCHUR, TEMPORAL_SCHUR3D and
+ *                        TEMPORAL_FULLSW
  *   TP_LAYOUT_P4         4D-parity (x+y+z+t) layout: the layout of SCHUR4D
  * Both internal layouts are unitary images of the canonical field (a permutation of sites
  * and components, and for P3 a colour rotation per site), so inner products and norms of F64
@@ -257,7 +269,7 @@ tp_status tp_reconstruct_field(tp_op op, int32_t scheme, const tp_field* x, cons
 
 /* ---- solve ------------------------------------------------------------------------ */
 typedef struct {
-  int32_t scheme;          /* TP_UNPREC ... TP_TEMPORAL_SCHUR3D                     */
+  int32_t scheme;          /* TP_UNPREC ... TP_TEMPORAL_FULLSW                      */
   int32_t solver;          /* TP_CGNR or TP_BICGSTAB                                */
   int32_t prec;            /* inner precision: TP_F64, TP_F32, TP_F16N              */
   int32_t max_iter;        /* cap on inner Krylov iterations summed over restarts  */

@@ -15,11 +15,17 @@ sampled output depends on.
 * T^-1 and T^dagger^-1 act on each time line separately (Sec. II.A), so the
   oracle applied to a lattice of one spatial site, holding one line's links
   and spinor, is exact for that line.
+* (A + mu - D_t)^-1 also acts on each time line separately, but A on the line
+  depends on the links one step away in two spatial directions; the oracle's
+  operator on the periodic 3x3x3 spatial window around the line, of full time
+  extent, has the exact clover term on the centre line, and its inverse there
+  is the lattice's.
 """
 import numpy as np
 
 from . import temporal as T
 from . import wilson as W
+from .schemes import Operator
 
 
 def _window_index(c, n):
@@ -57,4 +63,19 @@ def Tinv_on_lines(U, psi, lines, mu, b=-1.0, dagger=False):
         p = psi[:, z, y, x][:, None, None, None]
         f = T.apply_Tdaginv if dagger else T.apply_Tinv
         out.append(f(ut, p, mu, b)[:, 0, 0, 0])
+    return np.stack(out)
+
+
+def sw_temporal_inv_on_lines(U, psi, lines, m0, gamma_f, b=-1.0, c_s=0.0, c_t=0.0):
+    """(A + mu - D_t)^-1 psi on the time lines (x, y, z) in `lines`, the left factor of full
+    SW temporal preconditioning; returns [n, Lt, 4, 3]."""
+    lt, lz, ly, lx = psi.shape[:4]
+    if min(lx, ly, lz) < 3:
+        raise ValueError("spatial extents of at least 3 are needed for the window")
+    out = []
+    for (x, y, z) in lines:
+        sel = np.ix_(range(lt), _window_index(z, lz), _window_index(y, ly), _window_index(x, lx))
+        Uw = np.stack([U[mu][sel] for mu in range(4)])
+        op = Operator(Uw, m0, gamma_f, b, c_s, c_t)
+        out.append(op.T_inv(psi[sel].copy())[:, 1, 1, 1])
     return np.stack(out)

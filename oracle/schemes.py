@@ -20,6 +20,11 @@ TEMPORAL_SCHUR3D  the same p3 blocks with the even block inverted exactly (tempo
                 (M^ee)^-1 is a sparse direct solve of the assembled even block;
                 for Wilson fermions M^ee = mu - D_t = (C_R C_L)^-1 and the scheme is
                 eq:TPrecFull again.
+TEMPORAL_FULLSW full SW temporal preconditioning on the whole lattice (Sec. II.A, App. A):
+                with T = A + mu - D_t inverted exactly, C_L = T^-1 and C_R = 1, so
+                Q-bar = C_L T C_R = 1 and Mt = C_L M C_R = 1 - T^-1 D_s / gamma_f,
+                S_L = T^-1, S_R = 1.  Mt is not gamma5-hermitian: its adjoint is
+                gamma5 (1 - D_s T^-1 / gamma_f) gamma5.
 
 Blocks are formed literally: K^{ab} psi = mask_a * K(mask_b * psi) on the full
 lattice, so every identity below can be checked by eye against the paper.
@@ -36,7 +41,7 @@ from .dirac import GAMMA5, PT_MINUS, PT_PLUS, spin_apply
 from . import wilson as W
 from .temporal import Temporal
 
-SCHEMES = ("UNPREC", "SCHUR4D", "TEMPORAL", "TEMPORAL_SCHUR", "TEMPORAL_SCHUR3D")
+SCHEMES = ("UNPREC", "SCHUR4D", "TEMPORAL", "TEMPORAL_SCHUR", "TEMPORAL_SCHUR3D", "TEMPORAL_FULLSW")
 
 
 def parity_masks(dims, four_d: bool):
@@ -172,8 +177,9 @@ class Operator:
         return e * chi_e + o * chi_o
 
     # ---- temporal + 3D Schur with the exact even block (p3) --------------------------
-    def _mee_factor(self):
-        """Sparse LU of M^ee = A + mu - D_t on the even p3 sites (identity on odd sites).
+    def _mee_factor(self, rows=None):
+        """Sparse LU of M^ee = A + mu - D_t on the even p3 sites (identity on odd sites), or on
+        the sites where `rows` is true (all sites: the whole-lattice T = A + mu - D_t).
 
         Assembled from the definitions (Sec. II.B; D_t of Sec. II.A with the boundary phase b
         on the wrapping hops): diagonal blocks A(x) + mu, and the temporal hops
@@ -182,7 +188,7 @@ class Operator:
         lx, ly, lz, lt = self.dims
         n = lx * ly * lz * lt * 12
         idx = np.arange(n).reshape(lt, lz, ly, lx, 12)
-        even = self.e3[..., 0, 0] > 0.5
+        even = (self.e3[..., 0, 0] > 0.5) if rows is None else rows
         diag = np.broadcast_to(self.mu * np.eye(12), (lt, lz, ly, lx, 12, 12)).copy()
         if self.clover:
             diag = diag + self.A
@@ -236,6 +242,23 @@ class Operator:
         xo = o * self.tmp.CR(o * y)
         return e * y - self.Mee_inv(e * self.M(xo)) + xo
 
+    # ---- full SW temporal preconditioning on the whole lattice ------------------------
+    def T_inv(self, psi):
+        """(A + mu - D_t)^-1 on every site (a sparse direct solve of the assembled matrix)."""
+        if getattr(self, "_tfull", None) is None:
+            lx, ly, lz, lt = self.dims
+            self._tfull = self._mee_factor(np.ones((lt, lz, ly, lx), dtype=bool))
+        return self._tfull.solve(np.ascontiguousarray(psi.ravel())).reshape(psi.shape)
+
+    def fullsw(self, psi):
+        """Mt = 1 - T^-1 D_s / gamma_f."""
+        return psi - self.T_inv(self.Ds(psi)) / self.gamma_f
+
+    def fullsw_dag(self, psi):
+        """Mt^dagger = 1 - D_s^dagger T^-dagger / gamma_f = gamma5 (1 - D_s T^-1 / gamma_f) gamma5."""
+        phi = spin_apply(GAMMA5, psi)
+        return spin_apply(GAMMA5, phi - self.Ds(self.T_inv(phi)) / self.gamma_f)
+
     # ---- scheme dispatch -------------------------------------------------------------
     def prec(self, scheme, psi):
         if scheme == "UNPREC":
@@ -248,10 +271,14 @@ class Operator:
             return self.tschur(psi)
         if scheme == "TEMPORAL_SCHUR3D":
             return self.tschur3d(psi)
+        if scheme == "TEMPORAL_FULLSW":
+            return self.fullsw(psi)
         raise ValueError(scheme)
 
     def prec_dag(self, scheme, psi):
-        """Every Mt here is gamma5-hermitian, so Mt^dagger = gamma5 Mt gamma5."""
+        """Every Mt here but TEMPORAL_FULLSW is gamma5-hermitian, Mt^dagger = gamma5 Mt gamma5."""
+        if scheme == "TEMPORAL_FULLSW":
+            return self.fullsw_dag(psi)
         return spin_apply(GAMMA5, self.prec(scheme, spin_apply(GAMMA5, psi)))
 
     def prepare_source(self, scheme, eta):
@@ -265,6 +292,8 @@ class Operator:
             return self.tschur_SL(eta)
         if scheme == "TEMPORAL_SCHUR3D":
             return self.tschur3d_SL(eta)
+        if scheme == "TEMPORAL_FULLSW":
+            return self.T_inv(eta)
         raise ValueError(scheme)
 
     def reconstruct(self, scheme, y):
@@ -278,6 +307,8 @@ class Operator:
             return self.tschur_SR(y)
         if scheme == "TEMPORAL_SCHUR3D":
             return self.tschur3d_SR(y)
+        if scheme == "TEMPORAL_FULLSW":
+            return y.copy()
         raise ValueError(scheme)
 
     def solve_subspace(self, scheme):

@@ -13,7 +13,8 @@ LIB_PATH = os.path.join(_HERE, "libtprec.so")
 TP_OK, TP_EINVAL, TP_EDIMS, TP_ESINGULAR, TP_ENOCONV, TP_EBREAKDOWN, TP_ENOMEM, TP_EHIP = (
     0, -1, -2, -3, -4, -5, -6, -7)
 TP_HOST, TP_DEVICE = 0, 1
-SCHEMES = {"UNPREC": 0, "SCHUR4D": 1, "TEMPORAL": 2, "TEMPORAL_SCHUR": 3, "TEMPORAL_SCHUR3D": 4}
+SCHEMES = {"UNPREC": 0, "SCHUR4D": 1, "TEMPORAL": 2, "TEMPORAL_SCHUR": 3, "TEMPORAL_SCHUR3D": 4,
+           "TEMPORAL_FULLSW": 5}
 SOLVERS = {"CGNR": 0, "BICGSTAB": 1}
 PRECS = {"F64": 0, "F32": 1, "F16N": 2}
 LAYOUTS = {"CANONICAL": 0, "P3": 1, "P4": 2}

@@ -44,7 +44,16 @@ void check_prec(int prec) {
   if (prec != TP_F64 && prec != TP_F32 && prec != TP_F16N) TP_THROW(TP_EINVAL, "bad precision");
 }
 void check_scheme(int s) {
-  if (s < TP_UNPREC || s > TP_TEMPORAL_SCHUR3D) TP_THROW(TP_EINVAL, "bad scheme");
+  if (s < TP_UNPREC || s > TP_TEMPORAL_FULLSW) TP_THROW(TP_EINVAL, "bad scheme");
+}
+// Schemes with an exact block inverse (SCHUR4D's (A+mu)^-1, the block-LU T^-1) run in F64
+// and F32 only.
+void check_scheme_prec(int scheme, int prec) {
+  if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
+  if (scheme == TP_TEMPORAL_SCHUR3D && prec == TP_F16N)
+    TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
+  if (scheme == TP_TEMPORAL_FULLSW && prec == TP_F16N)
+    TP_THROW(TP_EINVAL, "TEMPORAL_FULLSW runs in F64 and F32");
 }
 void need(const void* p, const char* what) {
   if (!p) TP_THROW(TP_EINVAL, std::string("null pointer: ") + what);
@@ -279,6 +288,7 @@ int noalloc_fields(int scheme) {
     case TP_SCHUR4D: return 3;
     case TP_TEMPORAL: return 4;
     case TP_TEMPORAL_SCHUR: return 6;
+    case TP_TEMPORAL_FULLSW: return 4;
     default: return 7;  // TP_TEMPORAL_SCHUR3D
   }
 }
@@ -835,11 +845,13 @@ tp_status tp_apply_prec(tp_op op, int32_t scheme, int32_t prec, void* dst, const
                         int32_t dagger) {
   return guard([&] {
     check_scheme(scheme);
-    if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
-    if (scheme == TP_TEMPORAL_SCHUR3D && prec == TP_F16N)
-      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
+    check_scheme_prec(scheme, prec);
+    // dagger: gamma5 on the way in and out around N (Mt^dagger = gamma5 N gamma5)
     tp_status s = apply_wrap(op, prec, dst, src, scheme_layout4(scheme), dagger != 0,
-                             [&](Field& a, Field& b) { op_apply_prec(op, scheme, prec, a, b, false); });
+                             [&](Field& a, Field& b) {
+                               if (dagger) op_apply_prec_adj(op, scheme, prec, a, b);
+                               else op_apply_prec(op, scheme, prec, a, b, false);
+                             });
     if (s != TP_OK) TP_THROW(s, g_last_error);
   });
 }
@@ -850,13 +862,11 @@ tp_status tp_apply_prec_noalloc(tp_op op, int32_t scheme, int32_t prec, void* ds
     need(op, "op");
     check_scheme(scheme);
     check_prec(prec);
-    if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
-    if (scheme == TP_TEMPORAL_SCHUR3D && prec == TP_F16N)
-      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
-    if (scheme == TP_TEMPORAL_SCHUR3D &&
-        !(prec == TP_F64 ? static_cast<const void*>(op->s3_inv) : static_cast<const void*>(op->s3_inv_f)))
-      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D: its factors are built (and allocated) by the first "
-                          "tp_apply_prec of the scheme in this precision");
+    check_scheme_prec(scheme, prec);
+    if ((scheme == TP_TEMPORAL_SCHUR3D && !schur3d_ready(op, prec, 0)) ||
+        (scheme == TP_TEMPORAL_FULLSW && !(schur3d_ready(op, prec, 0) && schur3d_ready(op, prec, 1))))
+      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D, TEMPORAL_FULLSW: their factors are built (and allocated) "
+                          "by the first tp_apply_prec of the scheme in this precision");
     tp_ctx ctx = op->g->ctx;
     const size_t needb = size_t(noalloc_fields(scheme)) * field_bytes(ctx->lat, prec);
     if (needb > kScratchBytes)
@@ -881,8 +891,12 @@ tp_status tp_apply_prec_noalloc(tp_op op, int32_t scheme, int32_t prec, void* ds
         op->g->ctx->prof = prof;
       }
     } scope(op, ctx->scratch);
+    // dagger: gamma5 on the way in and out around N (Mt^dagger = gamma5 N gamma5)
     tp_status s = apply_wrap(op, prec, dst, src, scheme_layout4(scheme), dagger != 0,
-                             [&](Field& a, Field& b) { op_apply_prec(op, scheme, prec, a, b, false); });
+                             [&](Field& a, Field& b) {
+                               if (dagger) op_apply_prec_adj(op, scheme, prec, a, b);
+                               else op_apply_prec(op, scheme, prec, a, b, false);
+                             });
     if (s != TP_OK) TP_THROW(s, g_last_error);
   });
 }
@@ -890,9 +904,7 @@ tp_status tp_apply_prec_noalloc(tp_op op, int32_t scheme, int32_t prec, void* ds
 tp_status tp_prepare_source(tp_op op, int32_t scheme, int32_t prec, void* et, const void* eta) {
   return guard([&] {
     check_scheme(scheme);
-    if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
-    if (scheme == TP_TEMPORAL_SCHUR3D && prec == TP_F16N)
-      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
+    check_scheme_prec(scheme, prec);
     tp_status s = apply_wrap(op, prec, et, eta, scheme_layout4(scheme), false,
                              [&](Field& a, Field& b) { op_prepare(op, scheme, prec, a, b); });
     if (s != TP_OK) TP_THROW(s, g_last_error);
@@ -902,9 +914,7 @@ tp_status tp_prepare_source(tp_op op, int32_t scheme, int32_t prec, void* et, co
 tp_status tp_reconstruct(tp_op op, int32_t scheme, int32_t prec, void* x, const void* y) {
   return guard([&] {
     check_scheme(scheme);
-    if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
-    if (scheme == TP_TEMPORAL_SCHUR3D && prec == TP_F16N)
-      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
+    check_scheme_prec(scheme, prec);
     tp_status s = apply_wrap(op, prec, x, y, scheme_layout4(scheme), false,
                              [&](Field& a, Field& b) { op_reconstruct(op, scheme, prec, a, b); });
     if (s != TP_OK) TP_THROW(s, g_last_error);
@@ -973,8 +983,7 @@ tp_status tp_apply_prec_field(tp_op op, int32_t scheme, const tp_field* dst, con
     if (dst->prec != src->prec || dst->subset != src->subset || dst->nrhs != src->nrhs)
       TP_THROW(TP_EINVAL, "apply_prec_field: fields of different precision, subset or nrhs");
     const int prec = src->prec;
-    if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
-    if (scheme == TP_TEMPORAL_SCHUR3D && prec == TP_F16N) TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
+    check_scheme_prec(scheme, prec);
     if (src->subset == TP_SUBSET_EVEN) TP_THROW(TP_EINVAL, "apply_prec_field: FULL or ODD fields");
     if (src->subset == TP_SUBSET_ODD && !scheme_sub(op, scheme))
       TP_THROW(TP_EINVAL, "apply_prec_field: ODD fields only for schemes solved on the odd block");
@@ -1012,8 +1021,7 @@ tp_status tp_prepare_source_field(tp_op op, int32_t scheme, const tp_field* et, 
     if (eta->nrhs != et->nrhs) TP_THROW(TP_EINVAL, "prepare_source_field: different nrhs");
     if (eta->data == et->data) TP_THROW(TP_EINVAL, "prepare_source_field: eta_tilde and eta must differ");
     const int prec = et->prec;
-    if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
-    if (scheme == TP_TEMPORAL_SCHUR3D && prec == TP_F16N) TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
+    check_scheme_prec(scheme, prec);
     tp_ctx ctx = op->g->ctx;
     set_device(ctx);
     for (int r = 0; r < et->nrhs; ++r) {
@@ -1038,8 +1046,7 @@ tp_status tp_reconstruct_field(tp_op op, int32_t scheme, const tp_field* x, cons
     const int prec = y->prec;
     if (x->layout != TP_LAYOUT_CANONICAL && (x->layout != lay || x->prec != prec || x->subset != TP_SUBSET_FULL))
       TP_THROW(TP_EINVAL, "reconstruct_field: x must be canonical or a FULL field like y");
-    if (scheme == TP_SCHUR4D && prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
-    if (scheme == TP_TEMPORAL_SCHUR3D && prec == TP_F16N) TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
+    check_scheme_prec(scheme, prec);
     tp_ctx ctx = op->g->ctx;
     set_device(ctx);
     const Lattice& L = ctx->lat;
@@ -1073,9 +1080,7 @@ tp_status tp_solve(tp_op op, const tp_solve_params* params, void* x, const void*
     check_prec(P.prec);
     if (P.solver != TP_CGNR && P.solver != TP_BICGSTAB) TP_THROW(TP_EINVAL, "bad solver");
     if (P.dagger != 0 && P.dagger != 1) TP_THROW(TP_EINVAL, "dagger must be 0 or 1");
-    if (P.scheme == TP_SCHUR4D && P.prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
-    if (P.scheme == TP_TEMPORAL_SCHUR3D && P.prec == TP_F16N)
-      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
+    check_scheme_prec(P.scheme, P.prec);
     if (!(P.tol >= 0) || !(P.inner_tol >= 0)) TP_THROW(TP_EINVAL, "tolerances");
     tp_ctx ctx = op->g->ctx;
     set_device(ctx);
@@ -1121,9 +1126,7 @@ tp_status tp_solve_multi(tp_op op, const tp_solve_params* params, int32_t nrhs, 
     check_prec(P.prec);
     if (P.solver != TP_CGNR && P.solver != TP_BICGSTAB) TP_THROW(TP_EINVAL, "bad solver");
     if (P.dagger != 0 && P.dagger != 1) TP_THROW(TP_EINVAL, "dagger must be 0 or 1");
-    if (P.scheme == TP_SCHUR4D && P.prec == TP_F16N) TP_THROW(TP_EINVAL, "SCHUR4D supports F64 and F32");
-    if (P.scheme == TP_TEMPORAL_SCHUR3D && P.prec == TP_F16N)
-      TP_THROW(TP_EINVAL, "TEMPORAL_SCHUR3D runs in F64 and F32");
+    check_scheme_prec(P.scheme, P.prec);
     if (!(P.tol >= 0) || !(P.inner_tol >= 0)) TP_THROW(TP_EINVAL, "tolerances");
     tp_ctx ctx = op->g->ctx;
     set_device(ctx);

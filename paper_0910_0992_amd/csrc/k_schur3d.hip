@@ -1,15 +1,17 @@
-// Exact inverse of the even p3 block M^ee = A + mu - D_t: the even-site solve of temporal
-// preconditioning combined with 3D-Schur (Sec. II.B; App. A writes the block as a
-// tridiagonal matrix plus a corner term).  The factors are computed in FP64; the sweeps run
-// in FP64, or in FP32 on a rounded copy of the factors for the FP32 operator.
+// Exact inverse of T = A + mu - D_t on the sites of one p3 parity.  On the even sites this is
+// the block M^ee, the even-site solve of temporal preconditioning combined with 3D-Schur
+// (Sec. II.B); on both parities it is the left factor of full SW temporal preconditioning on
+// the whole lattice (Sec. II.A, App. A, which writes the matrix as a tridiagonal part plus a
+// corner term).  The factors are computed in FP64; the sweeps run in FP64, or in FP32 on a
+// rounded copy of the factors for the FP32 operator.
 //
-// In the axial frame every interior time link is the identity, so on an even time line
-//   (M^ee psi)(t) = B(t) psi(t) - P_- psi(t+1) - P_+ psi(t-1),   B(t) = A(t) + mu,
+// In the axial frame every interior time link is the identity, so on a time line
+//   (T psi)(t) = B(t) psi(t) - P_- psi(t+1) - P_+ psi(t-1),   B(t) = A(t) + mu,
 // with the wrapping hops -P_- P psi(0) in row Lt-1 and -P_+ P^dag psi(Lt-1) in row 0 (P is
 // the axial link U_t(Lt-1): the Polyakov loop times the boundary phase).  In the Dirac-Pauli
 // basis P_+ keeps spins 0-1 (rows 0-5, spin*3 + colour) and P_- spins 2-3 (rows 6-11).
 //
-// Split M^ee = T0 + V W^dag: T0 is the open block-tridiagonal part, and the corner term has
+// Split T = T0 + V W^dag: T0 is the open block-tridiagonal part, and the corner term has
 // rank 12 with W^dag psi = (rows 0-5 of psi(Lt-1), rows 6-11 of psi(0)).  By
 // Sherman-Morrison-Woodbury, as the paper does for the temporal matrix (Sec. II.A),
 //   x = T0^-1 (eta + c(beta)),   beta = K W^dag T0^-1 eta,   K = (1 + W^dag T0^-1 V)^-1,
@@ -20,7 +22,7 @@
 // x(t) = w(t) + S(t)^-1 P_- x(t+1).  An apply is two such solves: the first only yields
 // W^dag T0^-1 eta.  K comes from twelve solves with the unit vectors as beta and eta = 0.
 //
-// Storage: S(t)^-1 for every even site as [tile][t][column][row][line of the tile], so the
+// Storage per parity: S(t)^-1 for every site as [tile][t][column][row][line of the tile], so the
 // 48 lanes (row, line) of one wavefront that handle a tile read one column in a single
 // contiguous load (768 bytes in FP64).  K is [line][row][column].
 #include "tp_internal.h"
@@ -97,8 +99,8 @@ __device__ bool gj_invert(double2* m, int* perm, int th) {
   return ok;
 }
 
-// Block LU of T0 along each even line (one thread per line): S(t)^-1 for t = 0..Lt-1.
-// cl: even-parity clover planes (A, chiral blocks) or null for Wilson fermions.
+// Block LU of T0 along each line of one parity (one thread per line): S(t)^-1 for t = 0..Lt-1.
+// cl: that parity's clover planes (A, chiral blocks) or null for Wilson fermions.
 __global__ __launch_bounds__(kFacThreads) void k_s3_factor(const double2* __restrict__ cl,
                                                            int64_t V2, double mu, Geom g,
                                                            int nlines,
@@ -179,15 +181,16 @@ __global__ __launch_bounds__(kFacThreads) void k_s3_capacitance(const double2* _
   for (int k = 0; k < 144; ++k) kmat[(int64_t)s * 144 + k] = m[k * NT + th];
 }
 
-// One wavefront per tile of 4 even lines; lane = row * 4 + line for rows 0-11 (lanes 48-63
-// only join the barriers).
+// One wavefront per tile of 4 lines of parity slot blockIdx.y; lane = row * 4 + line for
+// rows 0-11 (lanes 48-63 only join the barriers).
 struct SweepLane {
-  int tile, lane, r, l, s;
+  int tile, lane, r, l, s, k;
   bool active;
 };
 __device__ SweepLane sweep_lane() {
   SweepLane q;
   q.tile = blockIdx.x;
+  q.k = blockIdx.y;
   q.lane = threadIdx.x;
   q.r = q.lane >> 2;
   q.l = q.lane & 3;
@@ -196,39 +199,49 @@ __device__ SweepLane sweep_lane() {
   return q;
 }
 
-// Element (row r, site i) of an even-parity spinor field of storage T: half r / 6,
+// Element (row r, site i) of one parity of a spinor field of storage T: half r / 6,
 // component r % 6 (FP32 planes are paired).
 template <typename T>
 __device__ int64_t row_off(int r, int64_t V2, int64_t i) {
   return comp_off<T>(r < 6 ? r : r - 6, 6, V2, i);
 }
 
-// Forward sweep: w(t) = S(t)^-1 (eta(t) + P_+ w(t-1) + c(beta)(t)), storage T (double2:
-// FP64; float2: FP32 factors and spinors, FP32 arithmetic).
-// eta: even-parity halves, or null for eta = 0.  beta per line: K q when kmat is given,
-// the unit vector `unit` when unit >= 0, else no corner term.
-// link_t: FP64 planes [9][V2] of the even-parity axial time links (P at t = Lt-1).
+// Operands of one sweep launch, per parity slot k = blockIdx.y (one or two parities).
 template <typename T>
-__global__ __launch_bounds__(64) void k_s3_forward(const T* __restrict__ eta_up,
-                                                   const T* __restrict__ eta_lo, int64_t V2,
-                                                   Geom g, const T* __restrict__ sinv,
-                                                   const double2* __restrict__ link_t,
-                                                   const T* __restrict__ kmat,
-                                                   const T* __restrict__ q, int unit,
-                                                   T* __restrict__ w_up, T* __restrict__ w_lo) {
+struct Sweep {
+  const T* in_up[2] = {};    // forward: eta (null: eta = 0); backward: w
+  const T* in_lo[2] = {};
+  T* out_up[2] = {};         // forward: w; backward: x (null: not stored)
+  T* out_lo[2] = {};
+  const T* base_up[2] = {};  // backward: x is stored as base - x when given
+  const T* base_lo[2] = {};
+  const T* sinv[2] = {};
+  const T* kmat[2] = {};     // forward: beta = K q per line when given
+  const T* q[2] = {};
+  T* qout[2] = {};           // backward: W^dag x per line when given
+  const double2* link_t[2] = {};  // FP64 planes [9][V2] of the parity's axial time links
+  int unit = -1;             // forward: beta = unit vector `unit` when >= 0
+};
+
+// Forward sweep: w(t) = S(t)^-1 (eta(t) + P_+ w(t-1) + c(beta)(t)), storage T (double2:
+// FP64; float2: FP32 factors and spinors, FP32 arithmetic).  The corner term is K q when
+// kmat is given, the unit vector `unit` when unit >= 0, else absent.
+template <typename T>
+__global__ __launch_bounds__(64) void k_s3_forward(Sweep<T> a, int64_t V2, Geom g) {
   using R = typename Prec<T>::R;
   __shared__ cx<R> zb[4][12];
   __shared__ cx<R> db[4][12];
   const SweepLane ln = sweep_lane();
-  const bool corner = kmat != nullptr || unit >= 0;
+  const T* kmat = a.kmat[ln.k];
+  const bool corner = kmat != nullptr || a.unit >= 0;
   if (ln.active && corner) {
     cx<R> d = czero<R>();
     if (kmat) {
       const T* kr = kmat + (int64_t)ln.s * 144 + ln.r * 12;
-      const T* qs = q + (int64_t)ln.s * 12;
+      const T* qs = a.q[ln.k] + (int64_t)ln.s * 12;
 #pragma unroll
       for (int c = 0; c < 12; ++c) d += cmul(ld<R, T>(kr + c), ld<R, T>(qs + c));
-    } else if (ln.r == unit) {
+    } else if (ln.r == a.unit) {
       d = cx<R>{R(1), R(0)};
     }
     db[ln.l][ln.r] = d;
@@ -237,23 +250,24 @@ __global__ __launch_bounds__(64) void k_s3_forward(const T* __restrict__ eta_up,
   // this lane's corner term: rows 0-5 at t = 0, rows 6-11 at t = Lt-1
   cx<R> corr = czero<R>();
   if (ln.active && corner) {
+    const double2* link_t = a.link_t[ln.k];
     const int64_t ib = p3_idx(g, g.Lt - 1, ln.s);
     const int rr = ln.r < 6 ? ln.r : ln.r - 6;
-    const int sp = rr / 3, a = rr % 3;
+    const int sp = rr / 3, c3 = rr % 3;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
       if (ln.r < 6) {
-        double2 u = link_t[(int64_t)(b * 3 + a) * V2 + ib];  // (P^dag)_{ab} = conj(P_{ba})
+        double2 u = link_t[(int64_t)(b * 3 + c3) * V2 + ib];  // (P^dag)_{ab} = conj(P_{ba})
         corr += cmulc(cx<R>{R(u.x), R(u.y)}, db[ln.l][sp * 3 + b]);
       } else {
-        double2 u = link_t[(int64_t)(a * 3 + b) * V2 + ib];
+        double2 u = link_t[(int64_t)(c3 * 3 + b) * V2 + ib];
         corr += cmul(cx<R>{R(u.x), R(u.y)}, db[ln.l][6 + sp * 3 + b]);
       }
     }
   }
-  const T* ep = ln.active && eta_up ? (ln.r < 6 ? eta_up : eta_lo) : nullptr;
-  T* wp = ln.active ? (ln.r < 6 ? w_up : w_lo) : nullptr;
-  const T* sbase = sinv + (int64_t)ln.tile * g.Lt * 576 + ln.lane;
+  const T* ep = ln.active && a.in_up[ln.k] ? (ln.r < 6 ? a.in_up[ln.k] : a.in_lo[ln.k]) : nullptr;
+  T* wp = ln.active ? (ln.r < 6 ? a.out_up[ln.k] : a.out_lo[ln.k]) : nullptr;
+  const T* sbase = a.sinv[ln.k] + (int64_t)ln.tile * g.Lt * 576 + ln.lane;
   cx<R> wprev = czero<R>();
 #pragma unroll 1
   for (int t = 0; t < g.Lt; ++t) {
@@ -282,20 +296,20 @@ __global__ __launch_bounds__(64) void k_s3_forward(const T* __restrict__ eta_up,
   }
 }
 
-// Backward sweep: x(t) = w(t) + S(t)^-1 P_- x(t+1).  x (optional) receives the solution;
-// qout (optional) receives W^dag x = (rows 0-5 of x(Lt-1), rows 6-11 of x(0)) per line.
+// Backward sweep: x(t) = w(t) + S(t)^-1 P_- x(t+1).  out (optional) receives x, or base - x
+// when base is given; qout (optional) receives W^dag x = (rows 0-5 of x(Lt-1), rows 6-11
+// of x(0)) per line.
 template <typename T>
-__global__ __launch_bounds__(64) void k_s3_backward(const T* __restrict__ w_up,
-                                                    const T* __restrict__ w_lo, int64_t V2,
-                                                    Geom g, const T* __restrict__ sinv,
-                                                    T* __restrict__ x_up, T* __restrict__ x_lo,
-                                                    T* __restrict__ qout) {
+__global__ __launch_bounds__(64) void k_s3_backward(Sweep<T> a, int64_t V2, Geom g) {
   using R = typename Prec<T>::R;
   __shared__ cx<R> xb[4][12];
   const SweepLane ln = sweep_lane();
-  const T* wp = ln.active ? (ln.r < 6 ? w_up : w_lo) : nullptr;
-  T* xp = ln.active && x_up ? (ln.r < 6 ? x_up : x_lo) : nullptr;
-  const T* sbase = sinv + (int64_t)ln.tile * g.Lt * 576 + ln.lane;
+  const T* wp = ln.active ? (ln.r < 6 ? a.in_up[ln.k] : a.in_lo[ln.k]) : nullptr;
+  T* xp = ln.active && a.out_up[ln.k] ? (ln.r < 6 ? a.out_up[ln.k] : a.out_lo[ln.k]) : nullptr;
+  const T* bp =
+      ln.active && a.base_up[ln.k] ? (ln.r < 6 ? a.base_up[ln.k] : a.base_lo[ln.k]) : nullptr;
+  T* qout = a.qout[ln.k];
+  const T* sbase = a.sinv[ln.k] + (int64_t)ln.tile * g.Lt * 576 + ln.lane;
 #pragma unroll 1
   for (int t = g.Lt - 1; t >= 0; --t) {
     const int64_t i = p3_idx(g, t, ln.s);
@@ -311,7 +325,10 @@ __global__ __launch_bounds__(64) void k_s3_backward(const T* __restrict__ w_up,
     __syncthreads();  // every lane has read x(t+1)
     if (ln.active) {
       if (ln.r >= 6) xb[ln.l][ln.r] = x;
-      if (xp) st(xp + row_off<T>(ln.r, V2, i), x);
+      if (xp) {
+        const int64_t o = row_off<T>(ln.r, V2, i);
+        st(xp + o, bp ? ld<R, T>(bp + o) - x : x);
+      }
       if (qout && ((t == g.Lt - 1 && ln.r < 6) || (t == 0 && ln.r >= 6)))
         st(qout + (int64_t)ln.s * 12 + ln.r, x);
     }
@@ -328,12 +345,12 @@ size_t factor_lds() { return size_t(kFacThreads) * (180 * sizeof(double2) + 12 *
 
 }  // namespace
 
-// Factorisation and capacitance of M^ee for this operator (even parity), FP64.
-void schur3d_setup(tp_op op) {
-  if (op->s3_inv) return;
+// Factorisation and capacitance of T = A + mu - D_t on p3 parity par for this operator, FP64.
+void schur3d_setup(tp_op op, int par) {
+  if (op->s3_inv[par]) return;
   tp_ctx ctx = op->g->ctx;
   const Lattice& L = ctx->lat;
-  if (factor_lds() > ctx->lds_max) TP_THROW(TP_EDIMS, "device LDS too small for the M^ee factorisation");
+  if (factor_lds() > ctx->lds_max) TP_THROW(TP_EDIMS, "device LDS too small for the T factorisation");
   const int nlines = L.Vs2;
   const int nblk = (nlines + kFacThreads - 1) / kFacThreads;
   double2* sinv = static_cast<double2*>(dev_alloc(ctx, size_t(L.V2) * 144 * sizeof(double2)));
@@ -347,22 +364,28 @@ void schur3d_setup(tp_op op) {
     bad = static_cast<int*>(dev_alloc(ctx, sizeof(int)));
     w = field_alloc(ctx, TP_F64);
     HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
-    const double2* cl = op->c ? op->c->a3_d : nullptr;  // even parity first
+    const double2* cl = op->c ? op->c->a3_d + (int64_t)par * 36 * L.V2 : nullptr;
     hipLaunchKernelGGL(k_s3_factor, dim3(nblk), dim3(kFacThreads), factor_lds(), ctx->stream, cl,
                        L.V2, op->mu, L.g, nlines, sinv, bad);
     LAUNCH_CHECK();
-    const double2* link_t = op->g->u3_d + (int64_t)(3 * 2 + 0) * 9 * L.V2;
-    SpinorF<double2> wf = w.par<double2>(0);
+    SpinorF<double2> wf = w.par<double2>(par);
     for (int j = 0; j < 12; ++j) {
-      hipLaunchKernelGGL(k_s3_forward<double2>, dim3(nlines / 4), dim3(64), 0, ctx->stream,
-                         (const double2*)nullptr, (const double2*)nullptr, L.V2, L.g,
-                         (const double2*)sinv, link_t, (const double2*)nullptr,
-                         (const double2*)nullptr, j, wf.p[0], wf.p[1]);
+      Sweep<double2> f;
+      f.out_up[0] = wf.p[0];
+      f.out_lo[0] = wf.p[1];
+      f.sinv[0] = sinv;
+      f.link_t[0] = op->g->u3_d + (int64_t)(3 * 2 + par) * 9 * L.V2;
+      f.unit = j;
+      hipLaunchKernelGGL(k_s3_forward<double2>, dim3(nlines / 4, 1), dim3(64), 0, ctx->stream, f,
+                         L.V2, L.g);
       LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_s3_backward<double2>, dim3(nlines / 4), dim3(64), 0, ctx->stream,
-                         (const double2*)wf.p[0], (const double2*)wf.p[1], L.V2, L.g,
-                         (const double2*)sinv, (double2*)nullptr, (double2*)nullptr,
-                         qbuf + (int64_t)j * nlines * 12);
+      Sweep<double2> b;
+      b.in_up[0] = wf.p[0];
+      b.in_lo[0] = wf.p[1];
+      b.sinv[0] = sinv;
+      b.qout[0] = qbuf + (int64_t)j * nlines * 12;
+      hipLaunchKernelGGL(k_s3_backward<double2>, dim3(nlines / 4, 1), dim3(64), 0, ctx->stream, b,
+                         L.V2, L.g);
       LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_s3_capacitance, dim3(nblk), dim3(kFacThreads),
@@ -372,7 +395,7 @@ void schur3d_setup(tp_op op) {
     int hb = 0;
     HIP_CHECK(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIP_CHECK(hipStreamSynchronize(ctx->stream));
-    if (hb) TP_THROW(TP_ESINGULAR, "M^ee factorisation: zero pivot");
+    if (hb) TP_THROW(TP_ESINGULAR, "A + mu - D_t factorisation: zero pivot");
   } catch (...) {
     field_free(ctx, w);
     dev_free(ctx, bad);
@@ -383,15 +406,16 @@ void schur3d_setup(tp_op op) {
   }
   field_free(ctx, w);
   dev_free(ctx, bad);
-  op->s3_inv = sinv;
-  op->s3_k = kmat;
-  op->s3_q = qbuf;  // the first 12 complex per line serve the applies
+  op->s3_inv[par] = sinv;
+  op->s3_k[par] = kmat;
+  op->s3_q[par] = qbuf;  // the first 12 complex per line serve the applies
 }
 
-// FP32 copies of the factors for the FP32 operator (rounded from the FP64 factorisation).
-void schur3d_setup_f32(tp_op op) {
-  schur3d_setup(op);
-  if (op->s3_inv_f) return;
+namespace {
+// FP32 copies of the factors of parity par for the FP32 operator (rounded from FP64).
+void schur3d_setup_f32(tp_op op, int par) {
+  schur3d_setup(op, par);
+  if (op->s3_inv_f[par]) return;
   tp_ctx ctx = op->g->ctx;
   const Lattice& L = ctx->lat;
   const int64_t ni = L.V2 * 144, nk = int64_t(L.Vs2) * 144;
@@ -402,10 +426,10 @@ void schur3d_setup_f32(tp_op op) {
     fk = static_cast<float2*>(dev_alloc(ctx, size_t(nk) * sizeof(float2)));
     fq = static_cast<float2*>(dev_alloc(ctx, size_t(L.Vs2) * 12 * sizeof(float2)));
     hipLaunchKernelGGL(k_s3_round, dim3(unsigned((ni + 255) / 256)), dim3(256), 0, ctx->stream,
-                       op->s3_inv, fi, ni);
+                       op->s3_inv[par], fi, ni);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_s3_round, dim3(unsigned((nk + 255) / 256)), dim3(256), 0, ctx->stream,
-                       op->s3_k, fk, nk);
+                       op->s3_k[par], fk, nk);
     LAUNCH_CHECK();
     HIP_CHECK(hipStreamSynchronize(ctx->stream));
   } catch (...) {
@@ -414,71 +438,104 @@ void schur3d_setup_f32(tp_op op) {
     dev_free(ctx, fi);
     throw;
   }
-  op->s3_inv_f = fi;
-  op->s3_k_f = fk;
-  op->s3_q_f = fq;
+  op->s3_inv_f[par] = fi;
+  op->s3_k_f[par] = fk;
+  op->s3_q_f[par] = fq;
+}
+}  // namespace
+
+bool schur3d_ready(tp_op op, int prec, int par) {
+  return prec == TP_F64 ? op->s3_inv[par] != nullptr : op->s3_inv_f[par] != nullptr;
 }
 
 void schur3d_free(tp_op op) {
   tp_ctx ctx = op->g->ctx;
-  dev_free(ctx, op->s3_inv);
-  dev_free(ctx, op->s3_k);
-  dev_free(ctx, op->s3_q);
-  dev_free(ctx, op->s3_inv_f);
-  dev_free(ctx, op->s3_k_f);
-  dev_free(ctx, op->s3_q_f);
-  op->s3_inv = op->s3_k = op->s3_q = nullptr;
-  op->s3_inv_f = op->s3_k_f = op->s3_q_f = nullptr;
+  for (int p = 0; p < 2; ++p) {
+    dev_free(ctx, op->s3_inv[p]);
+    dev_free(ctx, op->s3_k[p]);
+    dev_free(ctx, op->s3_q[p]);
+    dev_free(ctx, op->s3_inv_f[p]);
+    dev_free(ctx, op->s3_k_f[p]);
+    dev_free(ctx, op->s3_q_f[p]);
+    op->s3_inv[p] = op->s3_k[p] = op->s3_q[p] = nullptr;
+    op->s3_inv_f[p] = op->s3_k_f[p] = op->s3_q_f[p] = nullptr;
+  }
 }
 
 namespace {
+// Two solves of T0 per parity (Sherman-Morrison-Woodbury): the first only yields the
+// boundary values q = W^dag T0^-1 src, the second adds the corner term K q.  Both parities
+// of a call run in the same launches (blockIdx.y).
 template <typename T>
-void mee_inv_impl(tp_op op, const Field& src, Field& dst, Field& w, const T* sinv, const T* kmat,
-                  T* q) {
+void tinv_impl(tp_op op, int par0, int npar, const Field& src, Field& dst, Field& w,
+               const Field* base, T* const* sinv, T* const* kmat, T* const* q) {
   tp_ctx ctx = op->g->ctx;
   const Lattice& L = ctx->lat;
-  const int nlines = L.Vs2;
-  const double2* link_t = op->g->u3_d + (int64_t)(3 * 2 + 0) * 9 * L.V2;
+  const dim3 grid(L.Vs2 / 4, npar);
   for (int r = 0; r < src.nr; ++r) {
-    SpinorF<T> sf = src.view(r).template par<T>(0);
-    SpinorF<T> df = dst.view(r).template par<T>(0);
-    SpinorF<T> wf = w.view(r).template par<T>(0);
-    hipLaunchKernelGGL(k_s3_forward<T>, dim3(nlines / 4), dim3(64), 0, ctx->stream,
-                       (const T*)sf.p[0], (const T*)sf.p[1], L.V2, L.g, sinv, link_t,
-                       (const T*)nullptr, (const T*)nullptr, -1, wf.p[0], wf.p[1]);
+    Sweep<T> f1, b1, f2, b2;
+    for (int k = 0; k < npar; ++k) {
+      const int p = par0 + k;
+      SpinorF<T> sf = src.view(r).template par<T>(p);
+      SpinorF<T> df = dst.view(r).template par<T>(p);
+      SpinorF<T> wf = w.view(r).template par<T>(p);
+      const double2* link_t = op->g->u3_d + (int64_t)(3 * 2 + p) * 9 * L.V2;
+      f1.in_up[k] = f2.in_up[k] = sf.p[0];
+      f1.in_lo[k] = f2.in_lo[k] = sf.p[1];
+      f1.out_up[k] = f2.out_up[k] = wf.p[0];
+      f1.out_lo[k] = f2.out_lo[k] = wf.p[1];
+      f1.sinv[k] = f2.sinv[k] = b1.sinv[k] = b2.sinv[k] = sinv[p];
+      f1.link_t[k] = f2.link_t[k] = link_t;
+      f2.kmat[k] = kmat[p];
+      f2.q[k] = q[p];
+      b1.in_up[k] = b2.in_up[k] = wf.p[0];
+      b1.in_lo[k] = b2.in_lo[k] = wf.p[1];
+      b1.qout[k] = q[p];
+      b2.out_up[k] = df.p[0];
+      b2.out_lo[k] = df.p[1];
+      if (base) {
+        SpinorF<T> bf = base->view(r).template par<T>(p);
+        b2.base_up[k] = bf.p[0];
+        b2.base_lo[k] = bf.p[1];
+      }
+    }
+    hipLaunchKernelGGL(k_s3_forward<T>, grid, dim3(64), 0, ctx->stream, f1, L.V2, L.g);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_s3_backward<T>, dim3(nlines / 4), dim3(64), 0, ctx->stream,
-                       (const T*)wf.p[0], (const T*)wf.p[1], L.V2, L.g, sinv, (T*)nullptr,
-                       (T*)nullptr, q);
+    hipLaunchKernelGGL(k_s3_backward<T>, grid, dim3(64), 0, ctx->stream, b1, L.V2, L.g);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_s3_forward<T>, dim3(nlines / 4), dim3(64), 0, ctx->stream,
-                       (const T*)sf.p[0], (const T*)sf.p[1], L.V2, L.g, sinv, link_t, kmat,
-                       (const T*)q, -1, wf.p[0], wf.p[1]);
+    hipLaunchKernelGGL(k_s3_forward<T>, grid, dim3(64), 0, ctx->stream, f2, L.V2, L.g);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_s3_backward<T>, dim3(nlines / 4), dim3(64), 0, ctx->stream,
-                       (const T*)wf.p[0], (const T*)wf.p[1], L.V2, L.g, sinv, df.p[0], df.p[1],
-                       (T*)nullptr);
+    hipLaunchKernelGGL(k_s3_backward<T>, grid, dim3(64), 0, ctx->stream, b2, L.V2, L.g);
     LAUNCH_CHECK();
   }
 }
 }  // namespace
 
+void launch_tinv(tp_op op, int par0, int npar, const Field& src, Field& dst, Field& w,
+                 const Field* base) {
+  tp_ctx ctx = op->g->ctx;
+  const Lattice& L = ctx->lat;
+  if (src.prec != dst.prec || src.prec != w.prec || src.prec == TP_F16N ||
+      (base && base->prec != src.prec))
+    TP_THROW(TP_EINVAL, "the exact T^-1 runs in F64 or F32");
+  if (par0 < 0 || npar < 1 || par0 + npar > 2) TP_THROW(TP_EINVAL, "bad parity range");
+  // the one-off factorisation stays outside the timed scope of the sweeps
+  for (int p = par0; p < par0 + npar; ++p) {
+    if (src.prec == TP_F64) schur3d_setup(op, p);
+    else schur3d_setup_f32(op, p);
+  }
+  const double fb = src.prec == TP_F64 ? 16.0 : 8.0;
+  const double spin = (7 + (base ? 1 : 0)) * spinor_bytes(src.prec);
+  ProfScope ps(ctx, KID_SCHUR3D_MEE, double(L.V2) * (2 * (144 + 72) * fb + spin) * src.nr * npar);
+  if (src.prec == TP_F64)
+    tinv_impl<double2>(op, par0, npar, src, dst, w, base, op->s3_inv, op->s3_k, op->s3_q);
+  else
+    tinv_impl<float2>(op, par0, npar, src, dst, w, base, op->s3_inv_f, op->s3_k_f, op->s3_q_f);
+}
+
 // dst_e = (M^ee)^-1 src_e for each right-hand side of the batch, in the fields' precision
 // (F64, or F32 with the rounded factors).  dst may alias src; w is a work field of the same
 // precision and batch size.
 void launch_mee_inv(tp_op op, const Field& src, Field& dst, Field& w) {
-  tp_ctx ctx = op->g->ctx;
-  const Lattice& L = ctx->lat;
-  if (src.prec != dst.prec || src.prec != w.prec || src.prec == TP_F16N)
-    TP_THROW(TP_EINVAL, "the exact M^ee inverse runs in F64 or F32");
-  // the one-off factorisation stays outside the timed scope of the sweeps
-  if (src.prec == TP_F64) schur3d_setup(op);
-  else schur3d_setup_f32(op);
-  const double fb = src.prec == TP_F64 ? 16.0 : 8.0;
-  ProfScope ps(ctx, KID_SCHUR3D_MEE,
-               double(L.V2) * (2 * (144 + 72) * fb + 7 * spinor_bytes(src.prec)) * src.nr);
-  if (src.prec == TP_F64)
-    mee_inv_impl<double2>(op, src, dst, w, op->s3_inv, op->s3_k, op->s3_q);
-  else
-    mee_inv_impl<float2>(op, src, dst, w, op->s3_inv_f, op->s3_k_f, op->s3_q_f);
+  launch_tinv(op, 0, 1, src, dst, w);
 }

@@ -21,6 +21,11 @@
 //                   applied as a_o = C_R^o psi_o, u = D_s^eo a_o, f = (M^ee)^-1 u,
 //                   v = A^oo a_o - D_s^oe f / gamma_f^2, chi_o = psi_o + C_L^o v
 //                   (M^oo = C_L^-1 C_R^-1 + A^oo on odd sites); F64 or F32.
+//   TEMPORAL_FULLSW full SW temporal preconditioning on the whole lattice: C_L = T^-1 with
+//                   T = A + mu - D_t inverted exactly on both parities, C_R = 1:
+//                     Mt = 1 - T^-1 D_s / gamma_f,  Mt^dagger = g5 (1 - D_s T^-1 / gamma_f) g5,
+//                   applied as u = D_s psi / gamma_f (site hop), chi = psi - T^-1 u (block-LU
+//                   sweeps, the subtraction fused into the last one); F64 or F32.
 // All p3 operators act in the axial gauge (interior time links = 1), see k_line_impl.h.
 #include <math.h>
 #include <stdio.h>
@@ -186,6 +191,24 @@ void schur3d_so_odd(tp_op op, int prec, const Field& src, Field& dst) {
   launch_line(op, prec, LM_CL, 1, lio(&v, &src), dst);                      // chi_o
 }
 
+// Full SW temporal preconditioning on the whole lattice, T = A + mu - D_t:
+//   Mt dst = src - T^-1 D_s src / gamma_f, or with adj the operator N = 1 - D_s T^-1 / gamma_f
+//   of Mt^dagger = gamma5 N gamma5 (Mt is not gamma5-hermitian).
+void fullsw_full(tp_op op, int prec, const Field& src, Field& dst, bool adj) {
+  Field& t = ws_get(op, prec, W_T1);
+  Field& w = ws_get(op, prec, W_S3W);
+  const double ig = 1.0 / op->gf;
+  if (!adj) {
+    launch_site(op, prec, sio_nb(&src, &src), t, SiteCoef{0, 0, 0, ig, 0}, 0, 0, 2, false);
+    launch_tinv(op, 0, 2, t, dst, w, &src);
+  } else {
+    launch_tinv(op, 0, 2, src, t, w);
+    SiteIO io = sio_nb(&t, &t);
+    io.in2 = &src;
+    launch_site(op, prec, io, dst, SiteCoef{0, 0, 0, -ig, 1.0}, 0, 0, 2, false);
+  }
+}
+
 void temporal_full(tp_op op, int prec, const Field& src, Field& dst) {
   // C_L M C_R = 1 + C_L (A - D_s / gamma_f) C_R
   Field& a = ws_get(op, prec, W_T1);
@@ -210,7 +233,9 @@ void apply_M_p4(tp_op op, int prec, const Field& src, Field& dst) {
   launch_schur4d(op, prec, 1, 1, &src, dst, &src, -1.0, 0.0, 2);
 }
 
-void prec_noalias(tp_op op, int scheme, int prec, const Field& src, Field& dst) {
+// Mt of the scheme; with adj, the operator N with Mt^dagger = gamma5 N gamma5 (N = Mt for
+// every scheme but TEMPORAL_FULLSW).
+void prec_noalias(tp_op op, int scheme, int prec, const Field& src, Field& dst, bool adj = false) {
   switch (scheme) {
     case TP_UNPREC:
       apply_M_noalias(op, prec, src, dst);
@@ -233,6 +258,9 @@ void prec_noalias(tp_op op, int scheme, int prec, const Field& src, Field& dst) 
     case TP_TEMPORAL_SCHUR3D:
       schur3d_so_odd(op, prec, src, dst);
       blas(op->g->ctx, B_COPY, 0, 1, {&src, &dst});
+      break;
+    case TP_TEMPORAL_FULLSW:
+      fullsw_full(op, prec, src, dst, adj);
       break;
     default:
       TP_THROW(TP_EINVAL, "unknown scheme");
@@ -269,7 +297,7 @@ struct KrylovOp {
       else if (scheme == TP_TEMPORAL_SCHUR3D) schur3d_so_odd(op, prec, *in, *out);
       else wilson_so_odd(op, prec, *in, *out);
     } else {
-      prec_noalias(op, scheme, prec, *in, *out);
+      prec_noalias(op, scheme, prec, *in, *out, dagger);
     }
     if (dagger) blas(ctx, B_G5, par0, npar, {out, &dst});
   }
@@ -306,8 +334,12 @@ void op_apply_prec(tp_op op, int scheme, int prec, const Field& src, Field& dst,
   Field& a = ws_get(op, prec, W_G5A);
   Field& b = ws_get(op, prec, W_G5B);
   blas(ctx, B_G5, 0, 2, {&src, &a});
-  prec_noalias(op, scheme, prec, a, b);
+  prec_noalias(op, scheme, prec, a, b, true);
   blas(ctx, B_G5, 0, 2, {&b, &dst});
+}
+
+void op_apply_prec_adj(tp_op op, int scheme, int prec, const Field& src, Field& dst) {
+  prec_noalias(op, scheme, prec, src, dst, true);
 }
 
 void op_prepare(tp_op op, int scheme, int prec, const Field& eta, Field& et) {
@@ -350,6 +382,10 @@ void op_prepare(tp_op op, int scheme, int prec, const Field& eta, Field& et) {
       launch_line(op, prec, LM_CL, 1, lio(&v), et);
       break;
     }
+    case TP_TEMPORAL_FULLSW:
+      // eta~ = T^-1 eta on both parities
+      launch_tinv(op, 0, 2, eta, et, ws_get(op, prec, W_S3W));
+      break;
     default:
       TP_THROW(TP_EINVAL, "unknown scheme");
   }
@@ -394,6 +430,9 @@ void op_reconstruct(tp_op op, int scheme, int prec, const Field& y, Field& x) {
       blas(ctx, B_AXPY, 0, 1, {&f, &x}, cplx(1, 0));
       break;
     }
+    case TP_TEMPORAL_FULLSW:  // S_R = 1
+      blas(ctx, B_COPY, 0, 2, {&y, &x});
+      break;
     default:
       TP_THROW(TP_EINVAL, "unknown scheme");
   }

@@ -48,7 +48,7 @@ enum KernelId {
   KID_BLAS_OTHER,   // every other level-1 kernel
   KID_REDUCE,
   KID_FORCE,
-  KID_SCHUR3D_MEE,  // exact (M^ee)^-1: forward and backward sweeps of the 3D-Schur scheme
+  KID_SCHUR3D_MEE,  // exact (A + mu - D_t)^-1: forward and backward block-LU sweeps
   KID_COUNT
 };
 extern const char* const kKernelNames[KID_COUNT];
@@ -185,13 +185,14 @@ struct tp_op_s {
   __half2* a3_inv_h = nullptr;
   double* mupow_d = nullptr;    // mu^-k, k = 0..Lt
   float* mupow_f = nullptr;
-  // exact even-block inverse of the 3D-Schur scheme (FP64, built on first use):
-  double2* s3_inv = nullptr;  // block-LU S(t)^-1 [even tile][t][12 col][12 row][4 line]
-  double2* s3_k = nullptr;    // Woodbury capacitance K per even line [Vs2][12][12]
-  double2* s3_q = nullptr;    // boundary values W^dag T0^-1 eta [Vs2][12] (set-up: [12][Vs2][12])
-  float2* s3_inv_f = nullptr;  // the factors rounded to FP32 for the FP32 operator
-  float2* s3_k_f = nullptr;
-  float2* s3_q_f = nullptr;
+  // exact inverse of A + mu - D_t per p3 parity (FP64, built on first use; the even parity
+  // serves the 3D-Schur scheme, both the whole-lattice full-SW scheme):
+  double2* s3_inv[2] = {};  // block-LU S(t)^-1 [tile][t][12 col][12 row][4 line]
+  double2* s3_k[2] = {};    // Woodbury capacitance K per line [Vs2][12][12]
+  double2* s3_q[2] = {};    // boundary values W^dag T0^-1 eta [Vs2][12] (set-up: [12][Vs2][12])
+  float2* s3_inv_f[2] = {};  // the factors rounded to FP32 for the FP32 operator
+  float2* s3_k_f[2] = {};
+  float2* s3_q_f[2] = {};
   Workspace* ws = nullptr;
   int batch_nr = 1;  // right-hand sides of the batched apply in progress (workspace size)
   // No-allocation mode (tp_apply_prec_noalloc): while arena is set, workspace fields are
@@ -288,13 +289,19 @@ void launch_line(tp_op op, int prec, int mode, int par, const LineIO& io, Field&
 // u = D_s^eo a_o / gamma_f, chi_e = psi_e + C_L y and n_e = C_R C_L (y - u) with
 // y = A C_R (C_L u + psi_e).
 void launch_ilu_mid(tp_op op, int prec, const Field& psi, const Field& u, Field& chi, Field& n);
-// Exact (M^ee)^-1, M^ee = A + mu - D_t on the even p3 sites: block LU of each even time line
-// plus a rank-12 Woodbury correction for the wrapping hops.  schur3d_setup builds the FP64
-// factors once per operator (TP_ESINGULAR on a zero pivot); launch_mee_inv writes
-// dst_e = (M^ee)^-1 src_e per right-hand side in F64, or in F32 with the factors rounded to
-// FP32 on first use (w: work field of the same precision and batch size).
-void schur3d_setup(tp_op op);
+// Exact T^-1, T = A + mu - D_t on the sites of one p3 parity (M^ee on the even sites): block
+// LU of each time line plus a rank-12 Woodbury correction for the wrapping hops.
+// schur3d_setup builds the FP64 factors of parity par once per operator (TP_ESINGULAR on a
+// zero pivot); schur3d_ready tells whether those of precision prec exist.
+// launch_tinv writes dst_p = T^-1 src_p on the parities par0 .. par0+npar-1 per right-hand
+// side in F64, or in F32 with the factors rounded to FP32 on first use (w: work field of the
+// same precision and batch size).  With base given it writes dst_p = base_p - T^-1 src_p.
+// launch_mee_inv is the even-parity case.
+void schur3d_setup(tp_op op, int par);
+bool schur3d_ready(tp_op op, int prec, int par);
 void schur3d_free(tp_op op);
+void launch_tinv(tp_op op, int par0, int npar, const Field& src, Field& dst, Field& w,
+                 const Field* base = nullptr);
 void launch_mee_inv(tp_op op, const Field& src, Field& dst, Field& w);
 
 // Site kernel with operands assembled from half fields: for output parity p,
@@ -382,6 +389,9 @@ void launch_force(tp_op op, const Field& x, const Field& lam, double2* grad, boo
 // ---------------------------------------------------------------- composite operators (ops.cpp)
 void op_apply_M(tp_op op, int prec, const Field& src, Field& dst, bool dagger);
 void op_apply_prec(tp_op op, int scheme, int prec, const Field& src, Field& dst, bool dagger);
+// The operator N with Mt^dagger = gamma5 N gamma5: Mt itself for the gamma5-hermitian
+// schemes, 1 - D_s T^-1 / gamma_f for TEMPORAL_FULLSW.
+void op_apply_prec_adj(tp_op op, int scheme, int prec, const Field& src, Field& dst);
 void op_apply_odd(tp_op op, int scheme, int prec, const Field& src, Field& dst, bool dagger);
 bool scheme_sub(tp_op op, int scheme);
 void op_prepare(tp_op op, int scheme, int prec, const Field& eta, Field& et);

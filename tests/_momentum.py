@@ -80,7 +80,8 @@ def kappa_free(dims, m0, gamma_f, b, scheme):
     block diagonal in p).  TEMPORAL: 1 - C_L D_s C_R/gamma_f.  TEMPORAL_SCHUR
     (Wilson): 1 - (C_L D_s C_R)^2/gamma_f^2, since D_s(p + pi_s) = -D_s(p) and
     C_L, C_R do not depend on the spatial momentum.  TEMPORAL_SCHUR3D: C_L S_o C_R with the
-    Schur complement S_o = mu - D_t - D_s (mu - D_t)^-1 D_s/gamma_f^2 taken as defined."""
+    Schur complement S_o = mu - D_t - D_s (mu - D_t)^-1 D_s/gamma_f^2 taken as defined.
+    TEMPORAL_FULLSW: 1 - (mu - D_t)^-1 D_s/gamma_f (T = mu - D_t for the free Wilson field)."""
     mu, Ds, Dt, CL, CR = _blocks(dims, m0, gamma_f, b)
     if scheme == "UNPREC":
         m = mu * I4 - Dt - Ds / gamma_f
@@ -95,6 +96,8 @@ def kappa_free(dims, m0, gamma_f, b, scheme):
     elif scheme == "TEMPORAL_SCHUR3D":
         mee = mu * I4 - Dt
         m = CL @ (mee - Ds @ np.linalg.inv(mee) @ Ds / gamma_f ** 2) @ CR
+    elif scheme == "TEMPORAL_FULLSW":
+        m = I4 - np.linalg.inv(mu * I4 - Dt) @ Ds / gamma_f
     else:
         raise ValueError(scheme)
     sv = np.linalg.svd(m, compute_uv=False)

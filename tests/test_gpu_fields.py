@@ -60,7 +60,7 @@ def test_round_trip_and_subsets(case, layout, prec):
 
 @pytest.mark.parametrize("scheme,prec", [("TEMPORAL_SCHUR", "F16N"), ("TEMPORAL_SCHUR", "F64"),
                                          ("TEMPORAL", "F32"), ("UNPREC", "F64"), ("SCHUR4D", "F32"),
-                                         ("TEMPORAL_SCHUR3D", "F64")])
+                                         ("TEMPORAL_SCHUR3D", "F64"), ("TEMPORAL_FULLSW", "F32")])
 def test_field_applies_match_canonical_entry_points(case, scheme, prec):
     g, eta = case["g"], case["eta"]
     lay = "P4" if scheme == "SCHUR4D" else "P3"
@@ -130,7 +130,7 @@ def _bicgstab(A, b, tol, maxit=5000):
     raise RuntimeError("no convergence")
 
 
-@pytest.mark.parametrize("scheme", ["TEMPORAL_SCHUR", "TEMPORAL_SCHUR3D"])
+@pytest.mark.parametrize("scheme", ["TEMPORAL_SCHUR", "TEMPORAL_SCHUR3D", "TEMPORAL_FULLSW"])
 def test_external_krylov_on_internal_fields(case, scheme):
     """A solver outside the library: eta~ = S_L eta once, BiCGStab on Mt with the library's
     applies on F64 internal fields (the odd block for odd-block schemes, held in ODD fields),
@@ -138,7 +138,7 @@ def test_external_krylov_on_internal_fields(case, scheme):
     g, eta = case["g"], case["eta"]
     oop = OOp(case["U"], case["m0"], case["xi"], -1.0, case["cs"], case["ct"])
     et = g.prepare_source_field(eta, scheme)
-    sub = scheme == "TEMPORAL_SCHUR3D" or not case["clover"]
+    sub = scheme == "TEMPORAL_SCHUR3D" or (scheme == "TEMPORAL_SCHUR" and not case["clover"])
     if sub:
         eo = g.convert_field(g.field("P3", "F64", "ODD"), et)
         work = g.field("P3", "F64", "ODD")

@@ -83,7 +83,7 @@ def test_Tinv_sampled_lines(big, prec, dagger):
     assert _rel(got, ref) < TOL[prec], (b["name"], prec, _rel(got, ref))
 
 
-@pytest.mark.parametrize("scheme", ["TEMPORAL", "TEMPORAL_SCHUR", "TEMPORAL_SCHUR3D"])
+@pytest.mark.parametrize("scheme", ["TEMPORAL", "TEMPORAL_SCHUR", "TEMPORAL_SCHUR3D", "TEMPORAL_FULLSW"])
 def test_prec_is_SL_M_SR(big, scheme):
     """The fused preconditioned apply equals the composition of the separately
     parity-checked maps: S_L M S_R y = prepare(M(reconstruct(y)))."""
@@ -96,14 +96,28 @@ def test_prec_is_SL_M_SR(big, scheme):
     assert _rel(a32, c) < 2e-5
 
 
-@pytest.mark.parametrize("scheme", ["TEMPORAL_SCHUR", "SCHUR4D", "TEMPORAL_SCHUR3D"])
-def test_prec_gamma5_hermiticity(big, scheme):
+@pytest.mark.parametrize("scheme", ["TEMPORAL_SCHUR", "SCHUR4D", "TEMPORAL_SCHUR3D", "TEMPORAL_FULLSW"])
+def test_prec_adjoint(big, scheme):
+    """<phi, Mt psi> = <Mt^dagger phi, psi>: gamma5-hermiticity for all but TEMPORAL_FULLSW,
+    whose adjoint is applied as gamma5 (1 - D_s T^-1 / gamma_f) gamma5."""
     g = big["gop"]
     phi = torch.from_numpy(synth.make_source(big["dims"], 2003)).cuda()
     psi = big["teta"]
     lhs = torch.vdot(phi.flatten(), g.apply_prec(psi, scheme, "F64").flatten()).item()
     rhs = torch.vdot(g.apply_prec(phi, scheme, "F64", dagger=True).flatten(), psi.flatten()).item()
     assert abs(lhs - rhs) < 1e-11 * abs(lhs), (lhs, rhs)
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+def test_sw_temporal_inverse_sampled_lines(big, prec):
+    """(A + mu - D_t)^-1 eta, the prepared source of TEMPORAL_FULLSW, on 8 time lines of both
+    parities against the oracle's inverse on each line's 3x3x3 window."""
+    b = big
+    out = _np(b["gop"].prepare_source(b["teta"], "TEMPORAL_FULLSW", prec))
+    got = np.stack([out[:, z, y, x] for (x, y, z) in b["lines"]])
+    ref = sampled.sw_temporal_inv_on_lines(b["U"], b["eta"], b["lines"], b["m0"], b["xi"], -1.0,
+                                           b["c_s"], b["c_t"])
+    assert _rel(got, ref) < TOL[prec], (b["name"], prec, _rel(got, ref))
 
 
 def test_bench_solve_residual_sampled(big):
@@ -117,12 +131,13 @@ def test_bench_solve_residual_sampled(big):
     assert np.linalg.norm(r) <= 1.05e-10 * np.linalg.norm(b["eta"]), (np.linalg.norm(r), info)
 
 
-@pytest.mark.parametrize("prec", ["F64", "F32"])
-def test_schur3d_solve_residual_sampled(big, prec):
-    """The exact 3D-Schur scheme's FP64 and mixed FP32 solves; the oracle's residual on 48
-    sites cannot exceed the global one."""
+@pytest.mark.parametrize("scheme,prec", [("TEMPORAL_SCHUR3D", "F64"), ("TEMPORAL_SCHUR3D", "F32"),
+                                         ("TEMPORAL_FULLSW", "F32")])
+def test_block_lu_solve_residual_sampled(big, scheme, prec):
+    """The exact 3D-Schur scheme's FP64 and mixed FP32 solves, and the whole-lattice full-SW
+    scheme's mixed FP32 solve; the oracle's residual on 48 sites cannot exceed the global one."""
     b = big
-    x, info = b["gop"].solve(b["teta"], scheme="TEMPORAL_SCHUR3D", prec=prec, tol=1e-10)
+    x, info = b["gop"].solve(b["teta"], scheme=scheme, prec=prec, tol=1e-10)
     assert info["true_rel_resid"] <= 1e-10, info
     xs = _np(x)
     r = _at(b["eta"], b["sites"]) - sampled.M_at_sites(b["U"], xs, b["sites"], b["m0"], b["xi"], -1.0,

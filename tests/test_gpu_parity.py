@@ -152,8 +152,8 @@ def test_point_source_reduced_precision(case, prec):
 def test_apply_prec(case, scheme, prec):
     if scheme == "SCHUR4D" and prec == "F16N":
         pytest.skip("the 4D Schur baseline runs in F64/F32")
-    if scheme == "TEMPORAL_SCHUR3D" and prec == "F16N":
-        pytest.skip("the exact even-block inverse runs in F64 and F32")
+    if scheme in ("TEMPORAL_SCHUR3D", "TEMPORAL_FULLSW") and prec == "F16N":
+        pytest.skip("the exact block-LU inverse runs in F64 and F32")
     o, g = case["oop"], case["gop"]
     e, te = case["eta"], case["teta"]
     tol = TOL[prec][1]
@@ -371,13 +371,14 @@ def test_site_kernels_in_tile_order(dims):
         gop.close()
 
 
-def test_schur3d_rejects_f16n(case):
+@pytest.mark.parametrize("scheme", ["TEMPORAL_SCHUR3D", "TEMPORAL_FULLSW"])
+def test_block_lu_schemes_reject_f16n(case, scheme):
     from paper_0910_0992_amd._lib import TprecError
     g = case["gop"]
     with pytest.raises(TprecError, match="F64 and F32"):
-        g.apply_prec(case["teta"], "TEMPORAL_SCHUR3D", "F16N")
+        g.apply_prec(case["teta"], scheme, "F16N")
     with pytest.raises(TprecError, match="F64 and F32"):
-        g.solve(case["teta"], scheme="TEMPORAL_SCHUR3D", prec="F16N", tol=1e-10)
+        g.solve(case["teta"], scheme=scheme, prec="F16N", tol=1e-10)
 
 
 def test_schur3d_solve_mixed_f32(case):
@@ -400,8 +401,38 @@ def test_schur3d_even_block_inverse(case):
     _close(e * back, e * case["eta"], 1e-12, "M^ee (M^ee)^-1 eta_e")
 
 
+def test_fullsw_solve_mixed_f32(case):
+    """Full SW temporal preconditioning on the whole lattice: FP32 inner solves with the
+    FP32-rounded factors of both parities and FP64 reliable updates, single and batched
+    (two right-hand sides in lockstep), to 1e-10."""
+    o, g = case["oop"], case["gop"]
+    x, info = g.solve(case["teta"], scheme="TEMPORAL_FULLSW", prec="F32", tol=1e-10)
+    true = np.linalg.norm(case["eta"] - o.M(_np(x))) / np.linalg.norm(case["eta"])
+    assert true <= 1.05e-10, (info, true)
+    assert info["outer_iters"] >= 2
+    e2 = synth.make_source(case["dims"], 2004)
+    xs, infos = g.solve_multi([case["teta"], torch.from_numpy(e2).cuda()], scheme="TEMPORAL_FULLSW",
+                              prec="F32", tol=1e-10)
+    xs = _np(xs)
+    for k, e in enumerate([case["eta"], e2]):
+        true = np.linalg.norm(e - o.M(xs[k])) / np.linalg.norm(e)
+        assert true <= 1.05e-10, (k, infos[k], true)
+
+
+def test_fullsw_T_inverse(case):
+    """The prepared source of TEMPORAL_FULLSW is T^-1 eta with T = A + mu - D_t on both
+    parities: T = M + D_s / gamma_f applied to it (the separately checked M and D_s applies)
+    returns eta, in FP64 and with the FP32 factors."""
+    g, xi = case["gop"], case["xi"]
+    for prec, tol in (("F64", TOL["F64"][1]), ("F32", TOL["F32"][1])):
+        f = g.prepare_source(case["teta"], "TEMPORAL_FULLSW", prec)
+        back = _np(g.apply_M(f, "F64")) + _np(g.apply_Ds(f, "F64")) / xi
+        _close(back, case["eta"], tol, f"T T^-1 eta ({prec})")
+
+
 @pytest.mark.parametrize("scheme,prec", [("TEMPORAL_SCHUR", "F16N"), ("TEMPORAL_SCHUR", "F64"),
-                                         ("SCHUR4D", "F64"), ("TEMPORAL_SCHUR3D", "F32")])
+                                         ("SCHUR4D", "F64"), ("TEMPORAL_SCHUR3D", "F32"),
+                                         ("TEMPORAL_FULLSW", "F32")])
 def test_solve_dagger(case, scheme, prec):
     """M^dagger x = eta (tp_solve with dagger): the oracle's M^dagger residual of the solution,
     single and batched."""

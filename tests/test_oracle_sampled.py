@@ -1,4 +1,4 @@
-"""The sampled oracle (M at single sites, T^-1 on single time lines) against the
+"""The sampled oracle (M at single sites, T^-1 and (A + mu - D_t)^-1 on single time lines) against the
 full-lattice oracle at every kind of site: interior, spatial edges, both time
 boundaries, periodic and antiperiodic, Wilson and clover, and lattices with an
 extent of 2 (where both neighbours in a direction are the same site)."""
@@ -45,3 +45,18 @@ def test_Tinv_on_lines_matches_full_lattice(dims, b, dagger):
     got = sampled.Tinv_on_lines(U, psi, lines, mu, b, dagger=dagger)
     ref = np.stack([full[:, z, y, x] for (x, y, z) in lines])
     assert np.abs(got - ref).max() < 1e-14 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("dims,b,c_s,c_t", [((4, 6, 4, 8), -1.0, 1.2, 0.9), ((6, 4, 4, 5), 1.0, 0.0, 0.0)])
+def test_sw_temporal_inv_on_lines_matches_full_lattice(dims, b, c_s, c_t):
+    """(A + mu - D_t)^-1 on single lines from the 3x3x3 window against the full lattice's
+    inverse, on lines at the spatial edges (the window wraps) and inside."""
+    from oracle.schemes import Operator
+    U = synth.make_links(dims, 0.5, 0.3, 15)
+    psi = synth.make_source(dims, 16)
+    m0, gf = -0.05, 2.5
+    full = Operator(U, m0, gf, b, c_s, c_t).T_inv(psi)
+    lines = [(0, 0, 0), (dims[0] - 1, dims[1] - 1, dims[2] - 1), (1, 2, 3), (2, 5 % dims[1], 0)]
+    got = sampled.sw_temporal_inv_on_lines(U, psi, lines, m0, gf, b, c_s, c_t)
+    ref = np.stack([full[:, z, y, x] for (x, y, z) in lines])
+    assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max()

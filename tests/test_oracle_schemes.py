@@ -85,6 +85,22 @@ def test_schur3d_complement_inverts_odd_block(op):
     assert _rel(op.schur3d_S(op.o3 * x), psi) < 1e-12
 
 
+def test_fullsw_T_inverse(op):
+    """The whole-lattice T^-1 of TEMPORAL_FULLSW: (A + mu - D_t) T^-1 psi = psi on every site,
+    and for Wilson fermions T^-1 = C_R C_L, the scan form of Sec. II.A, while with a clover
+    term it differs from it; Mt = 1 - T^-1 D_s / gamma_f then follows from the definitions."""
+    psi = synth.make_source(DIMS, 2013)
+    f = op.T_inv(psi)
+    assert _rel(op.Amu(f) - op.Dt(f), psi) < 1e-13
+    scan = op.tmp.CR(op.tmp.CL(psi))
+    if op.clover:
+        assert _rel(f, scan) > 1e-3
+    else:
+        assert _rel(f, scan) < 1e-13
+    # M = T - D_s / gamma_f, so T^-1 M = Mt
+    assert _rel(op.T_inv(op.M(psi)), op.fullsw(psi)) < 1e-13
+
+
 def test_schur4d_ldu(op):
     """L diag(M^ee, S-hat) U = M, with L^-1 = S_L and U^-1 = S_R as applied."""
     psi = synth.make_source(DIMS, 2004)

@@ -61,16 +61,20 @@ def test_noalloc_matches_apply_prec(clover):
             op.close()
 
 
-def test_noalloc_schur3d_after_factorisation():
+@pytest.mark.parametrize("scheme,prec", [("TEMPORAL_SCHUR3D", "F64"), ("TEMPORAL_FULLSW", "F32")])
+def test_noalloc_block_lu_after_factorisation(scheme, prec):
+    """The block-LU schemes are refused until an allocating apply has built their factors,
+    then match it, both ways round."""
     dims = (6, 4, 4, 16)
     op = _op(dims)
     try:
         psi = torch.from_numpy(synth.make_source(dims, 2001)).cuda()
         from paper_0910_0992_amd._lib import TprecError
         with pytest.raises(TprecError, match="factors"):
-            _noalloc(op, psi, "TEMPORAL_SCHUR3D", "F64")
-        ref = op.apply_prec(psi, "TEMPORAL_SCHUR3D", "F64")  # builds the factors
-        assert torch.equal(_noalloc(op, psi, "TEMPORAL_SCHUR3D", "F64"), ref)
+            _noalloc(op, psi, scheme, prec)
+        ref = op.apply_prec(psi, scheme, prec)  # builds the factors
+        assert torch.equal(_noalloc(op, psi, scheme, prec), ref)
+        assert torch.equal(_noalloc(op, psi, scheme, prec, True), op.apply_prec(psi, scheme, prec, dagger=True))
     finally:
         op.close()
 

@@ -216,7 +216,7 @@ def compare_schemes(args):
     op = Operator(torch.from_numpy(U).cuda(), cfg["m0"], xi, cfg["csw_s"] / xi, cfg["csw_t"], -1)
     del U
     out = {}
-    schemes = ("UNPREC", "SCHUR4D", "TEMPORAL", "TEMPORAL_SCHUR", "TEMPORAL_SCHUR3D")
+    schemes = ("UNPREC", "SCHUR4D", "TEMPORAL", "TEMPORAL_SCHUR", "TEMPORAL_SCHUR3D", "TEMPORAL_FULLSW")
     if args.only:
         schemes = tuple(s.strip().upper() for s in args.only.split(","))
     for scheme in schemes:
@@ -234,8 +234,8 @@ def compare_schemes(args):
                       "GB_per_s": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None}
                   for k, v in op.profile_stats().items() if v["launches"] > 0}
         op.profile(False)
-        if scheme == "TEMPORAL_SCHUR3D":
-            # its production form: FP32 inner BiCGStab with FP64 reliable updates
+        if scheme in ("TEMPORAL_SCHUR3D", "TEMPORAL_FULLSW"):
+            # their production form: FP32 inner BiCGStab with FP64 reliable updates
             op.solve(eta, scheme=scheme, prec="F32", tol=1e-10)
             torch.cuda.synchronize()
             t0 = time.perf_counter()

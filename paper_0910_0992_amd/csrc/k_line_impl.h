@@ -42,194 +42,260 @@ struct ScanCtx {
   int s;
   int tile;     // tile of 4 lines within the workgroup
   bool active;
-  bool fast;    // NCH % 16 == 0: wavefront-shuffle scan (each wave = 16 chunks x 4 lines)
+  bool fast;    // NCH % 16 == 0: each wavefront holds 16 chunks of the 4 lines of one tile
   R inv_mu, f;  // 1/mu and mu^-CH
   const R* mupow;  // mu^-k, k = 0..Lt
-  const typename Cplx2<R>::T* G;  // closure planes [9][Vs2] of this parity
-  int64_t gstride;
+  // fast combine (lane = line * 16 + chunk within the wavefront)
+  int jw, lt, seg, nseg;  // chunk within the wavefront, line within the tile, segment, segments
+  R F;                    // mu^-(16 CH): factor between neighbouring segments
+  cx<R>* tabs;            // combine tables: [2 buffers][2 sets] x [tile][16 segments][4 lines][6]
+  int slot;               // complex values per table
+  int buf;                // table buffer of the next combine (alternates, so no trailing barrier)
+  const cx<R>* gl;        // closure G of the workgroup's lines, staged in LDS: [line][9]
 };
 
-template <typename R> TP_DEV cx<R> shdown(cx<R> v, int d) {
-  return cx<R>{__shfl_down(v.re, d, 64), __shfl_down(v.im, d, 64)};
+// DPP move inside rows of 16 lanes: with CTRL = 0x100 + d (row_shl) lane i receives lane i + d
+// of its row, with 0x110 + d (row_shr) lane i - d; lanes whose source lies outside the row
+// receive zero.
+template <int CTRL> TP_DEV float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
 }
-template <typename R> TP_DEV cx<R> shup(cx<R> v, int d) {
-  return cx<R>{__shfl_up(v.re, d, 64), __shfl_up(v.im, d, 64)};
+template <int CTRL> TP_DEV double dpp_f(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(u)), CTRL, 0xF, 0xF, false));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(u >> 32)), CTRL, 0xF, 0xF, false));
+  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+// The value d chunks further along the scan direction (backward scans run from high to low t,
+// so they take the value of chunk j + d; forward scans that of chunk j - d), zero past the row.
+template <typename R, bool BWD, int D> TP_DEV cx<R> from_next(cx<R> v) {
+  constexpr int ctrl = BWD ? 0x100 + D : 0x110 + D;
+  return cx<R>{dpp_f<ctrl>(v.re), dpp_f<ctrl>(v.im)};
+}
+template <typename R, bool BWD, int D> TP_DEV void ks_step(cx<R> (&X)[6], R fd) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) X[c] += fd * from_next<R, BWD, D>(X[c]);
 }
 
-// Exclusive carries of the chunk heads X (6 values) across a line, fast path.  A wave
-// holds 16 consecutive chunks of 4 lines (lane = (j % 16) * 4 + line).
-//   level 1: inclusive suffix (BWD) / prefix (FWD) within the 16-chunk segment by shuffles;
-//   level 2: the segment totals of each line are scanned by the tile's first wave
-//            (lane = segment * 4 + line), factor f^16;
-//   level 3: carry C_j = exclusive in-segment value + f^(distance) * next segment's total.
-// Z = the line's total at chunk 0 (BWD) or at the last chunk (FWD).
+// Level 1 of the fast combine: inclusive suffix (BWD) / prefix (FWD) of the chunk heads X over
+// the 16 chunks of each line held by the wavefront (one DPP row per line), factor f per chunk;
+// Cin receives the exclusive value (the neighbour chunk's inclusive value).
 template <typename R, bool BWD>
-TP_DEV void combine_fast(cx<R> (&X)[6], cx<R> (&C)[6], cx<R> (&Z)[6], cx<R>* lds, const ScanCtx<R>& sc) {
-  const int jw = sc.j & 15;
-  const int lt = sc.l & 3;
-  R fd = sc.f;
+TP_DEV void lvl1(cx<R> (&X)[6], cx<R> (&Cin)[6], R f) {
+  const R f2 = f * f, f4 = f2 * f2, f8 = f4 * f4;
+  ks_step<R, BWD, 1>(X, f);
+  ks_step<R, BWD, 2>(X, f2);
+  ks_step<R, BWD, 4>(X, f4);
+  ks_step<R, BWD, 8>(X, f8);
 #pragma unroll
-  for (int d = 1; d < 16; d <<= 1) {
+  for (int c = 0; c < 6; ++c) Cin[c] = from_next<R, BWD, 1>(X[c]);
+}
+
+template <typename R>
+TP_DEV cx<R>* tab_of(const ScanCtx<R>& sc, int set) {
+  return sc.tabs + (sc.buf * 2 + set) * sc.slot + sc.tile * 16 * 24 + sc.lt * 6;
+}
+
+// The segment total of each line and segment (the inclusive value at the segment's first chunk
+// for BWD, its last for FWD) goes to the table.
+template <typename R, bool BWD>
+TP_DEV void lvl2_put(const cx<R> (&X)[6], const ScanCtx<R>& sc, int set) {
+  if (sc.jw == (BWD ? 0 : 15)) {
+    cx<R>* p = tab_of(sc, set) + sc.seg * 24;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      cx<R> y = BWD ? shdown(X[c], 4 * d) : shup(X[c], 4 * d);
-      bool ok = BWD ? (jw + d < 16) : (jw - d >= 0);
-      if (ok) X[c] += fd * y;
-    }
-    fd = fd * fd;
+    for (int c = 0; c < 6; ++c) p[c] = X[c];
   }
-  // exclusive within the segment
-#pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    cx<R> y = BWD ? shdown(X[c], 4) : shup(X[c], 4);
-    bool ok = BWD ? (jw < 15) : (jw > 0);
-    C[c] = ok ? y : czero<R>();
-  }
-  const int nseg = sc.NCH >> 4;
-  const int seg = sc.j >> 4;
-  cx<R>* tab = lds + (sc.tile * 16) * kTile * 6;  // [segment][line][6] for this tile
-  if (jw == (BWD ? 0 : 15)) {
-#pragma unroll
-    for (int c = 0; c < 6; ++c) tab[(seg * kTile + lt) * 6 + c] = X[c];
-  }
-  __syncthreads();
-  // the tile's first wave (j < 16, uniform per wave) scans the segment totals;
-  // lane = segment * 4 + line
-  const int sg = sc.j;
+}
+
+// Level 2, run by the tile's first wavefront (lane = line * 16 + segment): the segment totals of
+// each line are scanned in place with factor F per segment.
+template <typename R, bool BWD>
+TP_DEV void lvl2_scan(const ScanCtx<R>& sc, int set) {
+  cx<R>* p = tab_of(sc, set) + sc.jw * 24;
+  const bool in = sc.jw < sc.nseg;
   cx<R> T[6];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) T[c] = czero<R>();
-  if (sc.j < 16) {
+  for (int c = 0; c < 6; ++c) T[c] = in ? p[c] : czero<R>();
+  const R F2 = sc.F * sc.F, F4 = F2 * F2, F8 = F4 * F4;
+  ks_step<R, BWD, 1>(T, sc.F);
+  ks_step<R, BWD, 2>(T, F2);
+  ks_step<R, BWD, 4>(T, F4);
+  ks_step<R, BWD, 8>(T, F8);
+  if (in) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) T[c] = sg < nseg ? tab[(sg * kTile + lt) * 6 + c] : czero<R>();
-    R Fd = sc.mupow[16 * sc.CH];
-    for (int d = 1; d < nseg; d <<= 1) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        cx<R> y = BWD ? shdown(T[c], 4 * d) : shup(T[c], 4 * d);
-        bool ok = BWD ? (sg + d < nseg) : (sg - d >= 0);
-        if (ok) T[c] += Fd * y;
-      }
-      Fd = Fd * Fd;
-    }
+    for (int c = 0; c < 6; ++c) p[c] = T[c];
   }
-  __syncthreads();  // every segment total has been read
-  if (sc.j < 16 && sg < nseg) {
-#pragma unroll
-    for (int c = 0; c < 6; ++c) tab[(sg * kTile + lt) * 6 + c] = T[c];
-  }
-  __syncthreads();
-  const int nxt = BWD ? seg + 1 : seg - 1;
-  const bool hasn = BWD ? (nxt < nseg) : (nxt >= 0);
-  const R w = sc.mupow[sc.CH * (BWD ? (15 - jw) : jw)];
-  const int zs = BWD ? 0 : nseg - 1;
-#pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    if (hasn) C[c] += w * tab[(nxt * kTile + lt) * 6 + c];
-    Z[c] = tab[(zs * kTile + lt) * 6 + c];
-  }
-  __syncthreads();  // the table is reused by the next group
 }
 
-// v: per time slice of the chunk, NV complex values (NV/3 colour vectors); on return
-// v holds the scan result (T^-1 for BWD, T^dagger^-1 otherwise) on those values.
-// Groups of 6 values (two colour vectors) are finished one at a time, so only one
-// group's carries are live.
-template <typename R, int CH, int NV, bool BWD>
-TP_DEV void scan_core(cx<R> (&v)[CH][NV], cx<R>* lds, const ScanCtx<R>& sc) {
+// Carry from the other segments and the line total Z (at chunk 0 for BWD, at the last chunk for FWD).
+template <typename R, bool BWD>
+TP_DEV void lvl2_get(cx<R> (&C)[6], cx<R> (&Z)[6], R w, const ScanCtx<R>& sc, int set) {
+  const cx<R>* p = tab_of(sc, set);
+  const int nxt = BWD ? sc.seg + 1 : sc.seg - 1;
+  const bool hasn = BWD ? (nxt < sc.nseg) : (nxt >= 0);
+  const cx<R>* pn = p + (hasn ? nxt : 0) * 24;
+  const cx<R>* pz = p + (BWD ? 0 : sc.nseg - 1) * 24;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    if (hasn) C[c] += w * pn[c];
+    Z[c] = pz[c];
+  }
+}
+
+// Weight of the carried-in segment total for this thread's chunk: f^(15-jw) (BWD), f^jw (FWD);
+// every index is below 16 CH <= Lt on the fast path.
+template <typename R, bool BWD> TP_DEV R seg_weight(const ScanCtx<R>& sc) {
+  return sc.mupow[sc.CH * (BWD ? 15 - sc.jw : sc.jw)];
+}
+// Closure weights of this thread's slices: mu^-(Lt-1-t) (BWD), mu^-t (FWD), 0 where the cutoff
+// drops the closure.
+template <typename R, int CH, bool BWD> TP_DEV void closure_weights(R (&cb)[CH], const ScanCtx<R>& sc) {
+#pragma unroll
+  for (int k = 0; k < CH; ++k) {
+    const int t = sc.t0 + k;
+    const bool keep = BWD ? (t >= sc.cut) : (t < sc.Lt - sc.cut);
+    cb[k] = keep ? sc.mupow[BWD ? sc.Lt - 1 - t : t] : R(0);
+  }
+}
+
+// Exclusive carries across the line in LDS (Hillis-Steele), for lines whose chunk count is not
+// a multiple of 16.  Z = the line's total at chunk 0 (BWD) or at the last chunk (FWD).
+template <typename R, bool BWD>
+TP_DEV void combine_lds(cx<R> (&X)[6], cx<R> (&C)[6], cx<R> (&Z)[6], cx<R>* lds, const ScanCtx<R>& sc) {
   const int me = (sc.j * sc.LPB + sc.l) * 6;
-#pragma unroll
-  for (int g = 0; g < NV / 6; ++g) {
-    // chunk-local recurrence
-    cx<R> X[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      cx<R> acc = czero<R>();
-      if constexpr (BWD) {
-#pragma unroll
-        for (int k = CH - 1; k >= 0; --k) {
-          acc = sc.inv_mu * (v[k][6 * g + c] + acc);
-          v[k][6 * g + c] = acc;
-        }
-      } else {
-#pragma unroll
-        for (int k = 0; k < CH; ++k) {
-          acc = sc.inv_mu * (v[k][6 * g + c] + acc);
-          v[k][6 * g + c] = acc;
-        }
-      }
-      X[c] = acc;
-    }
-    cx<R> C[6], D[6], Z[6];
-    if (sc.fast) {
-      combine_fast<R, BWD>(X, C, Z, lds, sc);
-    } else {
-    // combine chunk heads (backward) / tails (forward) across the line (Hillis-Steele)
-    R fd = sc.f;
-    for (int d = 1; d < sc.NCH; d <<= 1) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) lds[me + c] = X[c];
-      __syncthreads();
-      int jj = BWD ? sc.j + d : sc.j - d;
-      if (jj >= 0 && jj < sc.NCH) {
-        const int o = (jj * sc.LPB + sc.l) * 6;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) X[c] += fd * lds[o + c];
-      }
-      __syncthreads();
-      fd = fd * fd;
-    }
+  R fd = sc.f;
+  for (int d = 1; d < sc.NCH; d <<= 1) {
 #pragma unroll
     for (int c = 0; c < 6; ++c) lds[me + c] = X[c];
     __syncthreads();
-    int jc = BWD ? sc.j + 1 : sc.j - 1;
-    bool has = jc >= 0 && jc < sc.NCH;
-    const int oc = ((has ? jc : 0) * sc.LPB + sc.l) * 6;
-    const int oz = ((BWD ? 0 : sc.NCH - 1) * sc.LPB + sc.l) * 6;
+    int jj = BWD ? sc.j + d : sc.j - d;
+    if (jj >= 0 && jj < sc.NCH) {
+      const int o = (jj * sc.LPB + sc.l) * 6;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      C[c] = has ? lds[oc + c] : czero<R>();
-      Z[c] = lds[oz + c];
+      for (int c = 0; c < 6; ++c) X[c] += fd * lds[o + c];
     }
     __syncthreads();
-    }
-    // closure: delta = G z (backward) or G^dagger z (forward), per colour vector, on the
-    // slices the cutoff keeps (all of them when cut = 0)
-    const bool band = BWD ? (sc.t0 + CH - 1 >= sc.cut) : (sc.t0 < sc.Lt - sc.cut);
-    if (sc.active && band) {
+    fd = fd * fd;
+  }
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        cx<R> acc0 = czero<R>(), acc1 = czero<R>();
+  for (int c = 0; c < 6; ++c) lds[me + c] = X[c];
+  __syncthreads();
+  int jc = BWD ? sc.j + 1 : sc.j - 1;
+  bool has = jc >= 0 && jc < sc.NCH;
+  const int oc = ((has ? jc : 0) * sc.LPB + sc.l) * 6;
+  const int oz = ((BWD ? 0 : sc.NCH - 1) * sc.LPB + sc.l) * 6;
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-          int k = BWD ? 3 * a + b : 3 * b + a;
-          const auto e = sc.G[(int64_t)k * sc.gstride + sc.s];
-          cx<R> gk = cx<R>{R(e.x), R(e.y)};
-          if constexpr (BWD) {
-            acc0 += cmul(gk, Z[b]);
-            acc1 += cmul(gk, Z[3 + b]);
-          } else {
-            acc0 += cmulc(gk, Z[b]);
-            acc1 += cmulc(gk, Z[3 + b]);
-          }
-        }
-        D[a] = acc0;
-        D[3 + a] = acc1;
+  for (int c = 0; c < 6; ++c) {
+    C[c] = has ? lds[oc + c] : czero<R>();
+    Z[c] = lds[oz + c];
+  }
+  __syncthreads();
+}
+
+// Chunk-local recurrence of one group of 6 values; returns the chunk head (BWD) / tail (FWD).
+template <typename R, int CH, int NV, bool BWD>
+TP_DEV void local_scan(cx<R> (&v)[CH][NV], int g, cx<R> (&X)[6], const ScanCtx<R>& sc) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    cx<R> acc = czero<R>();
+    if constexpr (BWD) {
+#pragma unroll
+      for (int k = CH - 1; k >= 0; --k) {
+        acc = sc.inv_mu * (v[k][6 * g + c] + acc);
+        v[k][6 * g + c] = acc;
       }
     } else {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) D[c] = czero<R>();
+      for (int k = 0; k < CH; ++k) {
+        acc = sc.inv_mu * (v[k][6 * g + c] + acc);
+        v[k][6 * g + c] = acc;
+      }
     }
-#pragma unroll
-    for (int k = 0; k < CH; ++k) {
-      int t = sc.t0 + k;
-      R ca = BWD ? sc.mupow[CH - k] : sc.mupow[k + 1];
-      const bool keep = BWD ? (t >= sc.cut) : (t < sc.Lt - sc.cut);
-      R cb = keep ? (BWD ? sc.mupow[sc.Lt - 1 - t] : sc.mupow[t]) : R(0);
-#pragma unroll
-      for (int c = 0; c < 6; ++c) v[k][6 * g + c] += ca * C[c] + cb * D[c];
-    }
+    X[c] = acc;
   }
+}
+
+// Closure delta = G z (backward) or G^dagger z (forward), per colour vector, on the slices the
+// cutoff keeps (all of them when cut = 0), and the final values of the group:
+// v(t) += mu^-(distance to the carried-in chunk) C + mu^-(distance to the line's end) delta.
+template <typename R, int CH, int NV, bool BWD>
+TP_DEV void finish(cx<R> (&v)[CH][NV], int g, const cx<R> (&C)[6], const cx<R> (&Z)[6],
+                   const R (&cb)[CH], const ScanCtx<R>& sc) {
+  cx<R> D[6];
+  const bool band = BWD ? (sc.t0 + CH - 1 >= sc.cut) : (sc.t0 < sc.Lt - sc.cut);
+  if (sc.active && band) {
+    const cx<R>* G = sc.gl + sc.l * 9;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cx<R> acc0 = czero<R>(), acc1 = czero<R>();
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const cx<R> gk = G[BWD ? 3 * a + b : 3 * b + a];
+        if constexpr (BWD) {
+          acc0 += cmul(gk, Z[b]);
+          acc1 += cmul(gk, Z[3 + b]);
+        } else {
+          acc0 += cmulc(gk, Z[b]);
+          acc1 += cmulc(gk, Z[3 + b]);
+        }
+      }
+      D[a] = acc0;
+      D[3 + a] = acc1;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) D[c] = czero<R>();
+  }
+#pragma unroll
+  for (int k = 0; k < CH; ++k) {
+    const R ca = BWD ? sc.mupow[CH - k] : sc.mupow[k + 1];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[k][6 * g + c] += ca * C[c] + cb[k] * D[c];
+  }
+}
+
+// Scans of one or two sets of values per time slice (v1: NV1 values scanned in direction B1,
+// v2: NV2 values in direction B2; NV2 = 0 for one set): on return each holds the scan result
+// (T^-1 for a backward scan, T^dagger^-1 for a forward one).  Groups of 6 values (two colour
+// vectors) are finished one at a time; the two sets' groups share the combine's barriers.
+template <typename R, int CH, int NV1, bool B1, int NV2, bool B2, int N1, int N2>
+TP_DEV void scan_sets(cx<R> (&v1)[CH][N1], cx<R> (&v2)[CH][N2], cx<R>* lds, ScanCtx<R>& sc) {
+  constexpr int G1 = NV1 / 6, G2 = NV2 / 6, G = G1 > G2 ? G1 : G2;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    cx<R> X1[6], X2[6], C1[6], C2[6], Z1[6], Z2[6];
+    if (g < G1) local_scan<R, CH, N1, B1>(v1, g, X1, sc);
+    if (g < G2) local_scan<R, CH, N2, B2>(v2, g, X2, sc);
+    // weights, loaded ahead of the barriers that hide their latency
+    R cb1[CH], cb2[CH], w1 = R(0), w2 = R(0);
+    if (sc.fast) {
+      if (g < G1) { lvl1<R, B1>(X1, C1, sc.f); lvl2_put<R, B1>(X1, sc, 0); w1 = seg_weight<R, B1>(sc); }
+      if (g < G2) { lvl1<R, B2>(X2, C2, sc.f); lvl2_put<R, B2>(X2, sc, 1); w2 = seg_weight<R, B2>(sc); }
+      if (g < G1) closure_weights<R, CH, B1>(cb1, sc);
+      if (g < G2) closure_weights<R, CH, B2>(cb2, sc);
+      __syncthreads();
+      if (sc.seg == 0) {  // uniform per wavefront
+        if (g < G1) lvl2_scan<R, B1>(sc, 0);
+        if (g < G2) lvl2_scan<R, B2>(sc, 1);
+      }
+      __syncthreads();
+      if (g < G1) lvl2_get<R, B1>(C1, Z1, w1, sc, 0);
+      if (g < G2) lvl2_get<R, B2>(C2, Z2, w2, sc, 1);
+      sc.buf ^= 1;
+    } else {
+      if (g < G1) { closure_weights<R, CH, B1>(cb1, sc); combine_lds<R, B1>(X1, C1, Z1, lds, sc); }
+      if (g < G2) { closure_weights<R, CH, B2>(cb2, sc); combine_lds<R, B2>(X2, C2, Z2, lds, sc); }
+    }
+    if (g < G1) finish<R, CH, N1, B1>(v1, g, C1, Z1, cb1, sc);
+    if (g < G2) finish<R, CH, N2, B2>(v2, g, C2, Z2, cb2, sc);
+  }
+}
+
+// One set (NV values, direction BWD).
+template <typename R, int CH, int NV, bool BWD>
+TP_DEV void scan_core(cx<R> (&v)[CH][NV], cx<R>* lds, ScanCtx<R>& sc) {
+  cx<R> dummy[CH][1];
+  scan_sets<R, CH, NV, BWD, 0, BWD, NV, 1>(v, dummy, lds, sc);
 }
 
 template <int N> struct Arr { static constexpr int n = N > 0 ? N : 1; };
@@ -272,17 +338,37 @@ TP_DEV uint32_t batch_select(LineArgs<S>& a) {
   return blockIdx.x / nr;
 }
 
+// Thread layout and scan constants; stages the closure G of the workgroup's lines in LDS
+// (visible after the first barrier of the combine, which precedes every use).
+// Lines whose chunk count is a multiple of 16: a wavefront holds 16 consecutive chunks of the 4
+// lines of one tile, lane = line * 16 + chunk, so each line's chunks form one DPP row.  Its 64
+// lanes still cover one contiguous run of 16 slices x 4 lines of the tiled layout.  Otherwise
+// threads run in memory order (line in tile fastest, then chunk, then tile).
 template <typename S>
-TP_DEV ScanCtx<typename Prec<S>::R> make_ctx(const LineArgs<S>& a, int CH, uint32_t blk) {
+TP_DEV ScanCtx<typename Prec<S>::R> make_ctx(const LineArgs<S>& a, int CH, uint32_t blk, cx<typename Prec<S>::R>* lds) {
   using R = typename Prec<S>::R;
   ScanCtx<R> sc;
   const int tid = threadIdx.x;
-  const int rest = tid / kTile;
-  sc.j = rest % a.NCH;
-  sc.tile = rest / a.NCH;
-  sc.l = sc.tile * kTile + (tid % kTile);
-  sc.CH = CH;
   sc.fast = (a.NCH % 16) == 0;
+  if (sc.fast) {
+    const int lane = tid & 63, wv = tid >> 6, wpt = a.NCH >> 4;
+    sc.jw = lane & 15;
+    sc.lt = lane >> 4;
+    sc.seg = wv % wpt;
+    sc.nseg = wpt;
+    sc.tile = wv / wpt;
+    sc.j = sc.seg * 16 + sc.jw;
+    sc.l = sc.tile * kTile + sc.lt;
+  } else {
+    const int rest = tid / kTile;
+    sc.j = rest % a.NCH;
+    sc.tile = rest / a.NCH;
+    sc.lt = tid % kTile;
+    sc.l = sc.tile * kTile + sc.lt;
+    sc.jw = sc.seg = 0;
+    sc.nseg = 1;
+  }
+  sc.CH = CH;
   sc.LPB = a.LPB;
   sc.NCH = a.NCH;
   sc.t0 = sc.j * CH;
@@ -293,8 +379,20 @@ TP_DEV ScanCtx<typename Prec<S>::R> make_ctx(const LineArgs<S>& a, int CH, uint3
   sc.cut = a.cut;
   sc.f = R(a.f);
   sc.mupow = a.mupow;
-  sc.G = a.G + (int64_t)a.par * 9 * a.g.Vs2;
-  sc.gstride = a.g.Vs2;
+  sc.F = sc.fast ? a.mupow[16 * CH] : R(0);  // fast path: Lt = 16 CH nseg >= 16 CH
+  sc.tabs = lds;
+  sc.slot = a.LPB * 16 * 6;
+  sc.buf = 0;
+  cx<R>* gl = lds + (a.lds_table - a.LPB * 9);
+  sc.gl = gl;
+  if (tid < a.LPB * 9) {
+    const int ln = tid / 9, k = tid % 9;
+    const int sl = int(blk) * a.LPB + ln;
+    if (sl < a.g.Vs2) {
+      const auto e = a.G[((int64_t)a.par * 9 + k) * a.g.Vs2 + sl];
+      gl[ln * 9 + k] = cx<R>{R(e.x), R(e.y)};
+    }
+  }
   return sc;
 }
 
@@ -343,7 +441,7 @@ k_line(LineArgs<S> a) {
   extern __shared__ char smem_raw[];
   cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
   const uint32_t blk = batch_select(a);
-  ScanCtx<R> sc = make_ctx<S>(a, CH, blk);
+  ScanCtx<R> sc = make_ctx<S>(a, CH, blk, lds);
   const int s = sc.active ? sc.s : 0;
   cx<R> vb[CH][Arr<M::nb>::n], vf[CH][Arr<M::nf>::n];
   const R cout = R(a.c_out), cbase = R(a.c_base);
@@ -378,8 +476,12 @@ k_line(LineArgs<S> a) {
       for (int c = 0; c < Arr<M::nf>::n; ++c) vf[k][c] = czero<R>();
     }
   }
-  if constexpr (M::nb > 0) scan_core<R, CH, M::nb, true>(vb, lds, sc);
-  if constexpr (M::nf > 0) scan_core<R, CH, M::nf, false>(vf, lds, sc);
+  if constexpr (M::nb > 0 && M::nf > 0)
+    scan_sets<R, CH, M::nb, true, M::nf, false, Arr<M::nb>::n, Arr<M::nf>::n>(vb, vf, lds, sc);
+  else if constexpr (M::nb > 0)
+    scan_core<R, CH, M::nb, true>(vb, lds, sc);
+  else
+    scan_core<R, CH, M::nf, false>(vf, lds, sc);
   if (!sc.active) return;
 #pragma unroll
   for (int k = 0; k < CH; ++k) {
@@ -515,7 +617,7 @@ k_ilu_mid(LineArgs<S> a) {
     else return bkeep[k][c];
   };
   const uint32_t blk = batch_select(a);
-  ScanCtx<R> sc = make_ctx<S>(a, CH, blk);
+  ScanCtx<R> sc = make_ctx<S>(a, CH, blk, lds);
   const int s = sc.active ? sc.s : 0;
   cx<R> b[CH][6], f[CH][6], uup[NP ? 1 : CH][6];
 #pragma unroll
@@ -553,8 +655,7 @@ k_ilu_mid(LineArgs<S> a) {
 #pragma unroll
     for (int c = 0; c < 6; ++c) f[k][c] = u[c] + ps[c];
   }
-  scan_core<R, CH, 6, true>(b, lds, sc);
-  scan_core<R, CH, 6, false>(f, lds, sc);
+  scan_sets<R, CH, 6, true, 6, false, 6, 6>(b, f, lds, sc);
 #pragma unroll
   for (int k = 0; k < CH; ++k)
 #pragma unroll
@@ -603,8 +704,7 @@ k_ilu_mid(LineArgs<S> a) {
       for (int c = 0; c < 6; ++c) { f[k][c] = czero<R>(); b[k][c] = czero<R>(); }
     }
   }
-  scan_core<R, CH, 6, true>(b, lds, sc);   // T^-1 y_lo
-  scan_core<R, CH, 6, false>(f, lds, sc);  // T^dag^-1 (y_up - u_up)
+  scan_sets<R, CH, 6, true, 6, false, 6, 6>(b, f, lds, sc);  // T^-1 y_lo, T^dag^-1 (y_up - u_up)
   if (!sc.active) return;
 #pragma unroll
   for (int k = 0; k < CH; ++k) {
@@ -683,9 +783,12 @@ SpinorF<S> pv(const Field* f, int p) {
 }
 
 
-// LDS of a line kernel: the chunk-combine table (shuffle path: [tile][16 segments][4 lines][6];
-// LDS path: [chunk][line][6]) followed by `park` complex values per thread.
-int lds_table_of(Shape sh) { return sh.NCH % 16 == 0 ? sh.LPB * 16 * 6 : sh.LPB * sh.NCH * 6; }
+// LDS of a line kernel: the chunk-combine tables (DPP path: [2 buffers][2 sets] x [tile][16
+// segments][4 lines][6]; LDS path: [chunk][line][6]) and the staged closure G ([line][9]),
+// followed by `park` complex values per thread.
+int lds_table_of(Shape sh) {
+  return (sh.NCH % 16 == 0 ? 4 * sh.LPB * 16 * 6 : sh.LPB * sh.NCH * 6) + sh.LPB * 9;
+}
 
 template <typename S>
 size_t lds_bytes(Shape sh, int park) {

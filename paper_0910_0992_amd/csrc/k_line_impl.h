@@ -385,8 +385,9 @@ TP_DEV ScanCtx<typename Prec<S>::R> make_ctx(const LineArgs<S>& a, int CH, uint3
   sc.buf = 0;
   cx<R>* gl = lds + (a.lds_table - a.LPB * 9);
   sc.gl = gl;
-  if (tid < a.LPB * 9) {
-    const int ln = tid / 9, k = tid % 9;
+  // LPB * 9 entries; a workgroup can have fewer threads (short lines: LPB * NCH < LPB * 9)
+  for (int q = tid; q < a.LPB * 9; q += int(blockDim.x)) {
+    const int ln = q / 9, k = q % 9;
     const int sl = int(blk) * a.LPB + ln;
     if (sl < a.g.Vs2) {
       const auto e = a.G[((int64_t)a.par * 9 + k) * a.g.Vs2 + sl];

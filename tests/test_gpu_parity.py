@@ -36,6 +36,9 @@ CASES = {
     "clover_long": ((4, 2, 2, 256), 0.4, 0.1, 6.0, -0.01, 1.6, 1.0, -1),
     # 3 segments, many tiles per workgroup
     "clover_lt48": ((6, 6, 4, 48), 0.35, 0.12, 3.5, -0.01, 1.6, 1.0, -1),
+    # short lines: a workgroup of 16 lines x 6 slices has fewer threads than the 16 x 9 closure
+    # entries it stages
+    "clover_lt6": ((4, 4, 2, 6), 0.4, 0.2, 2.5, -0.05, 1.6, 1.0, -1),
     # U(3) spatial links (a random U(1) phase on each): not SU(3), so the reduced-precision
     # kernels read all nine link entries instead of rebuilding the third row
     "clover_u3_spatial": ((4, 4, 4, 16), 0.35, 0.12, 3.0, -0.05, 1.6, 1.0, -1, "u1_spatial"),

@@ -28,9 +28,9 @@ HBM_PEAK_GBS = 8000.0
 # change to those sources makes the figure stale and it is reported as null.
 TRAFFIC = {
     ("clover_32x256", "F16N", "ilu_mid"): {
-        "bytes_per_launch": 1.5522e+09,
+        "bytes_per_launch": 1.5486e+09,
         "sources": ["k_line_impl.h", "k_line_f16.hip", "k_line.hip", "tp_device.h"],
-        "sha256": "56aee1f3385ed15d0f570e8644d8b0956b4ab8716b63068b189194fbc89c9101",
+        "sha256": "4a3343e667e431cb3bf151d2f17e498da93d41c8dcc9631d070459f5e4f7b0b2",
     },
     ("clover_32x256", "F16N", "hop_clover"): {
         "bytes_per_launch": 2.6012e+09,
@@ -48,9 +48,9 @@ TRAFFIC = {
         "sha256": "e2f2a4d476761fba15de6e965f9202c1193f3ea59d1096a25dda0293644b84fe",
     },
     ("clover_32x256", "F16N", "scan_cl"): {
-        "bytes_per_launch": 7.0951e+08,
+        "bytes_per_launch": 7.0949e+08,
         "sources": ["k_line_impl.h", "k_line_f16.hip", "k_line.hip", "tp_device.h"],
-        "sha256": "56aee1f3385ed15d0f570e8644d8b0956b4ab8716b63068b189194fbc89c9101",
+        "sha256": "4a3343e667e431cb3bf151d2f17e498da93d41c8dcc9631d070459f5e4f7b0b2",
     },
 }
 

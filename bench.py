@@ -91,6 +91,8 @@ def parse():
     ap.add_argument("--point-sources", action="store_true",
                     help="only time the 12 spin-colour point sources at the origin: one after "
                          "another, as one batch, and with FP64 even-odd")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="only time the FP64 oracle's applies per workload on the host cores (no GPU)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -197,6 +199,69 @@ def cpu_baseline(cfg, timing, applies):
                    f"extrapolated from the all-core site throughput to {V} sites x {applies} applies "
                    f"of the GPU solve; per_core_value is the same from one core"),
     }
+
+
+def _oracle_config(job):
+    """One oracle process: M and S_L M S_R applies on one workload (the whole lattice, or a
+    16^3x16 slab of it, extrapolated by volume) -- median of 3 after a warm-up -- and for the
+    smallest workload a full CGNR solve to 1e-10."""
+    name, full = job
+    import numpy as np
+
+    import synth
+    from oracle import krylov
+    from oracle.schemes import Operator
+
+    cfg = synth.WORKLOADS[name]
+    dims = cfg["dims"] if full else (16, 16, 16, 16)
+    xi = cfg["xi"]
+    U = synth.make_links(dims, cfg["eps_s"], cfg["eps_t"], cfg["seed"])
+    eta = synth.make_source(dims, 2000)
+    t0 = time.perf_counter()
+    op = Operator(U, cfg["m0"], xi, -1.0, cfg["csw_s"] / xi, cfg["csw_t"])
+    setup = time.perf_counter() - t0
+    print(f"[oracle] {name} {dims}: operator built in {setup:.1f} s", file=sys.stderr, flush=True)
+    out = {"workload": name, "dims": list(cfg["dims"]), "timed_dims": list(dims), "setup_s": setup}
+    V = int(np.prod(cfg["dims"]))
+    scale = V / float(np.prod(dims))
+    for what, fn in (("M", op.M), ("TEMPORAL_SCHUR", lambda v: op.prec("TEMPORAL_SCHUR", v))):
+        fn(eta)
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            fn(eta)
+            ts.append(time.perf_counter() - t0)
+        med = float(np.median(ts)) * scale
+        print(f"[oracle] {name}: {what} {float(np.median(ts)):.3f} s per apply", file=sys.stderr, flush=True)
+        clover = cfg["csw_s"] != 0.0 or cfg["csw_t"] != 0.0
+        # FP64 byte models per lattice site: M = 3S + 4L (+ C); the ILU apply 13S + 12L + 2C per V/2
+        per_site = (3 * 192 + 4 * 144 + (576 if clover else 0)) if what == "M" else (13 * 192 + 12 * 144 + 2 * 576) / 2
+        out[what] = {"s_per_apply": med, "GB_per_s": per_site * V / med / 1e9,
+                     "extrapolated": not full}
+    if name == "wilson_4x16":
+        t0 = time.perf_counter()
+        _, info = krylov.solve(op, "TEMPORAL_SCHUR", eta, "cgnr", 1e-10)
+        out["cgnr_temporal_schur"] = {"s": time.perf_counter() - t0, "iters": info.get("iters"),
+                                      "true_rel_resid": info["true_rel_resid"]}
+    return out
+
+
+def oracle_timing(args):
+    """The oracle's applies on the host cores, one process (one core) per workload, side by
+    side: the small workloads whole, the large ones on a slab extrapolated by volume.  Touches
+    no GPU.  One JSON line."""
+    import multiprocessing as mp
+
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"
+    # the oracle's clover construction takes about a minute per 10^5 sites: 16^3x128 and up
+    # are timed on a slab
+    jobs = [("wilson_4x16", True), ("clover_12x64", True), ("clover_16x128", False),
+            ("clover_24x128", False), ("clover_32x256", False), ("clover_32x32_iso", False)]
+    with mp.get_context("fork").Pool(len(jobs)) as pool:
+        res = pool.map(_oracle_config, jobs)
+    print(json.dumps({"mode": "oracle_timing", "nproc": os.cpu_count(), "cpu_model": _cpu_model(),
+                      "threads_per_process": 1, "results": res}))
 
 
 def compare_schemes(args):
@@ -306,6 +371,9 @@ def point_sources(args):
 
 def main():
     args = parse()
+    if args.oracle_timing:
+        oracle_timing(args)
+        return
     if args.point_sources:
         point_sources(args)
         return

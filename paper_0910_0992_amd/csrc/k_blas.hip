@@ -44,6 +44,54 @@ TP_DEV void block_reduce(double (&acc)[8], int nred, double* partial, uint32_t b
 
 template <typename R> TP_DEV cx<R> cc(const double* z) { return cx<R>{R(z[0]), R(z[1])}; }
 
+// Streaming access for the reductions that write no field (norms and inner products): each field
+// is read once, in vectors larger than the caches, so the loads carry the non-temporal hint.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <typename T> TP_DEV T nt_load(const T* p) {
+  if constexpr (sizeof(T) == 16) {
+    return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p)));
+  } else if constexpr (sizeof(T) == 8) {
+    return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p)));
+  } else {
+    static_assert(sizeof(T) == 4, "4, 8 or 16 bytes");
+    return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const unsigned*>(p)));
+  }
+}
+// load_half of tp_device.h with non-temporal accesses (same values).
+template <typename S, typename R = typename Prec<S>::R>
+TP_DEV void nt_load_half(const SpinorF<S>& f, int h, uint32_t i, cx<R>* v) {
+  const S* b = f.p[h];
+  if constexpr (Prec<S>::half) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const Half2x2 e = nt_load(reinterpret_cast<const Half2x2*>(at(b + (int64_t)(2 * q) * f.stride, 2 * i)));
+      const float2 fa = __half22float2(e.a), fb = __half22float2(e.b);
+      v[2 * q] = {fa.x, fa.y};
+      v[2 * q + 1] = {fb.x, fb.y};
+    }
+    const R sc = nt_load(at(f.nrm[h], i));
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = sc * v[c];
+  } else if constexpr (paired<S>()) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const float4 e = nt_load(reinterpret_cast<const float4*>(at(b + (int64_t)(2 * q) * f.stride, 2 * i)));
+      v[2 * q] = {e.x, e.y};
+      v[2 * q + 1] = {e.z, e.w};
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const S e = nt_load(at(b + (int64_t)c * f.stride, i));
+      v[c] = {R(e.x), R(e.y)};
+    }
+  }
+}
+
+
+
+
 // acc[0..1] += <x, y> = sum conj(x) y over one half spinor, in FP64.
 template <typename R>
 TP_DEV void dot_acc(const cx<R>* x, const cx<R>* y, double* acc) {
@@ -104,11 +152,11 @@ __global__ void __launch_bounds__(kBlock) k_blas(BlasK<S> k) {
       for (int c = 0; c < 6; ++c) y[c] = x[c] + cmul(A, y[c]);
       store_half<S, R>(f1, h, i, y);
     } else if constexpr (OP == B_NORM2) {
-      load_half<S, R>(f0, h, i, x);
+      nt_load_half<S, R>(f0, h, i, x);
       for (int c = 0; c < 6; ++c) acc[0] += double(norm2(x[c]));
     } else if constexpr (OP == B_DOT || OP == B_DOT_NORM) {
-      load_half<S, R>(f0, h, i, x);
-      load_half<S, R>(f1, h, i, y);
+      nt_load_half<S, R>(f0, h, i, x);
+      nt_load_half<S, R>(f1, h, i, y);
       for (int c = 0; c < 6; ++c) {
         acc[0] += double(x[c].re) * double(y[c].re) + double(x[c].im) * double(y[c].im);
         acc[1] += double(x[c].re) * double(y[c].im) - double(x[c].im) * double(y[c].re);
@@ -131,9 +179,9 @@ __global__ void __launch_bounds__(kBlock) k_blas(BlasK<S> k) {
       }
       store_half<S, R>(f2, h, i, y);
     } else if constexpr (OP == B_DOT4_TS) {
-      load_half<S, R>(f0, h, i, x);  // t
-      load_half<S, R>(f1, h, i, y);  // s
-      load_half<S, R>(f2, h, i, z);  // rhat
+      nt_load_half<S, R>(f0, h, i, x);  // t
+      nt_load_half<S, R>(f1, h, i, y);  // s
+      nt_load_half<S, R>(f2, h, i, z);  // rhat
       dot_acc(x, y, acc);
       for (int c = 0; c < 6; ++c) acc[2] += double(norm2(x[c]));
       dot_acc(z, y, acc + 3);

@@ -298,6 +298,46 @@ TP_DEV void scan_core(cx<R> (&v)[CH][NV], cx<R>* lds, ScanCtx<R>& sc) {
   scan_sets<R, CH, NV, BWD, 0, BWD, NV, 1>(v, dummy, lds, sc);
 }
 
+// The line kernels read every input once per launch (the middle kernel parks what it needs
+// twice in LDS), in fields larger than the caches: their loads carry the non-temporal hint.
+typedef unsigned int lu32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int lu32x4 __attribute__((ext_vector_type(4)));
+template <typename T> TP_DEV T nt_ld(const T* p) {
+  if constexpr (sizeof(T) == 16) return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const lu32x4*>(p)));
+  else if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const lu32x2*>(p)));
+  else return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const unsigned*>(p)));
+}
+// load_half (64-bit index form) with non-temporal loads: the same values.
+template <typename S, typename R = typename Prec<S>::R>
+TP_DEV void nt_load_half(const SpinorF<S>& f, int h, int64_t i, cx<R>* v) {
+  const S* b = f.p[h];
+  if constexpr (Prec<S>::half) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const Half2x2 e = nt_ld(reinterpret_cast<const Half2x2*>(b + (int64_t)(2 * q) * f.stride + 2 * i));
+      const float2 fa = __half22float2(e.a), fb = __half22float2(e.b);
+      v[2 * q] = {fa.x, fa.y};
+      v[2 * q + 1] = {fb.x, fb.y};
+    }
+    const R sc = nt_ld(f.nrm[h] + i);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = sc * v[c];
+  } else if constexpr (paired<S>()) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const float4 e = nt_ld(reinterpret_cast<const float4*>(b + (int64_t)(2 * q) * f.stride + 2 * i));
+      v[2 * q] = {e.x, e.y};
+      v[2 * q + 1] = {e.z, e.w};
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const S e = nt_ld(b + (int64_t)c * f.stride + i);
+      v[c] = {R(e.x), R(e.y)};
+    }
+  }
+}
+
 template <int N> struct Arr { static constexpr int n = N > 0 ? N : 1; };
 
 // Which halves each mode scans: backward (T^-1) and forward (T^dagger^-1).
@@ -454,12 +494,12 @@ k_line(LineArgs<S> a) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const bool scanned = !passes<MODE>(h);
-        if (scanned || PASS) load_half<S, R>(a.in, h, i, v + 6 * h);
+        if (scanned || PASS) nt_load_half<S, R>(a.in, h, i, v + 6 * h);
         if (PASS && !scanned) {
           cx<R> o[6];
           if constexpr (BASE) {
             cx<R> bb[6];
-            load_half<S, R>(a.base, h, i, bb);
+            nt_load_half<S, R>(a.base, h, i, bb);
 #pragma unroll
             for (int c = 0; c < 6; ++c) o[c] = cout * v[6 * h + c] + cbase * bb[c];
           } else {
@@ -495,7 +535,7 @@ k_line(LineArgs<S> a) {
       cx<R> o[6];
       if constexpr (BASE) {
         cx<R> bb[6];
-        load_half<S, R>(a.base, h, i, bb);
+        nt_load_half<S, R>(a.base, h, i, bb);
 #pragma unroll
         for (int c = 0; c < 6; ++c) o[c] = cout * v[6 * h + c] + cbase * bb[c];
       } else {
@@ -532,10 +572,10 @@ struct RawHalf {
   TP_DEV void load(const SpinorF<S>& f, int h, int64_t i) {
     if constexpr (half) {
 #pragma unroll
-      for (int q = 0; q < 3; ++q) e[q] = *reinterpret_cast<const Half2x2*>(f.p[h] + (int64_t)(2 * q) * f.stride + 2 * i);
-      s = f.nrm[h][i];
+      for (int q = 0; q < 3; ++q) e[q] = nt_ld(reinterpret_cast<const Half2x2*>(f.p[h] + (int64_t)(2 * q) * f.stride + 2 * i));
+      s = nt_ld(f.nrm[h] + i);
     } else {
-      load_half<S, R>(f, h, i, e);
+      nt_load_half<S, R>(f, h, i, e);
     }
   }
   TP_DEV void zero() {
@@ -630,7 +670,7 @@ k_ilu_mid(LineArgs<S> a) {
       if (sc.active) {
         ru.load(a.aux, 0, i);
         rp.load(a.in, 0, i);
-        load_half<S, R>(a.aux, 1, i, b[k]);
+        nt_load_half<S, R>(a.aux, 1, i, b[k]);
       } else {
         ru.zero();
         rp.zero();
@@ -643,9 +683,9 @@ k_ilu_mid(LineArgs<S> a) {
       rp.unpack(ps);
     } else {
       if (sc.active) {
-        load_half<S, R>(a.aux, 0, i, u);
-        load_half<S, R>(a.aux, 1, i, b[k]);
-        load_half<S, R>(a.in, 0, i, ps);
+        nt_load_half<S, R>(a.aux, 0, i, u);
+        nt_load_half<S, R>(a.aux, 1, i, b[k]);
+        nt_load_half<S, R>(a.in, 0, i, ps);
       } else {
 #pragma unroll
         for (int c = 0; c < 6; ++c) { u[c] = czero<R>(); b[k][c] = czero<R>(); ps[c] = czero<R>(); }
@@ -674,7 +714,7 @@ k_ilu_mid(LineArgs<S> a) {
         rl.unpack(pl);
         if constexpr (NP == 3) rl.put(park_l, CH, nthr, k);
       } else {
-        load_half<S, R>(a.in, 1, i, pl);
+        nt_load_half<S, R>(a.in, 1, i, pl);
       }
 #pragma unroll
       for (int c = 0; c < 6; ++c) { w[c] = f[k][c]; w[6 + c] = bslot(k, c) + pl[c]; }
@@ -688,7 +728,7 @@ k_ilu_mid(LineArgs<S> a) {
         ru.unpack(u);
         if constexpr (NP == 2) rl.put(park_u, CH, nthr, k);
       } else {
-        load_half<S, R>(a.in, 0, i, ps);
+        nt_load_half<S, R>(a.in, 0, i, ps);
 #pragma unroll
         for (int c = 0; c < 6; ++c) u[c] = uup[k][c];
       }
@@ -716,7 +756,7 @@ k_ilu_mid(LineArgs<S> a) {
       rl.get(NP == 3 ? park_l : park_u, CH, nthr, k);
       rl.unpack(pl);
     } else {
-      load_half<S, R>(a.in, 1, i, pl);
+      nt_load_half<S, R>(a.in, 1, i, pl);
     }
 #pragma unroll
     for (int c = 0; c < 6; ++c) {

@@ -321,7 +321,7 @@ double link_bytes(int prec);
 double clov_bytes(int prec);
 
 // ---------------------------------------------------------------- BLAS
-constexpr int kRedBlocks = 4096;
+constexpr int kRedBlocks = 32768;  // one block per 256 sites of a parity at 32^3x256 (fused norms)
 constexpr int kMaxRhs = 16;  // right-hand sides of one batched solve
 // Generic unit-wise BLAS on fields over parities [par0, par0+npar).
 enum BlasOp {

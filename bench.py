@@ -30,27 +30,27 @@ TRAFFIC = {
     ("clover_32x256", "F16N", "ilu_mid"): {
         "bytes_per_launch": 1.5486e+09,
         "sources": ["k_line_impl.h", "k_line_f16.hip", "k_line.hip", "tp_device.h"],
-        "sha256": "4a3343e667e431cb3bf151d2f17e498da93d41c8dcc9631d070459f5e4f7b0b2",
+        "sha256": "ee8a3282f1bb50b88ef110fd5c6f7548dba2ce8dfe1b25cd6904ca6072c33c3f",
     },
     ("clover_32x256", "F16N", "hop_clover"): {
-        "bytes_per_launch": 2.6012e+09,
+        "bytes_per_launch": 2.6021e+09,
         "sources": ["k_site.hip", "tp_hop.h", "tp_device.h"],
         "sha256": "1ceae9d98c228f96b34a58207ca05e08e53f2d79357e2a743abbde45db7954dc",
     },
     ("clover_32x256", "F16N", "hop_ds"): {
-        "bytes_per_launch": 1.7930e+09,
+        "bytes_per_launch": 1.7938e+09,
         "sources": ["k_site.hip", "tp_hop.h", "tp_device.h"],
         "sha256": "1ceae9d98c228f96b34a58207ca05e08e53f2d79357e2a743abbde45db7954dc",
     },
     ("clover_32x256", "F16N", "blas_bicg_fused"): {
         "bytes_per_launch": 3.7582e+09,
         "sources": ["k_blas.hip", "tp_device.h"],
-        "sha256": "e2f2a4d476761fba15de6e965f9202c1193f3ea59d1096a25dda0293644b84fe",
+        "sha256": "f0545cad762087548e2089299855df73864e571e38b279a96f46c3f4d6d2ce42",
     },
     ("clover_32x256", "F16N", "scan_cl"): {
         "bytes_per_launch": 7.0949e+08,
         "sources": ["k_line_impl.h", "k_line_f16.hip", "k_line.hip", "tp_device.h"],
-        "sha256": "4a3343e667e431cb3bf151d2f17e498da93d41c8dcc9631d070459f5e4f7b0b2",
+        "sha256": "ee8a3282f1bb50b88ef110fd5c6f7548dba2ce8dfe1b25cd6904ca6072c33c3f",
     },
 }
 

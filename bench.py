@@ -30,7 +30,7 @@ TRAFFIC = {
     ("clover_32x256", "F16N", "ilu_mid"): {
         "bytes_per_launch": 1.5486e+09,
         "sources": ["k_line_impl.h", "k_line_f16.hip", "k_line.hip", "tp_device.h"],
-        "sha256": "ee8a3282f1bb50b88ef110fd5c6f7548dba2ce8dfe1b25cd6904ca6072c33c3f",
+        "sha256": "8bf62e857b69540bb3f28face2c9e14e3fdcd7ca73f306f910dd9a2175f7588b",
     },
     ("clover_32x256", "F16N", "hop_clover"): {
         "bytes_per_launch": 2.6021e+09,
@@ -50,7 +50,7 @@ TRAFFIC = {
     ("clover_32x256", "F16N", "scan_cl"): {
         "bytes_per_launch": 7.0949e+08,
         "sources": ["k_line_impl.h", "k_line_f16.hip", "k_line.hip", "tp_device.h"],
-        "sha256": "ee8a3282f1bb50b88ef110fd5c6f7548dba2ce8dfe1b25cd6904ca6072c33c3f",
+        "sha256": "8bf62e857b69540bb3f28face2c9e14e3fdcd7ca73f306f910dd9a2175f7588b",
     },
 }
 

@@ -15,17 +15,18 @@
 // i.e. the SMW back-substitution with X(t) = -b mu^-(Lt-t) P.  T^dagger mirrors
 // it with a prefix sum and delta' = G^dagger rho(Lt-1).  No link is read by a
 // scan.  Because the recurrence has a scalar coefficient, a line splits into
-// chunks whose partial sums combine exactly through LDS (carry = mu^-k times
-// the neighbour chunk's head).  The closure G = (I - mu^-Lt P)^-1 P / mu is formed
+// chunks whose partial sums combine exactly (carry = mu^-k times the neighbour
+// chunk's head), by DPP row operations within a wavefront and through LDS across
+// wavefronts.  The closure G = (I - mu^-Lt P)^-1 P / mu is formed
 // in FP64 at set-up (mu^-Lt is far below FP32 range on long lines) and applied in the
 // kernel's arithmetic precision.  With the cutoff trick (Sec. II.A, eq:cutoff) the closure
 // term is applied only on the slices whose Woodbury vector survives, t >= cut for T^-1 and
 // t < Lt - cut for T^dagger^-1; threads whose slices all fall outside skip the closure.
 //
 // Workgroup = LPB lines (whole tiles of 4 lines) x NCH chunks of CH consecutive
-// time slices.  Threads are numbered in memory order of the tiled p3 layout
-// (line-in-tile fastest, then chunk, then tile), so loads and stores are
-// contiguous across a wavefront.
+// time slices.  A wavefront covers one contiguous run of the tiled p3 layout (16
+// slices x 4 lines when NCH is a multiple of 16, with one line per 16-lane DPP row;
+// otherwise threads in memory order), so loads and stores are contiguous across it.
 #pragma once
 #include "tp_internal.h"
 

@@ -55,14 +55,15 @@ def M_at_sites(U, psi, sites, m0, gamma_f, b=-1.0, c_s=0.0, c_t=0.0, dagger=Fals
     return out
 
 
-def Tinv_on_lines(U, psi, lines, mu, b=-1.0, dagger=False):
-    """T^-1 (or T^dagger^-1) psi on the time lines (x, y, z) in `lines`; returns [n, Lt, 4, 3]."""
+def Tinv_on_lines(U, psi, lines, mu, b=-1.0, dagger=False, eps=0.0):
+    """T^-1 (or T^dagger^-1) psi on the time lines (x, y, z) in `lines`; returns [n, Lt, 4, 3].
+    eps > 0: with the cutoff trick of eq:cutoff at that threshold."""
     out = []
     for (x, y, z) in lines:
         ut = U[3][:, z, y, x][:, None, None, None]
         p = psi[:, z, y, x][:, None, None, None]
         f = T.apply_Tdaginv if dagger else T.apply_Tinv
-        out.append(f(ut, p, mu, b)[:, 0, 0, 0])
+        out.append(f(ut, p, mu, b, eps=eps)[:, 0, 0, 0])
     return np.stack(out)
 
 

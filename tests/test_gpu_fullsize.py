@@ -83,6 +83,28 @@ def test_Tinv_sampled_lines(big, prec, dagger):
     assert _rel(got, ref) < TOL[prec], (b["name"], prec, _rel(got, ref))
 
 
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_Tinv_cutoff_sampled_lines(big, prec, dagger):
+    """The cutoff trick (eq:cutoff) at full size: T^-1 and T^dagger^-1 with a threshold that
+    drops the closure on about half of each line, on 8 sampled lines, against the oracle's
+    cutoff variant; the operator returns to the exact inverse at eps = 0."""
+    b = big
+    g = b["gop"]
+    mu = b["m0"] + 1.0 + 3.0 / b["xi"]
+    lt = b["dims"][3]
+    eps = max(1.5 * 3 ** 0.5 * mu ** -(lt // 2), 1e-6)
+    try:
+        dropped = g.set_cutoff(eps)
+        assert 0 < dropped < lt
+        out = _np(g.apply_Tinv(b["teta"], prec, dagger=dagger))
+    finally:
+        g.set_cutoff(0.0)
+    got = np.stack([out[:, z, y, x] for (x, y, z) in b["lines"]])
+    ref = sampled.Tinv_on_lines(b["U"], b["eta"], b["lines"], mu, -1.0, dagger=dagger, eps=eps)
+    assert _rel(got, ref) < TOL[prec], (b["name"], prec, _rel(got, ref))
+
+
 @pytest.mark.parametrize("scheme", ["TEMPORAL", "TEMPORAL_SCHUR", "TEMPORAL_SCHUR3D", "TEMPORAL_FULLSW"])
 def test_prec_is_SL_M_SR(big, scheme):
     """The fused preconditioned apply equals the composition of the separately

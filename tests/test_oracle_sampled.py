@@ -36,13 +36,14 @@ def test_M_at_sites_matches_full_lattice(dims, b, c_s, c_t, dagger):
 
 @pytest.mark.parametrize("dims,b", [((4, 4, 2, 8), -1.0), ((2, 4, 2, 7), 1.0)])
 @pytest.mark.parametrize("dagger", [False, True])
-def test_Tinv_on_lines_matches_full_lattice(dims, b, dagger):
+@pytest.mark.parametrize("eps", [0.0, 0.05])
+def test_Tinv_on_lines_matches_full_lattice(dims, b, dagger, eps):
     U = synth.make_links(dims, 0.5, 0.3, 13)
     psi = synth.make_source(dims, 14)
     mu = 1.7
-    full = (T.apply_Tdaginv if dagger else T.apply_Tinv)(U[3], psi, mu, b)
+    full = (T.apply_Tdaginv if dagger else T.apply_Tinv)(U[3], psi, mu, b, eps=eps)
     lines = [(0, 0, 0), (dims[0] - 1, dims[1] - 1, dims[2] - 1), (1, 2 % dims[1], 1)]
-    got = sampled.Tinv_on_lines(U, psi, lines, mu, b, dagger=dagger)
+    got = sampled.Tinv_on_lines(U, psi, lines, mu, b, dagger=dagger, eps=eps)
     ref = np.stack([full[:, z, y, x] for (x, y, z) in lines])
     assert np.abs(got - ref).max() < 1e-14 * np.abs(ref).max()
 

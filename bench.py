@@ -30,27 +30,27 @@ TRAFFIC = {
     ("clover_32x256", "F16N", "ilu_mid"): {
         "bytes_per_launch": 1.5486e+09,
         "sources": ["k_line_impl.h", "k_line_f16.hip", "k_line.hip", "tp_device.h"],
-        "sha256": "8bf62e857b69540bb3f28face2c9e14e3fdcd7ca73f306f910dd9a2175f7588b",
+        "sha256": "03da316c1837240dac89de534cfcf376d9d81eb1b76a8768aae687375421c936",
     },
     ("clover_32x256", "F16N", "hop_clover"): {
-        "bytes_per_launch": 2.6021e+09,
+        "bytes_per_launch": 2.6941e+09,
         "sources": ["k_site.hip", "tp_hop.h", "tp_device.h"],
-        "sha256": "1ceae9d98c228f96b34a58207ca05e08e53f2d79357e2a743abbde45db7954dc",
+        "sha256": "55fa9283828739c0c1e7698af4d7b9906471c74a5be27c87a93b1ecb689662ab",
     },
     ("clover_32x256", "F16N", "hop_ds"): {
-        "bytes_per_launch": 1.7938e+09,
+        "bytes_per_launch": 1.6844e+09,
         "sources": ["k_site.hip", "tp_hop.h", "tp_device.h"],
-        "sha256": "1ceae9d98c228f96b34a58207ca05e08e53f2d79357e2a743abbde45db7954dc",
+        "sha256": "55fa9283828739c0c1e7698af4d7b9906471c74a5be27c87a93b1ecb689662ab",
     },
     ("clover_32x256", "F16N", "blas_bicg_fused"): {
         "bytes_per_launch": 3.7582e+09,
         "sources": ["k_blas.hip", "tp_device.h"],
-        "sha256": "f0545cad762087548e2089299855df73864e571e38b279a96f46c3f4d6d2ce42",
+        "sha256": "23a7b7e172b0d0e003412888a2493d81c67126a8c0e9f56bce1bfcadb2ab4072",
     },
     ("clover_32x256", "F16N", "scan_cl"): {
         "bytes_per_launch": 7.0949e+08,
         "sources": ["k_line_impl.h", "k_line_f16.hip", "k_line.hip", "tp_device.h"],
-        "sha256": "8bf62e857b69540bb3f28face2c9e14e3fdcd7ca73f306f910dd9a2175f7588b",
+        "sha256": "03da316c1837240dac89de534cfcf376d9d81eb1b76a8768aae687375421c936",
     },
 }
 

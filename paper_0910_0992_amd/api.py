@@ -3,7 +3,9 @@
 Argument marshalling only (tensor data pointers, the current stream); all
 arithmetic runs in libtprec.so.
 """
+import atexit
 import ctypes as C
+import weakref
 
 import torch
 
@@ -25,17 +27,30 @@ def _prec(p):
 
 def _torch_allocator(device):
     """tp_alloc_fn / tp_free_fn callbacks over torch's caching allocator on `device`."""
+    # bound now: an operator released while the interpreter shuts down must not look up
+    # module attributes that teardown may already have cleared
+    alloc_fn, delete_fn = torch.cuda.caching_allocator_alloc, torch.cuda.caching_allocator_delete
 
     def alloc(nbytes, stream, user):
         try:
-            return torch.cuda.caching_allocator_alloc(int(nbytes), device=device, stream=int(stream or 0))
+            return alloc_fn(int(nbytes), device=device, stream=int(stream or 0))
         except Exception:  # out of memory: the library reports TP_ENOMEM
             return None
 
     def free(ptr, nbytes, stream, user):
-        torch.cuda.caching_allocator_delete(int(ptr))
+        delete_fn(int(ptr))
 
     return L.ALLOC_FN(alloc), L.FREE_FN(free)
+
+
+# operators still open at exit are closed before torch's own exit handlers run
+_open_ops = weakref.WeakSet()
+
+
+@atexit.register
+def _close_open_ops():
+    for op in list(_open_ops):
+        op.close()
 
 
 def _scheme(s):
@@ -91,6 +106,7 @@ class Operator:
         L.check(lib.tp_ctx_create(d, int(bc_t), int(device), C.byref(self._ctx)))
         self._bind_stream()
         self._alloc_cb = None
+        _open_ops.add(self)
         if allocator == "torch":
             self._alloc_cb = _torch_allocator(device)
             L.check(lib.tp_ctx_set_allocator(self._ctx, self._alloc_cb[0], self._alloc_cb[1], None))

@@ -256,9 +256,17 @@ struct LinkF {
   const L* p;
   int64_t stride;
 };
+// The third row of an SU(3) matrix from its first two: the rows are orthonormal with unit
+// determinant, so the third row is the complex conjugate of the cross product of the first two.
+template <typename R> TP_DEV void su3_third_row(su3<R>& u) {
+  const cx<R>* a = u.e;
+  const cx<R>* b = u.e + 3;
+  u.e[6] = conj(cmul(a[1], b[2]) - cmul(a[2], b[1]));
+  u.e[7] = conj(cmul(a[2], b[0]) - cmul(a[0], b[2]));
+  u.e[8] = conj(cmul(a[0], b[1]) - cmul(a[1], b[0]));
+}
 // ROWS = 3 reads all nine entries; ROWS = 2 reads the first two rows of an SU(3) link and
-// rebuilds the third: the rows are orthonormal with unit determinant, so the third row is
-// the complex conjugate of the cross product of the first two.
+// rebuilds the third.
 template <typename R, typename L, int ROWS = 3>
 TP_DEV su3<R> load_su3(const LinkF<L>& f, uint32_t i) {
   su3<R> u;
@@ -271,13 +279,7 @@ TP_DEV su3<R> load_su3(const LinkF<L>& f, uint32_t i) {
 #pragma unroll
     for (int k = 0; k < 3 * ROWS; ++k) u.e[k] = ld<R, L>(at(f.p + (int64_t)k * f.stride, i));
   }
-  if constexpr (ROWS == 2) {
-    const cx<R>* a = u.e;
-    const cx<R>* b = u.e + 3;
-    u.e[6] = conj(cmul(a[1], b[2]) - cmul(a[2], b[1]));
-    u.e[7] = conj(cmul(a[2], b[0]) - cmul(a[0], b[2]));
-    u.e[8] = conj(cmul(a[0], b[1]) - cmul(a[1], b[0]));
-  }
+  if constexpr (ROWS == 2) su3_third_row(u);
   return u;
 }
 

@@ -168,3 +168,25 @@ def test_external_krylov_on_internal_fields(case, scheme):
     true = np.linalg.norm(e - oop.M(x)) / np.linalg.norm(e)
     print(f"[fields] external BiCGStab {scheme}: {its} iterations, true residual {true:.2e}", flush=True)
     assert true <= 1.05e-10
+
+
+@pytest.mark.gpu
+def test_operator_left_open_at_exit():
+    """An operator that is never closed is released at interpreter exit through the torch
+    allocator without errors (its memory callbacks must not outlive torch's teardown)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import torch, synth\n"
+            "from paper_0910_0992_amd import Operator\n"
+            "U = synth.make_links((4, 4, 4, 8), 0.3, 0.1, 1000)\n"
+            "op = Operator(torch.from_numpy(U).cuda(), -0.05, 3.0, 0.5, 1.0, -1)\n"
+            "eta = torch.from_numpy(synth.make_source((4, 4, 4, 8), 2000)).cuda()\n"
+            "x, info = op.solve(eta, scheme='TEMPORAL_SCHUR', prec='F32', tol=1e-8)\n"
+            "print('solved', info['iters'], flush=True)\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240,
+                       cwd=root, env=dict(os.environ, PYTHONPATH=root))
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "solved" in r.stdout
+    assert "Exception ignored" not in r.stderr and "Traceback" not in r.stderr, r.stderr[-2000:]

@@ -35,12 +35,12 @@ TRAFFIC = {
     ("clover_32x256", "F16N", "hop_clover"): {
         "bytes_per_launch": 2.6941e+09,
         "sources": ["k_site.hip", "tp_hop.h", "tp_device.h"],
-        "sha256": "55fa9283828739c0c1e7698af4d7b9906471c74a5be27c87a93b1ecb689662ab",
+        "sha256": "0b1b00099ce246b8116a5e4ce58cd64b49dca9bc8636c85fd5146f9810418788",
     },
     ("clover_32x256", "F16N", "hop_ds"): {
         "bytes_per_launch": 1.6844e+09,
         "sources": ["k_site.hip", "tp_hop.h", "tp_device.h"],
-        "sha256": "55fa9283828739c0c1e7698af4d7b9906471c74a5be27c87a93b1ecb689662ab",
+        "sha256": "0b1b00099ce246b8116a5e4ce58cd64b49dca9bc8636c85fd5146f9810418788",
     },
     ("clover_32x256", "F16N", "blas_bicg_fused"): {
         "bytes_per_launch": 3.7582e+09,

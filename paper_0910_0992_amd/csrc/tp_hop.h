@@ -128,8 +128,9 @@ TP_DEV HopIdx hop_idx(const Geom& g, int p, int t, int s) {
 }
 
 // D_s with FP16 storage and two-row links: each hop's loads are issued before the previous
-// hop's arithmetic, so that every wavefront keeps two hops' loads in flight.  Same order and
-// arithmetic as hop_dir.
+// hop's arithmetic, so that every wavefront keeps two hops' loads in flight.  The operations and
+// their order are hop_dir's (the compiler may still pair a few multiply-adds differently, which
+// moves the FP16 result by at most its last bit).
 TP_DEV void hop_space_raw(const HopIdx& x, const SpinorF<__half2>& nb, const LinkF<__half2>* u_here,
                           const LinkF<__half2>* u_there, float c, cx<float>* out) {
   HopRawH A, B;

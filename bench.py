@@ -35,12 +35,12 @@ TRAFFIC = {
     ("clover_32x256", "F16N", "hop_clover"): {
         "bytes_per_launch": 2.6941e+09,
         "sources": ["k_site.hip", "tp_hop.h", "tp_device.h"],
-        "sha256": "0b1b00099ce246b8116a5e4ce58cd64b49dca9bc8636c85fd5146f9810418788",
+        "sha256": "f3ee06be1968e6749e6d2c7fb0f86e78ee848cf435851b269700937e959e3e9b",
     },
     ("clover_32x256", "F16N", "hop_ds"): {
         "bytes_per_launch": 1.6844e+09,
         "sources": ["k_site.hip", "tp_hop.h", "tp_device.h"],
-        "sha256": "0b1b00099ce246b8116a5e4ce58cd64b49dca9bc8636c85fd5146f9810418788",
+        "sha256": "f3ee06be1968e6749e6d2c7fb0f86e78ee848cf435851b269700937e959e3e9b",
     },
     ("clover_32x256", "F16N", "blas_bicg_fused"): {
         "bytes_per_launch": 3.7582e+09,

@@ -549,15 +549,15 @@ tp_status tp_gauge_create(tp_ctx ctx, const void* links, int32_t where, tp_gauge
       g->w_d = static_cast<double2*>(dev_alloc(ctx, size_t(2) * 9 * L.V2 * sizeof(double2)));
       g->poly = static_cast<double2*>(dev_alloc(ctx, size_t(2) * 9 * L.Vs2 * sizeof(double2)));
       g->canon_ax = static_cast<double2*>(dev_alloc(ctx, lb));
-      int* flags = static_cast<int*>(dev_alloc(ctx, 3 * sizeof(int)));
-      int hf[3] = {1, 1, 1};
+      int* flags = static_cast<int*>(dev_alloc(ctx, 4 * sizeof(int)));
+      int hf[4] = {1, 1, 1, 1};
       try {
-        HIP_CHECK(hipMemsetAsync(flags, 0, 3 * sizeof(int), ctx->stream));
+        HIP_CHECK(hipMemsetAsync(flags, 0, 4 * sizeof(int), ctx->stream));
         launch_wline(ctx, g);
         launch_axial_links(ctx, g, flags);
         launch_to_half(ctx, g->u3_f, g->u3_h, int64_t(lb / sizeof(double2)));
         launch_pack_links(ctx, g);
-        HIP_CHECK(hipMemcpyAsync(hf, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_CHECK(hipMemcpyAsync(hf, flags, 4 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
         HIP_CHECK(hipStreamSynchronize(ctx->stream));
       } catch (...) {
         dev_free(ctx, flags);
@@ -567,6 +567,7 @@ tp_status tp_gauge_create(tp_ctx ctx, const void* links, int32_t where, tp_gauge
       if (hf[2]) TP_THROW(TP_EINVAL, "links contain NaN or Inf");
       if (hf[1]) TP_THROW(TP_EINVAL, "time links must be unitary (U U^dag = 1 to 1e-10)");
       g->su3_spatial = hf[0] == 0;
+      g->su3_spatial_f64 = hf[3] == 0;
     } catch (...) {
       tp_gauge_destroy(g);
       throw;

@@ -234,6 +234,7 @@ __global__ void k_axial_links(const double2* __restrict__ canon, const double2* 
       cx<double> det = cmul(m[0], c0) + cmul(m[1], c1) + cmul(m[2], c2);
       dev = fmax(dev, sqrt(norm2(det - cx<double>{1.0, 0.0})));
       if (!(dev <= 1e-9)) flags[0] = 1;
+      if (!(dev <= 1e-13)) flags[3] = 1;
     } else if (!(dev <= 1e-10)) {
       flags[1] = 1;
     }

@@ -415,21 +415,21 @@ int site_t(tp_op op, const SiteIO& io, Field& dst, SiteCoef cf, int ck, int par0
   a.ord = tile_order(L, nb, a.nr, Prec<S>::half);
   bool dt = cf.c_t != 0.0, ds = cf.c_s != 0.0;
   bool i2 = in2 != nullptr;
-  // reduced-precision spatial hops read SU(3) links as two rows
+  // spatial hops read SU(3) links as two rows (FP64: only links SU(3) to 1e-13)
   constexpr bool kReduced = !std::is_same<S, double2>::value;
-  const bool two = kReduced && op->g->su3_spatial;
+  const bool two = kReduced ? op->g->su3_spatial : op->g->su3_spatial_f64;
   if (dt && ds) {
     if (two) {
-      if (clov) site_in2<S, true, kReduced ? 2 : 3, true>(op, a, nb, i2, norm, par0, npar);
-      else site_in2<S, true, kReduced ? 2 : 3, false>(op, a, nb, i2, norm, par0, npar);
+      if (clov) site_in2<S, true, 2, true>(op, a, nb, i2, norm, par0, npar);
+      else site_in2<S, true, 2, false>(op, a, nb, i2, norm, par0, npar);
     } else {
       if (clov) site_in2<S, true, 3, true>(op, a, nb, i2, norm, par0, npar);
       else site_in2<S, true, 3, false>(op, a, nb, i2, norm, par0, npar);
     }
   } else if (ds) {
     if (two) {
-      if (clov) site_in2<S, false, kReduced ? 2 : 3, true>(op, a, nb, i2, norm, par0, npar);
-      else site_in2<S, false, kReduced ? 2 : 3, false>(op, a, nb, i2, norm, par0, npar);
+      if (clov) site_in2<S, false, 2, true>(op, a, nb, i2, norm, par0, npar);
+      else site_in2<S, false, 2, false>(op, a, nb, i2, norm, par0, npar);
     } else {
       if (clov) site_in2<S, false, 3, true>(op, a, nb, i2, norm, par0, npar);
       else site_in2<S, false, 3, false>(op, a, nb, i2, norm, par0, npar);
@@ -484,8 +484,8 @@ int launch_site(tp_op op, int prec, const SiteIO& io, Field& dst, SiteCoef cf, i
   tp_ctx ctx = op->g->ctx;
   const Lattice& L = ctx->lat;
   double S = spinor_bytes(prec), Lb = link_bytes(prec), C = clov_bytes(prec);
-  // spatial links read as two rows (12 reals) when they are SU(3) and the precision is reduced
-  double Ls = (prec != TP_F64 && op->g->su3_spatial) ? Lb * 2 / 3 : Lb;
+  // spatial links read as two rows (12 reals) when they are SU(3) (to 1e-13 for FP64)
+  double Ls = (prec != TP_F64 ? op->g->su3_spatial : op->g->su3_spatial_f64) ? Lb * 2 / 3 : Lb;
   bool self = cf.c_mu != 0 || (ck && cf.c_A != 0);
   // spinor bytes per right-hand side; links and clover once for a whole batch
   double sp = S + (self ? S : 0) + (cf.c_s != 0 ? S : 0) + (cf.c_t != 0 ? S : 0) + (io.in2 ? S : 0);

@@ -150,6 +150,9 @@ struct tp_gauge_s {
   double2* poly = nullptr;   // W(0) per line [2 par][9][Vs2]
   // every axial-frame spatial link is SU(3) to 1e-9: FP32/FP16 kernels read two rows
   bool su3_spatial = false;
+  // ... and to 1e-13: the FP64 site kernels read two rows as well (the rebuilt third row is
+  // then exact to that level)
+  bool su3_spatial_f64 = false;
 };
 
 struct tp_clover_s {

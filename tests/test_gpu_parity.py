@@ -345,6 +345,34 @@ def test_gauge_rejects_nonunitary_time_links():
     Operator(torch.from_numpy(U).cuda(), -0.05, 3.0, 0.5, 1.0, -1).close()
 
 
+@pytest.mark.parametrize("dev", [3e-11, 3e-7])
+def test_nearly_su3_spatial_links(dev):
+    """Spatial links off SU(3) by `dev` (a non-unitary factor 1 + dev*i*H per link): the FP64
+    hops read two rows only when every link is SU(3) to 1e-13 and the reduced-precision hops
+    when it is to 1e-9, so FP64 stays within 1e-12 and F32/F16N within their bounds either way
+    (a rebuilt third row would carry an error of order dev)."""
+    from paper_0910_0992_amd import Operator
+    dims = (4, 4, 4, 8)
+    U = synth.make_links(dims, 0.35, 0.12, 11)
+    rng = np.random.default_rng(12)
+    h = rng.standard_normal((3,) + U.shape[1:]) + 1j * rng.standard_normal((3,) + U.shape[1:])
+    h = 0.5 * (h + np.conj(np.swapaxes(h, -1, -2)))
+    U[:3] = U[:3] @ (np.eye(3) + 1j * dev * h)
+    o = OOp(U, -0.05, 3.0, -1.0, 0.5, 1.0)
+    g = Operator(torch.from_numpy(U).cuda(), -0.05, 3.0, 0.5, 1.0, -1)
+    try:
+        e = synth.make_source(dims, 2000)
+        te = torch.from_numpy(e).cuda()
+        for prec in ("F64", "F32", "F16N"):
+            tol = TOL[prec][0] * (1 if prec == "F64" else 2)
+            _close(_np(g.apply_M(te, prec)), o.M(e), tol, f"M {prec}")
+            _close(_np(g.apply_Ds(te, prec)), o.Ds(e), tol, f"D_s {prec}")
+        _close(_np(g.apply_prec(te, "TEMPORAL_SCHUR", "F64")), o.prec("TEMPORAL_SCHUR", e), TOL["F64"][1],
+               "temporal + 3D-ILU F64")
+    finally:
+        g.close()
+
+
 # Shapes on which the site kernels visit tiles in their XCD-aware order (time extent a
 # multiple of 64 up to 512, Lx/2 a multiple of 4): 1, 2, 4 and 8 blocks per tile, two tiles
 # per x row and several z blocks.

@@ -45,7 +45,7 @@ TRAFFIC = {
     ("clover_32x256", "F16N", "blas_bicg_fused"): {
         "bytes_per_launch": 3.7582e+09,
         "sources": ["k_blas.hip", "tp_device.h"],
-        "sha256": "23a7b7e172b0d0e003412888a2493d81c67126a8c0e9f56bce1bfcadb2ab4072",
+        "sha256": "88035dcc81646db7be2d2dc697b7cbf54b915edb3ca7d9a5470709df7449e16a",
     },
     ("clover_32x256", "F16N", "scan_cl"): {
         "bytes_per_launch": 7.0949e+08,

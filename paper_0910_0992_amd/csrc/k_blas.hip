@@ -217,10 +217,12 @@ __global__ void __launch_bounds__(kBlock) k_blas(BlasK<S> k) {
   if constexpr (nred > 0) block_reduce(acc, nred, k.partial + (int64_t)rhs * nblk * 8, blk);
 }
 
-// y (precision SY) = x (precision SX), or y += x when ACC.
-template <typename SX, typename SY, bool ACC>
+// y (precision SY) = x (precision SX) when MODE = 0, y += x when MODE = 1, y = z + x (z in
+// precision SY) when MODE = 2.
+template <typename SX, typename SY, int MODE>
 __global__ void __launch_bounds__(kBlock) k_convert(SpinorF<SX> x0, SpinorF<SX> x1, SpinorF<SY> y0,
-                                                    SpinorF<SY> y1, int par0, int npar, int64_t V2) {
+                                                    SpinorF<SY> y1, SpinorF<SY> z0, SpinorF<SY> z1,
+                                                    int par0, int npar, int64_t V2) {
   using RX = typename Prec<SX>::R;
   using RY = typename Prec<SY>::R;
   for (int q = 0; q < npar; ++q)
@@ -231,10 +233,11 @@ __global__ void __launch_bounds__(kBlock) k_convert(SpinorF<SX> x0, SpinorF<SX> 
     cx<RX> a[6];
     load_half<SX, RX>(p ? x1 : x0, h, i, a);
     cx<RY> b[6];
-    if constexpr (ACC) load_half<SY, RY>(p ? y1 : y0, h, i, b);
+    if constexpr (MODE == 1) load_half<SY, RY>(p ? y1 : y0, h, i, b);
+    if constexpr (MODE == 2) load_half<SY, RY>(p ? z1 : z0, h, i, b);
     for (int c = 0; c < 6; ++c) {
       cx<RY> t = cx<RY>{RY(a[c].re), RY(a[c].im)};
-      b[c] = ACC ? b[c] + t : t;
+      b[c] = MODE ? b[c] + t : t;
     }
     store_half<SY, RY>(p ? y1 : y0, h, i, b);
   }
@@ -370,32 +373,32 @@ int blas_prec(tp_ctx ctx, int prec, int par0, int npar, const Field* const* fs, 
   }
 }
 
-template <typename SX, typename SY, bool ACC>
-void conv_go(tp_ctx ctx, int par0, int npar, const Field& x, const Field& y) {
+template <typename SX, typename SY, int MODE>
+void conv_go(tp_ctx ctx, int par0, int npar, const Field& x, const Field& y, const Field* z) {
   int64_t V2 = ctx->lat.V2;
   int64_t nb = (V2 + kBlock - 1) / kBlock;
   if (nb > 2048) nb = 2048;
-  hipLaunchKernelGGL((k_convert<SX, SY, ACC>), dim3((unsigned)nb), dim3(kBlock), 0, ctx->stream,
+  hipLaunchKernelGGL((k_convert<SX, SY, MODE>), dim3((unsigned)nb), dim3(kBlock), 0, ctx->stream,
                      x.template par<SX>(0), x.template par<SX>(1), y.template par<SY>(0),
-                     y.template par<SY>(1), par0, npar, V2);
+                     y.template par<SY>(1), fv<SY>(z, 0), fv<SY>(z, 1), par0, npar, V2);
   LAUNCH_CHECK();
 }
 
-template <typename SX, bool ACC>
-void conv_y(tp_ctx ctx, int par0, int npar, const Field& x, const Field& y) {
+template <typename SX, int MODE>
+void conv_y(tp_ctx ctx, int par0, int npar, const Field& x, const Field& y, const Field* z) {
   switch (y.prec) {
-    case TP_F64: conv_go<SX, double2, ACC>(ctx, par0, npar, x, y); break;
-    case TP_F32: conv_go<SX, float2, ACC>(ctx, par0, npar, x, y); break;
-    default: conv_go<SX, __half2, ACC>(ctx, par0, npar, x, y); break;
+    case TP_F64: conv_go<SX, double2, MODE>(ctx, par0, npar, x, y, z); break;
+    case TP_F32: conv_go<SX, float2, MODE>(ctx, par0, npar, x, y, z); break;
+    default: conv_go<SX, __half2, MODE>(ctx, par0, npar, x, y, z); break;
   }
 }
 
-template <bool ACC>
-void conv(tp_ctx ctx, int par0, int npar, const Field& x, const Field& y) {
+template <int MODE>
+void conv(tp_ctx ctx, int par0, int npar, const Field& x, const Field& y, const Field* z = nullptr) {
   switch (x.prec) {
-    case TP_F64: conv_y<double2, ACC>(ctx, par0, npar, x, y); break;
-    case TP_F32: conv_y<float2, ACC>(ctx, par0, npar, x, y); break;
-    default: conv_y<__half2, ACC>(ctx, par0, npar, x, y); break;
+    case TP_F64: conv_y<double2, MODE>(ctx, par0, npar, x, y, z); break;
+    case TP_F32: conv_y<float2, MODE>(ctx, par0, npar, x, y, z); break;
+    default: conv_y<__half2, MODE>(ctx, par0, npar, x, y, z); break;
   }
 }
 
@@ -458,8 +461,18 @@ void blas_impl(tp_ctx ctx, BlasOp op, int par0, int npar, std::initializer_list<
   if (op == B_CONVERT || op == B_MIXED_ACC) {
     if (nr != 1) TP_THROW(TP_EINVAL, "blas: conversions take single fields");
     ProfScope ps(ctx, KID_BLAS_OTHER, n * (S + spinor_bytes(y->prec) * (op == B_MIXED_ACC ? 2 : 1)));
-    if (op == B_CONVERT) conv<false>(ctx, par0, npar, *x, *y);
-    else conv<true>(ctx, par0, npar, *x, *y);
+    if (op == B_CONVERT) conv<0>(ctx, par0, npar, *x, *y);
+    else conv<1>(ctx, par0, npar, *x, *y);
+    return;
+  }
+  if (op == B_MIXED_ADD) {
+    // fields x (any precision), z and y (same precision): y = z + x
+    const Field* z = fs[1];
+    const Field* out = fs[2];
+    if (nr != 1) TP_THROW(TP_EINVAL, "blas: conversions take single fields");
+    if (!x || !z || !out || z->prec != out->prec) TP_THROW(TP_EINVAL, "blas: mixed add fields");
+    ProfScope ps(ctx, KID_BLAS_OTHER, n * (S + spinor_bytes(out->prec) * 2));
+    conv<2>(ctx, par0, npar, *x, *out, z);
     return;
   }
   int nb = 0, nred = 0;

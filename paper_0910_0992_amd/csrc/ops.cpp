@@ -660,7 +660,16 @@ bool bicgstab_reliable(tp_op op, const tp_solve_params& P, const KrylovOp& A, bo
                        double delta, Field& x64, const Field& eta64, Field& r64, double eta2, double& r2,
                        double tol, int max_iter, tp_solve_info& info) {
   tp_ctx ctx = op->g->ctx;
-  Field& xbest = ws_get(op, TP_F64, W_TMP64);
+  // The FP64 iterate lives in x64 or in a spare field: xc is the current one, xb the best seen.
+  // A fold writes the new iterate next to the best one instead of over it, so keeping the best
+  // costs no copy; x64 receives the result once, at the end.
+  Field& spare = ws_get(op, TP_F64, W_TMP64);
+  Field* xc = &x64;
+  Field* xb = &x64;
+  auto finish = [&](bool ok) {
+    if (xc != &x64) blas(ctx, B_COPY, 0, 2, {xc, &x64});
+    return ok;
+  };
   const int pr = A.prec, p0 = A.par0, np = A.npar;
   Field& r = ws_get(op, pr, W_R);
   Field& rh = ws_get(op, pr, W_RHAT);
@@ -682,23 +691,30 @@ bool bicgstab_reliable(tp_op op, const tp_solve_params& P, const KrylovOp& A, bo
     blas(ctx, B_NORM2, p0, np, {&r}, BlasArgs{}, red);
     return red[0];
   };
-  // x64 += S_R y (with the even block of a subset scheme from the segment's source)
+  // x += S_R y (with the even block of a subset scheme from the segment's source)
   auto fold = [&]() {
     if (sub) {
       if (P.scheme == TP_SCHUR4D) launch_schur4d(op, pr, 4, 0, nullptr, y, &et, 0.0, 0.0, 3);
       else blas(ctx, B_COPY, 0, 1, {&et, &y});
     }
     op_reconstruct(op, P.scheme, pr, y, d);
-    blas(ctx, B_MIXED_ACC, 0, 2, {&d, &x64});
-    r2 = true_residual(op, l4, x64, eta64, r64);
+    if (xc == xb) {
+      Field* next = xb == &x64 ? &spare : &x64;
+      blas(ctx, B_MIXED_ADD, 0, 2, {&d, xc, next});
+      xc = next;
+    } else {
+      blas(ctx, B_MIXED_ACC, 0, 2, {&d, xc});
+    }
+    r2 = true_residual(op, l4, *xc, eta64, r64);
     info.outer_iters++;
   };
-  blas(ctx, B_COPY, 0, 2, {&x64, &xbest});
   // on failure: back to the best FP64 iterate seen
   auto give_up = [&]() {
-    blas(ctx, B_COPY, 0, 2, {&xbest, &x64});
-    r2 = true_residual(op, l4, x64, eta64, r64);
-    return false;
+    if (xc != xb) {
+      xc = xb;
+      r2 = true_residual(op, l4, *xc, eta64, r64);
+    }
+    return finish(false);
   };
   double rr2 = restart_residual();
   // the preconditioned residual that corresponds to the true target, scaled per segment
@@ -755,11 +771,11 @@ bool bicgstab_reliable(tp_op op, const tp_solve_params& P, const KrylovOp& A, bo
     if (getenv("TPREC_VERBOSE"))
       fprintf(stderr, "[tprec] reliable update %d at iteration %d: true %.3e\n", info.outer_iters,
               info.iters, sqrt(r2 / eta2));
-    if (sqrt(r2 / eta2) <= tol) return true;
+    if (sqrt(r2 / eta2) <= tol) return finish(true);
     if (r2 < best2) {
       best2 = r2;
       since_best = 0;
-      blas(ctx, B_COPY, 0, 2, {&x64, &xbest});
+      xb = xc;
     } else if (++since_best >= 3 || r2 > 1e4 * best2) {
       return give_up();  // the low-precision recurrence no longer reduces the true residual
     }

@@ -342,7 +342,8 @@ enum BlasOp {
   B_BICG_FUSED,   // x += a p + b s ; r = s - b t ; p = r + c (p - b v) ; |r|^2
                   //                                (fields x, p, s, t, v, r)
   B_G5,           // y = gamma5 x
-  B_MIXED_ACC     // y(F64) += x(any)
+  B_MIXED_ACC,    // y(F64) += x(any)
+  B_MIXED_ADD     // y = z + x (fields x, z, y; z and y of one precision, x any)
 };
 // Device-resident BiCGStab scalars (doubles in tp_ctx_s::bicg): the reduction that ends a
 // level-1 op can turn its results into the next op's coefficients without a host round trip.

@@ -682,7 +682,7 @@ bool bicgstab_reliable(tp_op op, const tp_solve_params& P, const KrylovOp& A, bo
   Field& et = ws_get(op, pr, W_D);
   Field& d = ws_get(op, pr, W_X);
   double red[8];
-  // preconditioned residual of the current x64 into `et` (and r), y = 0; returns |r|^2
+  // preconditioned residual of the current iterate (r64) into `et` (and r), y = 0; returns |r|^2
   auto restart_residual = [&]() {
     blas(ctx, B_CONVERT, 0, 2, {&r64, &rin});
     op_prepare(op, P.scheme, pr, rin, et);

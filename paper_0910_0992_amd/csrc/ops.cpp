@@ -940,7 +940,9 @@ tp_status op_solve_multi(tp_op op, const tp_solve_params& P, int nr, Field& x64,
   Field& s = ws_get_n(op, pr, W_S, nr);
   Field& t = ws_get_n(op, pr, W_T, nr);
   Field& y = ws_get_n(op, pr, W_Y, nr);
-  Field& xbest = ws_get_n(op, TP_F64, W_TMP64, nr);
+  // FP64 iterates of right-hand side q live in x64.view(q) or spare.view(q) (as in the single
+  // solver: a fold writes the new iterate beside the best one, so the best needs no copy)
+  Field& spare = ws_get_n(op, TP_F64, W_TMP64, nr);
   Field& r64 = ws_get_n(op, TP_F64, W_R64, 1);
   Field& rin = ws_get_n(op, pr, W_B, 1);
   Field& et = ws_get_n(op, pr, W_D, 1);
@@ -950,6 +952,7 @@ tp_status op_solve_multi(tp_op op, const tp_solve_params& P, int nr, Field& x64,
     double best2 = 0, seg_best = 0, al_r = 0, al_i = 0;
     int since_best = 0, seg_start = 0, seg_best_it = 0;
     bool done = false, failed = false, upd = false;
+    bool cur_spare = false, best_spare = false;  // where the current and the best iterate live
   };
   std::vector<St> S(nr);
   std::vector<double> red(8 * nr);
@@ -962,7 +965,7 @@ tp_status op_solve_multi(tp_op op, const tp_solve_params& P, int nr, Field& x64,
     if (!isfinite(S[q].eta2)) TP_THROW(TP_EINVAL, "source contains NaN or Inf");
   }
   if (!P.use_x0) blas(ctx, B_ZERO, 0, 2, {nullptr, &x64});
-  blas(ctx, B_COPY, 0, 2, {&x64, &xbest});
+  auto xview = [&](int q, bool in_spare) { return in_spare ? spare.view(q) : x64.view(q); };
   // preconditioned FP64 residual of right-hand side q into r[q]; y[q] = 0
   auto restart_residual = [&](int q) {
     Field rq = r.view(q), yq = y.view(q);
@@ -978,8 +981,7 @@ tp_status op_solve_multi(tp_op op, const tp_solve_params& P, int nr, Field& x64,
     z.seg_start = z.seg_best_it = info[q].iters;
   };
   auto give_up = [&](int q) {
-    Field xq = x64.view(q), bq = xbest.view(q);
-    blas(ctx, B_COPY, 0, 2, {&bq, &xq});
+    S[q].cur_spare = S[q].best_spare;
     S[q].failed = true;
   };
   for (int q = 0; q < nr; ++q) {
@@ -1100,9 +1102,17 @@ tp_status op_solve_multi(tp_op op, const tp_solve_params& P, int nr, Field& x64,
     for (int q = 0; q < nr; ++q) {
       St& z = S[q];
       if (!z.upd || z.failed) continue;
-      Field yq = y.view(q), xq = x64.view(q), rq = r.view(q), rhq = rh.view(q), pq = p.view(q);
+      Field yq = y.view(q), rq = r.view(q), rhq = rh.view(q), pq = p.view(q);
       op_reconstruct(op, P.scheme, pr, yq, d);
-      blas(ctx, B_MIXED_ACC, 0, 2, {&d, &xq});
+      Field xq = xview(q, z.cur_spare);
+      if (z.cur_spare == z.best_spare) {
+        Field nq = xview(q, !z.cur_spare);
+        blas(ctx, B_MIXED_ADD, 0, 2, {&d, &xq, &nq});
+        z.cur_spare = !z.cur_spare;
+        xq = nq;
+      } else {
+        blas(ctx, B_MIXED_ACC, 0, 2, {&d, &xq});
+      }
       z.r2 = true_residual(op, l4, xq, eta64.view(q), r64);
       info[q].outer_iters++;
       if (sqrt(z.r2 / z.eta2) <= tol) {
@@ -1112,8 +1122,7 @@ tp_status op_solve_multi(tp_op op, const tp_solve_params& P, int nr, Field& x64,
       if (z.r2 < z.best2) {
         z.best2 = z.r2;
         z.since_best = 0;
-        Field bq = xbest.view(q);
-        blas(ctx, B_COPY, 0, 2, {&xq, &bq});
+        z.best_spare = z.cur_spare;
       } else if (++z.since_best >= 3 || z.r2 > 1e4 * z.best2 || info[q].outer_iters >= max_upd) {
         give_up(q);
         continue;
@@ -1131,6 +1140,12 @@ tp_status op_solve_multi(tp_op op, const tp_solve_params& P, int nr, Field& x64,
         info[q].restarts++;
       }
     }
+  }
+  // every result (the converged iterate, or the best one of a stalled right-hand side) into x64
+  for (int q = 0; q < nr; ++q) {
+    if (!S[q].cur_spare) continue;
+    Field from = spare.view(q), to = x64.view(q);
+    blas(ctx, B_COPY, 0, 2, {&from, &to});
   }
   // right-hand sides that stalled continue alone from their best iterate
   for (int q = 0; q < nr; ++q) {
